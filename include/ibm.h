@@ -1,0 +1,238 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) solver for the discrete-forcing
+ * immersed-boundary, fractional-step incompressible Navier-Stokes method of
+ * Sundar, Majumdar, Shah & Sarkar (arXiv 2402.17337).
+ *
+ * The method (paper Sec. 2.1-2.3, Eqs. 1-4): a rigid ellipse (thickness /
+ * chord 0.12) plunging as y = h sin(k t) in a uniform stream, on a Cartesian
+ * staggered grid that is uniform around the body and stretched outward.  Each
+ * time step classifies mesh points as fluid or solid, forms the momentum
+ * predictor (Adams-Bashforth convection, Crank-Nicolson diffusion), applies
+ * the immersed-boundary forcing f at the solid points, solves the implicit
+ * velocity equations and the pressure-correction Poisson equation with
+ * red-black Gauss-Seidel SOR, and projects.
+ *
+ * Discrete reading used here (the paper prints no formulas):
+ *   - faces xf[0..nx], yf[0..ny]; p at cell centres (nx*ny), u at x-faces
+ *     ((nx+1)*ny), v at y-faces (nx*(ny+1)); every array row-major, x fastest;
+ *   - channel boundaries: inflow u = u_inf and v = 0 on the x = xf[0] face,
+ *     slip walls at y = yf[0], yf[ny], convective outflow for u and zero
+ *     gradient for v at x = xf[nx]; the pressure correction phi is Neumann
+ *     except phi = 0 on the outlet face;
+ *   - incremental pressure: A phi = V (D(u^) - q)/dt with A = V D G,
+ *     u^{n+1} = u^ - dt G phi, p^{n+1} = p^n + phi - dt/(2 Re) L phi;
+ *   - forced nodes are those strictly inside the ellipse; those with an
+ *     outside 4-neighbour take a target by linear extrapolation through the
+ *     boundary crossing on each grid line (weight d_f/d_o capped at
+ *     alpha_max), the others the body velocity; f = (target - u~)/dt;
+ *   - mass source q (Eq. 4): divergence of (u^ - body velocity) over a cell's
+ *     forced faces, so the Poisson source sees forced faces moving with the
+ *     body;
+ *   - forces F = -sum f dV + pi a b (0, a_body); C = 2 F / (u_inf^2 chord).
+ *
+ * Conventions for every entry point:
+ *   - return IBM_OK (0) on success, a positive soft status or a negative
+ *     error code; ibm_last_error() gives a message for the context;
+ *   - "host" pointers are ordinary CPU memory and are copied; "device"
+ *     pointers are HIP device memory on the context's device, borrowed for the
+ *     duration of the call only;
+ *   - all GPU work is enqueued on the HIP stream given to ibm_init and is
+ *     ordered with the caller's other work on that stream;
+ *   - a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IBM_OK 0
+#define IBM_NOT_CONVERGED 1 /* soft: an iterative solve stopped at its iteration limit */
+#define IBM_ERR_INVALID (-1) /* invalid argument; nothing was enqueued */
+#define IBM_ERR_HIP (-2)     /* a HIP runtime call failed */
+#define IBM_ERR_STATE (-3)   /* context in a state that forbids the call */
+#define IBM_ERR_NAN (-5)     /* a residual became NaN or Inf; the state is not usable */
+
+/* boundary conditions */
+#define IBM_BC_CHANNEL 0
+
+/* pressure solvers */
+#define IBM_SOLVER_RBSOR 0 /* red-black SOR, red = (i+j) even updated first */
+#define IBM_SOLVER_PCG 1   /* conjugate gradients on -A, Jacobi preconditioner */
+
+/* initial guess of the pressure correction at each step */
+#define IBM_INIT_ZERO 0
+#define IBM_INIT_PREVIOUS 1
+
+/* arithmetic of the sweeps */
+#define IBM_PREC_FP64 0
+
+/* Problem and solver parameters.  Lengths in chords, velocities in u_inf. */
+typedef struct ibm_params {
+    int32_t nx, ny;          /* cells in x and y; both even and >= 8 */
+    int32_t bc_mode;         /* IBM_BC_CHANNEL */
+    int32_t body;            /* 1: ellipse present; 0: no body */
+    double re;               /* Reynolds number u_inf c / nu, > 0 */
+    double dt;               /* time step, > 0 */
+    double u_inf;            /* free-stream (inflow) velocity */
+    double chord;            /* ellipse major axis (= 2a) */
+    double thickness;        /* thickness / chord (minor axis = thickness * chord) */
+    double x0, y0;           /* centre of the ellipse at rest position */
+    double amp, freq, phase; /* plunge y_c = y0 + amp sin(2 pi freq t + phase) (Eqs. 1-2, k = 2 pi freq) */
+    int32_t p_method;        /* IBM_SOLVER_RBSOR or IBM_SOLVER_PCG */
+    int32_t p_max_iter;      /* iteration limit of one pressure solve, >= 1 */
+    int32_t p_check_every;   /* SOR: residual tested every this many iterations, >= 1 */
+    int32_t p_init;          /* IBM_INIT_ZERO or IBM_INIT_PREVIOUS */
+    double p_omega;          /* SOR relaxation factor, 0 < omega < 2 */
+    double p_tol;            /* stop when ||V b - A phi||_2 <= p_tol ||V b||_2 */
+    double uv_omega;         /* relaxation factor of the implicit velocity solves */
+    double uv_tol;           /* their relative residual tolerance (tested every iteration) */
+    int32_t uv_max_iter;     /* their iteration limit, >= 1 */
+    int32_t q_mode;          /* 1: mass source in cells with forced faces; 0: q = 0 */
+    double alpha_max;        /* cap of the extrapolation weight d_f/d_o, >= 0 */
+    int32_t precision;       /* IBM_PREC_FP64 */
+    int32_t reserved;        /* must be 0 */
+} ibm_params;
+
+/* Statistics of the last step of an ibm_step call. */
+typedef struct ibm_step_stats {
+    int32_t status;                   /* worst status of the step */
+    int32_t p_iters;                  /* pressure iterations */
+    int32_t u_iters, v_iters;         /* implicit velocity iterations */
+    int32_t n_forced_u, n_forced_v;   /* forced u and v nodes */
+    int32_t n_msrc;                   /* cells with a forced face */
+    int32_t reserved;
+    double p_r0;                      /* initial residual / ||V b|| of the pressure solve */
+    double p_rel;                     /* final residual / ||V b|| */
+    double cd, cl;                    /* drag and lift coefficients */
+    double t;                         /* time reached */
+    double seconds;                   /* host wall time of the whole ibm_step call */
+} ibm_step_stats;
+
+/* Options of a stand-alone Poisson solve. */
+typedef struct ibm_solve_opts {
+    int32_t method;       /* IBM_SOLVER_RBSOR or IBM_SOLVER_PCG */
+    int32_t max_iter;     /* iteration limit, >= 1 */
+    int32_t check_every;  /* SOR residual test interval, >= 1 (PCG tests every iteration) */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations, tol ignored */
+    double omega;         /* SOR relaxation factor */
+    double tol;           /* relative residual tolerance */
+} ibm_solve_opts;
+
+typedef struct ibm_solve_stats {
+    int32_t status;       /* IBM_OK, IBM_NOT_CONVERGED or IBM_ERR_NAN */
+    int32_t iters;        /* iterations performed */
+    int32_t reserved0, reserved1;
+    double r0_rel;        /* initial residual / ||V b|| */
+    double rel;           /* final residual / ||V b|| */
+    double seconds;       /* GPU time of the solve (HIP events on the context stream) */
+} ibm_solve_stats;
+
+typedef struct ibm_ctx ibm_ctx;
+
+/* Device workspace a context needs for prm, in bytes (0 if prm is invalid).
+ * Pure function; no GPU call. */
+size_t ibm_workspace_bytes(const ibm_params* prm);
+
+/* Create a context.
+ *   xf[nx+1], yf[ny+1]     host; strictly increasing face coordinates;
+ *   u0[(nx+1)*ny], v0[nx*(ny+1)], p0[nx*ny]
+ *                          host initial fields, or NULL for u = u_inf, v = 0,
+ *                          p = 0; the inflow u and wall v are always reset to
+ *                          their boundary values;
+ *   workspace              device memory of at least ibm_workspace_bytes(prm)
+ *                          bytes, 256-byte aligned, owned by the caller, which
+ *                          must keep it alive until ibm_destroy; the library
+ *                          never frees it;
+ *   hip_stream             hipStream_t (NULL = the null stream), borrowed.
+ * Errors: IBM_ERR_INVALID for odd or too small nx/ny, non-increasing faces,
+ * dt <= 0, re <= 0, omega outside (0, 2), a body whose range of motion comes
+ * within two cells of the boundary, an unsupported bc_mode or precision, a
+ * small or misaligned workspace; IBM_ERR_HIP if the device rejects the setup.
+ * Validation happens before any GPU call. */
+int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, const double* u0,
+                 const double* v0, const double* p0, void* workspace, size_t workspace_bytes,
+                 void* hip_stream, ibm_ctx** out);
+
+/* Advance nsteps (>= 1) time steps.  Each step: classification at
+ * t^{n+1}, momentum predictor, forcing, implicit velocity solves, pressure
+ * Poisson solve (p_method, from zero or the previous phi), projection,
+ * pressure update, forces.  Returns the worst status; IBM_NOT_CONVERGED is
+ * soft (the step completed at the iteration limit), IBM_ERR_NAN stops the
+ * call.  last (nullable) receives the statistics of the last step. */
+int32_t ibm_step(ibm_ctx* ctx, int32_t nsteps, ibm_step_stats* last);
+
+/* Solve the cell-centred Poisson problem (D G) x = rhs on the context's grid
+ * and boundary conditions (the pressure-correction operator A / V).
+ *   rhs_dev[nx*ny]  device, per unit volume, natural layout; read only;
+ *   x_dev[nx*ny]    device; initial guess on entry, solution on exit.
+ * Stream-ordered; returns after the solve has finished.  rhs = 0 gives
+ * x = 0 with 0 iterations.  Does not touch the time-stepping state. */
+int32_t ibm_poisson_solve(ibm_ctx* ctx, const double* rhs_dev, double* x_dev, const ibm_solve_opts* opts,
+                          ibm_solve_stats* stats);
+
+/* Drag and lift coefficients of the last completed step (0 before the
+ * first).  Synchronizes the context stream. */
+int32_t ibm_forces(ibm_ctx* ctx, double* cd, double* cl);
+
+/* Host copies of the current fields; each pointer is nullable.
+ * u[(nx+1)*ny], v[nx*(ny+1)], p[nx*ny], phi[nx*ny].  Synchronizes. */
+int32_t ibm_get_fields(ibm_ctx* ctx, double* u, double* v, double* p, double* phi);
+
+/* Immersed-boundary data of the last step (each pointer nullable):
+ * flu[(nx+1)*ny], flv[nx*(ny+1)] (0 fluid, 1 forcing, 2 deep),
+ * msrc[nx*ny] (1 = cell with a forced face), fu, fv (forcing f, full-size
+ * arrays, zero away from forced nodes).  Synchronizes. */
+int32_t ibm_get_ibm(ibm_ctx* ctx, uint8_t* flu, uint8_t* flv, uint8_t* msrc, double* fu, double* fv);
+
+/* Checkpoint: bytes needed, then a host copy of the complete state (fields,
+ * phi, convection history, time, step count, forces) and its restore.  A run
+ * restored from a checkpoint continues bit for bit as the uninterrupted run.
+ * IBM_ERR_INVALID if bytes is too small or the blob does not match the grid. */
+size_t ibm_state_bytes(const ibm_ctx* ctx);
+int32_t ibm_get_state(ibm_ctx* ctx, void* host, size_t bytes);
+int32_t ibm_set_state(ibm_ctx* ctx, const void* host, size_t bytes);
+
+/* Replay schedule of pressure iterations: the next n steps each run exactly
+ * iters[k] pressure iterations (tolerance ignored), e.g. to reproduce the
+ * iteration sequence of a reference run.  n = 0 clears the schedule.  host
+ * array, copied. */
+int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
+
+/* Kernel timing with HIP events on the context stream.  sample_every > 0
+ * brackets every sample_every-th launch of each timed kernel with a pair of
+ * events; 0 switches it off and clears the samples.
+ * ibm_profile_query: kernel id (IBM_KERNEL_*), average duration of the
+ * sampled launches in ms, number of samples, number of launches, and the
+ * algorithmic bytes one launch moves on this grid.  Launches that only
+ * observed a finished solve (the tail enqueued ahead of the convergence
+ * test) are not sampled.  Synchronizes. */
+#define IBM_KERNEL_SOR_SWEEP 0    /* one colour of an SOR iteration: 24 B per cell updated */
+#define IBM_KERNEL_SOR_RESIDUAL 1 /* residual check: 16 B per cell (phi, V b) */
+#define IBM_KERNEL_PCG_SPMV 2     /* q = M p: 16 B per cell */
+#define IBM_KERNEL_PCG_UPDATE 3   /* x, r update: 48 B per cell */
+#define IBM_KERNEL_PCG_DIR 4      /* p = z + beta p: 24 B per cell */
+#define IBM_KERNEL_COUNT 5
+int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
+int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
+                          double* bytes_per_launch);
+
+/* Release the context (not the workspace).  Synchronizes the stream first. */
+void ibm_destroy(ibm_ctx* ctx);
+
+/* Static text of a status code. */
+const char* ibm_status_string(int32_t status);
+
+/* Last error message of the context ("" if none); valid until the next call. */
+const char* ibm_last_error(const ibm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_H */

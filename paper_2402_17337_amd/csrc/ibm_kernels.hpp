@@ -1,0 +1,934 @@
+// ibm_kernels.hpp -- gfx950 kernels of one time step of the discrete-forcing
+// immersed-boundary fractional-step solver (arXiv 2402.17337, Sec. 2.2).
+//
+// Layouts (FP64, row-major, x fastest):
+//   u[(nx+1)*ny] x-faces, v[nx*(ny+1)] y-faces, p/phi/vb[nx*ny] centres.
+//   Red-black split storage for the pressure sweeps: row j of the red array
+//   holds the nx/2 cells with (i+j) even, i = 2m + (j&1); the black array the
+//   cells with (i+j) odd, i = 2m + 1 - (j&1).  Both colours of a row are
+//   contiguous, so a colour sweep reads and writes unit-stride rows.
+//
+// The pointwise kernels of the step (momentum, forcing, right-hand side,
+// projection) evaluate their formulas without floating-point contraction, in
+// the operand order of a plain evaluation; the sweeps and reductions of the
+// iterative solvers use fused multiply-adds.
+#pragma once
+
+#include "ibm_device.hpp"
+
+namespace ibm {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void k_ctl_reset(Ctl* ctl, int n) {
+    const int t = threadIdx.x;
+    if (t < n) {
+        Ctl c = {};
+        ctl[t] = c;
+    }
+}
+
+__global__ void k_fill(double* a, size_t n, double val) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) a[k] = val;
+}
+
+__global__ void k_fill_u8(uint8_t* a, size_t n) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) a[k] = 0;
+}
+
+// Natural -> red/black split (optionally multiplied by the cell volume).
+__global__ __launch_bounds__(kBlock) void k_split(Grid g, const double* __restrict__ nat, double* __restrict__ red,
+                                                  double* __restrict__ black, int by_volume) {
+#pragma clang fp contract(off)
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (m >= g.nh || j >= g.ny) return;
+    const int ir = 2 * m + (j & 1), ib = 2 * m + 1 - (j & 1);
+    const size_t k = (size_t)j * g.nh + m;
+    const double xr = nat[(size_t)j * g.nx + ir], xb = nat[(size_t)j * g.nx + ib];
+    if (by_volume) {
+        red[k] = (g.dx[ir] * g.dy[j]) * xr;
+        black[k] = (g.dx[ib] * g.dy[j]) * xb;
+    } else {
+        red[k] = xr;
+        black[k] = xb;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge(Grid g, const double* __restrict__ red,
+                                                  const double* __restrict__ black, double* __restrict__ nat) {
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (m >= g.nh || j >= g.ny) return;
+    const int ir = 2 * m + (j & 1), ib = 2 * m + 1 - (j & 1);
+    const size_t k = (size_t)j * g.nh + m;
+    nat[(size_t)j * g.nx + ir] = red[k];
+    nat[(size_t)j * g.nx + ib] = black[k];
+}
+
+// ---------------------------------------------------------------------------
+// Pressure Poisson: red-black SOR on A phi = V b in split storage
+// ---------------------------------------------------------------------------
+// Neighbour sum and diagonal of row (i, j) of A, reading the other colour
+// (split index k of the cell, s = its position parity in the row).
+__device__ inline double rb_row(const Grid& g, const double* __restrict__ other, int i, int j, size_t k, int s,
+                                double& d) {
+    const double dyj = g.dy[j], dxi = g.dx[i];
+    double sum = 0.0;
+    if (i < g.nx - 1) {
+        const double a = dyj * g.pcE[i];
+        sum = a * other[k + s];
+        d = a;
+    } else {
+        d = dyj * g.pcD[i];
+    }
+    if (i > 0) {
+        const double a = dyj * g.pcW[i];
+        sum += a * other[k + s - 1];
+        d += a;
+    }
+    if (j < g.ny - 1) {
+        const double a = dxi * g.pcN[j];
+        sum += a * other[k + g.nh];
+        d += a;
+    }
+    if (j > 0) {
+        const double a = dxi * g.pcS[j];
+        sum += a * other[k - g.nh];
+        d += a;
+    }
+    return sum;
+}
+
+// One colour of a red-black SOR iteration:
+//   phi_P <- (1 - omega) phi_P + omega (sum a_nb phi_nb - V b_P) / (sum a_nb + a_D)
+// COLOR 0 updates the red cells ((i+j) even), COLOR 1 the black cells.
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_sor_sweep(Grid g, double* __restrict__ self,
+                                                      const double* __restrict__ other,
+                                                      const double* __restrict__ bself, double omega,
+                                                      const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (m >= g.nh || j >= g.ny) return;
+    const int s = (j + COLOR) & 1;
+    const int i = 2 * m + s;
+    const size_t k = (size_t)j * g.nh + m;
+    double d;
+    const double sum = rb_row(g, other, i, j, k, s, d);
+    const double gs = (sum - bself[k]) / d;
+    self[k] = (1.0 - omega) * self[k] + omega * gs;
+}
+
+// Residual r = V b - A phi over both colours; sum r^2 and (V b)^2, then the
+// stop test of the solve.  phase 0 is the check before the first iteration.
+__global__ __launch_bounds__(kBlock) void k_sor_residual(Grid g, const double* __restrict__ red,
+                                                         const double* __restrict__ black,
+                                                         const double* __restrict__ bred,
+                                                         const double* __restrict__ bblack, Ctl* ctl,
+                                                         double* partials, int phase, int it, int max_iter,
+                                                         double tol, int fixed, Slot* hs) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (ctl->done) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
+        return;
+    }
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[2] = {0.0, 0.0};
+    if (m < g.nh && j < g.ny) {
+        const size_t k = (size_t)j * g.nh + m;
+        {
+            const int s = j & 1, i = 2 * m + s;
+            double d;
+            const double sum = rb_row(g, black, i, j, k, s, d);
+            const double r = bred[k] - (sum - d * red[k]);
+            acc[0] += r * r;
+            acc[1] += bred[k] * bred[k];
+        }
+        {
+            const int s = (j + 1) & 1, i = 2 * m + s;
+            double d;
+            const double sum = rb_row(g, red, i, j, k, s, d);
+            const double r = bblack[k] - (sum - d * black[k]);
+            acc[0] += r * r;
+            acc[1] += bblack[k] * bblack[k];
+        }
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        check_finish(ctl, acc[0], acc[1], phase, it, max_iter, tol, fixed, 0);
+        publish(ctl, hs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pressure Poisson: Jacobi-preconditioned CG on M = -A, natural layout
+// ---------------------------------------------------------------------------
+__device__ inline double nat_row(const Grid& g, const double* __restrict__ x, int i, int j, size_t k, double& d) {
+    const double dyj = g.dy[j], dxi = g.dx[i];
+    double sum = 0.0;
+    if (i < g.nx - 1) {
+        const double a = dyj * g.pcE[i];
+        sum = a * x[k + 1];
+        d = a;
+    } else {
+        d = dyj * g.pcD[i];
+    }
+    if (i > 0) {
+        const double a = dyj * g.pcW[i];
+        sum += a * x[k - 1];
+        d += a;
+    }
+    if (j < g.ny - 1) {
+        const double a = dxi * g.pcN[j];
+        sum += a * x[k + g.nx];
+        d += a;
+    }
+    if (j > 0) {
+        const double a = dxi * g.pcS[j];
+        sum += a * x[k - g.nx];
+        d += a;
+    }
+    return sum;
+}
+
+__device__ inline double nat_diag(const Grid& g, int i, int j) {
+    const double dyj = g.dy[j], dxi = g.dx[i];
+    double d = (i < g.nx - 1) ? dyj * g.pcE[i] : dyj * g.pcD[i];
+    if (i > 0) d += dyj * g.pcW[i];
+    if (j < g.ny - 1) d += dxi * g.pcN[j];
+    if (j > 0) d += dxi * g.pcS[j];
+    return d;
+}
+
+// r = -V b + A x (residual of M x = -V b), p = z = r / diag(M); sums r.z,
+// r.r, (V b)^2 and the first stop test.
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const double* __restrict__ x,
+                                                     const double* __restrict__ vb, double* __restrict__ r,
+                                                     double* __restrict__ p, Ctl* ctl, double* partials,
+                                                     double tol, Slot* hs) {
+    __shared__ double lds[3 * kBlock / kWave];
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < g.nx && j < g.ny) {
+        const size_t k = (size_t)j * g.nx + i;
+        double d;
+        const double sum = nat_row(g, x, i, j, k, d);
+        const double rk = -vb[k] + (sum - d * x[k]);
+        const double zk = rk / d;
+        r[k] = rk;
+        p[k] = zk;
+        acc[0] = rk * zk;
+        acc[1] = rk * rk;
+        acc[2] = vb[k] * vb[k];
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        ctl->rz = acc[0];
+        ctl->beta = 0.0;
+        check_finish(ctl, acc[1], acc[2], 0, 0, 0, tol, 0, 0);
+        publish(ctl, hs);
+    }
+}
+
+// q = M p, alpha = r.z / p.q
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Grid g, const double* __restrict__ p, double* __restrict__ q,
+                                                     Ctl* ctl, double* partials) {
+    __shared__ double lds[kBlock / kWave];
+    if (ctl->done) return;
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[1] = {0.0};
+    if (i < g.nx && j < g.ny) {
+        const size_t k = (size_t)j * g.nx + i;
+        double d;
+        const double sum = nat_row(g, p, i, j, k, d);
+        const double qk = -(sum - d * p[k]);
+        q[k] = qk;
+        acc[0] = p[k] * qk;
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) ctl->alpha = ctl->rz / acc[0];
+}
+
+// x += alpha p, r -= alpha q; sums r.r and r.z with z = r / diag(M); stop
+// test on the recursive residual (kStConfirm asks the host for the true
+// residual), else beta = (r.z)_new / (r.z)_old.
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       Ctl* ctl, double* partials, int it, int max_iter, double tol,
+                                                       int fixed, Slot* hs) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (ctl->done) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
+        return;
+    }
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    const double alpha = ctl->alpha;
+    double acc[2] = {0.0, 0.0};
+    if (i < g.nx && j < g.ny) {
+        const size_t k = (size_t)j * g.nx + i;
+        x[k] += alpha * p[k];
+        const double rk = r[k] - alpha * q[k];
+        r[k] = rk;
+        acc[0] = rk * rk;
+        acc[1] = rk * (rk / nat_diag(g, i, j));
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(acc[0]);
+        ctl->rn = rn;
+        ctl->iters = it;
+        if (!isfinite(rn)) {
+            ctl->done = kDone;
+            ctl->status = kStNan;
+        } else if (rn <= tol * ctl->bn) {
+            ctl->done = kDone;
+            ctl->status = kStConfirm;
+        } else if (it >= max_iter) {
+            ctl->done = kDone;
+            ctl->status = fixed ? kStOk : kStNotConverged;
+        } else {
+            ctl->beta = acc[1] / ctl->rz;
+            ctl->rz = acc[1];
+        }
+        publish(ctl, hs);
+    }
+}
+
+// p = z + beta p with z = r / diag(M)
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(Grid g, const double* __restrict__ r, double* __restrict__ p,
+                                                    const Ctl* ctl) {
+    if (ctl->done) return;
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t k = (size_t)j * g.nx + i;
+    p[k] = r[k] / nat_diag(g, i, j) + ctl->beta * p[k];
+}
+
+// True residual r = -V b + A x; accepts the solve (status ok) or restarts the
+// recursion from it (r.z recomputed, beta = 0, solve running again).
+__global__ __launch_bounds__(kBlock) void k_pcg_true_residual(Grid g, const double* __restrict__ x,
+                                                              const double* __restrict__ vb, double* __restrict__ r,
+                                                              Ctl* ctl, double* partials, double tol, Slot* hs) {
+    __shared__ double lds[2 * kBlock / kWave];
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[2] = {0.0, 0.0};
+    if (i < g.nx && j < g.ny) {
+        const size_t k = (size_t)j * g.nx + i;
+        double d;
+        const double sum = nat_row(g, x, i, j, k, d);
+        const double rk = -vb[k] + (sum - d * x[k]);
+        r[k] = rk;
+        acc[0] = rk * rk;
+        acc[1] = rk * (rk / d);
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(acc[0]);
+        ctl->rn = rn;
+        if (!isfinite(rn)) {
+            ctl->status = kStNan;
+        } else if (rn <= tol * ctl->bn) {
+            ctl->status = kStOk;
+        } else {
+            ctl->rz = acc[1];
+            ctl->beta = 0.0;
+            ctl->status = kStOk;
+            ctl->done = kRunning;
+        }
+        publish(ctl, hs);
+    }
+}
+
+// Fixed-iteration PCG end: true residual for the statistics only.
+__global__ __launch_bounds__(kBlock) void k_pcg_final_residual(Grid g, const double* __restrict__ x,
+                                                               const double* __restrict__ vb, Ctl* ctl,
+                                                               double* partials, Slot* hs) {
+    __shared__ double lds[kBlock / kWave];
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[1] = {0.0};
+    if (i < g.nx && j < g.ny) {
+        const size_t k = (size_t)j * g.nx + i;
+        double d;
+        const double sum = nat_row(g, x, i, j, k, d);
+        const double rk = -vb[k] + (sum - d * x[k]);
+        acc[0] = rk * rk;
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        ctl->rn = sqrt(acc[0]);
+        publish(ctl, hs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Implicit viscous half: (I - beta L) x = rhs by red-black SOR, natural layout
+// ---------------------------------------------------------------------------
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_helm_u_sweep(Grid g, double* __restrict__ u,
+                                                         const double* __restrict__ rhs, double beta, double omega,
+                                                         const Ctl* ctl) {
+#pragma clang fp contract(off)
+    if (ctl->done) return;
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    const int i = 2 * m + ((j + COLOR) & 1);
+    if (j >= g.ny || i < 1 || i > g.nx - 1) return;
+    const int W = g.nx + 1;
+    const size_t k = (size_t)j * W + i;
+    const double ce = g.uce[i], cw = g.ucw[i];
+    double s = ce * u[k + 1] + cw * u[k - 1];
+    double cs = ce + cw;
+    if (j < g.ny - 1) {
+        const double a = g.ucn[j];
+        s += a * u[k + W];
+        cs += a;
+    }
+    if (j > 0) {
+        const double a = g.ucs[j];
+        s += a * u[k - W];
+        cs += a;
+    }
+    const double gs = (rhs[k] + beta * s) / (1.0 + beta * cs);
+    u[k] = (1.0 - omega) * u[k] + omega * gs;
+}
+
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_helm_v_sweep(Grid g, double* __restrict__ v,
+                                                         const double* __restrict__ rhs, double beta, double omega,
+                                                         const Ctl* ctl) {
+#pragma clang fp contract(off)
+    if (ctl->done) return;
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    const int i = 2 * m + ((j + COLOR) & 1);
+    if (j < 1 || j > g.ny - 1 || i > g.nx - 1) return;
+    const int W = g.nx;
+    const size_t k = (size_t)j * W + i;
+    const double cn = g.vcn[j], cso = g.vcs[j];
+    double s = cn * v[k + W] + cso * v[k - W];
+    double cs = cn + cso;
+    if (i < g.nx - 1) {
+        const double a = g.vce[i];
+        s += a * v[k + 1];
+        cs += a;
+    }
+    if (i > 0) {
+        const double a = g.vcw[i];
+        s += a * v[k - 1];
+        cs += a;
+    } else {
+        const double a = g.vcw[0];
+        s += a * 0.0;
+        cs += a;
+    }
+    const double gs = (rhs[k] + beta * s) / (1.0 + beta * cs);
+    v[k] = (1.0 - omega) * v[k] + omega * gs;
+}
+
+__device__ inline double lap_u(const Grid& g, const double* __restrict__ u, int i, int j) {
+#pragma clang fp contract(off)
+    const int W = g.nx + 1;
+    const size_t k = (size_t)j * W + i;
+    const double uP = u[k];
+    double L = (u[k + 1] - uP) / (g.dx[i] * g.dxu[i]) + (u[k - 1] - uP) / (g.dx[i - 1] * g.dxu[i]);
+    if (j < g.ny - 1) L += (u[k + W] - uP) / (g.dyv[j + 1] * g.dy[j]);
+    if (j > 0) L += (u[k - W] - uP) / (g.dyv[j] * g.dy[j]);
+    return L;
+}
+
+__device__ inline double lap_v(const Grid& g, const double* __restrict__ v, int i, int j) {
+#pragma clang fp contract(off)
+    const int W = g.nx;
+    const size_t k = (size_t)j * W + i;
+    const double vP = v[k];
+    double L = (v[k + W] - vP) / (g.dy[j] * g.dyv[j]) + (v[k - W] - vP) / (g.dy[j - 1] * g.dyv[j]);
+    if (i < g.nx - 1) L += (v[k + 1] - vP) / (g.dxu[i + 1] * g.dx[i]);
+    if (i > 0) L += (v[k - 1] - vP) / (g.dxu[i] * g.dx[i]);
+    else L += (0.0 - vP) / (g.dxu[0] * g.dx[0]);
+    return L;
+}
+
+// Residual of the implicit viscous equation, r = rhs - (x - beta L x), over
+// the unknowns of component `comp` (0: u faces 1..nx-1, 1: v faces 1..ny-1).
+__global__ __launch_bounds__(kBlock) void k_helm_residual(Grid g, int comp, const double* __restrict__ x,
+                                                          const double* __restrict__ rhs, double beta, Ctl* ctl,
+                                                          double* partials, int phase, int it, int max_iter,
+                                                          double tol, Slot* hs) {
+#pragma clang fp contract(off)
+    __shared__ double lds[2 * kBlock / kWave];
+    if (ctl->done) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
+        return;
+    }
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    double acc[2] = {0.0, 0.0};
+    if (comp == 0) {
+        if (i >= 1 && i <= g.nx - 1 && j < g.ny) {
+            const size_t k = (size_t)j * (g.nx + 1) + i;
+            const double r = rhs[k] - (x[k] - beta * lap_u(g, x, i, j));
+            acc[0] = r * r;
+            acc[1] = rhs[k] * rhs[k];
+        }
+    } else {
+        if (i < g.nx && j >= 1 && j <= g.ny - 1) {
+            const size_t k = (size_t)j * g.nx + i;
+            const double r = rhs[k] - (x[k] - beta * lap_v(g, x, i, j));
+            acc[0] = r * r;
+            acc[1] = rhs[k] * rhs[k];
+        }
+    }
+    if (!grid_sum(acc, partials, ctl, lds)) return;
+    if (threadIdx.x == 0) {
+        check_finish(ctl, acc[0], acc[1], phase, it, max_iter, tol, 0, 1);
+        publish(ctl, hs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Momentum predictor (Adams-Bashforth convection, Crank-Nicolson diffusion)
+//   R = u^n + dt [-(3/2 N^n - 1/2 N^{n-1}) - G p^n + 1/(2Re) L u^n]
+// N in divergence form with arithmetic averages; N^{-1} := N^0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_momentum_u(Grid g, const double* __restrict__ u,
+                                                       const double* __restrict__ v, const double* __restrict__ p,
+                                                       double* __restrict__ nu, double* __restrict__ ru, double dt,
+                                                       double re, double uinf, int have_hist) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i < 1 || i > g.nx || j >= g.ny) return;
+    const int nx = g.nx, W = nx + 1;
+    const size_t k = (size_t)j * W + i;
+    if (i == nx) {  // convective outlet, kept in the R array until committed
+        const double uo = u[k], ui = u[k - 1];
+        ru[k] = uo - dt * uinf * (uo - ui) / g.dx[nx - 1];
+        return;
+    }
+    const double uP = u[k];
+    const double ue = 0.5 * (uP + u[k + 1]);
+    const double uw = 0.5 * (u[k - 1] + uP);
+    const double nxp = (ue * ue - uw * uw) / g.dxu[i];
+    double fn = 0.0, fs = 0.0;
+    if (j < g.ny - 1) {
+        const double vc = 0.5 * (v[(size_t)(j + 1) * nx + i - 1] + v[(size_t)(j + 1) * nx + i]);
+        const double uc = 0.5 * (uP + u[k + W]);
+        fn = vc * uc;
+    }
+    if (j > 0) {
+        const double vc = 0.5 * (v[(size_t)j * nx + i - 1] + v[(size_t)j * nx + i]);
+        const double uc = 0.5 * (u[k - W] + uP);
+        fs = vc * uc;
+    }
+    const double N = nxp + (fn - fs) / g.dy[j];
+    const double L = lap_u(g, u, i, j);
+    const double G = (p[(size_t)j * nx + i] - p[(size_t)j * nx + i - 1]) / g.dxu[i];
+    const double Nold = have_hist ? nu[k] : N;
+    ru[k] = uP + dt * (-(1.5 * N - 0.5 * Nold) - G + (0.5 / re) * L);
+    nu[k] = N;
+}
+
+__global__ __launch_bounds__(kBlock) void k_momentum_v(Grid g, const double* __restrict__ u,
+                                                       const double* __restrict__ v, const double* __restrict__ p,
+                                                       double* __restrict__ nv, double* __restrict__ rv, double dt,
+                                                       double re, int have_hist) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j < 1 || j > g.ny - 1) return;
+    const int nx = g.nx, W = nx + 1;
+    const size_t k = (size_t)j * nx + i;
+    const double vP = v[k];
+    const double vn = 0.5 * (vP + v[k + nx]);
+    const double vs = 0.5 * (v[k - nx] + vP);
+    const double nyp = (vn * vn - vs * vs) / g.dyv[j];
+    const double ue = 0.5 * (u[(size_t)(j - 1) * W + i + 1] + u[(size_t)j * W + i + 1]);
+    const double ve = (i < nx - 1) ? 0.5 * (vP + v[k + 1]) : vP;
+    const double uw = 0.5 * (u[(size_t)(j - 1) * W + i] + u[(size_t)j * W + i]);
+    const double vw = (i > 0) ? 0.5 * (v[k - 1] + vP) : 0.0;
+    const double N = (ue * ve - uw * vw) / g.dx[i] + nyp;
+    const double L = lap_v(g, v, i, j);
+    const double G = (p[(size_t)j * nx + i] - p[(size_t)(j - 1) * nx + i]) / g.dyv[j];
+    const double Nold = have_hist ? nv[k] : N;
+    rv[k] = vP + dt * (-(1.5 * N - 0.5 * Nold) - G + (0.5 / re) * L);
+    nv[k] = N;
+}
+
+// Move the convective-outlet value from R into u before the implicit solve.
+__global__ void k_outlet_commit(int nx, int ny, double* __restrict__ u, const double* __restrict__ ru) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ny) return;
+    const size_t k = (size_t)j * (nx + 1) + nx;
+    u[k] = ru[k];
+}
+
+// ---------------------------------------------------------------------------
+// Immersed boundary: classification (one block over the body's motion box)
+// ---------------------------------------------------------------------------
+// Box in cell indices [bi0, bi1) x [bj0, bj1): u faces i in [bi0, bi1],
+// v faces j in [bj0, bj1]; every node that can be inside the body during the
+// run lies in it.  flu/flv = 0 fluid, 1 forcing, 2 deep; msrc = 1 for cells
+// with a forced face.  Forced nodes are listed in row-major order.
+struct Box {
+    int bi0, bi1, bj0, bj1;
+};
+
+__device__ inline int node_type_u(const Grid& g, const Body& B, int i, int j) {
+    if (!inside(g.xf[i], g.yc[j], B)) return 0;
+    const bool all = inside(g.xf[i + 1], g.yc[j], B) && inside(g.xf[i - 1], g.yc[j], B) &&
+                     inside(g.xf[i], g.yc[j + 1], B) && inside(g.xf[i], g.yc[j - 1], B);
+    return all ? 2 : 1;
+}
+__device__ inline int node_type_v(const Grid& g, const Body& B, int i, int j) {
+    if (!inside(g.xc[i], g.yf[j], B)) return 0;
+    const bool all = inside(g.xc[i + 1], g.yf[j], B) && inside(g.xc[i - 1], g.yf[j], B) &&
+                     inside(g.xc[i], g.yf[j + 1], B) && inside(g.xc[i], g.yf[j - 1], B);
+    return all ? 2 : 1;
+}
+
+// Block-wide ordered compaction: append the flagged items of this chunk
+// (one per thread, in thread order) at list[base...].  Returns the count.
+__device__ inline int block_append(bool flag, int value, int* list, int base, int* lds_w) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const unsigned long long mask = __ballot(flag);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) lds_w[w] = __popcll(mask);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int q = 0; q < nw; ++q) {
+        if (q < w) off += lds_w[q];
+        tot += lds_w[q];
+    }
+    if (flag) list[base + off + before] = value;
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(1024) void k_classify(Grid g, Body B, Box bx, uint8_t* __restrict__ flu,
+                                                   uint8_t* __restrict__ flv, uint8_t* __restrict__ msrc,
+                                                   int* __restrict__ list_u, int* __restrict__ list_v,
+                                                   int* __restrict__ counts) {
+    __shared__ int lds_w[1024 / kWave];
+    const int nx = g.nx;
+    const int wu = bx.bi1 - bx.bi0 + 1, hu = bx.bj1 - bx.bj0;
+    const int wv = bx.bi1 - bx.bi0, hv = bx.bj1 - bx.bj0 + 1;
+    const int nu = wu * hu, nvv = wv * hv;
+    // u nodes
+    int base = 0;
+    for (int c0 = 0; c0 < nu; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        int t = 0, k = 0;
+        if (c < nu) {
+            const int i = bx.bi0 + c % wu, j = bx.bj0 + c / wu;
+            t = B.present ? node_type_u(g, B, i, j) : 0;
+            k = j * (nx + 1) + i;
+            flu[k] = (uint8_t)t;
+        }
+        base += block_append(t != 0, k, list_u, base, lds_w);
+    }
+    const int cu = base;
+    base = 0;
+    for (int c0 = 0; c0 < nvv; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        int t = 0, k = 0;
+        if (c < nvv) {
+            const int i = bx.bi0 + c % wv, j = bx.bj0 + c / wv;
+            t = B.present ? node_type_v(g, B, i, j) : 0;
+            k = j * nx + i;
+            flv[k] = (uint8_t)t;
+        }
+        base += block_append(t != 0, k, list_v, base, lds_w);
+    }
+    const int cv = base;
+    __syncthreads();
+    // cells with at least one forced face (flags written above by this block)
+    const int wc = bx.bi1 - bx.bi0, hc = bx.bj1 - bx.bj0, nc = wc * hc;
+    int cm = 0;
+    for (int c0 = 0; c0 < nc; c0 += blockDim.x) {
+        const int c = c0 + threadIdx.x;
+        bool f = false;
+        if (c < nc) {
+            const int i = bx.bi0 + c % wc, j = bx.bj0 + c / wc;
+            const int nf = (flu[j * (nx + 1) + i] != 0) + (flu[j * (nx + 1) + i + 1] != 0) +
+                           (flv[j * nx + i] != 0) + (flv[(j + 1) * nx + i] != 0);
+            f = nf > 0;
+            msrc[j * nx + i] = f ? 1 : 0;
+        }
+        const unsigned long long mask = __ballot(f);
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        if (lane == 0) lds_w[w] = __popcll(mask);
+        __syncthreads();
+        for (int q = 0; q < (int)(blockDim.x / kWave); ++q) cm += lds_w[q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = cu;
+        counts[1] = cv;
+        counts[2] = cm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Immersed boundary: forcing at the listed nodes, and the force coefficients
+// ---------------------------------------------------------------------------
+__device__ inline double alpha_of(double df, double dout, double amax) {
+#pragma clang fp contract(off)
+    double al = dout > 0.0 ? df / dout : amax;
+    if (al > amax) al = amax;
+    if (al < 0.0) al = 0.0;
+    return al;
+}
+
+// explicit predictor u~ = R + dt/(2Re) L u^n at u node (i, j)
+__device__ inline double pred_u(const Grid& g, const double* u, const double* ru, int i, int j, double beta) {
+#pragma clang fp contract(off)
+    return ru[(size_t)j * (g.nx + 1) + i] + beta * lap_u(g, u, i, j);
+}
+__device__ inline double pred_v(const Grid& g, const double* v, const double* rv, int i, int j, double beta) {
+#pragma clang fp contract(off)
+    return rv[(size_t)j * g.nx + i] + beta * lap_v(g, v, i, j);
+}
+
+__device__ inline double target_u(const Grid& g, const Body& B, const double* u, const double* ru, int i, int j,
+                                  double beta, double amax) {
+#pragma clang fp contract(off)
+    const double ub = 0.0;
+    double sum = 0.0;
+    int cnt = 0;
+    double sy = 1.0 - ((g.yc[j] - B.yb) / B.b) * ((g.yc[j] - B.yb) / B.b);
+    if (sy < 0.0) sy = 0.0;
+    double sx = 1.0 - ((g.xf[i] - B.xb) / B.a) * ((g.xf[i] - B.xb) / B.a);
+    if (sx < 0.0) sx = 0.0;
+    if (!inside(g.xf[i + 1], g.yc[j], B)) {
+        const double xbd = B.xb + B.a * sqrt(sy);
+        const double al = alpha_of(xbd - g.xf[i], g.xf[i + 1] - xbd, amax);
+        sum += ub + (ub - pred_u(g, u, ru, i + 1, j, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xf[i - 1], g.yc[j], B)) {
+        const double xbd = B.xb - B.a * sqrt(sy);
+        const double al = alpha_of(g.xf[i] - xbd, xbd - g.xf[i - 1], amax);
+        sum += ub + (ub - pred_u(g, u, ru, i - 1, j, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xf[i], g.yc[j + 1], B)) {
+        const double ybd = B.yb + B.b * sqrt(sx);
+        const double al = alpha_of(ybd - g.yc[j], g.yc[j + 1] - ybd, amax);
+        sum += ub + (ub - pred_u(g, u, ru, i, j + 1, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xf[i], g.yc[j - 1], B)) {
+        const double ybd = B.yb - B.b * sqrt(sx);
+        const double al = alpha_of(g.yc[j] - ybd, ybd - g.yc[j - 1], amax);
+        sum += ub + (ub - pred_u(g, u, ru, i, j - 1, beta)) * al;
+        ++cnt;
+    }
+    return sum / cnt;
+}
+
+__device__ inline double target_v(const Grid& g, const Body& B, const double* v, const double* rv, int i, int j,
+                                  double beta, double amax) {
+#pragma clang fp contract(off)
+    const double vbd = B.vb;
+    double sum = 0.0;
+    int cnt = 0;
+    double sy = 1.0 - ((g.yf[j] - B.yb) / B.b) * ((g.yf[j] - B.yb) / B.b);
+    if (sy < 0.0) sy = 0.0;
+    double sx = 1.0 - ((g.xc[i] - B.xb) / B.a) * ((g.xc[i] - B.xb) / B.a);
+    if (sx < 0.0) sx = 0.0;
+    if (!inside(g.xc[i + 1], g.yf[j], B)) {
+        const double xbd = B.xb + B.a * sqrt(sy);
+        const double al = alpha_of(xbd - g.xc[i], g.xc[i + 1] - xbd, amax);
+        sum += vbd + (vbd - pred_v(g, v, rv, i + 1, j, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xc[i - 1], g.yf[j], B)) {
+        const double xbd = B.xb - B.a * sqrt(sy);
+        const double al = alpha_of(g.xc[i] - xbd, xbd - g.xc[i - 1], amax);
+        sum += vbd + (vbd - pred_v(g, v, rv, i - 1, j, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xc[i], g.yf[j + 1], B)) {
+        const double ybd = B.yb + B.b * sqrt(sx);
+        const double al = alpha_of(ybd - g.yf[j], g.yf[j + 1] - ybd, amax);
+        sum += vbd + (vbd - pred_v(g, v, rv, i, j + 1, beta)) * al;
+        ++cnt;
+    }
+    if (!inside(g.xc[i], g.yf[j - 1], B)) {
+        const double ybd = B.yb - B.b * sqrt(sx);
+        const double al = alpha_of(g.yf[j] - ybd, ybd - g.yf[j - 1], amax);
+        sum += vbd + (vbd - pred_v(g, v, rv, i, j - 1, beta)) * al;
+        ++cnt;
+    }
+    return sum / cnt;
+}
+
+// One block: f = (target - u~)/dt at every listed node, R += dt f; then the
+// force F = -sum f dV + pi a b (0, a_body) summed in list (row-major) order
+// and the coefficients C = F / (u_ref^2 chord / 2), u_ref = u_inf or 1.
+__global__ __launch_bounds__(1024) void k_forcing(Grid g, Body B, const double* __restrict__ u,
+                                                  const double* __restrict__ v, double* __restrict__ ru,
+                                                  double* __restrict__ rv, const uint8_t* __restrict__ flu,
+                                                  const uint8_t* __restrict__ flv, const int* __restrict__ list_u,
+                                                  const int* __restrict__ list_v, const int* __restrict__ counts,
+                                                  double* __restrict__ f_u, double* __restrict__ f_v, double dt,
+                                                  double beta, double amax, double qn, double* __restrict__ coef) {
+#pragma clang fp contract(off)
+    const int nx = g.nx;
+    const int cu = counts[0], cv = counts[1];
+    for (int n = threadIdx.x; n < cu; n += blockDim.x) {
+        const int k = list_u[n];
+        const int j = k / (nx + 1), i = k - j * (nx + 1);
+        const double ut = pred_u(g, u, ru, i, j, beta);
+        const double V = flu[k] == 2 ? 0.0 : target_u(g, B, u, ru, i, j, beta, amax);
+        const double f = (V - ut) / dt;
+        f_u[n] = f;
+    }
+    for (int n = threadIdx.x; n < cv; n += blockDim.x) {
+        const int k = list_v[n];
+        const int j = k / nx, i = k - j * nx;
+        const double vt = pred_v(g, v, rv, i, j, beta);
+        const double V = flv[k] == 2 ? B.vb : target_v(g, B, v, rv, i, j, beta, amax);
+        const double f = (V - vt) / dt;
+        f_v[n] = f;
+    }
+    __syncthreads();
+    // R is updated only after every target has read the predictor of its
+    // (fluid) neighbours.
+    for (int n = threadIdx.x; n < cu; n += blockDim.x) ru[list_u[n]] += dt * f_u[n];
+    for (int n = threadIdx.x; n < cv; n += blockDim.x) rv[list_v[n]] += dt * f_v[n];
+    if (threadIdx.x == 0) {
+        double fx = 0.0, fy = 0.0;
+        for (int n = 0; n < cu; ++n) {
+            const int k = list_u[n];
+            const int j = k / (nx + 1), i = k - j * (nx + 1);
+            fx -= f_u[n] * (g.dxu[i] * g.dy[j]);
+        }
+        for (int n = 0; n < cv; ++n) {
+            const int k = list_v[n];
+            const int j = k / nx, i = k - j * nx;
+            fy -= f_v[n] * (g.dx[i] * g.dyv[j]);
+        }
+        if (B.present) {
+            const double pi = 3.14159265358979323846;
+            fy += pi * B.a * B.b * B.ab;
+        }
+        coef[0] = qn > 0.0 ? fx / qn : 0.0;
+        coef[1] = qn > 0.0 ? fy / qn : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Poisson source, projection and pressure update
+// ---------------------------------------------------------------------------
+// V b = V (D(u^) - q) / dt; q = divergence of (u^ - body velocity) over the
+// forced faces of the cell (mass source), 0 when q_mode = 0.
+__global__ __launch_bounds__(kBlock) void k_poisson_rhs(Grid g, const double* __restrict__ u,
+                                                        const double* __restrict__ v,
+                                                        const uint8_t* __restrict__ flu,
+                                                        const uint8_t* __restrict__ flv,
+                                                        const uint8_t* __restrict__ msrc, double vbody, double dt,
+                                                        int q_mode, double* __restrict__ vb) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j >= g.ny) return;
+    const int nx = g.nx, W = nx + 1;
+    const size_t ku = (size_t)j * W + i, kv = (size_t)j * nx + i;
+    const double d = (u[ku + 1] - u[ku]) / g.dx[i] + (v[kv + nx] - v[kv]) / g.dy[j];
+    double q = 0.0;
+    if (q_mode && msrc[kv]) {
+        const double fe = flu[ku + 1] ? u[ku + 1] - 0.0 : 0.0;
+        const double fw = flu[ku] ? u[ku] - 0.0 : 0.0;
+        const double fn = flv[kv + nx] ? v[kv + nx] - vbody : 0.0;
+        const double fs = flv[kv] ? v[kv] - vbody : 0.0;
+        q = (fe - fw) / g.dx[i] + (fn - fs) / g.dy[j];
+    }
+    vb[kv] = (g.dx[i] * g.dy[j]) * ((d - q) / dt);
+}
+
+// u^{n+1} = u^ - dt G phi on the interior faces and the outlet face (phi = 0
+// on the outlet face, half a cell from the last centre).
+__global__ __launch_bounds__(kBlock) void k_project_u(Grid g, double* __restrict__ u, const double* __restrict__ phi,
+                                                      double dt) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i < 1 || i > g.nx || j >= g.ny) return;
+    const int nx = g.nx;
+    const size_t k = (size_t)j * (nx + 1) + i;
+    if (i < nx) {
+        u[k] -= dt * ((phi[(size_t)j * nx + i] - phi[(size_t)j * nx + i - 1]) / g.dxu[i]);
+    } else {
+        u[k] -= dt * (0.0 - phi[(size_t)j * nx + nx - 1]) / g.dxu[nx];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_v(Grid g, double* __restrict__ v, const double* __restrict__ phi,
+                                                      double dt) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j < 1 || j > g.ny - 1) return;
+    const int nx = g.nx;
+    const size_t k = (size_t)j * nx + i;
+    v[k] -= dt * ((phi[k] - phi[k - nx]) / g.dyv[j]);
+}
+
+// p^{n+1} = p^n + phi - dt/(2Re) (A phi)/V, A evaluated as a plain
+// finite-volume sum (coefficients by division).
+__global__ __launch_bounds__(kBlock) void k_update_p(Grid g, double* __restrict__ p, const double* __restrict__ phi,
+                                                     double beta) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j >= g.ny) return;
+    const int nx = g.nx, ny = g.ny;
+    const size_t k = (size_t)j * nx + i;
+    double s = 0.0, d = 0.0, a;
+    if (i < nx - 1) {
+        a = g.dy[j] / g.dxu[i + 1];
+        s += a * phi[k + 1];
+        d += a;
+    } else {
+        d += g.dy[j] / g.dxu[nx];
+    }
+    if (i > 0) {
+        a = g.dy[j] / g.dxu[i];
+        s += a * phi[k - 1];
+        d += a;
+    }
+    if (j < ny - 1) {
+        a = g.dx[i] / g.dyv[j + 1];
+        s += a * phi[k + nx];
+        d += a;
+    }
+    if (j > 0) {
+        a = g.dx[i] / g.dyv[j];
+        s += a * phi[k - nx];
+        d += a;
+    }
+    const double Aphi = s - d * phi[k];
+    p[k] += phi[k] - beta * (Aphi / (g.dx[i] * g.dy[j]));
+}
+
+// Scatter the listed forcing values into full-size arrays (diagnostics).
+__global__ void k_scatter_forcing(const int* __restrict__ list, const int* __restrict__ counts, int which,
+                                  const double* __restrict__ f, double* __restrict__ full) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < counts[which]) full[list[n]] = f[n];
+}
+
+}  // namespace ibm

@@ -1,0 +1,1103 @@
+// ibm_lib.hip -- host side of the gfx950 immersed-boundary fractional-step
+// solver (arXiv 2402.17337): workspace layout, the per-step pipeline, the
+// device-driven iterative solves and the C ABI declared in include/ibm.h.
+//
+// Every array lives in the caller's workspace; the library allocates only a
+// small pinned host block through which the convergence checks report to the
+// host, and HIP events.  Iterative solves run ahead of the host: the host
+// enqueues iterations in chunks, each chunk ending with a residual check that
+// writes the solve's state to device memory (read by every later kernel of
+// the solve, which returns at once when the solve has finished) and to the
+// pinned block.  The host waits on the check of an older chunk only, so the
+// GPU queue never drains while the solve runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "ibm.h"
+#include "ibm_kernels.hpp"
+
+using namespace ibm;
+
+namespace {
+
+constexpr int kSlots = 256;       // host-mapped check slots (ring)
+constexpr int kAheadSor = 24;     // SOR chunks in flight before the host waits
+constexpr int kAheadHelm = 3;     // implicit velocity iterations in flight
+constexpr int kAheadPcg = 48;     // PCG iterations in flight
+constexpr int kMaxSamples = 8192; // event pairs kept per timed kernel
+constexpr uint32_t kStateMagic = 0x49424d31u;  // "IBM1"
+
+enum { CTL_U = 0, CTL_V = 1, CTL_P = 2, CTL_N = 4 };
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace layout: one 256-byte aligned array after the other.
+struct Layout {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        size_t o = align_up(off, 256);
+        off = o + count * sizeof(T);
+        return o;
+    }
+};
+
+struct Offsets {
+    size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
+    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pq, phr, phb, vbr, vbb;
+    size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
+    size_t total;
+    int max_blocks;
+};
+
+inline int blocks_for(int cols, int rows) {
+    return ((cols + kWave - 1) / kWave) * ((rows + kBlockRows - 1) / kBlockRows);
+}
+
+Offsets layout_for(int nx, int ny) {
+    Offsets o;
+    Layout L;
+    const size_t NU = (size_t)(nx + 1) * ny, NV = (size_t)nx * (ny + 1), NC = (size_t)nx * ny;
+    const size_t NH = (size_t)(nx / 2) * ny;
+    o.xf = L.take<double>(nx + 1); o.yf = L.take<double>(ny + 1);
+    o.dx = L.take<double>(nx); o.dy = L.take<double>(ny);
+    o.xc = L.take<double>(nx); o.yc = L.take<double>(ny);
+    o.dxu = L.take<double>(nx + 1); o.dyv = L.take<double>(ny + 1);
+    o.pcE = L.take<double>(nx); o.pcW = L.take<double>(nx); o.pcD = L.take<double>(nx);
+    o.pcN = L.take<double>(ny); o.pcS = L.take<double>(ny);
+    o.uce = L.take<double>(nx + 1); o.ucw = L.take<double>(nx + 1);
+    o.ucn = L.take<double>(ny); o.ucs = L.take<double>(ny);
+    o.vce = L.take<double>(nx); o.vcw = L.take<double>(nx);
+    o.vcn = L.take<double>(ny + 1); o.vcs = L.take<double>(ny + 1);
+    o.u = L.take<double>(NU); o.nu = L.take<double>(NU); o.ru = L.take<double>(NU); o.fufull = L.take<double>(NU);
+    o.v = L.take<double>(NV); o.nv = L.take<double>(NV); o.rv = L.take<double>(NV); o.fvfull = L.take<double>(NV);
+    o.p = L.take<double>(NC); o.phi = L.take<double>(NC); o.vb = L.take<double>(NC);
+    o.pr = L.take<double>(NC); o.pp = L.take<double>(NC); o.pq = L.take<double>(NC);
+    o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
+    o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
+    o.coef = L.take<double>(4);
+    o.max_blocks = std::max(blocks_for(nx + 1, ny + 1), blocks_for(nx / 2, ny));
+    o.partials = L.take<double>((size_t)3 * o.max_blocks);
+    o.ctl = L.take<Ctl>(CTL_N);
+    o.list_u = L.take<int>(NU); o.list_v = L.take<int>(NV); o.counts = L.take<int>(4);
+    o.flu = L.take<uint8_t>(NU); o.flv = L.take<uint8_t>(NV); o.msrc = L.take<uint8_t>(NC);
+    o.total = align_up(L.off, 256);
+    return o;
+}
+
+// Plunge kinematics (Eqs. 1-2), k = 2 pi freq, evaluated without contraction.
+void kinematics(const ibm_params& P, double t, double* yb, double* vb, double* ab) {
+#pragma clang fp contract(off)
+    const double pi = 3.14159265358979323846;
+    double om = 2.0 * pi * P.freq, ph = om * t + P.phase;
+    *yb = P.y0 + P.amp * std::sin(ph);
+    *vb = om * P.amp * std::cos(ph);
+    *ab = -om * om * P.amp * std::sin(ph);
+}
+
+const char* validate(const ibm_params* P, const double* xf, const double* yf) {
+    if (!P) return "params is NULL";
+    if (P->nx < 8 || P->ny < 8 || (P->nx & 1) || (P->ny & 1)) return "nx and ny must be even and >= 8";
+    if ((int64_t)(P->nx + 1) * (P->ny + 1) > (int64_t)1 << 30) return "grid too large";
+    if (P->bc_mode != IBM_BC_CHANNEL) return "only IBM_BC_CHANNEL is supported";
+    if (P->precision != IBM_PREC_FP64 || P->reserved != 0) return "unsupported precision";
+    if (!(P->dt > 0.0) || !(P->re > 0.0) || !std::isfinite(P->u_inf)) return "dt and re must be > 0";
+    if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG) return "unknown p_method";
+    if (!(P->p_omega > 0.0 && P->p_omega < 2.0) || !(P->uv_omega > 0.0 && P->uv_omega < 2.0))
+        return "relaxation factors must lie in (0, 2)";
+    if (P->p_max_iter < 1 || P->p_check_every < 1 || P->uv_max_iter < 1) return "iteration limits must be >= 1";
+    if (P->p_init != IBM_INIT_ZERO && P->p_init != IBM_INIT_PREVIOUS) return "unknown p_init";
+    if (!(P->alpha_max >= 0.0) || !std::isfinite(P->p_tol) || !std::isfinite(P->uv_tol)) return "invalid tolerances";
+    if (!xf || !yf) return "face arrays are NULL";
+    for (int i = 0; i < P->nx; ++i)
+        if (!(xf[i + 1] > xf[i])) return "xf must be strictly increasing";
+    for (int j = 0; j < P->ny; ++j)
+        if (!(yf[j + 1] > yf[j])) return "yf must be strictly increasing";
+    if (P->body) {
+        const double a = 0.5 * P->chord, b = 0.5 * P->thickness * P->chord, amp = std::fabs(P->amp);
+        if (!(a > 0.0) || !(b > 0.0)) return "chord and thickness must be > 0";
+        const int nx = P->nx, ny = P->ny;
+        if (!(P->x0 - a > xf[2]) || !(P->x0 + a < xf[nx - 2]) || !(P->y0 - amp - b > yf[2]) ||
+            !(P->y0 + amp + b < yf[ny - 2]))
+            return "the body's range of motion must stay two cells clear of the boundary";
+    }
+    return nullptr;
+}
+
+struct Sample {
+    hipEvent_t a, b;
+    long solve;
+    int it;
+};
+
+}  // namespace
+
+struct ibm_ctx {
+    ibm_params P;
+    int nx = 0, ny = 0, nh = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Offsets off;
+    Grid g;
+    // device arrays
+    double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pq, *phr, *phb, *vbr, *vbb;
+    double *f_u, *f_v, *coef, *partials;
+    Ctl* ctl;
+    int *list_u, *list_v, *counts;
+    uint8_t *flu, *flv, *msrc;
+    Box box;
+    // host-mapped check slots and staging
+    Slot* hslots = nullptr;
+    Slot* dslots = nullptr;
+    long slot_seq = 0;
+    hipEvent_t ev[kSlots];
+    double* hstage = nullptr;  // pinned: coef[2], counts[3]
+    // time stepping
+    int have_hist = 0;
+    long step = 0;
+    double t = 0.0, cd = 0.0, cl = 0.0;
+    std::vector<int> schedule;
+    size_t sched_pos = 0;
+    // profiling
+    int prof_every = 0;
+    long launches[IBM_KERNEL_COUNT] = {};
+    std::vector<Sample> samples[IBM_KERNEL_COUNT];
+    std::vector<hipEvent_t> ev_pool;
+    long solve_id = 0;
+    std::string err;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);                        \
+            return IBM_ERR_HIP;                                                                \
+        }                                                                                      \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess) {                                                                \
+            c->err = std::string("kernel launch: ") + hipGetErrorString(e_);                   \
+            return IBM_ERR_HIP;                                                                \
+        }                                                                                      \
+    } while (0)
+
+inline dim3 grid2(int cols, int rows) {
+    return dim3((cols + kWave - 1) / kWave, (rows + kBlockRows - 1) / kBlockRows);
+}
+
+int next_slot(ibm_ctx* c) { return (int)(c->slot_seq++ % kSlots); }
+
+Slot read_slot(ibm_ctx* c, int s) {
+    volatile Slot* hs = c->hslots + s;
+    Slot r;
+    r.done = hs->done;
+    r.status = hs->status;
+    r.iters = hs->iters;
+    r.zero_rhs = hs->zero_rhs;
+    r.bn = hs->bn;
+    r.r0 = hs->r0;
+    r.rn = hs->rn;
+    return r;
+}
+
+hipEvent_t pool_event(ibm_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch f, bracketed by timing events for sampled launches of kernel kid.
+template <class F>
+void timed(ibm_ctx* c, int kid, int it, F&& f) {
+    bool take = c->prof_every > 0 && (c->launches[kid] % c->prof_every) == 0 &&
+                (int)c->samples[kid].size() < kMaxSamples;
+    c->launches[kid]++;
+    if (!take) {
+        f();
+        return;
+    }
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    if (!a || !b) {
+        f();
+        return;
+    }
+    (void)hipEventRecord(a, c->stream);
+    f();
+    (void)hipEventRecord(b, c->stream);
+    c->samples[kid].push_back(Sample{a, b, c->solve_id, it});
+}
+
+// Drop samples of the current solve taken after it had finished.
+void prune_samples(ibm_ctx* c, int last_it) {
+    for (int k = 0; k < IBM_KERNEL_COUNT; ++k) {
+        auto& v = c->samples[k];
+        size_t w = 0;
+        for (size_t r = 0; r < v.size(); ++r) {
+            if (v[r].solve == c->solve_id && v[r].it > last_it) {
+                c->ev_pool.push_back(v[r].a);
+                c->ev_pool.push_back(v[r].b);
+            } else {
+                v[w++] = v[r];
+            }
+        }
+        v.resize(w);
+    }
+}
+
+int32_t reset_ctl(ibm_ctx* c, int which) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, c->stream, c->ctl + which, 1);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+int32_t fill(ibm_ctx* c, double* a, size_t n, double val) {
+    if (n == 0) return IBM_OK;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, a, n, val);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+int32_t fill_u8(ibm_ctx* c, uint8_t* a, size_t n) {
+    if (n == 0) return IBM_OK;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, a, n);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+struct LoopOut {
+    int status = kStOk;
+    int iters = 0;
+    double bn = 0.0, r0 = 0.0, rn = 0.0;
+    int zero_rhs = 0;
+};
+
+int32_t map_status(int s) {
+    if (s == kStNan) return IBM_ERR_NAN;
+    if (s == kStNotConverged) return IBM_NOT_CONVERGED;
+    return IBM_OK;
+}
+
+// Wait for the check written to slot s and return its snapshot.
+int32_t wait_slot(ibm_ctx* c, int s, Slot* out) {
+    HIP_TRY(hipEventSynchronize(c->ev[s]));
+    *out = read_slot(c, s);
+    return IBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Red-black SOR on A x = vb, both in split storage (phr/phb, vbr/vbb).
+// fixed >= 0 with replay: exactly `fixed` iterations.
+// ---------------------------------------------------------------------------
+int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
+    Ctl* ctl = c->ctl + CTL_P;
+    const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+    const bool fixed_mode = fixed >= 0;
+    const double tol_e = fixed_mode ? -1.0 : tol;
+    const int max_e = fixed_mode ? fixed : max_iter;
+    int32_t rc = reset_ctl(c, CTL_P);
+    if (rc) return rc;
+    ++c->solve_id;
+    int s0 = next_slot(c);
+    timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&] {
+        hipLaunchKernelGGL(k_sor_residual, gr, bl, 0, c->stream, c->g, c->phr, c->phb, c->vbr, c->vbb, ctl,
+                           c->partials, 0, 0, max_e, tol_e, (int)fixed_mode, c->dslots + s0);
+    });
+    LAUNCH_CHECK();
+    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
+    Slot sn;
+    rc = wait_slot(c, s0, &sn);
+    if (rc) return rc;
+    out->bn = sn.bn;
+    out->r0 = sn.r0;
+    out->rn = sn.rn;
+    out->iters = 0;
+    out->zero_rhs = sn.zero_rhs;
+    if (sn.done || max_e == 0) {
+        out->status = sn.status;
+        prune_samples(c, 0);
+        return IBM_OK;
+    }
+    std::deque<int> pending;
+    int it = 0;
+    for (;;) {
+        if (it < max_e) {
+            const int n = std::min(K, max_e - it);
+            for (int k = 0; k < n; ++k) {
+                const int itk = it + k + 1;
+                timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&] {
+                    hipLaunchKernelGGL(k_sor_sweep<0>, gr, bl, 0, c->stream, c->g, c->phr, (const double*)c->phb,
+                                       (const double*)c->vbr, omega, (const Ctl*)ctl);
+                });
+                timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&] {
+                    hipLaunchKernelGGL(k_sor_sweep<1>, gr, bl, 0, c->stream, c->g, c->phb, (const double*)c->phr,
+                                       (const double*)c->vbb, omega, (const Ctl*)ctl);
+                });
+            }
+            it += n;
+            const int s = next_slot(c);
+            timed(c, IBM_KERNEL_SOR_RESIDUAL, it, [&] {
+                hipLaunchKernelGGL(k_sor_residual, gr, bl, 0, c->stream, c->g, c->phr, c->phb, c->vbr, c->vbb, ctl,
+                                   c->partials, 1, it, max_e, tol_e, (int)fixed_mode, c->dslots + s);
+            });
+            LAUNCH_CHECK();
+            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+            pending.push_back(s);
+            if ((int)pending.size() < kAheadSor && it < max_e) continue;
+        }
+        if (pending.empty()) {
+            c->err = "SOR loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int s = pending.front();
+        pending.pop_front();
+        rc = wait_slot(c, s, &sn);
+        if (rc) return rc;
+        if (sn.done) break;
+    }
+    out->status = sn.status;
+    out->iters = sn.iters;
+    out->rn = sn.rn;
+    prune_samples(c, sn.iters);
+    return IBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-PCG on M x = -vb (natural layout).  fixed >= 0: exactly that many.
+// ---------------------------------------------------------------------------
+int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_iter, int fixed, LoopOut* out) {
+    Ctl* ctl = c->ctl + CTL_P;
+    const dim3 gr = grid2(c->nx, c->ny), bl(kBlock);
+    const bool fixed_mode = fixed >= 0;
+    const double tol_e = fixed_mode ? -1.0 : tol;
+    const int max_e = fixed_mode ? fixed : max_iter;
+    int32_t rc = reset_ctl(c, CTL_P);
+    if (rc) return rc;
+    ++c->solve_id;
+    int s0 = next_slot(c);
+    hipLaunchKernelGGL(k_pcg_init, gr, bl, 0, c->stream, c->g, (const double*)x, vb, c->pr, c->pp, ctl, c->partials,
+                       tol_e, c->dslots + s0);
+    LAUNCH_CHECK();
+    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
+    Slot sn;
+    rc = wait_slot(c, s0, &sn);
+    if (rc) return rc;
+    out->bn = sn.bn;
+    out->r0 = sn.r0;
+    out->rn = sn.rn;
+    out->iters = 0;
+    out->zero_rhs = sn.zero_rhs;
+    if (sn.done || max_e == 0) {
+        out->status = sn.status;
+        prune_samples(c, 0);
+        return IBM_OK;
+    }
+    std::deque<int> pending;
+    int it = 0;
+    for (;;) {
+        if (it < max_e) {
+            const int itk = it + 1;
+            timed(c, IBM_KERNEL_PCG_SPMV, itk, [&] {
+                hipLaunchKernelGGL(k_pcg_spmv, gr, bl, 0, c->stream, c->g, (const double*)c->pp, c->pq, ctl,
+                                   c->partials);
+            });
+            const int s = next_slot(c);
+            timed(c, IBM_KERNEL_PCG_UPDATE, itk, [&] {
+                hipLaunchKernelGGL(k_pcg_update, gr, bl, 0, c->stream, c->g, x, c->pr, (const double*)c->pp,
+                                   (const double*)c->pq, ctl, c->partials, itk, max_e, tol_e, (int)fixed_mode,
+                                   c->dslots + s);
+            });
+            timed(c, IBM_KERNEL_PCG_DIR, itk, [&] {
+                hipLaunchKernelGGL(k_pcg_dir, gr, bl, 0, c->stream, c->g, (const double*)c->pr, c->pp,
+                                   (const Ctl*)ctl);
+            });
+            LAUNCH_CHECK();
+            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+            pending.push_back(s);
+            it = itk;
+            if ((int)pending.size() < kAheadPcg && it < max_e) continue;
+        }
+        if (pending.empty()) {
+            c->err = "PCG loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int s = pending.front();
+        pending.pop_front();
+        rc = wait_slot(c, s, &sn);
+        if (rc) return rc;
+        if (!sn.done) continue;
+        if (sn.status != kStConfirm) break;
+        // the recursive residual passed: confirm with the true residual
+        pending.clear();
+        const int sc = next_slot(c);
+        hipLaunchKernelGGL(k_pcg_true_residual, gr, bl, 0, c->stream, c->g, (const double*)x, vb, c->pr, ctl,
+                           c->partials, tol_e, c->dslots + sc);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[sc], c->stream));
+        rc = wait_slot(c, sc, &sn);
+        if (rc) return rc;
+        if (sn.done) break;
+        // restart from the true residual: p = z
+        it = sn.iters;
+        hipLaunchKernelGGL(k_pcg_dir, gr, bl, 0, c->stream, c->g, (const double*)c->pr, c->pp, (const Ctl*)ctl);
+        LAUNCH_CHECK();
+    }
+    if (fixed_mode && sn.status == kStOk) {
+        const int s = next_slot(c);
+        hipLaunchKernelGGL(k_pcg_final_residual, gr, bl, 0, c->stream, c->g, (const double*)x, vb, ctl, c->partials,
+                           c->dslots + s);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+        Slot f;
+        rc = wait_slot(c, s, &f);
+        if (rc) return rc;
+        sn.rn = f.rn;
+    }
+    out->status = sn.status;
+    out->iters = sn.iters;
+    out->rn = sn.rn;
+    prune_samples(c, sn.iters);
+    return IBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit viscous solve of one component, in place on u (comp 0) or v.
+// ---------------------------------------------------------------------------
+int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
+    const int which = comp == 0 ? CTL_U : CTL_V;
+    Ctl* ctl = c->ctl + which;
+    double* x = comp == 0 ? c->u : c->v;
+    const double* rhs = comp == 0 ? c->ru : c->rv;
+    const dim3 gs = grid2(c->nh, c->ny + 1), bl(kBlock);
+    const dim3 gres = comp == 0 ? grid2(c->nx + 1, c->ny) : grid2(c->nx, c->ny + 1);
+    const double omega = c->P.uv_omega, tol = c->P.uv_tol;
+    const int max_e = c->P.uv_max_iter;
+    int32_t rc = reset_ctl(c, which);
+    if (rc) return rc;
+    int s0 = next_slot(c);
+    hipLaunchKernelGGL(k_helm_residual, gres, bl, 0, c->stream, c->g, comp, (const double*)x, rhs, beta, ctl,
+                       c->partials, 0, 0, max_e, tol, c->dslots + s0);
+    LAUNCH_CHECK();
+    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
+    Slot sn;
+    rc = wait_slot(c, s0, &sn);
+    if (rc) return rc;
+    out->bn = sn.bn;
+    out->r0 = sn.r0;
+    out->rn = sn.rn;
+    out->iters = 0;
+    if (sn.done) {
+        out->status = sn.status;
+        return IBM_OK;
+    }
+    std::deque<int> pending;
+    int it = 0;
+    for (;;) {
+        if (it < max_e) {
+            if (comp == 0) {
+                hipLaunchKernelGGL(k_helm_u_sweep<0>, gs, bl, 0, c->stream, c->g, x, rhs, beta, omega, (const Ctl*)ctl);
+                hipLaunchKernelGGL(k_helm_u_sweep<1>, gs, bl, 0, c->stream, c->g, x, rhs, beta, omega, (const Ctl*)ctl);
+            } else {
+                hipLaunchKernelGGL(k_helm_v_sweep<0>, gs, bl, 0, c->stream, c->g, x, rhs, beta, omega, (const Ctl*)ctl);
+                hipLaunchKernelGGL(k_helm_v_sweep<1>, gs, bl, 0, c->stream, c->g, x, rhs, beta, omega, (const Ctl*)ctl);
+            }
+            ++it;
+            const int s = next_slot(c);
+            hipLaunchKernelGGL(k_helm_residual, gres, bl, 0, c->stream, c->g, comp, (const double*)x, rhs, beta, ctl,
+                               c->partials, 1, it, max_e, tol, c->dslots + s);
+            LAUNCH_CHECK();
+            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+            pending.push_back(s);
+            if ((int)pending.size() < kAheadHelm && it < max_e) continue;
+        }
+        if (pending.empty()) {
+            c->err = "viscous loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int s = pending.front();
+        pending.pop_front();
+        rc = wait_slot(c, s, &sn);
+        if (rc) return rc;
+        if (sn.done) break;
+    }
+    out->status = sn.status;
+    out->iters = sn.iters;
+    out->rn = sn.rn;
+    return IBM_OK;
+}
+
+int worst(int a, int b) {
+    if (a < 0 || b < 0) return std::min(a, b);
+    return std::max(a, b);
+}
+
+Body body_at(const ibm_ctx* c, double t) {
+    Body B;
+    double yb, vb, ab;
+    kinematics(c->P, t, &yb, &vb, &ab);
+    B.xb = c->P.x0;
+    B.yb = yb;
+    B.a = 0.5 * c->P.chord;
+    B.b = 0.5 * c->P.thickness * c->P.chord;
+    B.vb = vb;
+    B.ab = ab;
+    B.present = c->P.body ? 1 : 0;
+    return B;
+}
+
+// Pressure solve of the time step on phi (natural) with vb (natural, V b).
+int32_t pressure_solve(ibm_ctx* c, int fixed, LoopOut* out) {
+    const ibm_params& P = c->P;
+    if (P.p_method == IBM_SOLVER_PCG) {
+        int32_t rc = pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out);
+        if (rc) return rc;
+        if (out->zero_rhs) return fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
+        return IBM_OK;
+    }
+    const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+    hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
+    hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
+    LAUNCH_CHECK();
+    int32_t rc = sor_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out);
+    if (rc) return rc;
+    if (out->zero_rhs) return fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
+    hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb, c->phi);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
+    const ibm_params& P = c->P;
+    const int nx = c->nx, ny = c->ny;
+    const double dt = P.dt, re = P.re, beta = dt / (2.0 * re);
+    const double t1 = (double)(c->step + 1) * dt;
+    std::memset(st, 0, sizeof(*st));
+    const Body B = body_at(c, t1);
+    const dim3 bl(kBlock);
+
+    // flags and forced-node lists for the body at t^{n+1}
+    hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, c->stream, c->g, B, c->box, c->flu, c->flv, c->msrc,
+                       c->list_u, c->list_v, c->counts);
+    // explicit momentum predictor
+    hipLaunchKernelGGL(k_momentum_u, grid2(nx + 1, ny), bl, 0, c->stream, c->g, (const double*)c->u,
+                       (const double*)c->v, (const double*)c->p, c->nu, c->ru, dt, re, P.u_inf, c->have_hist);
+    hipLaunchKernelGGL(k_momentum_v, grid2(nx, ny + 1), bl, 0, c->stream, c->g, (const double*)c->u,
+                       (const double*)c->v, (const double*)c->p, c->nv, c->rv, dt, re, c->have_hist);
+    // discrete forcing and forces
+    const double uref = P.u_inf != 0.0 ? P.u_inf : 1.0;
+    const double qn = 0.5 * uref * uref * P.chord;
+    hipLaunchKernelGGL(k_forcing, dim3(1), dim3(1024), 0, c->stream, c->g, B, (const double*)c->u,
+                       (const double*)c->v, c->ru, c->rv, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
+                       (const int*)c->list_u, (const int*)c->list_v, (const int*)c->counts, c->f_u, c->f_v, dt, beta,
+                       P.alpha_max, qn, c->coef);
+    hipLaunchKernelGGL(k_outlet_commit, dim3((ny + 255) / 256), dim3(256), 0, c->stream, nx, ny, c->u,
+                       (const double*)c->ru);
+    LAUNCH_CHECK();
+    c->have_hist = 1;
+
+    // implicit viscous half
+    LoopOut hu, hv;
+    int32_t rc = helm_loop(c, 0, beta, &hu);
+    if (rc) return rc;
+    rc = helm_loop(c, 1, beta, &hv);
+    if (rc) return rc;
+    st->u_iters = hu.iters;
+    st->v_iters = hv.iters;
+    int status = worst(map_status(hu.status), map_status(hv.status));
+    if (status < 0) {
+        st->status = status;
+        return status;
+    }
+
+    // pressure correction
+    hipLaunchKernelGGL(k_poisson_rhs, grid2(nx, ny), bl, 0, c->stream, c->g, (const double*)c->u,
+                       (const double*)c->v, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
+                       (const uint8_t*)c->msrc, B.vb, dt, P.q_mode, c->vb);
+    LAUNCH_CHECK();
+    if (P.p_init == IBM_INIT_ZERO) {
+        rc = fill(c, c->phi, (size_t)nx * ny, 0.0);
+        if (rc) return rc;
+    }
+    int fixed = -1;
+    if (c->sched_pos < c->schedule.size()) fixed = c->schedule[c->sched_pos++];
+    LoopOut po;
+    rc = pressure_solve(c, fixed, &po);
+    if (rc) return rc;
+    st->p_iters = po.iters;
+    st->p_r0 = po.bn > 0.0 ? po.r0 / po.bn : 0.0;
+    st->p_rel = po.bn > 0.0 ? po.rn / po.bn : 0.0;
+    status = worst(status, map_status(po.status));
+    if (status < 0) {
+        st->status = status;
+        return status;
+    }
+
+    // projection and pressure update
+    hipLaunchKernelGGL(k_project_u, grid2(nx + 1, ny), bl, 0, c->stream, c->g, c->u, (const double*)c->phi, dt);
+    hipLaunchKernelGGL(k_project_v, grid2(nx, ny + 1), bl, 0, c->stream, c->g, c->v, (const double*)c->phi, dt);
+    hipLaunchKernelGGL(k_update_p, grid2(nx, ny), bl, 0, c->stream, c->g, c->p, (const double*)c->phi, beta);
+    LAUNCH_CHECK();
+
+    // statistics of the step
+    HIP_TRY(hipMemcpyAsync(c->hstage, c->coef, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync((int*)(c->hstage + 2), c->counts, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->cd = c->hstage[0];
+    c->cl = c->hstage[1];
+    const int* cnt = (const int*)(c->hstage + 2);
+    st->n_forced_u = cnt[0];
+    st->n_forced_v = cnt[1];
+    st->n_msrc = cnt[2];
+    c->step += 1;
+    c->t = t1;
+    st->cd = c->cd;
+    st->cl = c->cl;
+    st->t = c->t;
+    st->status = status;
+    return status;
+}
+
+// Face metrics and operator coefficients, computed on the host.
+void host_metrics(const ibm_params& P, const double* xf, const double* yf, std::vector<std::vector<double>>& A) {
+    const int nx = P.nx, ny = P.ny;
+    std::vector<double> dx(nx), dy(ny), xc(nx), yc(ny), dxu(nx + 1), dyv(ny + 1);
+    for (int i = 0; i < nx; ++i) { dx[i] = xf[i + 1] - xf[i]; xc[i] = 0.5 * (xf[i] + xf[i + 1]); }
+    for (int j = 0; j < ny; ++j) { dy[j] = yf[j + 1] - yf[j]; yc[j] = 0.5 * (yf[j] + yf[j + 1]); }
+    for (int i = 1; i < nx; ++i) dxu[i] = xc[i] - xc[i - 1];
+    for (int j = 1; j < ny; ++j) dyv[j] = yc[j] - yc[j - 1];
+    dxu[0] = 0.5 * dx[0];
+    dxu[nx] = 0.5 * dx[nx - 1];
+    dyv[0] = 0.5 * dy[0];
+    dyv[ny] = 0.5 * dy[ny - 1];
+    std::vector<double> pcE(nx, 0.0), pcW(nx, 0.0), pcD(nx, 0.0), pcN(ny, 0.0), pcS(ny, 0.0);
+    for (int i = 0; i < nx; ++i) {
+        if (i < nx - 1) pcE[i] = 1.0 / dxu[i + 1];
+        if (i > 0) pcW[i] = 1.0 / dxu[i];
+        if (i == nx - 1) pcD[i] = 1.0 / dxu[nx];
+    }
+    for (int j = 0; j < ny; ++j) {
+        if (j < ny - 1) pcN[j] = 1.0 / dyv[j + 1];
+        if (j > 0) pcS[j] = 1.0 / dyv[j];
+    }
+    std::vector<double> uce(nx + 1, 0.0), ucw(nx + 1, 0.0), ucn(ny, 0.0), ucs(ny, 0.0);
+    for (int i = 1; i < nx; ++i) {
+        uce[i] = 1.0 / (dx[i] * dxu[i]);
+        ucw[i] = 1.0 / (dx[i - 1] * dxu[i]);
+    }
+    for (int j = 0; j < ny; ++j) {
+        if (j < ny - 1) ucn[j] = 1.0 / (dyv[j + 1] * dy[j]);
+        if (j > 0) ucs[j] = 1.0 / (dyv[j] * dy[j]);
+    }
+    std::vector<double> vce(nx, 0.0), vcw(nx, 0.0), vcn(ny + 1, 0.0), vcs(ny + 1, 0.0);
+    for (int i = 0; i < nx; ++i) {
+        if (i < nx - 1) vce[i] = 1.0 / (dxu[i + 1] * dx[i]);
+        vcw[i] = 1.0 / (dxu[i] * dx[i]);
+    }
+    for (int j = 1; j < ny; ++j) {
+        vcn[j] = 1.0 / (dy[j] * dyv[j]);
+        vcs[j] = 1.0 / (dy[j - 1] * dyv[j]);
+    }
+    A = {std::vector<double>(xf, xf + nx + 1), std::vector<double>(yf, yf + ny + 1), dx, dy, xc, yc, dxu, dyv,
+         pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs};
+}
+
+// Motion box: cells that any forced node of the run can touch, with margin.
+Box motion_box(const ibm_params& P, const double* xf, const double* yf) {
+    Box b;
+    const int nx = P.nx, ny = P.ny;
+    if (!P.body) {
+        b.bi0 = 1; b.bi1 = 1; b.bj0 = 1; b.bj1 = 1;
+        return b;
+    }
+    const double a = 0.5 * P.chord, bb = 0.5 * P.thickness * P.chord, amp = std::fabs(P.amp);
+    const double xlo = P.x0 - a, xhi = P.x0 + a, ylo = P.y0 - amp - bb, yhi = P.y0 + amp + bb;
+    int i0 = 0, i1 = nx, j0 = 0, j1 = ny;
+    while (i0 < nx && xf[i0 + 1] < xlo) ++i0;
+    while (i1 > 0 && xf[i1 - 1] > xhi) --i1;
+    while (j0 < ny && yf[j0 + 1] < ylo) ++j0;
+    while (j1 > 0 && yf[j1 - 1] > yhi) --j1;
+    b.bi0 = std::max(1, i0 - 3);
+    b.bi1 = std::min(nx - 1, i1 + 3);
+    b.bj0 = std::max(1, j0 - 3);
+    b.bj1 = std::min(ny - 1, j1 + 3);
+    return b;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t ibm_workspace_bytes(const ibm_params* prm) {
+    if (!prm || prm->nx < 8 || prm->ny < 8 || (prm->nx & 1) || (prm->ny & 1)) return 0;
+    if ((int64_t)(prm->nx + 1) * (prm->ny + 1) > (int64_t)1 << 30) return 0;
+    return layout_for(prm->nx, prm->ny).total;
+}
+
+const char* ibm_status_string(int32_t s) {
+    switch (s) {
+        case IBM_OK: return "ok";
+        case IBM_NOT_CONVERGED: return "iteration limit reached before the tolerance";
+        case IBM_ERR_INVALID: return "invalid argument";
+        case IBM_ERR_HIP: return "HIP runtime error";
+        case IBM_ERR_STATE: return "invalid context state";
+        case IBM_ERR_NAN: return "residual became NaN or Inf";
+        default: return "unknown status";
+    }
+}
+
+const char* ibm_last_error(const ibm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void ibm_destroy(ibm_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int s = 0; s < kSlots; ++s)
+        if (c->ev[s]) (void)hipEventDestroy(c->ev[s]);
+    for (int k = 0; k < IBM_KERNEL_COUNT; ++k)
+        for (auto& smp : c->samples[k]) {
+            (void)hipEventDestroy(smp.a);
+            (void)hipEventDestroy(smp.b);
+        }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->t0) (void)hipEventDestroy(c->t0);
+    if (c->t1) (void)hipEventDestroy(c->t1);
+    if (c->hslots) (void)hipHostFree(c->hslots);
+    if (c->hstage) (void)hipHostFree(c->hstage);
+    delete c;
+}
+
+int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, const double* u0, const double* v0,
+                 const double* p0, void* workspace, size_t workspace_bytes, void* hip_stream, ibm_ctx** out) {
+    if (!out) return IBM_ERR_INVALID;
+    *out = nullptr;
+    if (validate(prm, xf, yf)) return IBM_ERR_INVALID;
+    const Offsets off = layout_for(prm->nx, prm->ny);
+    if (!workspace || workspace_bytes < off.total || ((uintptr_t)workspace & 255u)) return IBM_ERR_INVALID;
+
+    ibm_ctx* c = new ibm_ctx();
+    for (int s = 0; s < kSlots; ++s) c->ev[s] = nullptr;
+    c->P = *prm;
+    c->nx = prm->nx;
+    c->ny = prm->ny;
+    c->nh = prm->nx / 2;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)workspace;
+    c->off = off;
+    const int nx = c->nx, ny = c->ny;
+    char* w = c->ws;
+    auto D = [&](size_t o) { return (double*)(w + o); };
+    Grid& g = c->g;
+    g.nx = nx; g.ny = ny; g.nh = c->nh;
+    g.xf = D(off.xf); g.yf = D(off.yf); g.dx = D(off.dx); g.dy = D(off.dy); g.xc = D(off.xc); g.yc = D(off.yc);
+    g.dxu = D(off.dxu); g.dyv = D(off.dyv);
+    g.pcE = D(off.pcE); g.pcW = D(off.pcW); g.pcD = D(off.pcD); g.pcN = D(off.pcN); g.pcS = D(off.pcS);
+    g.uce = D(off.uce); g.ucw = D(off.ucw); g.ucn = D(off.ucn); g.ucs = D(off.ucs);
+    g.vce = D(off.vce); g.vcw = D(off.vcw); g.vcn = D(off.vcn); g.vcs = D(off.vcs);
+    c->u = D(off.u); c->nu = D(off.nu); c->ru = D(off.ru); c->fufull = D(off.fufull);
+    c->v = D(off.v); c->nv = D(off.nv); c->rv = D(off.rv); c->fvfull = D(off.fvfull);
+    c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp); c->pq = D(off.pq);
+    c->phr = D(off.phr); c->phb = D(off.phb); c->vbr = D(off.vbr); c->vbb = D(off.vbb);
+    c->f_u = D(off.f_u); c->f_v = D(off.f_v); c->coef = D(off.coef); c->partials = D(off.partials);
+    c->ctl = (Ctl*)(w + off.ctl);
+    c->list_u = (int*)(w + off.list_u); c->list_v = (int*)(w + off.list_v); c->counts = (int*)(w + off.counts);
+    c->flu = (uint8_t*)(w + off.flu); c->flv = (uint8_t*)(w + off.flv); c->msrc = (uint8_t*)(w + off.msrc);
+    c->box = motion_box(*prm, xf, yf);
+
+    auto fail = [&](int32_t rc) {
+        ibm_destroy(c);
+        return rc;
+    };
+    if (hipHostMalloc((void**)&c->hslots, sizeof(Slot) * kSlots, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return fail(IBM_ERR_HIP);
+    std::memset(c->hslots, 0, sizeof(Slot) * kSlots);
+    if (hipHostGetDevicePointer((void**)&c->dslots, c->hslots, 0) != hipSuccess) return fail(IBM_ERR_HIP);
+    if (hipHostMalloc((void**)&c->hstage, 64, hipHostMallocDefault) != hipSuccess) return fail(IBM_ERR_HIP);
+    for (int s = 0; s < kSlots; ++s)
+        if (hipEventCreateWithFlags(&c->ev[s], hipEventDisableTiming) != hipSuccess) return fail(IBM_ERR_HIP);
+    if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess) return fail(IBM_ERR_HIP);
+
+    // metrics
+    std::vector<std::vector<double>> A;
+    host_metrics(*prm, xf, yf, A);
+    const size_t dst[] = {off.xf, off.yf, off.dx, off.dy, off.xc, off.yc, off.dxu, off.dyv, off.pcE, off.pcW, off.pcD,
+                          off.pcN, off.pcS, off.uce, off.ucw, off.ucn, off.ucs, off.vce, off.vcw, off.vcn, off.vcs};
+    for (size_t k = 0; k < A.size(); ++k)
+        if (hipMemcpyAsync(w + dst[k], A[k].data(), A[k].size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess)
+            return fail(IBM_ERR_HIP);
+    // initial fields with their boundary values
+    const size_t NU = (size_t)(nx + 1) * ny, NV = (size_t)nx * (ny + 1), NC = (size_t)nx * ny;
+    std::vector<double> hu(NU), hv(NV), hp(NC);
+    for (size_t k = 0; k < NU; ++k) hu[k] = u0 ? u0[k] : prm->u_inf;
+    for (size_t k = 0; k < NV; ++k) hv[k] = v0 ? v0[k] : 0.0;
+    for (size_t k = 0; k < NC; ++k) hp[k] = p0 ? p0[k] : 0.0;
+    for (int j = 0; j < ny; ++j) hu[(size_t)j * (nx + 1)] = prm->u_inf;
+    for (int i = 0; i < nx; ++i) {
+        hv[i] = 0.0;
+        hv[(size_t)ny * nx + i] = 0.0;
+    }
+    if (hipMemcpyAsync(c->u, hu.data(), NU * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->v, hv.data(), NV * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->p, hp.data(), NC * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return fail(IBM_ERR_HIP);
+    int32_t rc = IBM_OK;
+    double* zero_d[] = {c->phi, c->nu, c->nv, c->ru, c->rv, c->coef, c->fufull, c->fvfull};
+    size_t zero_n[] = {NC, NU, NV, NU, NV, 4, NU, NV};
+    for (int k = 0; k < 8 && !rc; ++k) rc = fill(c, zero_d[k], zero_n[k], 0.0);
+    if (!rc) rc = fill_u8(c, c->flu, NU);
+    if (!rc) rc = fill_u8(c, c->flv, NV);
+    if (!rc) rc = fill_u8(c, c->msrc, NC);
+    if (!rc) rc = fill_u8(c, (uint8_t*)c->counts, 4 * sizeof(int));
+    if (!rc) {
+        hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, c->stream, c->ctl, (int)CTL_N);
+        if (hipGetLastError() != hipSuccess) rc = IBM_ERR_HIP;
+    }
+    if (rc) return fail(rc);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(IBM_ERR_HIP);
+    *out = c;
+    return IBM_OK;
+}
+
+int32_t ibm_step(ibm_ctx* c, int32_t nsteps, ibm_step_stats* last) {
+    if (!c) return IBM_ERR_INVALID;
+    if (nsteps < 1) {
+        c->err = "nsteps must be >= 1";
+        return IBM_ERR_INVALID;
+    }
+    c->err.clear();
+    const auto w0 = std::chrono::steady_clock::now();
+    int32_t status = IBM_OK;
+    ibm_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    for (int s = 0; s < nsteps; ++s) {
+        int32_t rc = step_once(c, &st);
+        status = worst(status, rc);
+        if (rc < 0) break;
+    }
+    const auto w1 = std::chrono::steady_clock::now();
+    st.seconds = std::chrono::duration<double>(w1 - w0).count();
+    if (last) *last = st;
+    return status;
+}
+
+int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, const ibm_solve_opts* o,
+                          ibm_solve_stats* st) {
+    if (!c) return IBM_ERR_INVALID;
+    if (!rhs_dev || !x_dev || !o || o->max_iter < 1 || o->check_every < 1 || o->fixed_iters < 0 ||
+        (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG) ||
+        (o->method == IBM_SOLVER_RBSOR && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol)) {
+        c->err = "invalid solve options";
+        return IBM_ERR_INVALID;
+    }
+    c->err.clear();
+    const dim3 bl(kBlock);
+    const int fixed = o->fixed_iters > 0 ? o->fixed_iters : -1;
+    LoopOut lo;
+    HIP_TRY(hipEventRecord(c->t0, c->stream));
+    int32_t rc;
+    if (o->method == IBM_SOLVER_PCG) {
+        // V b in the natural-layout scratch, x in place
+        const dim3 gr = grid2(c->nh, c->ny);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
+        hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->vbr, (const double*)c->vbb, c->vb);
+        LAUNCH_CHECK();
+        rc = pcg_loop(c, x_dev, c->vb, o->tol, o->max_iter, fixed, &lo);
+        if (rc) return rc;
+        if (lo.zero_rhs) {
+            rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
+            if (rc) return rc;
+        }
+    } else {
+        const dim3 gr = grid2(c->nh, c->ny);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)x_dev, c->phr, c->phb, 0);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
+        LAUNCH_CHECK();
+        rc = sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo);
+        if (rc) return rc;
+        if (lo.zero_rhs) {
+            rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb,
+                               x_dev);
+            LAUNCH_CHECK();
+        }
+    }
+    HIP_TRY(hipEventRecord(c->t1, c->stream));
+    HIP_TRY(hipEventSynchronize(c->t1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->t0, c->t1));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->status = map_status(lo.status);
+        st->iters = lo.iters;
+        st->r0_rel = lo.bn > 0.0 ? lo.r0 / lo.bn : 0.0;
+        st->rel = lo.bn > 0.0 ? lo.rn / lo.bn : 0.0;
+        st->seconds = 1e-3 * ms;
+    }
+    return map_status(lo.status);
+}
+
+int32_t ibm_forces(ibm_ctx* c, double* cd, double* cl) {
+    if (!c || !cd || !cl) return IBM_ERR_INVALID;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *cd = c->cd;
+    *cl = c->cl;
+    return IBM_OK;
+}
+
+int32_t ibm_get_fields(ibm_ctx* c, double* u, double* v, double* p, double* phi) {
+    if (!c) return IBM_ERR_INVALID;
+    const size_t NU = (size_t)(c->nx + 1) * c->ny, NV = (size_t)c->nx * (c->ny + 1), NC = (size_t)c->nx * c->ny;
+    if (u) HIP_TRY(hipMemcpyAsync(u, c->u, NU * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (v) HIP_TRY(hipMemcpyAsync(v, c->v, NV * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (p) HIP_TRY(hipMemcpyAsync(p, c->p, NC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (phi) HIP_TRY(hipMemcpyAsync(phi, c->phi, NC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IBM_OK;
+}
+
+int32_t ibm_get_ibm(ibm_ctx* c, uint8_t* flu, uint8_t* flv, uint8_t* msrc, double* fu, double* fv) {
+    if (!c) return IBM_ERR_INVALID;
+    const size_t NU = (size_t)(c->nx + 1) * c->ny, NV = (size_t)c->nx * (c->ny + 1), NC = (size_t)c->nx * c->ny;
+    if (flu) HIP_TRY(hipMemcpyAsync(flu, c->flu, NU, hipMemcpyDeviceToHost, c->stream));
+    if (flv) HIP_TRY(hipMemcpyAsync(flv, c->flv, NV, hipMemcpyDeviceToHost, c->stream));
+    if (msrc) HIP_TRY(hipMemcpyAsync(msrc, c->msrc, NC, hipMemcpyDeviceToHost, c->stream));
+    if (fu || fv) {
+        int32_t rc = fill(c, c->fufull, NU, 0.0);
+        if (!rc) rc = fill(c, c->fvfull, NV, 0.0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_scatter_forcing, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, c->stream,
+                           (const int*)c->list_u, (const int*)c->counts, 0, (const double*)c->f_u, c->fufull);
+        hipLaunchKernelGGL(k_scatter_forcing, dim3((unsigned)((NV + 255) / 256)), dim3(256), 0, c->stream,
+                           (const int*)c->list_v, (const int*)c->counts, 1, (const double*)c->f_v, c->fvfull);
+        LAUNCH_CHECK();
+        if (fu) HIP_TRY(hipMemcpyAsync(fu, c->fufull, NU * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (fv) HIP_TRY(hipMemcpyAsync(fv, c->fvfull, NV * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IBM_OK;
+}
+
+// State blob: header then u, v, p, phi, nu, nv.
+struct StateHeader {
+    uint32_t magic;
+    int32_t nx, ny, have_hist;
+    int64_t step;
+    double t, cd, cl;
+};
+
+size_t ibm_state_bytes(const ibm_ctx* c) {
+    if (!c) return 0;
+    const size_t NU = (size_t)(c->nx + 1) * c->ny, NV = (size_t)c->nx * (c->ny + 1), NC = (size_t)c->nx * c->ny;
+    return sizeof(StateHeader) + sizeof(double) * (2 * NU + 2 * NV + 2 * NC);
+}
+
+int32_t ibm_get_state(ibm_ctx* c, void* host, size_t bytes) {
+    if (!c || !host || bytes < ibm_state_bytes(c)) return IBM_ERR_INVALID;
+    const size_t NU = (size_t)(c->nx + 1) * c->ny, NV = (size_t)c->nx * (c->ny + 1), NC = (size_t)c->nx * c->ny;
+    StateHeader h{kStateMagic, c->nx, c->ny, c->have_hist, (int64_t)c->step, c->t, c->cd, c->cl};
+    std::memcpy(host, &h, sizeof(h));
+    double* d = (double*)((char*)host + sizeof(h));
+    const double* src[] = {c->u, c->v, c->p, c->phi, c->nu, c->nv};
+    const size_t n[] = {NU, NV, NC, NC, NU, NV};
+    for (int k = 0; k < 6; ++k) {
+        HIP_TRY(hipMemcpyAsync(d, src[k], n[k] * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        d += n[k];
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IBM_OK;
+}
+
+int32_t ibm_set_state(ibm_ctx* c, const void* host, size_t bytes) {
+    if (!c || !host || bytes < ibm_state_bytes(c)) return IBM_ERR_INVALID;
+    StateHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (h.magic != kStateMagic || h.nx != c->nx || h.ny != c->ny) {
+        c->err = "state blob does not match this grid";
+        return IBM_ERR_INVALID;
+    }
+    const size_t NU = (size_t)(c->nx + 1) * c->ny, NV = (size_t)c->nx * (c->ny + 1), NC = (size_t)c->nx * c->ny;
+    const double* d = (const double*)((const char*)host + sizeof(h));
+    double* dst[] = {c->u, c->v, c->p, c->phi, c->nu, c->nv};
+    const size_t n[] = {NU, NV, NC, NC, NU, NV};
+    for (int k = 0; k < 6; ++k) {
+        HIP_TRY(hipMemcpyAsync(dst[k], d, n[k] * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        d += n[k];
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_hist = h.have_hist;
+    c->step = h.step;
+    c->t = h.t;
+    c->cd = h.cd;
+    c->cl = h.cl;
+    return IBM_OK;
+}
+
+int32_t ibm_set_poisson_schedule(ibm_ctx* c, const int32_t* iters, int32_t n) {
+    if (!c || n < 0 || (n > 0 && !iters)) return IBM_ERR_INVALID;
+    for (int k = 0; k < n; ++k)
+        if (iters[k] < 0) return IBM_ERR_INVALID;
+    c->schedule.assign(iters, iters + n);
+    c->sched_pos = 0;
+    return IBM_OK;
+}
+
+int32_t ibm_profile(ibm_ctx* c, int32_t sample_every) {
+    if (!c || sample_every < 0) return IBM_ERR_INVALID;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < IBM_KERNEL_COUNT; ++k) {
+        for (auto& s : c->samples[k]) {
+            c->ev_pool.push_back(s.a);
+            c->ev_pool.push_back(s.b);
+        }
+        c->samples[k].clear();
+        c->launches[k] = 0;
+    }
+    c->prof_every = sample_every;
+    return IBM_OK;
+}
+
+int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
+                          double* bytes_per_launch) {
+    if (!c || kernel < 0 || kernel >= IBM_KERNEL_COUNT) return IBM_ERR_INVALID;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (auto& s : c->samples[kernel]) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, s.a, s.b));
+        tot += ms;
+    }
+    const size_t n = c->samples[kernel].size();
+    const double cells = (double)c->nx * c->ny;
+    const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 16.0 * cells, 48.0 * cells, 24.0 * cells};
+    if (avg_ms) *avg_ms = n ? tot / n : 0.0;
+    if (samples) *samples = (int64_t)n;
+    if (launches) *launches = c->launches[kernel];
+    if (bytes_per_launch) *bytes_per_launch = bytes[kernel];
+    return IBM_OK;
+}
+
+}  // extern "C"

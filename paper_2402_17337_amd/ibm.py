@@ -1,0 +1,321 @@
+"""Thin ctypes binding of the gfx950 immersed-boundary solver library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libibm_hip.so`` (declared in ``include/ibm.h``).  PyTorch provides the
+device workspace and the HIP stream.  There is no CPU fallback: if the library
+is not built or no GPU is visible, construction raises.
+
+Array conventions (float64, row-major, x fastest):
+    u (ny, nx+1) x-faces, v (ny+1, nx) y-faces, p and phi (ny, nx) centres.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibm_hip.so")
+
+OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, -5
+BC_CHANNEL = 0
+RBSOR, PCG = 0, 1
+INIT_ZERO, INIT_PREVIOUS = 0, 1
+KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_SPMV, KERNEL_PCG_UPDATE, KERNEL_PCG_DIR = range(5)
+KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
+                KERNEL_PCG_SPMV: "k_pcg_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
+                KERNEL_PCG_DIR: "k_pcg_dir"}
+
+EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
+            "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
+            "ibm_set_poisson_schedule", "ibm_profile", "ibm_profile_query", "ibm_destroy",
+            "ibm_status_string", "ibm_last_error")
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("bc_mode", C.c_int32), ("body", C.c_int32),
+        ("re", C.c_double), ("dt", C.c_double), ("u_inf", C.c_double),
+        ("chord", C.c_double), ("thickness", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+        ("amp", C.c_double), ("freq", C.c_double), ("phase", C.c_double),
+        ("p_method", C.c_int32), ("p_max_iter", C.c_int32), ("p_check_every", C.c_int32),
+        ("p_init", C.c_int32),
+        ("p_omega", C.c_double), ("p_tol", C.c_double),
+        ("uv_omega", C.c_double), ("uv_tol", C.c_double),
+        ("uv_max_iter", C.c_int32), ("q_mode", C.c_int32),
+        ("alpha_max", C.c_double),
+        ("precision", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("p_iters", C.c_int32), ("u_iters", C.c_int32),
+                ("v_iters", C.c_int32), ("n_forced_u", C.c_int32), ("n_forced_v", C.c_int32),
+                ("n_msrc", C.c_int32), ("reserved", C.c_int32),
+                ("p_r0", C.c_double), ("p_rel", C.c_double), ("cd", C.c_double), ("cl", C.c_double),
+                ("t", C.c_double), ("seconds", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+                ("fixed_iters", C.c_int32), ("omega", C.c_double), ("tol", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32), ("r0_rel", C.c_double), ("rel", C.c_double),
+                ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        u8 = C.POINTER(C.c_uint8)
+        L.ibm_workspace_bytes.argtypes = [C.POINTER(Params)]
+        L.ibm_workspace_bytes.restype = C.c_size_t
+        L.ibm_init.argtypes = [C.POINTER(Params), dp, dp, dp, dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.ibm_init.restype = C.c_int32
+        L.ibm_step.argtypes = [vp, C.c_int32, C.POINTER(StepStats)]
+        L.ibm_step.restype = C.c_int32
+        L.ibm_poisson_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
+        L.ibm_poisson_solve.restype = C.c_int32
+        L.ibm_forces.argtypes = [vp, dp, dp]
+        L.ibm_forces.restype = C.c_int32
+        L.ibm_get_fields.argtypes = [vp, dp, dp, dp, dp]
+        L.ibm_get_fields.restype = C.c_int32
+        L.ibm_get_ibm.argtypes = [vp, u8, u8, u8, dp, dp]
+        L.ibm_get_ibm.restype = C.c_int32
+        L.ibm_state_bytes.argtypes = [vp]
+        L.ibm_state_bytes.restype = C.c_size_t
+        L.ibm_get_state.argtypes = [vp, vp, C.c_size_t]
+        L.ibm_get_state.restype = C.c_int32
+        L.ibm_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.ibm_set_state.restype = C.c_int32
+        L.ibm_set_poisson_schedule.argtypes = [vp, ip, C.c_int32]
+        L.ibm_set_poisson_schedule.restype = C.c_int32
+        L.ibm_profile.argtypes = [vp, C.c_int32]
+        L.ibm_profile.restype = C.c_int32
+        L.ibm_profile_query.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp]
+        L.ibm_profile_query.restype = C.c_int32
+        L.ibm_destroy.argtypes = [vp]
+        L.ibm_destroy.restype = None
+        L.ibm_status_string.argtypes = [C.c_int32]
+        L.ibm_status_string.restype = C.c_char_p
+        L.ibm_last_error.argtypes = [vp]
+        L.ibm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+# Parameter names shared with the workload presets -> ibm_params fields.
+_MAP = dict(bc="bc_mode", body="body", re="re", dt="dt", uinf="u_inf", chord="chord",
+            thick="thickness", x0="x0", y0="y0", amp="amp", freq="freq", phase="phase",
+            p_method="p_method", p_max_iter="p_max_iter", p_check="p_check_every",
+            p_init_prev="p_init", p_omega="p_omega", p_tol="p_tol", uv_omega="uv_omega",
+            uv_tol="uv_tol", uv_max_iter="uv_max_iter", q_mode="q_mode", alpha_max="alpha_max")
+
+DEFAULTS = dict(bc=0, body=1, re=100.0, dt=1e-3, uinf=1.0, chord=1.0, thick=0.12, x0=4.0, y0=6.0,
+                amp=0.0, freq=0.0, phase=0.0, p_method=RBSOR, p_max_iter=2_000_000, p_check=10,
+                p_init_prev=1, p_omega=1.8, p_tol=1e-8, uv_omega=1.0, uv_tol=1e-10,
+                uv_max_iter=200, q_mode=1, alpha_max=1.0)
+
+
+def make_params(nx: int, ny: int, **kw) -> Params:
+    d = dict(DEFAULTS)
+    for k, v in kw.items():
+        if k not in d:
+            raise KeyError(f"unknown parameter {k!r}")
+        d[k] = v
+    P = Params()
+    P.nx, P.ny = nx, ny
+    for k, v in d.items():
+        setattr(P, _MAP[k], v)
+    P.precision = 0
+    P.reserved = 0
+    return P
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def status_string(s: int) -> str:
+    return lib().ibm_status_string(s).decode()
+
+
+class IbmError(RuntimeError):
+    pass
+
+
+class Solver:
+    """One solver context on a CUDA/HIP device; workspace is a torch tensor."""
+
+    def __init__(self, nx, ny, xf, yf, u0=None, v0=None, p0=None, device="cuda:0", stream=None,
+                 **params):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the solver runs only on the HIP device")
+        L = lib()
+        self.torch = torch
+        self.nx, self.ny = nx, ny
+        self.device = torch.device(device)
+        self.P = make_params(nx, ny, **params)
+        nbytes = L.ibm_workspace_bytes(C.byref(self.P))
+        if nbytes == 0:
+            raise ValueError("invalid grid size")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        xf = np.ascontiguousarray(xf, dtype=np.float64)
+        yf = np.ascontiguousarray(yf, dtype=np.float64)
+        arrs = []
+        for a, shp in ((u0, (ny, nx + 1)), (v0, (ny + 1, nx)), (p0, (ny, nx))):
+            if a is None:
+                arrs.append(None)
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                if a.shape != shp:
+                    raise ValueError(f"initial field shape {a.shape}, expected {shp}")
+                arrs.append(a)
+        h = C.c_void_p()
+        rc = L.ibm_init(C.byref(self.P), _dp(xf), _dp(yf), _dp(arrs[0]), _dp(arrs[1]), _dp(arrs[2]),
+                        C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(self.stream.cuda_stream),
+                        C.byref(h))
+        if rc != OK:
+            raise IbmError(f"ibm_init failed: {status_string(rc)}")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().ibm_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, what, rc):
+        msg = lib().ibm_last_error(self._h).decode()
+        raise IbmError(f"{what} failed: {status_string(rc)} {msg}")
+
+    # -- time stepping -------------------------------------------------------
+    def step(self, n: int = 1):
+        st = StepStats()
+        rc = lib().ibm_step(self._h, n, C.byref(st))
+        if rc < 0 and rc != ERR_NAN:
+            self._err("ibm_step", rc)
+        d = {k: getattr(st, k) for k, _ in StepStats._fields_ if k != "reserved"}
+        d["rc"] = rc
+        return d
+
+    def forces(self):
+        cd, cl = C.c_double(), C.c_double()
+        rc = lib().ibm_forces(self._h, C.byref(cd), C.byref(cl))
+        if rc != OK:
+            self._err("ibm_forces", rc)
+        return cd.value, cl.value
+
+    def fields(self):
+        nx, ny = self.nx, self.ny
+        u = np.empty((ny, nx + 1)); v = np.empty((ny + 1, nx))
+        p = np.empty((ny, nx)); phi = np.empty((ny, nx))
+        rc = lib().ibm_get_fields(self._h, _dp(u), _dp(v), _dp(p), _dp(phi))
+        if rc != OK:
+            self._err("ibm_get_fields", rc)
+        return u, v, p, phi
+
+    def ibm(self):
+        nx, ny = self.nx, self.ny
+        flu = np.zeros((ny, nx + 1), np.uint8); flv = np.zeros((ny + 1, nx), np.uint8)
+        ms = np.zeros((ny, nx), np.uint8)
+        fu = np.zeros((ny, nx + 1)); fv = np.zeros((ny + 1, nx))
+        u8 = C.POINTER(C.c_uint8)
+        rc = lib().ibm_get_ibm(self._h, flu.ctypes.data_as(u8), flv.ctypes.data_as(u8),
+                               ms.ctypes.data_as(u8), _dp(fu), _dp(fv))
+        if rc != OK:
+            self._err("ibm_get_ibm", rc)
+        return dict(flu=flu, flv=flv, msrc=ms, fu=fu, fv=fv)
+
+    def get_state(self) -> bytes:
+        n = lib().ibm_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        rc = lib().ibm_get_state(self._h, buf, n)
+        if rc != OK:
+            self._err("ibm_get_state", rc)
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        rc = lib().ibm_set_state(self._h, buf, len(blob))
+        if rc != OK:
+            self._err("ibm_set_state", rc)
+
+    def set_poisson_schedule(self, iters):
+        a = (C.c_int32 * len(iters))(*[int(x) for x in iters])
+        rc = lib().ibm_set_poisson_schedule(self._h, a, len(iters))
+        if rc != OK:
+            self._err("ibm_set_poisson_schedule", rc)
+
+    # -- stand-alone Poisson solve ------------------------------------------
+    def poisson_solve(self, rhs, x, method=RBSOR, omega=1.8, tol=1e-8, max_iter=2_000_000,
+                      check_every=10, fixed_iters=0):
+        """Solve (D G) x = rhs in place on device tensors (float64, (ny, nx))."""
+        torch = self.torch
+        for t in (rhs, x):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device \
+                    or t.numel() != self.nx * self.ny:
+                raise ValueError("rhs and x must be contiguous float64 device tensors of nx*ny")
+        o = SolveOpts(method, max_iter, check_every, fixed_iters, omega, tol)
+        st = SolveStats()
+        rc = lib().ibm_poisson_solve(self._h, C.c_void_p(rhs.data_ptr()), C.c_void_p(x.data_ptr()),
+                                     C.byref(o), C.byref(st))
+        if rc < 0 and rc != ERR_NAN:
+            self._err("ibm_poisson_solve", rc)
+        d = {k: getattr(st, k) for k, _ in SolveStats._fields_ if not k.startswith("reserved")}
+        d["rc"] = rc
+        return d
+
+    # -- kernel timing --------------------------------------------------------
+    def profile(self, sample_every: int):
+        rc = lib().ibm_profile(self._h, sample_every)
+        if rc != OK:
+            self._err("ibm_profile", rc)
+
+    def profile_query(self, kernel: int):
+        avg, ns, nl, by = C.c_double(), C.c_int64(), C.c_int64(), C.c_double()
+        rc = lib().ibm_profile_query(self._h, kernel, C.byref(avg), C.byref(ns), C.byref(nl), C.byref(by))
+        if rc != OK:
+            self._err("ibm_profile_query", rc)
+        return dict(avg_ms=avg.value, samples=ns.value, launches=nl.value, bytes_per_launch=by.value)
+
+
+def workspace_bytes(nx, ny, **params) -> int:
+    P = make_params(nx, ny, **params)
+    return lib().ibm_workspace_bytes(C.byref(P))
+
+
+def init_status(nx, ny, xf, yf, workspace_ptr=0, workspace_bytes_=None, **params) -> int:
+    """Call ibm_init with a given (possibly bogus) workspace; for argument
+    validation, which happens before any GPU call.  Returns the status."""
+    P = make_params(nx, ny, **params)
+    xf = np.ascontiguousarray(xf, dtype=np.float64)
+    yf = np.ascontiguousarray(yf, dtype=np.float64)
+    h = C.c_void_p()
+    nb = workspace_bytes_ if workspace_bytes_ is not None else lib().ibm_workspace_bytes(C.byref(P))
+    return lib().ibm_init(C.byref(P), _dp(xf), _dp(yf), None, None, None, C.c_void_p(workspace_ptr),
+                          nb, None, C.byref(h))

@@ -1,0 +1,174 @@
+"""GPU parity of the pressure Poisson solvers (red-black SOR, Jacobi-PCG)
+against the FP64 oracle, through the C ABI.
+
+Paper: the pressure-correction equation, solved by red-black Gauss-Seidel SOR,
+is the dominant cost of a step (Table 1, Sec. 3.4.1).  Bar: relative L2
+difference <= 1e-10 in FP64 (and equal iteration counts for SOR, which runs
+the same iteration sequence as the oracle)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_17337_amd import ibm
+from paper_2402_17337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+def _grid(nx, ny, stretched):
+    if not stretched:
+        return W.uniform_faces(nx, 16.0), W.uniform_faces(ny, 12.0)
+    s = W.uniform_faces(nx, 1.0)
+    xf = 16.0 * (s - 0.12 * np.sin(2 * np.pi * s) / (2 * np.pi))
+    s = W.uniform_faces(ny, 1.0)
+    yf = 12.0 * (s - 0.10 * np.sin(2 * np.pi * s) / (2 * np.pi))
+    return xf, yf
+
+
+def _pair(torch, nx, ny, stretched=False, faces=None):
+    xf, yf = faces if faces is not None else _grid(nx, ny, stretched)
+    o = O.Oracle(nx, ny, xf, yf, body=0)
+    g = ibm.Solver(nx, ny, xf, yf, body=0)
+    return o, g
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+# (nx, ny): several 64-wide tiles with ragged tails in x (nx/2 = 100) and y
+@pytest.mark.parametrize("nx,ny,stretched", [(128, 96, False), (200, 150, True), (16, 8, False)])
+def test_sor_fixed_iterations_match_oracle(torch, nx, ny, stretched):
+    o, g = _pair(torch, nx, ny, stretched)
+    rng = np.random.default_rng(nx + ny)
+    b = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    xo, so, rc = o.poisson_solve(b, x0=x0, omega=1.8, fixed=37, check=10)
+    xd = _dev(torch, x0)
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR, omega=1.8, fixed_iters=37, check_every=10)
+    xg = xd.cpu().numpy()
+    print(f"case nx={nx} ny={ny} rel={rel_l2(xg, xo):.3e}", flush=True)
+    assert sg["iters"] == so["iters"] == 37
+    assert rel_l2(xg, xo) <= 1e-12
+    assert np.max(np.abs(xg - xo)) <= 1e-12 * np.max(np.abs(xo))
+    assert abs(sg["rel"] - so["rel"]) <= 1e-9 * so["rel"]
+
+
+@pytest.mark.parametrize("stretched", [False, True])
+def test_sor_to_tolerance_same_iterations(torch, stretched):
+    nx, ny = 128, 96
+    o, g = _pair(torch, nx, ny, stretched)
+    xf, yf = _grid(nx, ny, stretched)
+    xc, yc = 0.5 * (xf[1:] + xf[:-1]), 0.5 * (yf[1:] + yf[:-1])
+    X, Y = np.meshgrid(xc, yc)
+    b = np.cos(np.pi * X / 32.0) * np.cos(np.pi * Y / 12.0) + 0.3 * np.sin(3 * X) * np.cos(2 * Y)
+    xo, so, rc = o.poisson_solve(b, omega=1.8, tol=1e-8, check=10)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR, omega=1.8, tol=1e-8, check_every=10)
+    xg = xd.cpu().numpy()
+    print(f"iters gpu {sg['iters']} oracle {so['iters']} rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert rc == O.OK and sg["rc"] == ibm.OK
+    assert sg["iters"] == so["iters"]
+    assert sg["rel"] <= 1e-8
+    assert rel_l2(xg, xo) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,stretched", [(128, 96, False), (200, 150, True)])
+def test_pcg_fixed_iterations_match_oracle(torch, nx, ny, stretched):
+    o, g = _pair(torch, nx, ny, stretched)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal((ny, nx))
+    xo, so, rc = o.poisson_solve(b, method=O.PCG, fixed=60)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.PCG, fixed_iters=60)
+    xg = xd.cpu().numpy()
+    print(f"pcg rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert sg["iters"] == so["iters"] == 60
+    assert rel_l2(xg, xo) <= TOL
+
+
+def test_pcg_to_tolerance_agrees_with_oracle(torch):
+    nx, ny = 96, 64
+    o, g = _pair(torch, nx, ny, True)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((ny, nx))
+    xo, so, rc = o.poisson_solve(b, method=O.PCG, tol=1e-12, max_iter=20000)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.PCG, tol=1e-12, max_iter=20000)
+    xg = xd.cpu().numpy()
+    print(f"pcg iters gpu {sg['iters']} oracle {so['iters']} rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert rc == O.OK and sg["rc"] == ibm.OK
+    assert abs(sg["iters"] - so["iters"]) <= 3
+    assert sg["rel"] <= 1e-12
+    assert rel_l2(xg, xo) <= TOL
+    # the GPU solution's true residual measured by the oracle's own operator
+    V = np.outer(np.diff(o.yf), np.diff(o.xf))
+    r = V * b - o.apply_A(xg)
+    assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(V * b)
+
+
+@pytest.mark.parametrize("method", [ibm.RBSOR, ibm.PCG])
+def test_zero_rhs_gives_zero(torch, method):
+    nx, ny = 64, 48
+    _, g = _pair(torch, nx, ny)
+    xd = torch.ones((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(torch.zeros_like(xd), xd, method=method)
+    assert sg["iters"] == 0 and sg["rc"] == ibm.OK
+    assert float(xd.abs().max()) == 0.0
+
+
+def test_iteration_limit_is_soft(torch):
+    nx, ny = 64, 48
+    _, g = _pair(torch, nx, ny)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    b = torch.ones_like(xd)
+    sg = g.poisson_solve(b, xd, method=ibm.RBSOR, tol=1e-14, max_iter=25, check_every=10)
+    assert sg["rc"] == ibm.NOT_CONVERGED and sg["iters"] == 25
+
+
+def test_nan_rhs_reports_nan(torch):
+    nx, ny = 64, 48
+    _, g = _pair(torch, nx, ny)
+    b = torch.ones((ny, nx), dtype=torch.float64, device="cuda")
+    b[5, 7] = float("nan")
+    xd = torch.zeros_like(b)
+    sg = g.poisson_solve(b, xd, method=ibm.RBSOR)
+    assert sg["rc"] == ibm.ERR_NAN
+
+
+def test_full_size_grid_fixed_iterations(torch):
+    """The 1024x768 stretched grid of the plunging workload, in the launch
+    configuration the benchmark times: 40 SOR iterations and 20 PCG
+    iterations against the oracle."""
+    c = W.plunging_1024x768()
+    nx, ny = c["nx"], c["ny"]
+    o, g = _pair(torch, nx, ny, faces=(c["xf"], c["yf"]))
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    xo, so, _ = o.poisson_solve(b, x0=x0, omega=1.8, fixed=40, check=10)
+    xd = _dev(torch, x0)
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR, omega=1.8, fixed_iters=40, check_every=10)
+    xg = xd.cpu().numpy()
+    print(f"full SOR rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert rel_l2(xg, xo) <= 1e-12
+    xo, so, _ = o.poisson_solve(b, method=O.PCG, fixed=20)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    g.poisson_solve(_dev(torch, b), xd, method=ibm.PCG, fixed_iters=20)
+    xg = xd.cpu().numpy()
+    print(f"full PCG rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert rel_l2(xg, xo) <= TOL
