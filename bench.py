@@ -1,0 +1,246 @@
+#!/usr/bin/env python
+"""Benchmark of the plain FP64 hot path on one MI355X.
+
+Workload: plunging ellipse (chord 1, thickness 0.12, y = 0.5 sin(2 pi 0.4 t)),
+Re 500, dt 5e-4, on the 1024x768 grid that is uniform (0.01c) around the body's
+path and stretched geometrically outward on a 16c x 12c channel; u = 1, v = 0,
+p = 0 at t = 0.  A step is one whole time step on the GPU: classification,
+momentum predictor, forcing, implicit viscous solves, the pressure Poisson
+solve to a relative residual of 1e-8, projection and forces.
+
+Reported: Poisson cell-updates/s over the timed steps (nx*ny*iterations /
+wall time; `value`), seconds per time step, the dominant kernel against the
+HBM roofline (HIP events on the solver stream), a Jacobi-PCG leg, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s per time step + Poisson cell-updates/s at 1024x768; learned/FP32 vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_17337_amd", "csrc", f)
+                  for f in ("ibm_kernels.hpp", "ibm_device.hpp")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken with the current kernel sources; else None."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload_tag}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if "=" in line:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_if_missing():
+    from paper_2402_17337_amd import ibm
+    from oracle import oracle as O
+    if not os.path.exists(ibm.LIB_PATH) or not os.path.exists(O._LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0):
+    import torch
+    from paper_2402_17337_amd import ibm
+
+    prm = dict(case["params"], p_method=method)
+    if max_iters > 0:
+        prm["p_max_iter"] = max_iters
+    g = ibm.Solver(case["nx"], case["ny"], case["xf"], case["yf"], case["u0"], case["v0"], case["p0"],
+                   device="cuda:0", **prm)
+    for _ in range(warmup):
+        st = g.step(1)
+        if st["rc"] < 0:
+            raise RuntimeError(f"warmup step failed: {st}")
+    g.profile(profile_every)
+    iters, stats = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = g.step(1)
+        if st["rc"] < 0:
+            raise RuntimeError(f"timed step failed: {st}")
+        iters.append(st["p_iters"])
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {k: g.profile_query(k) for k in ibm.KERNEL_NAMES}
+    g.close()
+    cells = case["nx"] * case["ny"]
+    return dict(wall=wall, iters=iters, stats=stats, prof=prof,
+                cell_updates_per_s=cells * sum(iters) / wall if wall > 0 else 0.0)
+
+
+def cpu_leg(case, target_seconds, gpu_iters_per_step):
+    """Oracle on a bounded sample: one time step of the same workload with the
+    pressure solve capped at M red-black SOR iterations (tolerance unreachable),
+    at two values of M; per-iteration and per-step costs from the difference."""
+    from oracle import oracle as O
+
+    prm = dict(case["params"], p_tol=1e-300)
+
+    def one(m):
+        o = O.Oracle(case["nx"], case["ny"], case["xf"], case["yf"], case["u0"], case["v0"], case["p0"],
+                     **dict(prm, p_max_iter=m))
+        t0 = time.perf_counter()
+        o.step(1)
+        return time.perf_counter() - t0
+
+    m1 = 10
+    t1 = one(m1)
+    probe = one(m1 + 40)
+    per_it = max((probe - t1) / 40.0, 1e-9)
+    m2 = int(max(100, min(20000, (target_seconds - t1) / per_it)))
+    t2 = one(m2)
+    per_it = (t2 - t1) / (m2 - m1)
+    overhead = max(t1 - m1 * per_it, 0.0)
+    cells = case["nx"] * case["ny"]
+    est_step = overhead + per_it * gpu_iters_per_step
+    return dict(value=cells / per_it, unit="cell-updates/s", cores=O.num_threads(), kind="oracle",
+                sample=(f"one {case['nx']}x{case['ny']} time step of the same workload with the "
+                        f"pressure solve capped at {m1} and at {m2} red-black SOR iterations; "
+                        f"rate from the difference"),
+                seconds=round(t1 + probe + t2, 2),
+                s_per_time_step_est=est_step,
+                step_overhead_s=overhead)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--solver", choices=("sor", "pcg"), default="sor",
+                    help="pressure solver of the headline leg")
+    ap.add_argument("--pcg-steps", type=int, default=4, help="timed steps of the PCG leg (0: skip)")
+    ap.add_argument("--profile-every", type=int, default=16,
+                    help="bracket every n-th launch of each timed kernel with HIP events")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample (0: skip the CPU baseline)")
+    ap.add_argument("--max-poisson-iters", type=int, default=0,
+                    help="profiling aid: cap each pressure solve at this many iterations "
+                         "(same kernels and launch shapes; the line is then marked capped)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run only a plain device-to-device copy of this many MiB, 20 times "
+                         "(reference kernel for scaling the HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.calibrate_copy > 0:
+        import torch
+        n = args.calibrate_copy * 2 ** 20 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8, "launches": 20}))
+        return
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the solver is single-device "
+                                   "(grid sharding is described but not implemented); use --gpus 1"}))
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+
+    build_if_missing()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import workloads as W
+
+    case = W.plunging_1024x768()
+    tag = "plunging1024x768"
+    method = ibm.RBSOR if args.solver == "sor" else ibm.PCG
+    main_leg = gpu_leg(case, method, args.steps, args.warmup, args.profile_every, args.max_poisson_iters)
+    pcg_leg = None
+    if args.solver == "sor" and args.pcg_steps > 0:
+        pcg_leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, args.profile_every,
+                          args.max_poisson_iters)
+
+    # dominant kernel of the headline leg
+    if method == ibm.RBSOR:
+        kid = ibm.KERNEL_SOR_SWEEP
+    else:
+        kid = max((ibm.KERNEL_PCG_SPMV, ibm.KERNEL_PCG_UPDATE, ibm.KERNEL_PCG_DIR),
+                  key=lambda k: main_leg["prof"][k]["avg_ms"] * main_leg["prof"][k]["launches"])
+    q = main_leg["prof"][kid]
+    kname = ibm.KERNEL_NAMES[kid]
+    achieved = q["bytes_per_launch"] / (q["avg_ms"] * 1e-3) / 1e9 if q["avg_ms"] > 0 else 0.0
+    traffic = read_traffic(kname, tag)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "avg_us": round(q["avg_ms"] * 1e3, 3), "samples": q["samples"],
+                "launches": q["launches"], "alg_bytes_per_launch": q["bytes_per_launch"]}
+
+    steps = args.steps
+    ms_per_step = 1e3 * main_leg["wall"] / steps
+    iters_per_step = sum(main_leg["iters"]) / steps
+    out = {
+        "metric": METRIC,
+        "value": round(main_leg["cell_updates_per_s"], 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case["name"] + ", dt 5e-4, h 0.5, f 0.4, stretched 16c x 12c grid",
+                   "nx": case["nx"], "ny": case["ny"],
+                   "solver": ("red-black SOR omega 1.8, tol 1e-8 every 10 iterations"
+                              if method == ibm.RBSOR else "Jacobi-PCG, tol 1e-8"),
+                   "initial_guess": "previous phi", "first_timed_step": args.warmup + 1,
+                   "poisson_iteration_cap": args.max_poisson_iters or None},
+        "s_per_time_step": round(main_leg["wall"] / steps, 6),
+        "poisson_iters_per_step": main_leg["iters"],
+        "poisson_iters_mean": iters_per_step,
+        "roofline": roofline,
+    }
+    if pcg_leg is not None:
+        out["pcg"] = {"s_per_time_step": round(pcg_leg["wall"] / args.pcg_steps, 6),
+                      "poisson_iters_per_step": pcg_leg["iters"],
+                      "cell_updates_per_s": round(pcg_leg["cell_updates_per_s"], 1),
+                      "kernels_avg_us": {ibm.KERNEL_NAMES[k]: round(pcg_leg["prof"][k]["avg_ms"] * 1e3, 3)
+                                         for k in (ibm.KERNEL_PCG_SPMV, ibm.KERNEL_PCG_UPDATE,
+                                                   ibm.KERNEL_PCG_DIR)}}
+    if args.cpu_seconds > 0:
+        cb = cpu_leg(case, args.cpu_seconds, iters_per_step)
+        cb["speedup_s_per_step"] = round(cb["s_per_time_step_est"] / (main_leg["wall"] / steps), 2)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
