@@ -212,15 +212,33 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
  * algorithmic bytes one launch moves on this grid.  Launches that only
  * observed a finished solve (the tail enqueued ahead of the convergence
  * test) are not sampled.  Synchronizes. */
-#define IBM_KERNEL_SOR_SWEEP 0    /* one colour of an SOR iteration: 24 B per cell updated */
-#define IBM_KERNEL_SOR_RESIDUAL 1 /* residual check: 16 B per cell (phi, V b) */
-#define IBM_KERNEL_PCG_SPMV 2     /* q = M p: 16 B per cell */
-#define IBM_KERNEL_PCG_UPDATE 3   /* x, r update: 48 B per cell */
-#define IBM_KERNEL_PCG_DIR 4      /* p = z + beta p: 24 B per cell */
+#define IBM_KERNEL_SOR_SWEEP 0      /* one colour of an SOR iteration: 24 B per cell updated */
+#define IBM_KERNEL_SOR_RESIDUAL 1   /* residual check: 16 B per cell (phi, V b) */
+#define IBM_KERNEL_PCG_DIR_SPMV 2   /* p = z + beta p and q = M p: 32 B per cell */
+#define IBM_KERNEL_PCG_UPDATE 3     /* x, r update: 48 B per cell */
+#define IBM_KERNEL_SOR_TB 4         /* temporally blocked SOR: 24 B per cell and iteration */
 #define IBM_KERNEL_COUNT 5
 int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
 int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
                           double* bytes_per_launch);
+
+/* Tuning options of the red-black SOR sweeps (they change the launch shape,
+ * never the arithmetic: every choice gives bit-identical iterates).
+ *   IBM_OPT_SOR_KERNEL  IBM_SOR_TEMPORAL (default): one launch performs
+ *                       IBM_OPT_TB_SWEEPS iterations on LDS tiles with halos;
+ *                       IBM_SOR_PER_COLOUR: one launch per colour sweep;
+ *   IBM_OPT_TB_SWEEPS   iterations per blocked launch, 1..8 (default 5);
+ *   IBM_OPT_TB_TILE_X   interior tile width, even (default 64);
+ *   IBM_OPT_TB_TILE_Y   interior tile height (default 48).
+ * IBM_ERR_INVALID for an unknown option or a tile shape whose halo does not
+ * fit the block's LDS.  Applies to solves started after the call. */
+#define IBM_OPT_SOR_KERNEL 0
+#define IBM_OPT_TB_SWEEPS 1
+#define IBM_OPT_TB_TILE_X 2
+#define IBM_OPT_TB_TILE_Y 3
+#define IBM_SOR_TEMPORAL 0
+#define IBM_SOR_PER_COLOUR 1
+int32_t ibm_set_option(ibm_ctx* ctx, int32_t option, int64_t value);
 
 /* Release the context (not the workspace).  Synchronizes the stream first. */
 void ibm_destroy(ibm_ctx* ctx);

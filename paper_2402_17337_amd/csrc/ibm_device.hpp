@@ -48,14 +48,10 @@ struct Ctl {
     int status;     // kSt*
     int iters;      // iterations when it finished (or latest check)
     int zero_rhs;   // 1: ||rhs|| = 0, solution is 0
-    unsigned ticket;  // arrival counter of the last-block reduction
-    unsigned pad;
     double bn;      // ||rhs||
     double r0;      // initial residual norm
     double rn;      // latest residual norm
-    double rz;      // PCG: r.z
-    double alpha;   // PCG step length
-    double beta;    // PCG direction update
+    double rz[2];   // PCG: r.z of iteration k in rz[k & 1]
 };
 
 // Host-mapped snapshot of a control block after a check.
@@ -97,36 +93,34 @@ __device__ inline void block_sum(double (&v)[N], double* lds) {
     }
 }
 
-// Grid-wide sum with the last-arriving block finishing the reduction in a
-// fixed order.  Every block calls it with its own partial values v.  Returns
-// true in the one block that holds the totals (valid in wave 0); that block
-// also resets the ticket for the next kernel that uses ctl.
+// Cross-block reductions without fences: a producer kernel writes one
+// partial per block with plain stores; a later kernel in the stream (after
+// the kernel boundary has made them visible) sums the nb partials in index
+// order.  Deterministic for a fixed launch shape.  Reduction kernels use at
+// most kRedMax blocks (grid-stride loops), so a consumer can afford to sum
+// all partials in every block.
+constexpr int kRedMax = 256;      // blocks of a reduction kernel
+constexpr int kRedThreads = 1024; // threads per block of a reduction kernel
+
 template <int N>
-__device__ inline bool grid_sum(double (&v)[N], double* partials, Ctl* ctl, double* lds) {
-    __shared__ int am_last;
-    const unsigned nb = gridDim.x * gridDim.y;
-    const unsigned b = blockIdx.y * gridDim.x + blockIdx.x;
+__device__ inline void block_partials(double (&v)[N], double* partials, int nb, int slot, double* lds) {
     block_sum(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) partials[(size_t)k * nb + b] = v[k];
-        __threadfence();
-        const unsigned t = atomicAdd(&ctl->ticket, 1u);
-        am_last = (t == nb - 1);
+        for (int k = 0; k < N; ++k) partials[(size_t)k * nb + slot] = v[k];
     }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
+}
+
+// Sum of the nb partials of each of N quantities; valid in wave 0.
+template <int N>
+__device__ inline void sum_partials(double (&v)[N], const double* partials, int nb, double* lds) {
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = 0.0;
-    for (unsigned q = threadIdx.x; q < nb; q += blockDim.x) {
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < N; ++k)
-            v[k] += __hip_atomic_load(&partials[(size_t)k * nb + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < N; ++k) v[k] += partials[(size_t)k * nb + q];
     }
     block_sum(v, lds);
-    if (threadIdx.x == 0) ctl->ticket = 0;
-    return true;
 }
 
 __device__ inline void publish(const Ctl* ctl, Slot* hs) {

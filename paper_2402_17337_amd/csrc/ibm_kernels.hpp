@@ -72,38 +72,45 @@ __global__ __launch_bounds__(kBlock) void k_merge(Grid g, const double* __restri
 // ---------------------------------------------------------------------------
 // Pressure Poisson: red-black SOR on A phi = V b in split storage
 // ---------------------------------------------------------------------------
+// Neighbour sum and diagonal of row (i, j) of A with explicit fused
+// multiply-adds, so that every kernel that updates a cell rounds alike:
+//   sum = aE xE + aW xW + aN xN + aS xS   (absent neighbours: a = 0, x = 0)
+//   d   = (((aE + aD) + aW) + aN) + aS    (aD: outlet term, nonzero at i = nx-1)
+// with aE = dy_j pcE_i, aW = dy_j pcW_i, aD = dy_j pcD_i, aN = dx_i pcN_j,
+// aS = dx_i pcS_j; the coefficient arrays are zero on Neumann faces.
+__device__ inline double rb_sum(double aE, double xE, double aW, double xW, double aN, double xN, double aS,
+                                double xS) {
+    double sum = aE * xE;
+    sum = __fma_rn(aW, xW, sum);
+    sum = __fma_rn(aN, xN, sum);
+    return __fma_rn(aS, xS, sum);
+}
+__device__ inline double rb_diag(double aE, double aD, double aW, double aN, double aS) {
+    return (((aE + aD) + aW) + aN) + aS;
+}
+// SOR update with the reciprocal diagonal rd = 1/d:
+//   phi <- (1 - omega) phi + omega (sum - V b) rd
+__device__ inline double sor_update(double x, double sum, double b, double rd, double omega) {
+    const double gs = (sum - b) * rd;
+    return __fma_rn(omega, gs, (1.0 - omega) * x);
+}
+
 // Neighbour sum and diagonal of row (i, j) of A, reading the other colour
 // (split index k of the cell, s = its position parity in the row).
 __device__ inline double rb_row(const Grid& g, const double* __restrict__ other, int i, int j, size_t k, int s,
                                 double& d) {
     const double dyj = g.dy[j], dxi = g.dx[i];
-    double sum = 0.0;
-    if (i < g.nx - 1) {
-        const double a = dyj * g.pcE[i];
-        sum = a * other[k + s];
-        d = a;
-    } else {
-        d = dyj * g.pcD[i];
-    }
-    if (i > 0) {
-        const double a = dyj * g.pcW[i];
-        sum += a * other[k + s - 1];
-        d += a;
-    }
-    if (j < g.ny - 1) {
-        const double a = dxi * g.pcN[j];
-        sum += a * other[k + g.nh];
-        d += a;
-    }
-    if (j > 0) {
-        const double a = dxi * g.pcS[j];
-        sum += a * other[k - g.nh];
-        d += a;
-    }
-    return sum;
+    const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+    const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+    const double xE = i < g.nx - 1 ? other[k + s] : 0.0;
+    const double xW = i > 0 ? other[k + s - 1] : 0.0;
+    const double xN = j < g.ny - 1 ? other[k + g.nh] : 0.0;
+    const double xS = j > 0 ? other[k - g.nh] : 0.0;
+    d = rb_diag(aE, aD, aW, aN, aS);
+    return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
 
-// One colour of a red-black SOR iteration:
+// One colour of a red-black SOR iteration (one launch per colour):
 //   phi_P <- (1 - omega) phi_P + omega (sum a_nb phi_nb - V b_P) / (sum a_nb + a_D)
 // COLOR 0 updates the red cells ((i+j) even), COLOR 1 the black cells.
 template <int COLOR>
@@ -120,28 +127,22 @@ __global__ __launch_bounds__(kBlock) void k_sor_sweep(Grid g, double* __restrict
     const size_t k = (size_t)j * g.nh + m;
     double d;
     const double sum = rb_row(g, other, i, j, k, s, d);
-    const double gs = (sum - bself[k]) / d;
-    self[k] = (1.0 - omega) * self[k] + omega * gs;
+    self[k] = sor_update(self[k], sum, bself[k], 1.0 / d, omega);
 }
 
-// Residual r = V b - A phi over both colours; sum r^2 and (V b)^2, then the
-// stop test of the solve.  phase 0 is the check before the first iteration.
-__global__ __launch_bounds__(kBlock) void k_sor_residual(Grid g, const double* __restrict__ red,
-                                                         const double* __restrict__ black,
-                                                         const double* __restrict__ bred,
-                                                         const double* __restrict__ bblack, Ctl* ctl,
-                                                         double* partials, int phase, int it, int max_iter,
-                                                         double tol, int fixed, Slot* hs) {
-    __shared__ double lds[2 * kBlock / kWave];
-    if (ctl->done) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
-        return;
-    }
-    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+// Residual r = V b - A phi over both colours: per-block partial sums of r^2
+// and (V b)^2 (grid-stride over the split positions, at most kRedMax blocks).
+__global__ __launch_bounds__(kRedThreads) void k_sor_residual(Grid g, const double* __restrict__ red,
+                                                              const double* __restrict__ black,
+                                                              const double* __restrict__ bred,
+                                                              const double* __restrict__ bblack, const Ctl* ctl,
+                                                              double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    if (ctl->done) return;
     double acc[2] = {0.0, 0.0};
-    if (m < g.nh && j < g.ny) {
-        const size_t k = (size_t)j * g.nh + m;
+    const size_t n = (size_t)g.nh * g.ny;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(k / g.nh), m = (int)(k - (size_t)j * g.nh);
         {
             const int s = j & 1, i = 2 * m + s;
             double d;
@@ -159,11 +160,216 @@ __global__ __launch_bounds__(kBlock) void k_sor_residual(Grid g, const double* _
             acc[1] += bblack[k] * bblack[k];
         }
     }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// One block: sum the residual partials (r^2, b^2) and run the stop test of a
+// solve (phase 0 = before the first iteration).  den_one: ||rhs|| = 0 turns
+// the test absolute instead of meaning a zero solution.
+__global__ __launch_bounds__(kBlock) void k_check(Ctl* ctl, const double* __restrict__ partials, int nb, int phase,
+                                                  int it, int max_iter, double tol, int fixed, int den_one, Slot* hs) {
+    __shared__ double lds[2 * kBlock / kWave];
+    if (ctl->done) {
+        if (threadIdx.x == 0) publish(ctl, hs);
+        return;
+    }
+    double acc[2];
+    sum_partials(acc, partials, nb, lds);
     if (threadIdx.x == 0) {
-        check_finish(ctl, acc[0], acc[1], phase, it, max_iter, tol, fixed, 0);
+        check_finish(ctl, acc[0], acc[1], phase, it, max_iter, tol, fixed, den_one);
         publish(ctl, hs);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Temporally blocked red-black SOR.  One block per tile: the tile interior
+// plus a halo of depth H (clamped to the domain) is loaded into LDS in split
+// layout, S red-black iterations run there, and the interior is written back.
+// After h half-sweeps only cells farther than h-1 from the loaded edge are
+// still exact, so with H >= 2S (+1 when the residual of the interior is
+// summed at the end) the interior equals S global iterations bit for bit: each
+// cell is updated by sor_update with the same neighbour values.  Half-sweep h
+// updates only the cells within e_h = 2S - h (+1) of the interior.
+//
+// Work layout: lane l of every wave owns split column l of the loaded tile
+// (at most 64 columns, i.e. a loaded width of 128 cells); wave w owns rows
+// w, w + 16, w + 32, w + 48.  A thread keeps phi, V b and 1/d of its cells
+// (both colours) and the x coefficients of its two columns in registers; row
+// coefficients are uniform over a wave; LDS holds phi for the neighbours.
+// ---------------------------------------------------------------------------
+constexpr int kTbThreads = 1024;
+constexpr int kTbWaves = kTbThreads / kWave;   // 16
+constexpr int kTbRows = 4;                     // rows per wave: loaded height <= 64
+constexpr int kTbCols = kWave;                 // split columns: loaded width <= 128
+
+struct TbShape {
+    int tx, ty;    // interior tile size (tx even)
+    int halo;      // H (even)
+    int ntx, nty;  // tiles in x and y
+    int swizzle;   // 1: tiles of one XCD form a contiguous band
+};
+
+// Per-thread state of the blocked sweep (registers).
+struct TbCells {
+    double b[2][kTbRows];   // V b of the red (0) and black (1) cell of each owned row
+    double rd[2][kTbRows];  // 1 / diagonal
+};
+
+// One half-sweep of colour C over the owned rows inside [ilo, ihi) x [jlo, jhi).
+// Rows go in groups of kTbGroup: reads of the group first, then its updates,
+// then its writes (colour-C cells read only the other colour), so the rows'
+// latencies overlap within the register budget.
+constexpr int kTbGroup = 2;
+
+template <int C>
+__device__ inline void tb_half(const Grid& g, TbCells& st, double* __restrict__ self, const double* __restrict__ other,
+                               int w, int lane, bool col, int ic, int ya, int ly, int lxh, int xa, int xb, int yb,
+                               int ilo, int ihi, int jlo, int jhi, const double (&cdx)[2], const double (&cE)[2],
+                               const double (&cW)[2], double omega) {
+#pragma unroll
+    for (int r0 = 0; r0 < kTbRows; r0 += kTbGroup) {
+        double vE[kTbGroup], vW[kTbGroup], vN[kTbGroup], vS[kTbGroup], vP[kTbGroup];
+        bool ok[kTbGroup];
+#pragma unroll
+        for (int q = 0; q < kTbGroup; ++q) {
+            const int jl = w + kTbWaves * (r0 + q);
+            const int j = ya + jl;
+            const int s = (j + C) & 1;
+            const int i = ic + s;
+            ok[q] = jl < ly && j >= jlo && j < jhi && col && i >= ilo && i < ihi && !(i > 0 && i - 1 < xa) &&
+                    !(i < g.nx - 1 && i + 1 >= xb) && !(j > 0 && j - 1 < ya) && !(j < g.ny - 1 && j + 1 >= yb);
+            vE[q] = vW[q] = vN[q] = vS[q] = vP[q] = 0.0;
+            if (ok[q]) {
+                const int p = jl * lxh + lane;
+                vP[q] = self[p];
+                if (i < g.nx - 1) vE[q] = other[p + s];
+                if (i > 0) vW[q] = other[p + s - 1];
+                if (j < g.ny - 1) vN[q] = other[p + lxh];
+                if (j > 0) vS[q] = other[p - lxh];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kTbGroup; ++q) {
+            if (!ok[q]) continue;
+            const int r = r0 + q;
+            const int j = ya + w + kTbWaves * r;
+            const int s = (j + C) & 1;
+            const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];  // scalar loads (j is wave-uniform)
+            const double aE = dyj * cE[s], aW = dyj * cW[s];
+            const double aN = cdx[s] * pn, aS = cdx[s] * ps;
+            const double sum = rb_sum(aE, vE[q], aW, vW[q], aN, vN[q], aS, vS[q]);
+            vP[q] = sor_update(vP[q], sum, st.b[C][r], st.rd[C][r], omega);
+        }
+#pragma unroll
+        for (int q = 0; q < kTbGroup; ++q)
+            if (ok[q]) self[(w + kTbWaves * (r0 + q)) * lxh + lane] = vP[q];
+    }
+}
+
+__global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, double* __restrict__ red, double* __restrict__ black,
+                                                       const double* __restrict__ bred,
+                                                       const double* __restrict__ bblack, double omega,
+                                                       const Ctl* __restrict__ ctl, TbShape ts, int nsweep,
+                                                       int residual, double* __restrict__ partials) {
+    extern __shared__ double tile[];
+    __shared__ double lds[2 * kTbWaves];
+    if (ctl->done) return;
+    const int nt = ts.ntx * ts.nty;
+    int t = blockIdx.x;
+    if (ts.swizzle) t = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
+    const int txi = t % ts.ntx, tyi = t / ts.ntx;
+    const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
+    const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
+    const int H = ts.halo;
+    const int xa = max(0, X0 - H), xb = min(g.nx, X1 + H);
+    const int ya = max(0, Y0 - H), yb = min(g.ny, Y1 + H);
+    const int lxh = (xb - xa) >> 1, ly = yb - ya, np = lxh * ly;
+    const int m0 = xa >> 1;
+    double* lr = tile;
+    double* lb = tile + np;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave index, uniform
+    const bool col = lane < lxh;
+    // x coefficients of the two cells of split column `lane`: i = 2(m0+lane) + q
+    const int ic = 2 * (m0 + lane);
+    double cdx[2], cE[2], cW[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int i = col ? ic + q : 0;
+        cdx[q] = g.dx[i];
+        cE[q] = g.pcE[i];
+        cW[q] = g.pcW[i];
+    }
+    TbCells st;
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = w + kTbWaves * r;
+        const int j = min(ya + jl, g.ny - 1);
+        const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) st.b[c][r] = st.rd[c][r] = 0.0;
+        if (jl < ly && col) {
+            const size_t kg = (size_t)(ya + jl) * g.nh + m0 + lane;
+            st.b[0][r] = bred[kg];
+            st.b[1][r] = bblack[kg];
+            lr[jl * lxh + lane] = red[kg];
+            lb[jl * lxh + lane] = black[kg];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = (ya + jl + c) & 1;  // position parity of the colour-c cell in the row
+                const double d = rb_diag(dyj * cE[q], dyj * g.pcD[ic + q], dyj * cW[q], cdx[q] * pn, cdx[q] * ps);
+                st.rd[c][r] = 1.0 / d;
+            }
+        }
+    }
+    __syncthreads();
+    const int extra = residual ? 1 : 0;
+    for (int it = 0; it < nsweep; ++it) {
+        // red half-sweep h = 2 it + 1, black h = 2 it + 2; region within e of the interior
+        int e = 2 * nsweep - (2 * it + 1) + extra;
+        tb_half<0>(g, st, lr, lb, w, lane, col, ic, ya, ly, lxh, xa, xb, yb, max(xa, X0 - e), min(xb, X1 + e),
+                   max(ya, Y0 - e), min(yb, Y1 + e), cdx, cE, cW, omega);
+        __syncthreads();
+        e -= 1;
+        tb_half<1>(g, st, lb, lr, w, lane, col, ic, ya, ly, lxh, xa, xb, yb, max(xa, X0 - e), min(xb, X1 + e),
+                   max(ya, Y0 - e), min(yb, Y1 + e), cdx, cE, cW, omega);
+        __syncthreads();
+    }
+    // interior back to global memory (both colours), and its residual
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = w + kTbWaves * r;
+        const int j = ya + jl;
+        if (jl >= ly || j < Y0 || j >= Y1 || !col) continue;
+        const size_t kg = (size_t)j * g.nh + m0 + lane;
+        const int p = jl * lxh + lane;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int s = (j + c) & 1;
+            const int i = ic + s;
+            if (i < X0 || i >= X1) continue;
+            const double x = (c ? lb : lr)[p];
+            (c ? black : red)[kg] = x;
+            if (residual) {
+                const double* other = c ? lr : lb;
+                const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];
+                const double aE = dyj * cE[s], aW = dyj * cW[s], aD = dyj * g.pcD[i];
+                const double aN = cdx[s] * pn, aS = cdx[s] * ps;
+                const double xE = i < g.nx - 1 ? other[p + s] : 0.0;
+                const double xW = i > 0 ? other[p + s - 1] : 0.0;
+                const double xN = j < g.ny - 1 ? other[p + lxh] : 0.0;
+                const double xS = j > 0 ? other[p - lxh] : 0.0;
+                const double d = rb_diag(aE, aD, aW, aN, aS);
+                const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+                const double bb = st.b[c][r];
+                const double rres = bb - (sum - d * x);
+                acc[0] += rres * rres;
+                acc[1] += bb * bb;
+            }
+        }
+    }
+    if (residual) block_partials(acc, partials, nt, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,203 +377,204 @@ __global__ __launch_bounds__(kBlock) void k_sor_residual(Grid g, const double* _
 // ---------------------------------------------------------------------------
 __device__ inline double nat_row(const Grid& g, const double* __restrict__ x, int i, int j, size_t k, double& d) {
     const double dyj = g.dy[j], dxi = g.dx[i];
-    double sum = 0.0;
-    if (i < g.nx - 1) {
-        const double a = dyj * g.pcE[i];
-        sum = a * x[k + 1];
-        d = a;
-    } else {
-        d = dyj * g.pcD[i];
-    }
-    if (i > 0) {
-        const double a = dyj * g.pcW[i];
-        sum += a * x[k - 1];
-        d += a;
-    }
-    if (j < g.ny - 1) {
-        const double a = dxi * g.pcN[j];
-        sum += a * x[k + g.nx];
-        d += a;
-    }
-    if (j > 0) {
-        const double a = dxi * g.pcS[j];
-        sum += a * x[k - g.nx];
-        d += a;
-    }
-    return sum;
+    const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+    const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+    const double xE = i < g.nx - 1 ? x[k + 1] : 0.0;
+    const double xW = i > 0 ? x[k - 1] : 0.0;
+    const double xN = j < g.ny - 1 ? x[k + g.nx] : 0.0;
+    const double xS = j > 0 ? x[k - g.nx] : 0.0;
+    d = rb_diag(aE, aD, aW, aN, aS);
+    return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
 
 __device__ inline double nat_diag(const Grid& g, int i, int j) {
     const double dyj = g.dy[j], dxi = g.dx[i];
-    double d = (i < g.nx - 1) ? dyj * g.pcE[i] : dyj * g.pcD[i];
-    if (i > 0) d += dyj * g.pcW[i];
-    if (j < g.ny - 1) d += dxi * g.pcN[j];
-    if (j > 0) d += dxi * g.pcS[j];
-    return d;
+    return rb_diag(dyj * g.pcE[i], dyj * g.pcD[i], dyj * g.pcW[i], dxi * g.pcN[j], dxi * g.pcS[j]);
 }
 
-// r = -V b + A x (residual of M x = -V b), p = z = r / diag(M); sums r.z,
-// r.r, (V b)^2 and the first stop test.
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Grid g, const double* __restrict__ x,
-                                                     const double* __restrict__ vb, double* __restrict__ r,
-                                                     double* __restrict__ p, Ctl* ctl, double* partials,
-                                                     double tol, Slot* hs) {
-    __shared__ double lds[3 * kBlock / kWave];
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+// All PCG kernels are grid-stride over the nx*ny cells with at most kRedMax
+// blocks of kRedThreads; cross-block sums go through per-block partials.
+#define IBM_CELLS_LOOP(k)                                                                       \
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)g.nx * g.ny;    \
+         k += (size_t)gridDim.x * blockDim.x)
+
+// New search direction of one cell, p = z + beta p_old with z = r / d (the
+// same rounding wherever it is evaluated).
+__device__ inline double pcg_dir(double r, double pold, double d, double beta) {
+    return __fma_rn(beta, pold, r / d);
+}
+
+// r = -V b + A x (residual of M x = -V b); partials of r.r, r.z, (V b)^2.
+__global__ __launch_bounds__(kRedThreads) void k_pcg_init(Grid g, const double* __restrict__ x,
+                                                          const double* __restrict__ vb, double* __restrict__ r,
+                                                          double* partials) {
+    __shared__ double lds[3 * kRedThreads / kWave];
     double acc[3] = {0.0, 0.0, 0.0};
-    if (i < g.nx && j < g.ny) {
-        const size_t k = (size_t)j * g.nx + i;
+    IBM_CELLS_LOOP(k) {
+        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
         double d;
         const double sum = nat_row(g, x, i, j, k, d);
         const double rk = -vb[k] + (sum - d * x[k]);
-        const double zk = rk / d;
         r[k] = rk;
-        p[k] = zk;
-        acc[0] = rk * zk;
-        acc[1] = rk * rk;
-        acc[2] = vb[k] * vb[k];
+        acc[0] += rk * rk;
+        acc[1] += rk * (rk / d);
+        acc[2] += vb[k] * vb[k];
     }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// One block: r.z of iteration 0 and the first stop test.  Partials of every
+// r-producing PCG kernel come in the order (r.r, r.z[, b.b]).
+__global__ __launch_bounds__(kBlock) void k_pcg_init_check(Ctl* ctl, const double* __restrict__ partials, int nb,
+                                                           double tol, Slot* hs) {
+    __shared__ double lds[3 * kBlock / kWave];
+    double acc[3];
+    sum_partials(acc, partials, nb, lds);
     if (threadIdx.x == 0) {
-        ctl->rz = acc[0];
-        ctl->beta = 0.0;
-        check_finish(ctl, acc[1], acc[2], 0, 0, 0, tol, 0, 0);
+        ctl->rz[0] = acc[1];
+        check_finish(ctl, acc[0], acc[2], 0, 0, 0, tol, 0, 0);
         publish(ctl, hs);
     }
 }
 
-// q = M p, alpha = r.z / p.q
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Grid g, const double* __restrict__ p, double* __restrict__ q,
-                                                     Ctl* ctl, double* partials) {
-    __shared__ double lds[kBlock / kWave];
-    if (ctl->done) return;
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    double acc[1] = {0.0};
-    if (i < g.nx && j < g.ny) {
-        const size_t k = (size_t)j * g.nx + i;
-        double d;
-        const double sum = nat_row(g, p, i, j, k, d);
-        const double qk = -(sum - d * p[k]);
-        q[k] = qk;
-        acc[0] = p[k] * qk;
-    }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
-    if (threadIdx.x == 0) ctl->alpha = ctl->rz / acc[0];
-}
-
-// x += alpha p, r -= alpha q; sums r.r and r.z with z = r / diag(M); stop
-// test on the recursive residual (kStConfirm asks the host for the true
-// residual), else beta = (r.z)_new / (r.z)_old.
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Grid g, double* __restrict__ x, double* __restrict__ r,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       Ctl* ctl, double* partials, int it, int max_iter, double tol,
-                                                       int fixed, Slot* hs) {
-    __shared__ double lds[2 * kBlock / kWave];
-    if (ctl->done) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
+// Iteration kk, first kernel.  Every block sums the r.r, r.z partials of r_kk
+// and takes the same decision: for kk > 0 stop (NaN, the recursive residual
+// passed -> kStConfirm, or the iteration limit) or beta = (r.z)_kk /
+// (r.z)_{kk-1}; kk = 0 and restarts use beta = 0 (p = z).  Block 0 records the
+// decision and publishes it.  Then p_kk = z + beta p_{kk-1} (into pnew,
+// recomputed for the four neighbours as well) and q = M p_kk; partials of p.q.
+__global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const double* __restrict__ r,
+                                                              const double* __restrict__ pold,
+                                                              double* __restrict__ pnew, double* __restrict__ q,
+                                                              Ctl* ctl, const double* __restrict__ rpart, int nb,
+                                                              double* __restrict__ pqpart, int kk, int max_iter,
+                                                              double tol, int fixed, int restart, Slot* hs) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    __shared__ double s_beta;
+    __shared__ int s_stop, s_done;
+    // Block 0 of this launch may set ctl->done while other blocks start:
+    // read it once per block so every thread of a block takes one branch.
+    if (threadIdx.x == 0) s_done = ctl->done;
+    __syncthreads();
+    if (s_done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish(ctl, hs);
         return;
     }
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    const double alpha = ctl->alpha;
-    double acc[2] = {0.0, 0.0};
-    if (i < g.nx && j < g.ny) {
-        const size_t k = (size_t)j * g.nx + i;
-        x[k] += alpha * p[k];
-        const double rk = r[k] - alpha * q[k];
-        r[k] = rk;
-        acc[0] = rk * rk;
-        acc[1] = rk * (rk / nat_diag(g, i, j));
-    }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
+    double acc[2];
+    sum_partials(acc, rpart, nb, lds);
     if (threadIdx.x == 0) {
         const double rn = sqrt(acc[0]);
-        ctl->rn = rn;
-        ctl->iters = it;
-        if (!isfinite(rn)) {
-            ctl->done = kDone;
-            ctl->status = kStNan;
-        } else if (rn <= tol * ctl->bn) {
-            ctl->done = kDone;
-            ctl->status = kStConfirm;
-        } else if (it >= max_iter) {
-            ctl->done = kDone;
-            ctl->status = fixed ? kStOk : kStNotConverged;
-        } else {
-            ctl->beta = acc[1] / ctl->rz;
-            ctl->rz = acc[1];
+        const bool first = (kk == 0) || restart;
+        int stop = 0, status = kStOk;
+        if (!first) {
+            if (!isfinite(rn)) { stop = 1; status = kStNan; }
+            else if (rn <= tol * ctl->bn) { stop = 1; status = kStConfirm; }
+            else if (kk >= max_iter) { stop = 1; status = fixed ? kStOk : kStNotConverged; }
         }
-        publish(ctl, hs);
+        s_stop = stop;
+        s_beta = first ? 0.0 : acc[1] / ctl->rz[(kk - 1) & 1];
+        if (blockIdx.x == 0) {
+            ctl->rn = rn;
+            ctl->iters = kk;
+            if (stop) {
+                ctl->done = kDone;
+                ctl->status = status;
+            } else {
+                ctl->rz[kk & 1] = acc[1];
+            }
+            publish(ctl, hs);
+        }
     }
+    __syncthreads();
+    if (s_stop) return;
+    const double beta = s_beta;
+    double pacc[1] = {0.0};
+    IBM_CELLS_LOOP(k) {
+        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+        const double dyj = g.dy[j], dxi = g.dx[i];
+        const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+        const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+        const double d = rb_diag(aE, aD, aW, aN, aS);
+        const double pk = pcg_dir(r[k], pold[k], d, beta);
+        const double pE = i < g.nx - 1 ? pcg_dir(r[k + 1], pold[k + 1], nat_diag(g, i + 1, j), beta) : 0.0;
+        const double pW = i > 0 ? pcg_dir(r[k - 1], pold[k - 1], nat_diag(g, i - 1, j), beta) : 0.0;
+        const double pN = j < g.ny - 1 ? pcg_dir(r[k + g.nx], pold[k + g.nx], nat_diag(g, i, j + 1), beta) : 0.0;
+        const double pS = j > 0 ? pcg_dir(r[k - g.nx], pold[k - g.nx], nat_diag(g, i, j - 1), beta) : 0.0;
+        const double sum = rb_sum(aE, pE, aW, pW, aN, pN, aS, pS);
+        const double qk = d * pk - sum;  // M p = -A p
+        pnew[k] = pk;
+        q[k] = qk;
+        pacc[0] += pk * qk;
+    }
+    block_partials(pacc, pqpart, gridDim.x, blockIdx.x, lds);
 }
 
-// p = z + beta p with z = r / diag(M)
-__global__ __launch_bounds__(kBlock) void k_pcg_dir(Grid g, const double* __restrict__ r, double* __restrict__ p,
-                                                    const Ctl* ctl) {
+// Iteration kk, second kernel: alpha = (r.z)_kk / p.q (every block sums the
+// p.q partials); x += alpha p, r -= alpha q; partials of r.r and r.z.
+__global__ __launch_bounds__(kRedThreads) void k_pcg_update(Grid g, double* __restrict__ x, double* __restrict__ r,
+                                                            const double* __restrict__ p, const double* __restrict__ q,
+                                                            const Ctl* ctl, const double* __restrict__ pqpart, int nb,
+                                                            double* __restrict__ rpart, int kk) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    __shared__ double s_alpha;
     if (ctl->done) return;
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (i >= g.nx || j >= g.ny) return;
-    const size_t k = (size_t)j * g.nx + i;
-    p[k] = r[k] / nat_diag(g, i, j) + ctl->beta * p[k];
+    {
+        double pq[1];
+        sum_partials(pq, pqpart, nb, lds);
+        if (threadIdx.x == 0) s_alpha = ctl->rz[kk & 1] / pq[0];
+        __syncthreads();
+    }
+    const double alpha = s_alpha;
+    double acc[2] = {0.0, 0.0};
+    IBM_CELLS_LOOP(k) {
+        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+        x[k] = __fma_rn(alpha, p[k], x[k]);
+        const double rk = __fma_rn(-alpha, q[k], r[k]);
+        r[k] = rk;
+        acc[0] += rk * rk;
+        acc[1] += rk * (rk / nat_diag(g, i, j));
+    }
+    block_partials(acc, rpart, gridDim.x, blockIdx.x, lds);
 }
 
-// True residual r = -V b + A x; accepts the solve (status ok) or restarts the
-// recursion from it (r.z recomputed, beta = 0, solve running again).
-__global__ __launch_bounds__(kBlock) void k_pcg_true_residual(Grid g, const double* __restrict__ x,
-                                                              const double* __restrict__ vb, double* __restrict__ r,
-                                                              Ctl* ctl, double* partials, double tol, Slot* hs) {
-    __shared__ double lds[2 * kBlock / kWave];
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+// True residual r = -V b + A x (written to r); partials of r.r, r.z.
+__global__ __launch_bounds__(kRedThreads) void k_pcg_true_residual(Grid g, const double* __restrict__ x,
+                                                                   const double* __restrict__ vb,
+                                                                   double* __restrict__ r, double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
     double acc[2] = {0.0, 0.0};
-    if (i < g.nx && j < g.ny) {
-        const size_t k = (size_t)j * g.nx + i;
+    IBM_CELLS_LOOP(k) {
+        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
         double d;
         const double sum = nat_row(g, x, i, j, k, d);
         const double rk = -vb[k] + (sum - d * x[k]);
         r[k] = rk;
-        acc[0] = rk * rk;
-        acc[1] = rk * (rk / d);
+        acc[0] += rk * rk;
+        acc[1] += rk * (rk / d);
     }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// One block: the true residual accepts the solve (status ok, done) or the
+// solve resumes (done = 0) and restarts from it; stats_only records rn.
+__global__ __launch_bounds__(kBlock) void k_pcg_confirm(Ctl* ctl, const double* __restrict__ partials, int nb,
+                                                        double tol, int stats_only, Slot* hs) {
+    __shared__ double lds[2 * kBlock / kWave];
+    double acc[2];
+    sum_partials(acc, partials, nb, lds);
     if (threadIdx.x == 0) {
         const double rn = sqrt(acc[0]);
         ctl->rn = rn;
-        if (!isfinite(rn)) {
-            ctl->status = kStNan;
-        } else if (rn <= tol * ctl->bn) {
-            ctl->status = kStOk;
-        } else {
-            ctl->rz = acc[1];
-            ctl->beta = 0.0;
-            ctl->status = kStOk;
-            ctl->done = kRunning;
+        if (!stats_only) {
+            if (!isfinite(rn)) {
+                ctl->status = kStNan;
+            } else if (rn <= tol * ctl->bn) {
+                ctl->status = kStOk;
+            } else {
+                ctl->status = kStOk;
+                ctl->done = kRunning;
+            }
         }
-        publish(ctl, hs);
-    }
-}
-
-// Fixed-iteration PCG end: true residual for the statistics only.
-__global__ __launch_bounds__(kBlock) void k_pcg_final_residual(Grid g, const double* __restrict__ x,
-                                                               const double* __restrict__ vb, Ctl* ctl,
-                                                               double* partials, Slot* hs) {
-    __shared__ double lds[kBlock / kWave];
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    double acc[1] = {0.0};
-    if (i < g.nx && j < g.ny) {
-        const size_t k = (size_t)j * g.nx + i;
-        double d;
-        const double sum = nat_row(g, x, i, j, k, d);
-        const double rk = -vb[k] + (sum - d * x[k]);
-        acc[0] = rk * rk;
-    }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
-    if (threadIdx.x == 0) {
-        ctl->rn = sqrt(acc[0]);
         publish(ctl, hs);
     }
 }
@@ -461,40 +668,35 @@ __device__ inline double lap_v(const Grid& g, const double* __restrict__ v, int 
 }
 
 // Residual of the implicit viscous equation, r = rhs - (x - beta L x), over
-// the unknowns of component `comp` (0: u faces 1..nx-1, 1: v faces 1..ny-1).
-__global__ __launch_bounds__(kBlock) void k_helm_residual(Grid g, int comp, const double* __restrict__ x,
-                                                          const double* __restrict__ rhs, double beta, Ctl* ctl,
-                                                          double* partials, int phase, int it, int max_iter,
-                                                          double tol, Slot* hs) {
+// the unknowns of component comp (0: u faces 1..nx-1, 1: v faces 1..ny-1):
+// per-block partials of r^2 and rhs^2 (grid-stride, at most kRedMax blocks).
+__global__ __launch_bounds__(kRedThreads) void k_helm_residual(Grid g, int comp, const double* __restrict__ x,
+                                                               const double* __restrict__ rhs, double beta,
+                                                               const Ctl* ctl, double* partials) {
 #pragma clang fp contract(off)
-    __shared__ double lds[2 * kBlock / kWave];
-    if (ctl->done) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) publish(ctl, hs);
-        return;
-    }
-    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    __shared__ double lds[2 * kRedThreads / kWave];
+    if (ctl->done) return;
+    const int w = comp == 0 ? g.nx - 1 : g.nx;   // unknowns per row
+    const int h = comp == 0 ? g.ny : g.ny - 1;   // rows of unknowns
+    const size_t n = (size_t)w * h;
     double acc[2] = {0.0, 0.0};
-    if (comp == 0) {
-        if (i >= 1 && i <= g.nx - 1 && j < g.ny) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const int jr = (int)(q / w), ir = (int)(q - (size_t)jr * w);
+        if (comp == 0) {
+            const int i = ir + 1, j = jr;
             const size_t k = (size_t)j * (g.nx + 1) + i;
             const double r = rhs[k] - (x[k] - beta * lap_u(g, x, i, j));
-            acc[0] = r * r;
-            acc[1] = rhs[k] * rhs[k];
-        }
-    } else {
-        if (i < g.nx && j >= 1 && j <= g.ny - 1) {
+            acc[0] += r * r;
+            acc[1] += rhs[k] * rhs[k];
+        } else {
+            const int i = ir, j = jr + 1;
             const size_t k = (size_t)j * g.nx + i;
             const double r = rhs[k] - (x[k] - beta * lap_v(g, x, i, j));
-            acc[0] = r * r;
-            acc[1] = rhs[k] * rhs[k];
+            acc[0] += r * r;
+            acc[1] += rhs[k] * rhs[k];
         }
     }
-    if (!grid_sum(acc, partials, ctl, lds)) return;
-    if (threadIdx.x == 0) {
-        check_finish(ctl, acc[0], acc[1], phase, it, max_iter, tol, 0, 1);
-        publish(ctl, hs);
-    }
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------

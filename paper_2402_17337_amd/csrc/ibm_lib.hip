@@ -10,6 +10,7 @@
 // the solve, which returns at once when the solve has finished) and to the
 // pinned block.  The host waits on the check of an older chunk only, so the
 // GPU queue never drains while the solve runs.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,7 +53,7 @@ struct Layout {
 
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
-    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pq, phr, phb, vbr, vbb;
+    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -80,12 +81,14 @@ Offsets layout_for(int nx, int ny) {
     o.u = L.take<double>(NU); o.nu = L.take<double>(NU); o.ru = L.take<double>(NU); o.fufull = L.take<double>(NU);
     o.v = L.take<double>(NV); o.nv = L.take<double>(NV); o.rv = L.take<double>(NV); o.fvfull = L.take<double>(NV);
     o.p = L.take<double>(NC); o.phi = L.take<double>(NC); o.vb = L.take<double>(NC);
-    o.pr = L.take<double>(NC); o.pp = L.take<double>(NC); o.pq = L.take<double>(NC);
+    o.pr = L.take<double>(NC); o.pp = L.take<double>(NC); o.pp2 = L.take<double>(NC); o.pq = L.take<double>(NC);
     o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
-    o.max_blocks = std::max(blocks_for(nx + 1, ny + 1), blocks_for(nx / 2, ny));
-    o.partials = L.take<double>((size_t)3 * o.max_blocks);
+    // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
+    // two sums per tile of the blocked sweep (tiles of at least 2x1 cells)
+    o.max_blocks = kRedMax;
+    o.partials = L.take<double>((size_t)4 * kRedMax + (size_t)2 * (nx / 2) * ny);
     o.ctl = L.take<Ctl>(CTL_N);
     o.list_u = L.take<int>(NU); o.list_v = L.take<int>(NV); o.counts = L.take<int>(4);
     o.flu = L.take<uint8_t>(NU); o.flv = L.take<uint8_t>(NV); o.msrc = L.take<uint8_t>(NC);
@@ -148,7 +151,7 @@ struct ibm_ctx {
     Offsets off;
     Grid g;
     // device arrays
-    double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pq, *phr, *phb, *vbr, *vbb;
+    double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pp2, *pq, *phr, *phb, *vbr, *vbb;
     double *f_u, *f_v, *coef, *partials;
     Ctl* ctl;
     int *list_u, *list_v, *counts;
@@ -174,6 +177,10 @@ struct ibm_ctx {
     long solve_id = 0;
     std::string err;
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    // red-black SOR launch shape
+    int sor_kernel = IBM_SOR_TEMPORAL;
+    int tb_sweeps = 5;
+    int tb_tx = 104, tb_ty = 32;
 };
 
 namespace {
@@ -226,26 +233,34 @@ hipEvent_t pool_event(ibm_ctx* c) {
     return e;
 }
 
-// Launch f, bracketed by timing events for sampled launches of kernel kid.
+// Launch through f(start, stop): sampled launches of kernel kid get a pair
+// of events that the runtime records at the dispatch's own start and end
+// (hipExtLaunchKernelGGL), so the sampled duration is the kernel's, without
+// the dispatch overhead; other launches get null events.
 template <class F>
 void timed(ibm_ctx* c, int kid, int it, F&& f) {
-    bool take = c->prof_every > 0 && (c->launches[kid] % c->prof_every) == 0 &&
-                (int)c->samples[kid].size() < kMaxSamples;
+    const bool take = c->prof_every > 0 && (c->launches[kid] % c->prof_every) == 0 &&
+                      (int)c->samples[kid].size() < kMaxSamples;
     c->launches[kid]++;
     if (!take) {
-        f();
+        f(nullptr, nullptr);
         return;
     }
     hipEvent_t a = pool_event(c), b = pool_event(c);
     if (!a || !b) {
-        f();
+        f(nullptr, nullptr);
         return;
     }
-    (void)hipEventRecord(a, c->stream);
-    f();
-    (void)hipEventRecord(b, c->stream);
+    f(a, b);
     c->samples[kid].push_back(Sample{a, b, c->solve_id, it});
 }
+
+// Launch with optional dispatch-timing events (see timed()).
+#define LAUNCH_EV(ea, eb, kernel, grid, block, shmem, ...)                                              \
+    do {                                                                                                \
+        if (ea) hipExtLaunchKernelGGL(kernel, grid, block, shmem, c->stream, ea, eb, 0, __VA_ARGS__);  \
+        else hipLaunchKernelGGL(kernel, grid, block, shmem, c->stream, __VA_ARGS__);                    \
+    } while (0)
 
 // Drop samples of the current solve taken after it had finished.
 void prune_samples(ibm_ctx* c, int last_it) {
@@ -304,9 +319,35 @@ int32_t wait_slot(ibm_ctx* c, int s, Slot* out) {
     return IBM_OK;
 }
 
+inline int red_blocks(size_t n) {
+    return (int)std::max<size_t>(1, std::min<size_t>(kRedMax, (n + kRedThreads - 1) / kRedThreads));
+}
+
+// Tile shape of the temporally blocked sweep for S iterations per launch:
+// halo H = 2S + 2 (even, one ring more for the fused residual).  Returns false
+// when the loaded tile would not fit the LDS budget or the per-thread
+// position registers.
+bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts, size_t* lds_bytes) {
+    if (S < 1 || S > 8 || tx < 2 || (tx & 1) || ty < 1) return false;
+    const int H = 2 * S + 2;
+    const int lx = std::min(c->nx, tx + 2 * H), ly = std::min(c->ny, ty + 2 * H);
+    // one lane per split column, kTbRows rows per wave
+    if (lx / 2 > kTbCols || ly > kTbWaves * kTbRows) return false;
+    ts->tx = tx;
+    ts->ty = ty;
+    ts->halo = H;
+    ts->ntx = (c->nx + tx - 1) / tx;
+    ts->nty = (c->ny + ty - 1) / ty;
+    ts->swizzle = ((ts->ntx * ts->nty) % 8 == 0) ? 1 : 0;
+    *lds_bytes = (size_t)lx * ly * sizeof(double);
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Red-black SOR on A x = vb, both in split storage (phr/phb, vbr/vbb).
-// fixed >= 0 with replay: exactly `fixed` iterations.
+// The residual is tested before the first iteration and after iterations
+// K, 2K, ... (fused into the last blocked launch of each interval).
+// fixed >= 0: exactly `fixed` iterations (tolerance ignored).
 // ---------------------------------------------------------------------------
 int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
@@ -314,54 +355,74 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     const bool fixed_mode = fixed >= 0;
     const double tol_e = fixed_mode ? -1.0 : tol;
     const int max_e = fixed_mode ? fixed : max_iter;
+    const int nbr = red_blocks((size_t)c->nh * c->ny);
+    TbShape ts;
+    size_t lds_bytes = 0;
+    const bool use_tb = c->sor_kernel == IBM_SOR_TEMPORAL && tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts, &lds_bytes);
+    const int S = c->tb_sweeps;
+    const int ntiles = use_tb ? ts.ntx * ts.nty : 0;
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
     ++c->solve_id;
-    int s0 = next_slot(c);
-    timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&] {
-        hipLaunchKernelGGL(k_sor_residual, gr, bl, 0, c->stream, c->g, c->phr, c->phb, c->vbr, c->vbb, ctl,
-                           c->partials, 0, 0, max_e, tol_e, (int)fixed_mode, c->dslots + s0);
-    });
-    LAUNCH_CHECK();
-    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
-    Slot sn;
-    rc = wait_slot(c, s0, &sn);
-    if (rc) return rc;
-    out->bn = sn.bn;
-    out->r0 = sn.r0;
-    out->rn = sn.rn;
-    out->iters = 0;
-    out->zero_rhs = sn.zero_rhs;
-    if (sn.done || max_e == 0) {
-        out->status = sn.status;
-        prune_samples(c, 0);
-        return IBM_OK;
-    }
     std::deque<int> pending;
+    auto check = [&](int phase, int it, int nb) -> int32_t {
+        const int s = next_slot(c);
+        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
+                           tol_e, (int)fixed_mode, 0, c->dslots + s);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+        pending.push_back(s);
+        return IBM_OK;
+    };
+    timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&](hipEvent_t ea, hipEvent_t eb) {
+        LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)c->phr,
+                  (const double*)c->phb, (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl, c->partials);
+    });
+    rc = check(0, 0, nbr);
+    if (rc) return rc;
+    Slot sn;
+    bool first = true;
     int it = 0;
     for (;;) {
         if (it < max_e) {
-            const int n = std::min(K, max_e - it);
-            for (int k = 0; k < n; ++k) {
-                const int itk = it + k + 1;
-                timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&] {
-                    hipLaunchKernelGGL(k_sor_sweep<0>, gr, bl, 0, c->stream, c->g, c->phr, (const double*)c->phb,
-                                       (const double*)c->vbr, omega, (const Ctl*)ctl);
-                });
-                timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&] {
-                    hipLaunchKernelGGL(k_sor_sweep<1>, gr, bl, 0, c->stream, c->g, c->phb, (const double*)c->phr,
-                                       (const double*)c->vbb, omega, (const Ctl*)ctl);
+            const int next = std::min(it + K, max_e);
+            int nb_check = nbr;
+            while (it < next) {
+                if (use_tb) {
+                    const int n = std::min(S, next - it);
+                    const int resid = (it + n == next) ? 1 : 0;
+                    auto launch = [&](hipEvent_t ea, hipEvent_t eb) {
+                        LAUNCH_EV(ea, eb, k_sor_tb, dim3(ntiles), dim3(kTbThreads), lds_bytes, c->g, c->phr, c->phb,
+                                  (const double*)c->vbr, (const double*)c->vbb, omega, (const Ctl*)ctl, ts, n, resid,
+                                  c->partials);
+                    };
+                    if (n == S) timed(c, IBM_KERNEL_SOR_TB, it + n, launch);
+                    else launch(nullptr, nullptr);
+                    it += n;
+                    if (resid) nb_check = ntiles;
+                } else {
+                    const int itk = it + 1;
+                    timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
+                        LAUNCH_EV(ea, eb, k_sor_sweep<0>, gr, bl, 0, c->g, c->phr, (const double*)c->phb,
+                                  (const double*)c->vbr, omega, (const Ctl*)ctl);
+                    });
+                    timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
+                        LAUNCH_EV(ea, eb, k_sor_sweep<1>, gr, bl, 0, c->g, c->phb, (const double*)c->phr,
+                                  (const double*)c->vbb, omega, (const Ctl*)ctl);
+                    });
+                    it = itk;
+                }
+            }
+            LAUNCH_CHECK();
+            if (!use_tb) {
+                timed(c, IBM_KERNEL_SOR_RESIDUAL, it, [&](hipEvent_t ea, hipEvent_t eb) {
+                    LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)c->phr,
+                              (const double*)c->phb, (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl,
+                              c->partials);
                 });
             }
-            it += n;
-            const int s = next_slot(c);
-            timed(c, IBM_KERNEL_SOR_RESIDUAL, it, [&] {
-                hipLaunchKernelGGL(k_sor_residual, gr, bl, 0, c->stream, c->g, c->phr, c->phb, c->vbr, c->vbb, ctl,
-                                   c->partials, 1, it, max_e, tol_e, (int)fixed_mode, c->dslots + s);
-            });
-            LAUNCH_CHECK();
-            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-            pending.push_back(s);
+            rc = check(1, it, nb_check);
+            if (rc) return rc;
             if ((int)pending.size() < kAheadSor && it < max_e) continue;
         }
         if (pending.empty()) {
@@ -372,7 +433,14 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
         pending.pop_front();
         rc = wait_slot(c, s, &sn);
         if (rc) return rc;
+        if (first) {
+            out->bn = sn.bn;
+            out->r0 = sn.r0;
+            out->zero_rhs = sn.zero_rhs;
+            first = false;
+        }
         if (sn.done) break;
+        if (it >= max_e && pending.empty()) break;  // max_e == 0: only the first check
     }
     out->status = sn.status;
     out->iters = sn.iters;
@@ -383,58 +451,59 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
 
 // ---------------------------------------------------------------------------
 // Jacobi-PCG on M x = -vb (natural layout).  fixed >= 0: exactly that many.
+// Iteration kk: k_pcg_dir_spmv (stop test of r_kk, new direction, q = M p)
+// then k_pcg_update (x, r); the direction is double-buffered in pp / pq2.
 // ---------------------------------------------------------------------------
 int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_iter, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
-    const dim3 gr = grid2(c->nx, c->ny), bl(kBlock);
+    const dim3 bl(kBlock), rb(kRedThreads);
     const bool fixed_mode = fixed >= 0;
     const double tol_e = fixed_mode ? -1.0 : tol;
     const int max_e = fixed_mode ? fixed : max_iter;
+    const size_t n = (size_t)c->nx * c->ny;
+    const int nb = red_blocks(n);
+    double* part_r = c->partials;                          // r.r, r.z (and b.b at the start)
+    double* part_pq = c->partials + 3 * (size_t)kRedMax;  // p.q
+    double* pbuf[2] = {c->pp, c->pp2};
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
+    rc = fill(c, c->pp, n, 0.0);
+    if (!rc) rc = fill(c, c->pp2, n, 0.0);
+    if (rc) return rc;
     ++c->solve_id;
-    int s0 = next_slot(c);
-    hipLaunchKernelGGL(k_pcg_init, gr, bl, 0, c->stream, c->g, (const double*)x, vb, c->pr, c->pp, ctl, c->partials,
-                       tol_e, c->dslots + s0);
+    std::deque<int> pending;
+    hipLaunchKernelGGL(k_pcg_init, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr, part_r);
+    const int s0 = next_slot(c);
+    hipLaunchKernelGGL(k_pcg_init_check, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e,
+                       c->dslots + s0);
     LAUNCH_CHECK();
     HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
+    pending.push_back(s0);
     Slot sn;
-    rc = wait_slot(c, s0, &sn);
-    if (rc) return rc;
-    out->bn = sn.bn;
-    out->r0 = sn.r0;
-    out->rn = sn.rn;
-    out->iters = 0;
-    out->zero_rhs = sn.zero_rhs;
-    if (sn.done || max_e == 0) {
-        out->status = sn.status;
-        prune_samples(c, 0);
-        return IBM_OK;
-    }
-    std::deque<int> pending;
-    int it = 0;
+    bool first = true;
+    int kk = 0;          // next iteration to enqueue
+    int restart = 0;
     for (;;) {
-        if (it < max_e) {
-            const int itk = it + 1;
-            timed(c, IBM_KERNEL_PCG_SPMV, itk, [&] {
-                hipLaunchKernelGGL(k_pcg_spmv, gr, bl, 0, c->stream, c->g, (const double*)c->pp, c->pq, ctl,
-                                   c->partials);
-            });
+        if (kk <= max_e) {
             const int s = next_slot(c);
-            timed(c, IBM_KERNEL_PCG_UPDATE, itk, [&] {
-                hipLaunchKernelGGL(k_pcg_update, gr, bl, 0, c->stream, c->g, x, c->pr, (const double*)c->pp,
-                                   (const double*)c->pq, ctl, c->partials, itk, max_e, tol_e, (int)fixed_mode,
-                                   c->dslots + s);
+            const int k0 = kk, rs = restart;
+            timed(c, IBM_KERNEL_PCG_DIR_SPMV, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
+                LAUNCH_EV(ea, eb, k_pcg_dir_spmv, dim3(nb), rb, 0, c->g, (const double*)c->pr,
+                          (const double*)pbuf[(k0 + 1) & 1], pbuf[k0 & 1], c->pq, ctl, (const double*)part_r, nb,
+                          part_pq, k0, max_e, tol_e, (int)fixed_mode, rs, c->dslots + s);
             });
-            timed(c, IBM_KERNEL_PCG_DIR, itk, [&] {
-                hipLaunchKernelGGL(k_pcg_dir, gr, bl, 0, c->stream, c->g, (const double*)c->pr, c->pp,
-                                   (const Ctl*)ctl);
-            });
+            restart = 0;
+            if (k0 < max_e) {
+                timed(c, IBM_KERNEL_PCG_UPDATE, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
+                    LAUNCH_EV(ea, eb, k_pcg_update, dim3(nb), rb, 0, c->g, x, c->pr, (const double*)pbuf[k0 & 1],
+                              (const double*)c->pq, (const Ctl*)ctl, (const double*)part_pq, nb, part_r, k0);
+                });
+            }
             LAUNCH_CHECK();
             HIP_TRY(hipEventRecord(c->ev[s], c->stream));
             pending.push_back(s);
-            it = itk;
-            if ((int)pending.size() < kAheadPcg && it < max_e) continue;
+            ++kk;
+            if ((int)pending.size() < kAheadPcg && kk <= max_e) continue;
         }
         if (pending.empty()) {
             c->err = "PCG loop ended without a finishing check";
@@ -444,26 +513,35 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
         pending.pop_front();
         rc = wait_slot(c, s, &sn);
         if (rc) return rc;
+        if (first) {
+            out->bn = sn.bn;
+            out->r0 = sn.r0;
+            out->zero_rhs = sn.zero_rhs;
+            first = false;
+        }
         if (!sn.done) continue;
         if (sn.status != kStConfirm) break;
         // the recursive residual passed: confirm with the true residual
         pending.clear();
+        hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr,
+                           part_r);
         const int sc = next_slot(c);
-        hipLaunchKernelGGL(k_pcg_true_residual, gr, bl, 0, c->stream, c->g, (const double*)x, vb, c->pr, ctl,
-                           c->partials, tol_e, c->dslots + sc);
+        hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e, 0,
+                           c->dslots + sc);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[sc], c->stream));
         rc = wait_slot(c, sc, &sn);
         if (rc) return rc;
         if (sn.done) break;
-        // restart from the true residual: p = z
-        it = sn.iters;
-        hipLaunchKernelGGL(k_pcg_dir, gr, bl, 0, c->stream, c->g, (const double*)c->pr, c->pp, (const Ctl*)ctl);
-        LAUNCH_CHECK();
+        // resume from the true residual: iteration sn.iters again with p = z
+        kk = sn.iters;
+        restart = 1;
     }
-    if (fixed_mode && sn.status == kStOk) {
+    if (fixed_mode && sn.status == kStOk && sn.iters > 0) {
+        hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr,
+                           part_r);
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_pcg_final_residual, gr, bl, 0, c->stream, c->g, (const double*)x, vb, ctl, c->partials,
+        hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e, 1,
                            c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
@@ -488,28 +566,28 @@ int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
     double* x = comp == 0 ? c->u : c->v;
     const double* rhs = comp == 0 ? c->ru : c->rv;
     const dim3 gs = grid2(c->nh, c->ny + 1), bl(kBlock);
-    const dim3 gres = comp == 0 ? grid2(c->nx + 1, c->ny) : grid2(c->nx, c->ny + 1);
+    const size_t nunk = comp == 0 ? (size_t)(c->nx - 1) * c->ny : (size_t)c->nx * (c->ny - 1);
+    const int nb = red_blocks(nunk);
     const double omega = c->P.uv_omega, tol = c->P.uv_tol;
     const int max_e = c->P.uv_max_iter;
     int32_t rc = reset_ctl(c, which);
     if (rc) return rc;
-    int s0 = next_slot(c);
-    hipLaunchKernelGGL(k_helm_residual, gres, bl, 0, c->stream, c->g, comp, (const double*)x, rhs, beta, ctl,
-                       c->partials, 0, 0, max_e, tol, c->dslots + s0);
-    LAUNCH_CHECK();
-    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
-    Slot sn;
-    rc = wait_slot(c, s0, &sn);
-    if (rc) return rc;
-    out->bn = sn.bn;
-    out->r0 = sn.r0;
-    out->rn = sn.rn;
-    out->iters = 0;
-    if (sn.done) {
-        out->status = sn.status;
-        return IBM_OK;
-    }
     std::deque<int> pending;
+    auto check = [&](int phase, int it) -> int32_t {
+        hipLaunchKernelGGL(k_helm_residual, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, comp, (const double*)x,
+                           rhs, beta, (const Ctl*)ctl, c->partials);
+        const int s = next_slot(c);
+        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
+                           tol, 0, 1, c->dslots + s);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+        pending.push_back(s);
+        return IBM_OK;
+    };
+    rc = check(0, 0);
+    if (rc) return rc;
+    Slot sn;
+    bool first = true;
     int it = 0;
     for (;;) {
         if (it < max_e) {
@@ -521,12 +599,8 @@ int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
                 hipLaunchKernelGGL(k_helm_v_sweep<1>, gs, bl, 0, c->stream, c->g, x, rhs, beta, omega, (const Ctl*)ctl);
             }
             ++it;
-            const int s = next_slot(c);
-            hipLaunchKernelGGL(k_helm_residual, gres, bl, 0, c->stream, c->g, comp, (const double*)x, rhs, beta, ctl,
-                               c->partials, 1, it, max_e, tol, c->dslots + s);
-            LAUNCH_CHECK();
-            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-            pending.push_back(s);
+            rc = check(1, it);
+            if (rc) return rc;
             if ((int)pending.size() < kAheadHelm && it < max_e) continue;
         }
         if (pending.empty()) {
@@ -537,6 +611,11 @@ int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
         pending.pop_front();
         rc = wait_slot(c, s, &sn);
         if (rc) return rc;
+        if (first) {
+            out->bn = sn.bn;
+            out->r0 = sn.r0;
+            first = false;
+        }
         if (sn.done) break;
     }
     out->status = sn.status;
@@ -816,7 +895,8 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     g.vce = D(off.vce); g.vcw = D(off.vcw); g.vcn = D(off.vcn); g.vcs = D(off.vcs);
     c->u = D(off.u); c->nu = D(off.nu); c->ru = D(off.ru); c->fufull = D(off.fufull);
     c->v = D(off.v); c->nv = D(off.nv); c->rv = D(off.rv); c->fvfull = D(off.fvfull);
-    c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp); c->pq = D(off.pq);
+    c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp);
+    c->pp2 = D(off.pp2); c->pq = D(off.pq);
     c->phr = D(off.phr); c->phb = D(off.phb); c->vbr = D(off.vbr); c->vbb = D(off.vbb);
     c->f_u = D(off.f_u); c->f_v = D(off.f_v); c->coef = D(off.coef); c->partials = D(off.partials);
     c->ctl = (Ctl*)(w + off.ctl);
@@ -1065,6 +1145,33 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* c, const int32_t* iters, int32_t n) {
     return IBM_OK;
 }
 
+int32_t ibm_set_option(ibm_ctx* c, int32_t option, int64_t value) {
+    if (!c) return IBM_ERR_INVALID;
+    int kern = c->sor_kernel, S = c->tb_sweeps, tx = c->tb_tx, ty = c->tb_ty;
+    switch (option) {
+        case IBM_OPT_SOR_KERNEL:
+            if (value != IBM_SOR_TEMPORAL && value != IBM_SOR_PER_COLOUR) return IBM_ERR_INVALID;
+            kern = (int)value;
+            break;
+        case IBM_OPT_TB_SWEEPS: S = (int)value; break;
+        case IBM_OPT_TB_TILE_X: tx = (int)value; break;
+        case IBM_OPT_TB_TILE_Y: ty = (int)value; break;
+        default: return IBM_ERR_INVALID;
+    }
+    if (value < 0 || value > (1 << 20)) return IBM_ERR_INVALID;
+    TbShape ts;
+    size_t lds = 0;
+    if (!tb_shape(c, S, tx, ty, &ts, &lds)) {
+        c->err = "tile shape does not fit the blocked sweep";
+        return IBM_ERR_INVALID;
+    }
+    c->sor_kernel = kern;
+    c->tb_sweeps = S;
+    c->tb_tx = tx;
+    c->tb_ty = ty;
+    return IBM_OK;
+}
+
 int32_t ibm_profile(ibm_ctx* c, int32_t sample_every) {
     if (!c || sample_every < 0) return IBM_ERR_INVALID;
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1092,7 +1199,8 @@ int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* s
     }
     const size_t n = c->samples[kernel].size();
     const double cells = (double)c->nx * c->ny;
-    const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 16.0 * cells, 48.0 * cells, 24.0 * cells};
+    const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 48.0 * cells,
+                                            24.0 * cells * c->tb_sweeps};
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (samples) *samples = (int64_t)n;
     if (launches) *launches = c->launches[kernel];

@@ -22,14 +22,17 @@ OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, 
 BC_CHANNEL = 0
 RBSOR, PCG = 0, 1
 INIT_ZERO, INIT_PREVIOUS = 0, 1
-KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_SPMV, KERNEL_PCG_UPDATE, KERNEL_PCG_DIR = range(5)
+KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB = range(5)
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
-                KERNEL_PCG_SPMV: "k_pcg_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
-                KERNEL_PCG_DIR: "k_pcg_dir"}
+                KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
+                KERNEL_SOR_TB: "k_sor_tb"}
+OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y = range(4)
+SOR_TEMPORAL, SOR_PER_COLOUR = 0, 1
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
-            "ibm_set_poisson_schedule", "ibm_profile", "ibm_profile_query", "ibm_destroy",
+            "ibm_set_poisson_schedule", "ibm_set_option", "ibm_profile", "ibm_profile_query",
+            "ibm_destroy",
             "ibm_status_string", "ibm_last_error")
 
 
@@ -103,6 +106,8 @@ def lib():
         L.ibm_set_state.restype = C.c_int32
         L.ibm_set_poisson_schedule.argtypes = [vp, ip, C.c_int32]
         L.ibm_set_poisson_schedule.restype = C.c_int32
+        L.ibm_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+        L.ibm_set_option.restype = C.c_int32
         L.ibm_profile.argtypes = [vp, C.c_int32]
         L.ibm_profile.restype = C.c_int32
         L.ibm_profile_query.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp]
@@ -270,6 +275,10 @@ class Solver:
         rc = lib().ibm_set_poisson_schedule(self._h, a, len(iters))
         if rc != OK:
             self._err("ibm_set_poisson_schedule", rc)
+
+    def set_option(self, option: int, value: int) -> int:
+        """Tuning option (launch shape of the SOR sweeps); returns the status."""
+        return lib().ibm_set_option(self._h, option, int(value))
 
     # -- stand-alone Poisson solve ------------------------------------------
     def poisson_solve(self, rhs, x, method=RBSOR, omega=1.8, tol=1e-8, max_iter=2_000_000,

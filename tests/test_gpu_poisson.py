@@ -172,3 +172,53 @@ def test_full_size_grid_fixed_iterations(torch):
     xg = xd.cpu().numpy()
     print(f"full PCG rel {rel_l2(xg, xo):.3e}", flush=True)
     assert rel_l2(xg, xo) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,sweeps,tile", [
+    (128, 96, 5, (64, 40)),      # 2x3 tiles
+    (200, 150, 5, (104, 32)),    # the default shape; ragged tiles in x and y, stretched
+    (200, 150, 1, (32, 24)),
+    (200, 150, 3, (16, 8)),      # many small tiles
+    (256, 192, 2, (16, 12)),     # 256 tiles in the XCD-banded order
+    (64, 48, 8, (64, 48)),       # one tile, deep halo clipped by the domain
+    (1024, 768, 5, (104, 32)),   # the plunging-workload grid, 240 tiles
+])
+def test_blocked_sweep_is_bitwise_the_per_colour_sweep(torch, nx, ny, sweeps, tile):
+    """The temporally blocked launch performs the same cell updates with the
+    same neighbour values as one launch per colour: identical iterates, for
+    fixed iteration counts that are not multiples of the sweep count, and the
+    same stop decision in tolerance mode."""
+    xf, yf = _grid(nx, ny, stretched=(nx != 128))
+    g = ibm.Solver(nx, ny, xf, yf, body=0)
+    rng = np.random.default_rng(nx * 7 + sweeps)
+    b = _dev(torch, rng.standard_normal((ny, nx)))
+    x0 = rng.standard_normal((ny, nx))
+    out = {}
+    for kern in (ibm.SOR_PER_COLOUR, ibm.SOR_TEMPORAL):
+        assert g.set_option(ibm.OPT_SOR_KERNEL, kern) == ibm.OK
+        assert g.set_option(ibm.OPT_TB_SWEEPS, sweeps) == ibm.OK
+        assert g.set_option(ibm.OPT_TB_TILE_X, tile[0]) == ibm.OK
+        assert g.set_option(ibm.OPT_TB_TILE_Y, tile[1]) == ibm.OK
+        xd = _dev(torch, x0)
+        st = g.poisson_solve(b, xd, method=ibm.RBSOR, omega=1.8, fixed_iters=23, check_every=10)
+        xt = _dev(torch, np.zeros((ny, nx)))
+        st2 = g.poisson_solve(b, xt, method=ibm.RBSOR, omega=1.7, tol=1e-3, check_every=10)
+        out[kern] = (xd.cpu().numpy(), st, xt.cpu().numpy(), st2)
+    a, bb_ = out[ibm.SOR_PER_COLOUR], out[ibm.SOR_TEMPORAL]
+    print(f"nx={nx} S={sweeps} tile={tile} maxdiff={np.max(np.abs(a[0] - bb_[0])):.3e} "
+          f"iters {a[3]['iters']} {bb_[3]['iters']}", flush=True)
+    assert np.array_equal(a[0], bb_[0])
+    assert a[1]["iters"] == bb_[1]["iters"] == 23
+    assert abs(a[1]["rel"] - bb_[1]["rel"]) <= 1e-12 * a[1]["rel"]
+    assert a[3]["iters"] == bb_[3]["iters"]
+    assert np.array_equal(a[2], bb_[2])
+
+
+def test_blocked_sweep_rejects_shapes_that_do_not_fit(torch):
+    xf, yf = _grid(256, 192, False)
+    g = ibm.Solver(256, 192, xf, yf, body=0)
+    assert g.set_option(ibm.OPT_TB_TILE_X, 63) == ibm.ERR_INVALID      # odd width
+    assert g.set_option(ibm.OPT_TB_SWEEPS, 9) == ibm.ERR_INVALID       # too deep
+    assert g.set_option(ibm.OPT_TB_TILE_X, 256) == ibm.ERR_INVALID     # halo tile > LDS
+    assert g.set_option(99, 1) == ibm.ERR_INVALID
+    assert g.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK
