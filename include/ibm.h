@@ -214,8 +214,8 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
  * test) are not sampled.  Synchronizes. */
 #define IBM_KERNEL_SOR_SWEEP 0      /* one colour of an SOR iteration: 24 B per cell updated */
 #define IBM_KERNEL_SOR_RESIDUAL 1   /* residual check: 16 B per cell (phi, V b) */
-#define IBM_KERNEL_PCG_DIR_SPMV 2   /* p = z + beta p and q = M p: 32 B per cell */
-#define IBM_KERNEL_PCG_UPDATE 3     /* x, r update: 48 B per cell */
+#define IBM_KERNEL_PCG_DIR_SPMV 2   /* p = z + beta p, q = M p: 32 B per cell (z, p in; p, q out) */
+#define IBM_KERNEL_PCG_UPDATE 3     /* x, r, z = r/d: 64 B per cell (x, r, p, q, d in; x, r, z out) */
 #define IBM_KERNEL_SOR_TB 4         /* temporally blocked SOR: 24 B per cell and iteration */
 #define IBM_KERNEL_COUNT 5
 int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
@@ -225,11 +225,15 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
 /* Tuning options of the red-black SOR sweeps (they change the launch shape,
  * never the arithmetic: every choice gives bit-identical iterates).
  *   IBM_OPT_SOR_KERNEL  IBM_SOR_TEMPORAL (default): one launch performs
- *                       IBM_OPT_TB_SWEEPS iterations on LDS tiles with halos;
- *                       IBM_SOR_PER_COLOUR: one launch per colour sweep;
+ *                       IBM_OPT_TB_SWEEPS iterations on a tile with halos
+ *                       held in registers; IBM_SOR_TEMPORAL_LDS: the same
+ *                       with the tile in LDS; IBM_SOR_PER_COLOUR: one launch
+ *                       per colour sweep;
  *   IBM_OPT_TB_SWEEPS   iterations per blocked launch, 1..8 (default 5);
- *   IBM_OPT_TB_TILE_X   interior tile width, even (default 64);
- *   IBM_OPT_TB_TILE_Y   interior tile height (default 48).
+ *   IBM_OPT_TB_TILE_X   interior tile width, even (default 104);
+ *   IBM_OPT_TB_TILE_Y   interior tile height (default 32).
+ * The loaded tile (interior plus a halo of 2 S + 2 on each side, clamped to
+ * the grid) must fit 128 x 64 cells.
  * IBM_ERR_INVALID for an unknown option or a tile shape whose halo does not
  * fit the block's LDS.  Applies to solves started after the call. */
 #define IBM_OPT_SOR_KERNEL 0
@@ -238,6 +242,7 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
 #define IBM_OPT_TB_TILE_Y 3
 #define IBM_SOR_TEMPORAL 0
 #define IBM_SOR_PER_COLOUR 1
+#define IBM_SOR_TEMPORAL_LDS 2
 int32_t ibm_set_option(ibm_ctx* ctx, int32_t option, int64_t value);
 
 /* Release the context (not the workspace).  Synchronizes the stream first. */

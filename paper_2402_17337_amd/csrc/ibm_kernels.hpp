@@ -188,188 +188,437 @@ __global__ __launch_bounds__(kBlock) void k_check(Ctl* ctl, const double* __rest
 // After h half-sweeps only cells farther than h-1 from the loaded edge are
 // still exact, so with H >= 2S (+1 when the residual of the interior is
 // summed at the end) the interior equals S global iterations bit for bit: each
-// cell is updated by sor_update with the same neighbour values.  Half-sweep h
-// updates only the cells within e_h = 2S - h (+1) of the interior.
+// cell is updated by sor_update with the same neighbour values.  The tiles
+// read one pair of split arrays and write the other (a tile's halo is another
+// tile's interior, and blocks of one launch run in no fixed order).  Half-sweep h
+// updates only the cells within e_h = 2S - h (+1) of the interior; with
+// H = 2S + 2 those cells never touch the loaded edge, so only a domain edge
+// can bound them, and there the LDS holds a ring of zeros (the coefficient of
+// an absent neighbour is zero as well).
 //
 // Work layout: lane l of every wave owns split column l of the loaded tile
 // (at most 64 columns, i.e. a loaded width of 128 cells); wave w owns rows
-// w, w + 16, w + 32, w + 48.  A thread keeps phi, V b and 1/d of its cells
-// (both colours) and the x coefficients of its two columns in registers; row
-// coefficients are uniform over a wave; LDS holds phi for the neighbours.
+// w, w + 16, w + 32, w + 48, so the position parity of a wave's colour-C cell
+// is the same in all its rows and the x coefficients of a lane are fixed per
+// colour.  A thread keeps phi, V b and 1/d of its cells in registers (it is
+// the only writer of phi); the LDS copy of phi serves the neighbours.  The LDS
+// pitch is fixed, so every neighbour address is a register plus a constant.
 // ---------------------------------------------------------------------------
 constexpr int kTbThreads = 1024;
 constexpr int kTbWaves = kTbThreads / kWave;   // 16
 constexpr int kTbRows = 4;                     // rows per wave: loaded height <= 64
 constexpr int kTbCols = kWave;                 // split columns: loaded width <= 128
+constexpr int kTbPitch = kTbCols + 2;          // LDS row: ghost, 64 columns, ghost
+constexpr int kTbLdsRows = kTbWaves * kTbRows + 2;
+constexpr int kTbLds = kTbLdsRows * kTbPitch;  // doubles per colour
+constexpr int kTbGroup = 2;                    // rows whose reads are issued together
 
 struct TbShape {
     int tx, ty;    // interior tile size (tx even)
-    int halo;      // H (even)
+    int halo;      // H = 2S + 2
     int ntx, nty;  // tiles in x and y
-    int swizzle;   // 1: tiles of one XCD form a contiguous band
+    int per;       // tiles per XCD band: block b takes tile (b % 8) * per + b / 8
 };
 
-// Per-thread state of the blocked sweep (registers).
-struct TbCells {
-    double b[2][kTbRows];   // V b of the red (0) and black (1) cell of each owned row
-    double rd[2][kTbRows];  // 1 / diagonal
-};
+// Tile of block b.  Blocks are dispatched to the 8 XCDs round-robin, so each
+// XCD gets a contiguous band of tiles and the halos its tiles share stay in
+// its L2.  The launch has 8 * per blocks; those past the last tile return.
+__device__ inline int tb_tile(const TbShape& ts) { return (blockIdx.x & 7) * ts.per + (blockIdx.x >> 3); }
 
-// One half-sweep of colour C over the owned rows inside [ilo, ihi) x [jlo, jhi).
-// Rows go in groups of kTbGroup: reads of the group first, then its updates,
-// then its writes (colour-C cells read only the other colour), so the rows'
-// latencies overlap within the register budget.
-constexpr int kTbGroup = 2;
-
-template <int C>
-__device__ inline void tb_half(const Grid& g, TbCells& st, double* __restrict__ self, const double* __restrict__ other,
-                               int w, int lane, bool col, int ic, int ya, int ly, int lxh, int xa, int xb, int yb,
-                               int ilo, int ihi, int jlo, int jhi, const double (&cdx)[2], const double (&cE)[2],
-                               const double (&cW)[2], double omega) {
-#pragma unroll
-    for (int r0 = 0; r0 < kTbRows; r0 += kTbGroup) {
-        double vE[kTbGroup], vW[kTbGroup], vN[kTbGroup], vS[kTbGroup], vP[kTbGroup];
-        bool ok[kTbGroup];
-#pragma unroll
-        for (int q = 0; q < kTbGroup; ++q) {
-            const int jl = w + kTbWaves * (r0 + q);
-            const int j = ya + jl;
-            const int s = (j + C) & 1;
-            const int i = ic + s;
-            ok[q] = jl < ly && j >= jlo && j < jhi && col && i >= ilo && i < ihi && !(i > 0 && i - 1 < xa) &&
-                    !(i < g.nx - 1 && i + 1 >= xb) && !(j > 0 && j - 1 < ya) && !(j < g.ny - 1 && j + 1 >= yb);
-            vE[q] = vW[q] = vN[q] = vS[q] = vP[q] = 0.0;
-            if (ok[q]) {
-                const int p = jl * lxh + lane;
-                vP[q] = self[p];
-                if (i < g.nx - 1) vE[q] = other[p + s];
-                if (i > 0) vW[q] = other[p + s - 1];
-                if (j < g.ny - 1) vN[q] = other[p + lxh];
-                if (j > 0) vS[q] = other[p - lxh];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kTbGroup; ++q) {
-            if (!ok[q]) continue;
-            const int r = r0 + q;
-            const int j = ya + w + kTbWaves * r;
-            const int s = (j + C) & 1;
-            const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];  // scalar loads (j is wave-uniform)
-            const double aE = dyj * cE[s], aW = dyj * cW[s];
-            const double aN = cdx[s] * pn, aS = cdx[s] * ps;
-            const double sum = rb_sum(aE, vE[q], aW, vW[q], aN, vN[q], aS, vS[q]);
-            vP[q] = sor_update(vP[q], sum, st.b[C][r], st.rd[C][r], omega);
-        }
-#pragma unroll
-        for (int q = 0; q < kTbGroup; ++q)
-            if (ok[q]) self[(w + kTbWaves * (r0 + q)) * lxh + lane] = vP[q];
-    }
-}
-
-__global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, double* __restrict__ red, double* __restrict__ black,
-                                                       const double* __restrict__ bred,
-                                                       const double* __restrict__ bblack, double omega,
+__global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __restrict__ red,
+                                                       const double* __restrict__ black, double* __restrict__ ored,
+                                                       double* __restrict__ oblack, const double* __restrict__ bred,
+                                                       const double* __restrict__ bblack,
+                                                       double omega,
                                                        const Ctl* __restrict__ ctl, TbShape ts, int nsweep,
                                                        int residual, double* __restrict__ partials) {
-    extern __shared__ double tile[];
+    __shared__ double tile[2 * kTbLds];
     __shared__ double lds[2 * kTbWaves];
-    if (ctl->done) return;
     const int nt = ts.ntx * ts.nty;
-    int t = blockIdx.x;
-    if (ts.swizzle) t = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
+    const int t = tb_tile(ts);
+    if (t >= nt || ctl->done) return;
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
     const int H = ts.halo;
     const int xa = max(0, X0 - H), xb = min(g.nx, X1 + H);
     const int ya = max(0, Y0 - H), yb = min(g.ny, Y1 + H);
-    const int lxh = (xb - xa) >> 1, ly = yb - ya, np = lxh * ly;
+    const int lxh = (xb - xa) >> 1, ly = yb - ya;
     const int m0 = xa >> 1;
-    double* lr = tile;
-    double* lb = tile + np;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave index, uniform
     const bool col = lane < lxh;
-    // x coefficients of the two cells of split column `lane`: i = 2(m0+lane) + q
+
+    // zero ring (and everything outside the loaded tile)
+    for (int k = threadIdx.x; k < 2 * kTbLds; k += kTbThreads) tile[k] = 0.0;
+
+    // per colour C: position parity s of the lane's cells, their x
+    // coefficients and their x distance from the interior (far if no cell)
     const int ic = 2 * (m0 + lane);
-    double cdx[2], cE[2], cW[2];
+    double cdx[2], cE[2], cW[2], cD[2];
+    int sC[2], dist[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int i = col ? ic + q : 0;
-        cdx[q] = g.dx[i];
-        cE[q] = g.pcE[i];
-        cW[q] = g.pcW[i];
+    for (int c = 0; c < 2; ++c) {
+        sC[c] = (ya + w + c) & 1;
+        const int i = ic + sC[c];
+        const int ii = col ? i : 0;
+        cdx[c] = g.dx[ii];
+        cE[c] = g.pcE[ii];
+        cW[c] = g.pcW[ii];
+        cD[c] = g.pcD[ii];
+        dist[c] = col ? max(max(X0 - i, i - (X1 - 1)), 0) : (1 << 20);
     }
-    TbCells st;
+    // per row: wave-uniform coefficients and y distance from the interior
+    double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
+    int rdist[kTbRows];
+    double x[2][kTbRows], b[2][kTbRows], rd[2][kTbRows];
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
         const int jl = w + kTbWaves * r;
         const int j = min(ya + jl, g.ny - 1);
-        const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];
+        rdy[r] = g.dy[j];
+        rpn[r] = g.pcN[j];
+        rps[r] = g.pcS[j];
+        rdist[r] = jl < ly ? max(max(Y0 - j, j - (Y1 - 1)), 0) : (1 << 20);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) st.b[c][r] = st.rd[c][r] = 0.0;
+        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = rd[c][r] = 0.0;
         if (jl < ly && col) {
             const size_t kg = (size_t)(ya + jl) * g.nh + m0 + lane;
-            st.b[0][r] = bred[kg];
-            st.b[1][r] = bblack[kg];
-            lr[jl * lxh + lane] = red[kg];
-            lb[jl * lxh + lane] = black[kg];
+            x[0][r] = red[kg];
+            x[1][r] = black[kg];
+            b[0][r] = bred[kg];
+            b[1][r] = bblack[kg];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int q = (ya + jl + c) & 1;  // position parity of the colour-c cell in the row
-                const double d = rb_diag(dyj * cE[q], dyj * g.pcD[ic + q], dyj * cW[q], cdx[q] * pn, cdx[q] * ps);
-                st.rd[c][r] = 1.0 / d;
+                const double d = rb_diag(rdy[r] * cE[c], rdy[r] * cD[c], rdy[r] * cW[c], cdx[c] * rpn[r],
+                                         cdx[c] * rps[r]);
+                rd[c][r] = 1.0 / d;
             }
+            const int p = (jl + 1) * kTbPitch + lane + 1;
+            tile[p] = x[0][r];
+            tile[kTbLds + p] = x[1][r];
         }
     }
     __syncthreads();
+
+    const int p0 = (w + 1) * kTbPitch + lane + 1;  // LDS position of row 0 of this thread
     const int extra = residual ? 1 : 0;
     for (int it = 0; it < nsweep; ++it) {
-        // red half-sweep h = 2 it + 1, black h = 2 it + 2; region within e of the interior
-        int e = 2 * nsweep - (2 * it + 1) + extra;
-        tb_half<0>(g, st, lr, lb, w, lane, col, ic, ya, ly, lxh, xa, xb, yb, max(xa, X0 - e), min(xb, X1 + e),
-                   max(ya, Y0 - e), min(yb, Y1 + e), cdx, cE, cW, omega);
-        __syncthreads();
-        e -= 1;
-        tb_half<1>(g, st, lb, lr, w, lane, col, ic, ya, ly, lxh, xa, xb, yb, max(xa, X0 - e), min(xb, X1 + e),
-                   max(ya, Y0 - e), min(yb, Y1 + e), cdx, cE, cW, omega);
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            // red half-sweep h = 2 it + 1, black h = 2 it + 2: cells within e of the interior
+            const int e = 2 * nsweep - (2 * it + 1 + c) + extra;
+            double* self = tile + c * kTbLds;
+            const double* other = tile + (1 - c) * kTbLds;
+            const int pe = p0 + sC[c];  // east neighbour of row 0 in the other colour
+            const bool upd = dist[c] <= e;
+            // rows in groups of kTbGroup: the group's reads, then its updates
+#pragma unroll
+            for (int r0 = 0; r0 < kTbRows; r0 += kTbGroup) {
+                double vE[kTbGroup], vW[kTbGroup], vN[kTbGroup], vS[kTbGroup];
+#pragma unroll
+                for (int q = 0; q < kTbGroup; ++q) {
+                    // in bounds for every row slot (ghost rows 0 and 65)
+                    const int o = (r0 + q) * kTbWaves * kTbPitch;
+                    vE[q] = other[pe + o];
+                    vW[q] = other[pe + o - 1];
+                    vN[q] = other[p0 + o + kTbPitch];
+                    vS[q] = other[p0 + o - kTbPitch];
+                }
+#pragma unroll
+                for (int q = 0; q < kTbGroup; ++q) {
+                    const int r = r0 + q;
+                    if (rdist[r] <= e) {
+                        const double aE = rdy[r] * cE[c], aW = rdy[r] * cW[c];
+                        const double aN = cdx[c] * rpn[r], aS = cdx[c] * rps[r];
+                        const double sum = rb_sum(aE, vE[q], aW, vW[q], aN, vN[q], aS, vS[q]);
+                        const double xn = sor_update(x[c][r], sum, b[c][r], rd[c][r], omega);
+                        x[c][r] = upd ? xn : x[c][r];
+                        self[p0 + r * kTbWaves * kTbPitch] = x[c][r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
+
     // interior back to global memory (both colours), and its residual
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
         const int jl = w + kTbWaves * r;
         const int j = ya + jl;
-        if (jl >= ly || j < Y0 || j >= Y1 || !col) continue;
+        if (rdist[r] != 0) continue;  // rows of the interior only
         const size_t kg = (size_t)j * g.nh + m0 + lane;
-        const int p = jl * lxh + lane;
+        const int o = r * kTbWaves * kTbPitch;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const int s = (j + c) & 1;
-            const int i = ic + s;
-            if (i < X0 || i >= X1) continue;
-            const double x = (c ? lb : lr)[p];
-            (c ? black : red)[kg] = x;
+            if (dist[c] != 0) continue;
+            (c ? oblack : ored)[kg] = x[c][r];
             if (residual) {
-                const double* other = c ? lr : lb;
-                const double dyj = g.dy[j], pn = g.pcN[j], ps = g.pcS[j];
-                const double aE = dyj * cE[s], aW = dyj * cW[s], aD = dyj * g.pcD[i];
-                const double aN = cdx[s] * pn, aS = cdx[s] * ps;
-                const double xE = i < g.nx - 1 ? other[p + s] : 0.0;
-                const double xW = i > 0 ? other[p + s - 1] : 0.0;
-                const double xN = j < g.ny - 1 ? other[p + lxh] : 0.0;
-                const double xS = j > 0 ? other[p - lxh] : 0.0;
+                const double* other = tile + (1 - c) * kTbLds;
+                const int i = ic + sC[c];
+                const double aE = rdy[r] * cE[c], aW = rdy[r] * cW[c], aD = rdy[r] * cD[c];
+                const double aN = cdx[c] * rpn[r], aS = cdx[c] * rps[r];
+                const double xE = other[p0 + sC[c] + o], xW = other[p0 + sC[c] + o - 1];
+                const double xN = other[p0 + o + kTbPitch], xS = other[p0 + o - kTbPitch];
                 const double d = rb_diag(aE, aD, aW, aN, aS);
                 const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
-                const double bb = st.b[c][r];
-                const double rres = bb - (sum - d * x);
+                const double bb = b[c][r];
+                const double rres = bb - (sum - d * x[c][r]);
                 acc[0] += rres * rres;
                 acc[1] += bb * bb;
             }
         }
     }
     if (residual) block_partials(acc, partials, nt, t, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident variant of the blocked sweep.  Same tile, halo, shrinking
+// update region and arithmetic as k_sor_tb, so the interior again equals S
+// global iterations bit for bit; only the data movement differs.  Wave w owns
+// the kTbRows consecutive tile rows starting at kTbRows * w, lane l split
+// column l (both colours), all in registers:
+//   north/south neighbours: the thread's own next/previous row, or (at the
+//     ends of the wave's strip) the neighbouring wave's edge row, exchanged
+//     through LDS once per half-sweep;
+//   east/west neighbours: the other colour in the same row, either in the
+//     same lane or in the adjacent lane (a cross-lane move; lanes 0 and 63
+//     read zero, the ghost value at a domain edge).
+// ---------------------------------------------------------------------------
+// Cross-lane moves of a double over the whole wave: lane l receives lane l-1
+// (from_lower_lane) or lane l+1 (from_upper_lane); the lane without a source
+// receives 0.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double from_lower_lane(double v) { return dpp_move<0x138>(v); }  // wave_shr:1
+__device__ inline double from_upper_lane(double v) { return dpp_move<0x130>(v); }  // wave_shl:1
+
+constexpr int kTrSlots = 2 * kTbWaves + 2;  // edge rows: zero, (first, last) per wave, zero
+
+// Sum of the neighbours of the colour-C cell of row r (position parity
+// s = (P + r + C) & 1) in the thread's registers; xS0 / xNR are the other
+// colour's rows below the strip and above it.
+template <int C, int P, int R>
+__device__ inline double tbr_sum(const double (&x)[2][kTbRows], double xS0, double xNR, const double (&cdx)[2],
+                                 const double (&cE)[2], const double (&cW)[2], double dy, double pn, double ps) {
+    constexpr int O = 1 - C;
+    constexpr int s = (P + R + C) & 1;
+    const double xo = x[O][R];
+    double xE, xW;
+    if (s) {
+        xE = from_upper_lane(xo);
+        xW = xo;
+    } else {
+        xE = xo;
+        xW = from_lower_lane(xo);
+    }
+    const double xN = (R + 1 < kTbRows) ? x[O][R + 1 < kTbRows ? R + 1 : R] : xNR;
+    const double xS = (R > 0) ? x[O][R > 0 ? R - 1 : 0] : xS0;
+    const double aE = dy * cE[s], aW = dy * cW[s];
+    const double aN = cdx[s] * pn, aS = cdx[s] * ps;
+    return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+}
+
+template <int C, int P, int R>
+__device__ inline void tbr_row(double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
+                               const double (&rd)[2][kTbRows], double xS0, double xNR, const double (&cdx)[2],
+                               const double (&cE)[2], const double (&cW)[2], const int (&dq)[2],
+                               const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
+                               const double (&rps)[kTbRows], const int (&rdist)[kTbRows], int e, double omega) {
+    if (rdist[R] > e) return;  // wave-uniform
+    constexpr int s = (P + R + C) & 1;
+    const double sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
+    const double xn = sor_update(x[C][R], sum, b[C][R], rd[C][R], omega);
+    x[C][R] = dq[s] <= e ? xn : x[C][R];
+}
+
+template <int C, int P>
+__device__ inline void tbr_half(double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
+                                const double (&rd)[2][kTbRows], double xS0, double xNR, double (&cdx)[2],
+                                double (&cE)[2], double (&cW)[2], const int (&dq)[2],
+                                const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
+                                const double (&rps)[kTbRows], const int (&rdist)[kTbRows], int e, double omega) {
+    static_assert(kTbRows == 4, "rows of a strip are unrolled by hand");
+    // Keep the east/west coefficient products inside the sweep loop: all
+    // four products hoisted out of it would need 64 more registers per
+    // thread; the north/south ones (32 registers) may be hoisted.
+    asm volatile("" : "+v"(cE[0]), "+v"(cE[1]), "+v"(cW[0]), "+v"(cW[1]));
+    tbr_row<C, P, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+    tbr_row<C, P, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+    tbr_row<C, P, 2>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+    tbr_row<C, P, 3>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+}
+
+// Residual contribution of the colour-C cell of row R (interior cells only).
+template <int C, int P, int R>
+__device__ inline void tbr_resid(const double (&x)[2][kTbRows], const double (&b)[2][kTbRows], double xS0, double xNR,
+                                 const double (&cdx)[2], const double (&cE)[2], const double (&cW)[2],
+                                 const double (&cD)[2], const int (&dq)[2], const double (&rdy)[kTbRows],
+                                 const double (&rpn)[kTbRows], const double (&rps)[kTbRows],
+                                 const int (&rdist)[kTbRows], double (&acc)[2]) {
+    if (rdist[R] != 0) return;
+    constexpr int s = (P + R + C) & 1;
+    const double sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
+    if (dq[s] != 0) return;
+    const double dy = rdy[R];
+    const double d = rb_diag(dy * cE[s], dy * cD[s], dy * cW[s], cdx[s] * rpn[R], cdx[s] * rps[R]);
+    const double bb = b[C][R];
+    const double rres = bb - (sum - d * x[C][R]);
+    acc[0] += rres * rres;
+    acc[1] += bb * bb;
+}
+
+template <int P>
+__device__ inline void tbr_residual(const double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
+                                    const double (&xS0)[2], const double (&xNR)[2], const double (&cdx)[2],
+                                    const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
+                                    const int (&dq)[2], const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
+                                    const double (&rps)[kTbRows], const int (&rdist)[kTbRows], double (&acc)[2]) {
+    tbr_resid<0, P, 0>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<1, P, 0>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<0, P, 1>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<1, P, 1>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<0, P, 2>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<1, P, 2>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<0, P, 3>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<1, P, 3>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+}
+
+__global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __restrict__ red,
+                                                        const double* __restrict__ black, double* __restrict__ ored,
+                                                        double* __restrict__ oblack, const double* __restrict__ bred,
+                                                        const double* __restrict__ bblack,
+                                                        double omega,
+                                                        const Ctl* __restrict__ ctl, TbShape ts, int nsweep,
+                                                        int residual, double* __restrict__ partials) {
+    __shared__ double edge[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    const int nt = ts.ntx * ts.nty;
+    const int t = tb_tile(ts);
+    if (t >= nt) return;
+    // The stop flag is tested after the tile's loads are issued, so that its
+    // latency overlaps theirs (a finished solve only wastes the loads).
+    const int done = ctl->done;
+    const int txi = t % ts.ntx, tyi = t / ts.ntx;
+    const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
+    const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
+    const int H = ts.halo;
+    const int xa = max(0, X0 - H), xb = min(g.nx, X1 + H);
+    const int ya = max(0, Y0 - H), yb = min(g.ny, Y1 + H);
+    const int lxh = (xb - xa) >> 1, ly = yb - ya;
+    const int m0 = xa >> 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave index, uniform
+    const bool col = lane < lxh;
+    const int jw = kTbRows * w;       // first tile row of the wave's strip
+    const int P = (ya + jw) & 1;      // position parity of colour C in row r: (P + r + C) & 1
+
+    // x coefficients and distance from the interior of the lane's two cells,
+    // by position parity q (cell i = ic + q)
+    const int ic = 2 * (m0 + lane);
+    double cdx[2], cE[2], cW[2], cD[2];
+    int dq[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int i = ic + q;
+        const int ii = col ? i : 0;
+        cdx[q] = g.dx[ii];
+        cE[q] = g.pcE[ii];
+        cW[q] = g.pcW[ii];
+        cD[q] = g.pcD[ii];
+        dq[q] = col ? max(max(X0 - i, i - (X1 - 1)), 0) : (1 << 20);
+    }
+    double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
+    int rdist[kTbRows];
+    double x[2][kTbRows], b[2][kTbRows], rd[2][kTbRows];
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = jw + r;
+        const int j = min(ya + jl, g.ny - 1);
+        rdy[r] = g.dy[j];
+        rpn[r] = g.pcN[j];
+        rps[r] = g.pcS[j];
+        rdist[r] = jl < ly ? max(max(Y0 - j, j - (Y1 - 1)), 0) : (1 << 20);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = rd[c][r] = 0.0;
+        if (jl < ly && col) {
+            const size_t kg = (size_t)(ya + jl) * g.nh + m0 + lane;
+            x[0][r] = red[kg];
+            x[1][r] = black[kg];
+            b[0][r] = bred[kg];
+            b[1][r] = bblack[kg];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int q = (P + r + c) & 1;
+                const double d = rb_diag(rdy[r] * cE[q], rdy[r] * cD[q], rdy[r] * cW[q], cdx[q] * rpn[r],
+                                         cdx[q] * rps[r]);
+                rd[c][r] = 1.0 / d;
+            }
+        }
+    }
+    if (done) return;
+    // edge rows of both colours; slots 0 and kTrSlots-1 stay zero
+    if (w == 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            edge[c][0][lane] = 0.0;
+            edge[c][kTrSlots - 1][lane] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        edge[c][2 * w + 1][lane] = x[c][0];
+        edge[c][2 * w + 2][lane] = x[c][kTbRows - 1];
+    }
+    __syncthreads();
+
+    const int extra = residual ? 1 : 0;
+    for (int it = 0; it < nsweep; ++it) {
+        {   // red half-sweep h = 2 it + 1: cells within e of the interior
+            const int e = 2 * nsweep - (2 * it + 1) + extra;
+            const double xS0 = edge[1][2 * w][lane], xNR = edge[1][2 * w + 3][lane];
+            if (P) tbr_half<0, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            else tbr_half<0, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            edge[0][2 * w + 1][lane] = x[0][0];
+            edge[0][2 * w + 2][lane] = x[0][kTbRows - 1];
+            __syncthreads();
+        }
+        {   // black half-sweep h = 2 it + 2
+            const int e = 2 * nsweep - (2 * it + 2) + extra;
+            const double xS0 = edge[0][2 * w][lane], xNR = edge[0][2 * w + 3][lane];
+            if (P) tbr_half<1, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            else tbr_half<1, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            edge[1][2 * w + 1][lane] = x[1][0];
+            edge[1][2 * w + 2][lane] = x[1][kTbRows - 1];
+            __syncthreads();
+        }
+    }
+
+    // interior back to global memory (both colours), and its residual
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        if (rdist[r] != 0) continue;  // rows of the interior only
+        const size_t kg = (size_t)(ya + jw + r) * g.nh + m0 + lane;
+        const int s0 = (P + r) & 1;   // position parity of the red cell
+        if (dq[s0] == 0) ored[kg] = x[0][r];
+        if (dq[s0 ^ 1] == 0) oblack[kg] = x[1][r];
+    }
+    if (residual) {
+        double acc[2] = {0.0, 0.0};
+        const double xS0[2] = {edge[0][2 * w][lane], edge[1][2 * w][lane]};
+        const double xNR[2] = {edge[0][2 * w + 3][lane], edge[1][2 * w + 3][lane]};
+        if (P) tbr_residual<1>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+        else tbr_residual<0>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+        block_partials(acc, partials, nt, t, lds);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -392,32 +641,66 @@ __device__ inline double nat_diag(const Grid& g, int i, int j) {
     return rb_diag(dyj * g.pcE[i], dyj * g.pcD[i], dyj * g.pcW[i], dxi * g.pcN[j], dxi * g.pcS[j]);
 }
 
-// All PCG kernels are grid-stride over the nx*ny cells with at most kRedMax
-// blocks of kRedThreads; cross-block sums go through per-block partials.
-#define IBM_CELLS_LOOP(k)                                                                       \
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)g.nx * g.ny;    \
-         k += (size_t)gridDim.x * blockDim.x)
+// Grid-stride walk over the nx*ny cells of the natural layout that keeps the
+// cell's (i, j) up to date without an integer division per step.
+struct CellWalk {
+    size_t k, n, stride;
+    int i, j, si, sj, nx;
+    __device__ explicit CellWalk(const Grid& g) {
+        nx = g.nx;
+        n = (size_t)g.nx * g.ny;
+        stride = (size_t)gridDim.x * blockDim.x;
+        sj = (int)(stride / nx);
+        si = (int)(stride - (size_t)sj * nx);
+        k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        j = (int)(k / nx);
+        i = (int)(k - (size_t)j * nx);
+    }
+    __device__ bool ok() const { return k < n; }
+    __device__ void next() {
+        k += stride;
+        i += si;
+        j += sj;
+        if (i >= nx) {
+            i -= nx;
+            ++j;
+        }
+    }
+};
 
-// New search direction of one cell, p = z + beta p_old with z = r / d (the
-// same rounding wherever it is evaluated).
-__device__ inline double pcg_dir(double r, double pold, double d, double beta) {
-    return __fma_rn(beta, pold, r / d);
+// Diagonal of M = -A in natural layout (fixed by the grid: once per context).
+__global__ __launch_bounds__(kBlock) void k_ndiag(Grid g, double* __restrict__ dn) {
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j >= g.ny) return;
+    dn[(size_t)j * g.nx + i] = nat_diag(g, i, j);
 }
 
-// r = -V b + A x (residual of M x = -V b); partials of r.r, r.z, (V b)^2.
+// All PCG kernels are grid-stride over the nx*ny cells with at most kRedMax
+// blocks of kRedThreads; cross-block sums go through per-block partials.  The
+// preconditioned residual z = r / diag(M) is stored wherever r is written, so
+// every reader of z (a cell and its neighbours) sees the same value.
+
+// New search direction of one cell, p = z + beta p_old.
+__device__ inline double pcg_dir(double z, double pold, double beta) { return __fma_rn(beta, pold, z); }
+
+// r = -V b + A x (residual of M x = -V b), z = r / d; partials of r.r, r.z,
+// (V b)^2.
 __global__ __launch_bounds__(kRedThreads) void k_pcg_init(Grid g, const double* __restrict__ x,
                                                           const double* __restrict__ vb, double* __restrict__ r,
-                                                          double* partials) {
+                                                          double* __restrict__ z, double* partials) {
     __shared__ double lds[3 * kRedThreads / kWave];
     double acc[3] = {0.0, 0.0, 0.0};
-    IBM_CELLS_LOOP(k) {
-        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const size_t k = c.k;
         double d;
-        const double sum = nat_row(g, x, i, j, k, d);
+        const double sum = nat_row(g, x, c.i, c.j, k, d);
         const double rk = -vb[k] + (sum - d * x[k]);
+        const double zk = rk / d;
         r[k] = rk;
+        z[k] = zk;
         acc[0] += rk * rk;
-        acc[1] += rk * (rk / d);
+        acc[1] += rk * zk;
         acc[2] += vb[k] * vb[k];
     }
     block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
@@ -443,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init_check(Ctl* ctl, const doubl
 // (r.z)_{kk-1}; kk = 0 and restarts use beta = 0 (p = z).  Block 0 records the
 // decision and publishes it.  Then p_kk = z + beta p_{kk-1} (into pnew,
 // recomputed for the four neighbours as well) and q = M p_kk; partials of p.q.
-__global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const double* __restrict__ r,
+__global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const double* __restrict__ z,
                                                               const double* __restrict__ pold,
                                                               double* __restrict__ pnew, double* __restrict__ q,
                                                               Ctl* ctl, const double* __restrict__ rpart, int nb,
@@ -489,17 +772,19 @@ __global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const doub
     if (s_stop) return;
     const double beta = s_beta;
     double pacc[1] = {0.0};
-    IBM_CELLS_LOOP(k) {
-        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+    const size_t nx = g.nx;
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const size_t k = c.k;
+        const int i = c.i, j = c.j;
         const double dyj = g.dy[j], dxi = g.dx[i];
         const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
         const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
         const double d = rb_diag(aE, aD, aW, aN, aS);
-        const double pk = pcg_dir(r[k], pold[k], d, beta);
-        const double pE = i < g.nx - 1 ? pcg_dir(r[k + 1], pold[k + 1], nat_diag(g, i + 1, j), beta) : 0.0;
-        const double pW = i > 0 ? pcg_dir(r[k - 1], pold[k - 1], nat_diag(g, i - 1, j), beta) : 0.0;
-        const double pN = j < g.ny - 1 ? pcg_dir(r[k + g.nx], pold[k + g.nx], nat_diag(g, i, j + 1), beta) : 0.0;
-        const double pS = j > 0 ? pcg_dir(r[k - g.nx], pold[k - g.nx], nat_diag(g, i, j - 1), beta) : 0.0;
+        const double pk = pcg_dir(z[k], pold[k], beta);
+        const double pE = i < g.nx - 1 ? pcg_dir(z[k + 1], pold[k + 1], beta) : 0.0;
+        const double pW = i > 0 ? pcg_dir(z[k - 1], pold[k - 1], beta) : 0.0;
+        const double pN = j < g.ny - 1 ? pcg_dir(z[k + nx], pold[k + nx], beta) : 0.0;
+        const double pS = j > 0 ? pcg_dir(z[k - nx], pold[k - nx], beta) : 0.0;
         const double sum = rb_sum(aE, pE, aW, pW, aN, pN, aS, pS);
         const double qk = d * pk - sum;  // M p = -A p
         pnew[k] = pk;
@@ -510,10 +795,13 @@ __global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const doub
 }
 
 // Iteration kk, second kernel: alpha = (r.z)_kk / p.q (every block sums the
-// p.q partials); x += alpha p, r -= alpha q; partials of r.r and r.z.
+// p.q partials); x += alpha p, r -= alpha q, z = r / d; partials of r.r and
+// r.z.
 __global__ __launch_bounds__(kRedThreads) void k_pcg_update(Grid g, double* __restrict__ x, double* __restrict__ r,
-                                                            const double* __restrict__ p, const double* __restrict__ q,
-                                                            const Ctl* ctl, const double* __restrict__ pqpart, int nb,
+                                                            double* __restrict__ z, const double* __restrict__ p,
+                                                            const double* __restrict__ q,
+                                                            const double* __restrict__ dn, const Ctl* ctl,
+                                                            const double* __restrict__ pqpart, int nb,
                                                             double* __restrict__ rpart, int kk) {
     __shared__ double lds[2 * kRedThreads / kWave];
     __shared__ double s_alpha;
@@ -526,31 +814,37 @@ __global__ __launch_bounds__(kRedThreads) void k_pcg_update(Grid g, double* __re
     }
     const double alpha = s_alpha;
     double acc[2] = {0.0, 0.0};
-    IBM_CELLS_LOOP(k) {
-        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+    const size_t n = (size_t)g.nx * g.ny;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
         x[k] = __fma_rn(alpha, p[k], x[k]);
         const double rk = __fma_rn(-alpha, q[k], r[k]);
+        const double zk = rk / dn[k];
         r[k] = rk;
+        z[k] = zk;
         acc[0] += rk * rk;
-        acc[1] += rk * (rk / nat_diag(g, i, j));
+        acc[1] += rk * zk;
     }
     block_partials(acc, rpart, gridDim.x, blockIdx.x, lds);
 }
 
-// True residual r = -V b + A x (written to r); partials of r.r, r.z.
+// True residual r = -V b + A x and z = r / d (written to r, z); partials of
+// r.r, r.z.
 __global__ __launch_bounds__(kRedThreads) void k_pcg_true_residual(Grid g, const double* __restrict__ x,
                                                                    const double* __restrict__ vb,
-                                                                   double* __restrict__ r, double* partials) {
+                                                                   double* __restrict__ r, double* __restrict__ z,
+                                                                   double* partials) {
     __shared__ double lds[2 * kRedThreads / kWave];
     double acc[2] = {0.0, 0.0};
-    IBM_CELLS_LOOP(k) {
-        const int j = (int)(k / g.nx), i = (int)(k - (size_t)j * g.nx);
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const size_t k = c.k;
         double d;
-        const double sum = nat_row(g, x, i, j, k, d);
+        const double sum = nat_row(g, x, c.i, c.j, k, d);
         const double rk = -vb[k] + (sum - d * x[k]);
+        const double zk = rk / d;
         r[k] = rk;
+        z[k] = zk;
         acc[0] += rk * rk;
-        acc[1] += rk * (rk / d);
+        acc[1] += rk * zk;
     }
     block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
 }

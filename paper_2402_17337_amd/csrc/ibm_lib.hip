@@ -20,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ibm.h"
@@ -53,7 +54,7 @@ struct Layout {
 
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
-    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb;
+    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -83,6 +84,8 @@ Offsets layout_for(int nx, int ny) {
     o.p = L.take<double>(NC); o.phi = L.take<double>(NC); o.vb = L.take<double>(NC);
     o.pr = L.take<double>(NC); o.pp = L.take<double>(NC); o.pp2 = L.take<double>(NC); o.pq = L.take<double>(NC);
     o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
+    o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
+    o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
     // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
@@ -152,6 +155,8 @@ struct ibm_ctx {
     Grid g;
     // device arrays
     double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pp2, *pq, *phr, *phb, *vbr, *vbb;
+    double *pz, *dn;    // PCG: z = r / diag(M), and diag(M) (natural layout)
+    double *phr2, *phb2;  // second pair of split phi arrays (blocked sweeps alternate)
     double *f_u, *f_v, *coef, *partials;
     Ctl* ctl;
     int *list_u, *list_v, *counts;
@@ -327,7 +332,7 @@ inline int red_blocks(size_t n) {
 // halo H = 2S + 2 (even, one ring more for the fused residual).  Returns false
 // when the loaded tile would not fit the LDS budget or the per-thread
 // position registers.
-bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts, size_t* lds_bytes) {
+bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts) {
     if (S < 1 || S > 8 || tx < 2 || (tx & 1) || ty < 1) return false;
     const int H = 2 * S + 2;
     const int lx = std::min(c->nx, tx + 2 * H), ly = std::min(c->ny, ty + 2 * H);
@@ -338,8 +343,7 @@ bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts, size_t* lds_
     ts->halo = H;
     ts->ntx = (c->nx + tx - 1) / tx;
     ts->nty = (c->ny + ty - 1) / ty;
-    ts->swizzle = ((ts->ntx * ts->nty) % 8 == 0) ? 1 : 0;
-    *lds_bytes = (size_t)lx * ly * sizeof(double);
+    ts->per = (ts->ntx * ts->nty + 7) / 8;
     return true;
 }
 
@@ -348,6 +352,10 @@ bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts, size_t* lds_
 // The residual is tested before the first iteration and after iterations
 // K, 2K, ... (fused into the last blocked launch of each interval).
 // fixed >= 0: exactly `fixed` iterations (tolerance ignored).
+// Blocked launches read one pair of phi arrays and write the other; the
+// launches enqueued after the finishing check do nothing, so the pair that
+// holds the result follows from the number of blocked launches enqueued
+// before that check.  On return phr/phb hold the result.
 // ---------------------------------------------------------------------------
 int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
@@ -357,21 +365,25 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     const int max_e = fixed_mode ? fixed : max_iter;
     const int nbr = red_blocks((size_t)c->nh * c->ny);
     TbShape ts;
-    size_t lds_bytes = 0;
-    const bool use_tb = c->sor_kernel == IBM_SOR_TEMPORAL && tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts, &lds_bytes);
+    const bool use_tb = c->sor_kernel != IBM_SOR_PER_COLOUR && tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts);
+    auto* tb_kernel = c->sor_kernel == IBM_SOR_TEMPORAL_LDS ? k_sor_tb : k_sor_tbr;
     const int S = c->tb_sweeps;
     const int ntiles = use_tb ? ts.ntx * ts.nty : 0;
+    const int tb_blocks = use_tb ? 8 * ts.per : 0;
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
     ++c->solve_id;
-    std::deque<int> pending;
+    std::deque<std::pair<int, long>> pending;  // (slot, blocked launches before the check)
+    double* cur[2] = {c->phr, c->phb};
+    double* alt[2] = {c->phr2, c->phb2};
+    long nlaunch = 0;
     auto check = [&](int phase, int it, int nb) -> int32_t {
         const int s = next_slot(c);
         hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
                            tol_e, (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-        pending.push_back(s);
+        pending.emplace_back(s, nlaunch);
         return IBM_OK;
     };
     timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&](hipEvent_t ea, hipEvent_t eb) {
@@ -383,6 +395,7 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     Slot sn;
     bool first = true;
     int it = 0;
+    long done_launches = 0;
     for (;;) {
         if (it < max_e) {
             const int next = std::min(it + K, max_e);
@@ -392,22 +405,26 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                     const int n = std::min(S, next - it);
                     const int resid = (it + n == next) ? 1 : 0;
                     auto launch = [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, k_sor_tb, dim3(ntiles), dim3(kTbThreads), lds_bytes, c->g, c->phr, c->phb,
-                                  (const double*)c->vbr, (const double*)c->vbb, omega, (const Ctl*)ctl, ts, n, resid,
+                        LAUNCH_EV(ea, eb, tb_kernel, dim3(tb_blocks), dim3(kTbThreads), 0, c->g,
+                                  (const double*)cur[0], (const double*)cur[1], alt[0], alt[1],
+                                  (const double*)c->vbr, (const double*)c->vbb, omega, (const Ctl*)ctl, ts, n,
+                                  resid,
                                   c->partials);
                     };
                     if (n == S) timed(c, IBM_KERNEL_SOR_TB, it + n, launch);
                     else launch(nullptr, nullptr);
+                    std::swap(cur, alt);
+                    ++nlaunch;
                     it += n;
                     if (resid) nb_check = ntiles;
                 } else {
                     const int itk = it + 1;
                     timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, k_sor_sweep<0>, gr, bl, 0, c->g, c->phr, (const double*)c->phb,
+                        LAUNCH_EV(ea, eb, k_sor_sweep<0>, gr, bl, 0, c->g, cur[0], (const double*)cur[1],
                                   (const double*)c->vbr, omega, (const Ctl*)ctl);
                     });
                     timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, k_sor_sweep<1>, gr, bl, 0, c->g, c->phb, (const double*)c->phr,
+                        LAUNCH_EV(ea, eb, k_sor_sweep<1>, gr, bl, 0, c->g, cur[1], (const double*)cur[0],
                                   (const double*)c->vbb, omega, (const Ctl*)ctl);
                     });
                     it = itk;
@@ -416,8 +433,8 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
             LAUNCH_CHECK();
             if (!use_tb) {
                 timed(c, IBM_KERNEL_SOR_RESIDUAL, it, [&](hipEvent_t ea, hipEvent_t eb) {
-                    LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)c->phr,
-                              (const double*)c->phb, (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl,
+                    LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)cur[0],
+                              (const double*)cur[1], (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl,
                               c->partials);
                 });
             }
@@ -429,7 +446,8 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
             c->err = "SOR loop ended without a finishing check";
             return IBM_ERR_STATE;
         }
-        const int s = pending.front();
+        const int s = pending.front().first;
+        done_launches = pending.front().second;
         pending.pop_front();
         rc = wait_slot(c, s, &sn);
         if (rc) return rc;
@@ -441,6 +459,10 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
         }
         if (sn.done) break;
         if (it >= max_e && pending.empty()) break;  // max_e == 0: only the first check
+    }
+    if (done_launches & 1) {  // the result is in the second pair
+        std::swap(c->phr, c->phr2);
+        std::swap(c->phb, c->phb2);
     }
     out->status = sn.status;
     out->iters = sn.iters;
@@ -472,7 +494,7 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
     if (rc) return rc;
     ++c->solve_id;
     std::deque<int> pending;
-    hipLaunchKernelGGL(k_pcg_init, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr, part_r);
+    hipLaunchKernelGGL(k_pcg_init, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr, c->pz, part_r);
     const int s0 = next_slot(c);
     hipLaunchKernelGGL(k_pcg_init_check, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e,
                        c->dslots + s0);
@@ -488,15 +510,15 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
             const int s = next_slot(c);
             const int k0 = kk, rs = restart;
             timed(c, IBM_KERNEL_PCG_DIR_SPMV, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
-                LAUNCH_EV(ea, eb, k_pcg_dir_spmv, dim3(nb), rb, 0, c->g, (const double*)c->pr,
+                LAUNCH_EV(ea, eb, k_pcg_dir_spmv, dim3(nb), rb, 0, c->g, (const double*)c->pz,
                           (const double*)pbuf[(k0 + 1) & 1], pbuf[k0 & 1], c->pq, ctl, (const double*)part_r, nb,
                           part_pq, k0, max_e, tol_e, (int)fixed_mode, rs, c->dslots + s);
             });
             restart = 0;
             if (k0 < max_e) {
                 timed(c, IBM_KERNEL_PCG_UPDATE, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
-                    LAUNCH_EV(ea, eb, k_pcg_update, dim3(nb), rb, 0, c->g, x, c->pr, (const double*)pbuf[k0 & 1],
-                              (const double*)c->pq, (const Ctl*)ctl, (const double*)part_pq, nb, part_r, k0);
+                    LAUNCH_EV(ea, eb, k_pcg_update, dim3(nb), rb, 0, c->g, x, c->pr, c->pz, (const double*)pbuf[k0 & 1],
+                              (const double*)c->pq, (const double*)c->dn, (const Ctl*)ctl, (const double*)part_pq, nb, part_r, k0);
                 });
             }
             LAUNCH_CHECK();
@@ -524,7 +546,7 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
         // the recursive residual passed: confirm with the true residual
         pending.clear();
         hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr,
-                           part_r);
+                           c->pz, part_r);
         const int sc = next_slot(c);
         hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e, 0,
                            c->dslots + sc);
@@ -539,7 +561,7 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
     }
     if (fixed_mode && sn.status == kStOk && sn.iters > 0) {
         hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr,
-                           part_r);
+                           c->pz, part_r);
         const int s = next_slot(c);
         hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e, 1,
                            c->dslots + s);
@@ -898,6 +920,8 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp);
     c->pp2 = D(off.pp2); c->pq = D(off.pq);
     c->phr = D(off.phr); c->phb = D(off.phb); c->vbr = D(off.vbr); c->vbb = D(off.vbb);
+    c->pz = D(off.pz); c->dn = D(off.dn);
+    c->phr2 = D(off.phr2); c->phb2 = D(off.phb2);
     c->f_u = D(off.f_u); c->f_v = D(off.f_v); c->coef = D(off.coef); c->partials = D(off.partials);
     c->ctl = (Ctl*)(w + off.ctl);
     c->list_u = (int*)(w + off.list_u); c->list_v = (int*)(w + off.list_v); c->counts = (int*)(w + off.counts);
@@ -952,6 +976,7 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     if (!rc) rc = fill_u8(c, (uint8_t*)c->counts, 4 * sizeof(int));
     if (!rc) {
         hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, c->stream, c->ctl, (int)CTL_N);
+        hipLaunchKernelGGL(k_ndiag, grid2(nx, ny), dim3(kBlock), 0, c->stream, c->g, c->dn);
         if (hipGetLastError() != hipSuccess) rc = IBM_ERR_HIP;
     }
     if (rc) return fail(rc);
@@ -1150,7 +1175,8 @@ int32_t ibm_set_option(ibm_ctx* c, int32_t option, int64_t value) {
     int kern = c->sor_kernel, S = c->tb_sweeps, tx = c->tb_tx, ty = c->tb_ty;
     switch (option) {
         case IBM_OPT_SOR_KERNEL:
-            if (value != IBM_SOR_TEMPORAL && value != IBM_SOR_PER_COLOUR) return IBM_ERR_INVALID;
+            if (value != IBM_SOR_TEMPORAL && value != IBM_SOR_PER_COLOUR && value != IBM_SOR_TEMPORAL_LDS)
+                return IBM_ERR_INVALID;
             kern = (int)value;
             break;
         case IBM_OPT_TB_SWEEPS: S = (int)value; break;
@@ -1160,8 +1186,7 @@ int32_t ibm_set_option(ibm_ctx* c, int32_t option, int64_t value) {
     }
     if (value < 0 || value > (1 << 20)) return IBM_ERR_INVALID;
     TbShape ts;
-    size_t lds = 0;
-    if (!tb_shape(c, S, tx, ty, &ts, &lds)) {
+    if (!tb_shape(c, S, tx, ty, &ts)) {
         c->err = "tile shape does not fit the blocked sweep";
         return IBM_ERR_INVALID;
     }
@@ -1199,7 +1224,7 @@ int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* s
     }
     const size_t n = c->samples[kernel].size();
     const double cells = (double)c->nx * c->ny;
-    const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 48.0 * cells,
+    const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 64.0 * cells,
                                             24.0 * cells * c->tb_sweeps};
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (samples) *samples = (int64_t)n;

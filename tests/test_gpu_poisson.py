@@ -182,19 +182,24 @@ def test_full_size_grid_fixed_iterations(torch):
     (256, 192, 2, (16, 12)),     # 256 tiles in the XCD-banded order
     (64, 48, 8, (64, 48)),       # one tile, deep halo clipped by the domain
     (1024, 768, 5, (104, 32)),   # the plunging-workload grid, 240 tiles
+    (1024, 768, 5, (104, 28)),   # 280 tiles: more blocks than compute units
+    (512, 384, 2, (16, 12)),     # 1024 small tiles, several blocks per compute unit in turn
 ])
 def test_blocked_sweep_is_bitwise_the_per_colour_sweep(torch, nx, ny, sweeps, tile):
     """The temporally blocked launch performs the same cell updates with the
     same neighbour values as one launch per colour: identical iterates, for
     fixed iteration counts that are not multiples of the sweep count, and the
-    same stop decision in tolerance mode."""
+    same stop decision in tolerance mode.  Grids with more tiles than compute
+    units check that no tile reads a halo another tile of the same launch has
+    already rewritten."""
     xf, yf = _grid(nx, ny, stretched=(nx != 128))
     g = ibm.Solver(nx, ny, xf, yf, body=0)
     rng = np.random.default_rng(nx * 7 + sweeps)
     b = _dev(torch, rng.standard_normal((ny, nx)))
     x0 = rng.standard_normal((ny, nx))
     out = {}
-    for kern in (ibm.SOR_PER_COLOUR, ibm.SOR_TEMPORAL):
+    kernels = (ibm.SOR_PER_COLOUR, ibm.SOR_TEMPORAL, ibm.SOR_TEMPORAL_LDS)
+    for kern in kernels:
         assert g.set_option(ibm.OPT_SOR_KERNEL, kern) == ibm.OK
         assert g.set_option(ibm.OPT_TB_SWEEPS, sweeps) == ibm.OK
         assert g.set_option(ibm.OPT_TB_TILE_X, tile[0]) == ibm.OK
@@ -204,14 +209,16 @@ def test_blocked_sweep_is_bitwise_the_per_colour_sweep(torch, nx, ny, sweeps, ti
         xt = _dev(torch, np.zeros((ny, nx)))
         st2 = g.poisson_solve(b, xt, method=ibm.RBSOR, omega=1.7, tol=1e-3, check_every=10)
         out[kern] = (xd.cpu().numpy(), st, xt.cpu().numpy(), st2)
-    a, bb_ = out[ibm.SOR_PER_COLOUR], out[ibm.SOR_TEMPORAL]
-    print(f"nx={nx} S={sweeps} tile={tile} maxdiff={np.max(np.abs(a[0] - bb_[0])):.3e} "
-          f"iters {a[3]['iters']} {bb_[3]['iters']}", flush=True)
-    assert np.array_equal(a[0], bb_[0])
-    assert a[1]["iters"] == bb_[1]["iters"] == 23
-    assert abs(a[1]["rel"] - bb_[1]["rel"]) <= 1e-12 * a[1]["rel"]
-    assert a[3]["iters"] == bb_[3]["iters"]
-    assert np.array_equal(a[2], bb_[2])
+    a = out[ibm.SOR_PER_COLOUR]
+    for kern in kernels[1:]:
+        bb_ = out[kern]
+        print(f"kernel {kern} nx={nx} S={sweeps} tile={tile} maxdiff={np.max(np.abs(a[0] - bb_[0])):.3e} "
+              f"iters {a[3]['iters']} {bb_[3]['iters']}", flush=True)
+        assert np.array_equal(a[0], bb_[0])
+        assert a[1]["iters"] == bb_[1]["iters"] == 23
+        assert abs(a[1]["rel"] - bb_[1]["rel"]) <= 1e-12 * a[1]["rel"]
+        assert a[3]["iters"] == bb_[3]["iters"]
+        assert np.array_equal(a[2], bb_[2])
 
 
 def test_blocked_sweep_rejects_shapes_that_do_not_fit(torch):
