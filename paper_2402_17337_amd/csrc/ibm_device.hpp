@@ -163,6 +163,13 @@ __device__ inline void check_finish(Ctl* ctl, double r2, double b2, int phase, i
     if (it >= max_iter) { ctl->done = kDone; ctl->status = fixed ? kStOk : kStNotConverged; return; }
 }
 
+// Whether a residual test after `it` iterations ends the solve (the decision
+// check_finish records for phase 1): NaN, converged, or the iteration limit.
+__device__ inline bool check_stops(double rn, double bn, int it, int max_iter, double tol) {
+    const double den = bn > 0.0 ? bn : 1.0;
+    return !isfinite(rn) || rn <= tol * den || it >= max_iter;
+}
+
 // Strict inside test of the ellipse, evaluated without contraction so that it
 // takes exactly the decision of a plain IEEE evaluation.
 __device__ inline bool inside(double x, double y, const Body& B) {

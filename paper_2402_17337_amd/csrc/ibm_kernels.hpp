@@ -220,6 +220,46 @@ struct TbShape {
     int per;       // tiles per XCD band: block b takes tile (b % 8) * per + b / 8
 };
 
+// Stop test of the previous check interval, carried by the first blocked
+// launch of the next one (nb = 0: none in this launch).
+struct TbCheck {
+    const double* partials;  // residual partials of that interval: nb sums of r^2, then nb of b^2
+    int nb;
+    int it;                  // iterations at the test
+    int max_iter, fixed;
+    double tol;
+    Slot* slot;              // host-visible snapshot of the decision
+};
+
+// Start of a blocked launch: returns the solve's stop flag (block-uniform).
+// With a carried test, every block sums the partials in the same order and
+// takes the same decision; block 0 records it in ctl (as k_check does).  The
+// host-visible snapshot is written by tb_end, or here when the solve stops,
+// so that the system-scope fence does not delay block 0's sweeps.
+__device__ inline int tb_begin(Ctl* ctl, const TbCheck& chk, double* lds, int* s_flag) {
+    if (threadIdx.x == 0) *s_flag = ctl->done;
+    if (chk.nb > 0) {
+        double acc[2];
+        sum_partials(acc, chk.partials, chk.nb, lds);
+        if (threadIdx.x == 0) {
+            if (!*s_flag) {
+                const bool stop = check_stops(sqrt(acc[0]), ctl->bn, chk.it, chk.max_iter, chk.tol);
+                if (blockIdx.x == 0) check_finish(ctl, acc[0], acc[1], 1, chk.it, chk.max_iter, chk.tol, chk.fixed, 0);
+                *s_flag = stop ? 1 : 0;
+            }
+            if (blockIdx.x == 0 && *s_flag) publish(ctl, chk.slot);
+        }
+    }
+    __syncthreads();
+    return *s_flag;
+}
+
+// End of a blocked launch that did not stop: block 0 publishes the carried
+// test's decision.
+__device__ inline void tb_end(const Ctl* ctl, const TbCheck& chk) {
+    if (chk.nb > 0 && blockIdx.x == 0 && threadIdx.x == 0) publish(ctl, chk.slot);
+}
+
 // Tile of block b.  Blocks are dispatched to the 8 XCDs round-robin, so each
 // XCD gets a contiguous band of tiles and the halos its tiles share stay in
 // its L2.  The launch has 8 * per blocks; those past the last tile return.
@@ -229,14 +269,15 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
                                                        const double* __restrict__ black, double* __restrict__ ored,
                                                        double* __restrict__ oblack, const double* __restrict__ bred,
                                                        const double* __restrict__ bblack,
-                                                       double omega,
-                                                       const Ctl* __restrict__ ctl, TbShape ts, int nsweep,
-                                                       int residual, double* __restrict__ partials) {
+                                                       double omega, Ctl* ctl, TbCheck chk, TbShape ts,
+                                                       int nsweep, int residual, double* __restrict__ partials) {
     __shared__ double tile[2 * kTbLds];
     __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
     const int nt = ts.ntx * ts.nty;
     const int t = tb_tile(ts);
-    if (t >= nt || ctl->done) return;
+    if (t >= nt) return;
+    if (tb_begin(ctl, chk, lds, &s_flag)) return;
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
@@ -373,6 +414,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
         }
     }
     if (residual) block_partials(acc, partials, nt, t, lds);
+    tb_end(ctl, chk);
 }
 
 // ---------------------------------------------------------------------------
@@ -496,17 +538,14 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
                                                         const double* __restrict__ black, double* __restrict__ ored,
                                                         double* __restrict__ oblack, const double* __restrict__ bred,
                                                         const double* __restrict__ bblack,
-                                                        double omega,
-                                                        const Ctl* __restrict__ ctl, TbShape ts, int nsweep,
-                                                        int residual, double* __restrict__ partials) {
+                                                        double omega, Ctl* ctl, TbCheck chk, TbShape ts,
+                                                        int nsweep, int residual, double* __restrict__ partials) {
     __shared__ double edge[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
     const int nt = ts.ntx * ts.nty;
     const int t = tb_tile(ts);
     if (t >= nt) return;
-    // The stop flag is tested after the tile's loads are issued, so that its
-    // latency overlaps theirs (a finished solve only wastes the loads).
-    const int done = ctl->done;
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
@@ -564,7 +603,9 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
             }
         }
     }
-    if (done) return;
+    // The stop test comes after the tile's loads are issued, so that its
+    // latency overlaps theirs (a finished solve only wastes the loads).
+    if (tb_begin(ctl, chk, lds, &s_flag)) return;
     // edge rows of both colours; slots 0 and kTrSlots-1 stay zero
     if (w == 0) {
 #pragma unroll
@@ -619,6 +660,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
         else tbr_residual<0>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
         block_partials(acc, partials, nt, t, lds);
     }
+    tb_end(ctl, chk);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,7 +684,10 @@ __device__ inline double nat_diag(const Grid& g, int i, int j) {
 }
 
 // Grid-stride walk over the nx*ny cells of the natural layout that keeps the
-// cell's (i, j) up to date without an integer division per step.
+// cell's (i, j) up to date without an integer division per step.  Blocks go
+// to the 8 XCDs round-robin; when the grid is a multiple of 8 blocks the walk
+// gives each XCD a contiguous range of block positions, so that the rows
+// above and below a block's cells were mostly fetched into the same L2.
 struct CellWalk {
     size_t k, n, stride;
     int i, j, si, sj, nx;
@@ -652,7 +697,9 @@ struct CellWalk {
         stride = (size_t)gridDim.x * blockDim.x;
         sj = (int)(stride / nx);
         si = (int)(stride - (size_t)sj * nx);
-        k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const unsigned b = blockIdx.x, nb = gridDim.x;
+        const unsigned lb = (nb & 7u) ? b : (b & 7u) * (nb >> 3) + (b >> 3);
+        k = (size_t)lb * blockDim.x + threadIdx.x;
         j = (int)(k / nx);
         i = (int)(k - (size_t)j * nx);
     }

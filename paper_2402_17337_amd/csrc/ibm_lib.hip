@@ -344,18 +344,22 @@ bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts) {
     ts->ntx = (c->nx + tx - 1) / tx;
     ts->nty = (c->ny + ty - 1) / ty;
     ts->per = (ts->ntx * ts->nty + 7) / 8;
+    // two sets of per-tile residual partials (r^2, b^2) must fit the partials area
+    if (4 * (size_t)ts->ntx * ts->nty > 4 * (size_t)kRedMax + (size_t)c->nx * c->ny) return false;
     return true;
 }
 
 // ---------------------------------------------------------------------------
 // Red-black SOR on A x = vb, both in split storage (phr/phb, vbr/vbb).
 // The residual is tested before the first iteration and after iterations
-// K, 2K, ... (fused into the last blocked launch of each interval).
-// fixed >= 0: exactly `fixed` iterations (tolerance ignored).
-// Blocked launches read one pair of phi arrays and write the other; the
-// launches enqueued after the finishing check do nothing, so the pair that
-// holds the result follows from the number of blocked launches enqueued
-// before that check.  On return phr/phb hold the result.
+// K, 2K, ...  fixed >= 0: exactly `fixed` iterations (tolerance ignored).
+// Blocked launches: the residual of each interval is summed by its last
+// launch (per-tile partials, two alternating sets) and tested by the first
+// launch of the next interval; the last interval's test is a k_check.  They
+// read one pair of phi arrays and write the other; the launches enqueued
+// after the finishing test do nothing, so the pair that holds the result
+// follows from the number of blocked launches enqueued before that test.  On
+// return phr/phb hold the result.
 // ---------------------------------------------------------------------------
 int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
@@ -370,27 +374,32 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     const int S = c->tb_sweeps;
     const int ntiles = use_tb ? ts.ntx * ts.nty : 0;
     const int tb_blocks = use_tb ? 8 * ts.per : 0;
+    double* tb_part[2] = {c->partials, c->partials + 2 * (size_t)ntiles};
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
     ++c->solve_id;
-    std::deque<std::pair<int, long>> pending;  // (slot, blocked launches before the check)
+    std::deque<std::pair<int, long>> pending;  // (slot, blocked launches before the test)
     double* cur[2] = {c->phr, c->phb};
     double* alt[2] = {c->phr2, c->phb2};
     long nlaunch = 0;
-    auto check = [&](int phase, int it, int nb) -> int32_t {
+    int nint = 0;  // intervals enqueued
+    // test of the last interval not yet enqueued (blocked launches)
+    TbCheck carry = {nullptr, 0, 0, max_e, (int)fixed_mode, tol_e, nullptr};
+    long carry_nl = 0;
+    auto check = [&](int phase, int it, int nb, const double* part, long nl) -> int32_t {
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
-                           tol_e, (int)fixed_mode, 0, c->dslots + s);
+        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, part, nb, phase, it, max_e, tol_e,
+                           (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-        pending.emplace_back(s, nlaunch);
+        pending.emplace_back(s, nl);
         return IBM_OK;
     };
     timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&](hipEvent_t ea, hipEvent_t eb) {
         LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)c->phr,
                   (const double*)c->phb, (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl, c->partials);
     });
-    rc = check(0, 0, nbr);
+    rc = check(0, 0, nbr, c->partials, 0);
     if (rc) return rc;
     Slot sn;
     bool first = true;
@@ -399,24 +408,39 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     for (;;) {
         if (it < max_e) {
             const int next = std::min(it + K, max_e);
-            int nb_check = nbr;
+            double* part = tb_part[nint & 1];
             while (it < next) {
                 if (use_tb) {
                     const int n = std::min(S, next - it);
                     const int resid = (it + n == next) ? 1 : 0;
+                    TbCheck chk = carry;
+                    int cs = -1;
+                    if (chk.nb > 0) {
+                        cs = next_slot(c);
+                        chk.slot = c->dslots + cs;
+                    }
                     auto launch = [&](hipEvent_t ea, hipEvent_t eb) {
                         LAUNCH_EV(ea, eb, tb_kernel, dim3(tb_blocks), dim3(kTbThreads), 0, c->g,
                                   (const double*)cur[0], (const double*)cur[1], alt[0], alt[1],
-                                  (const double*)c->vbr, (const double*)c->vbb, omega, (const Ctl*)ctl, ts, n,
-                                  resid,
-                                  c->partials);
+                                  (const double*)c->vbr, (const double*)c->vbb, omega, ctl, chk, ts, n, resid,
+                                  part);
                     };
                     if (n == S) timed(c, IBM_KERNEL_SOR_TB, it + n, launch);
                     else launch(nullptr, nullptr);
+                    if (cs >= 0) {
+                        HIP_TRY(hipEventRecord(c->ev[cs], c->stream));
+                        pending.emplace_back(cs, carry_nl);
+                        carry.nb = 0;
+                    }
                     std::swap(cur, alt);
                     ++nlaunch;
                     it += n;
-                    if (resid) nb_check = ntiles;
+                    if (resid) {
+                        carry.partials = part;
+                        carry.nb = ntiles;
+                        carry.it = it;
+                        carry_nl = nlaunch;
+                    }
                 } else {
                     const int itk = it + 1;
                     timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
@@ -431,16 +455,22 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                 }
             }
             LAUNCH_CHECK();
+            ++nint;
             if (!use_tb) {
                 timed(c, IBM_KERNEL_SOR_RESIDUAL, it, [&](hipEvent_t ea, hipEvent_t eb) {
                     LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)cur[0],
                               (const double*)cur[1], (const double*)c->vbr, (const double*)c->vbb, (const Ctl*)ctl,
                               c->partials);
                 });
+                rc = check(1, it, nbr, c->partials, nlaunch);
+                if (rc) return rc;
             }
-            rc = check(1, it, nb_check);
-            if (rc) return rc;
             if ((int)pending.size() < kAheadSor && it < max_e) continue;
+        }
+        if (it >= max_e && carry.nb > 0) {  // the last interval's test
+            rc = check(1, carry.it, carry.nb, carry.partials, carry_nl);
+            if (rc) return rc;
+            carry.nb = 0;
         }
         if (pending.empty()) {
             c->err = "SOR loop ended without a finishing check";

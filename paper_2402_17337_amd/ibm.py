@@ -23,9 +23,11 @@ BC_CHANNEL = 0
 RBSOR, PCG = 0, 1
 INIT_ZERO, INIT_PREVIOUS = 0, 1
 KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB = range(5)
+# KERNEL_SOR_TB times whichever blocked sweep runs; named for the default one
+# (k_sor_tb is the LDS-tile variant).
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
-                KERNEL_SOR_TB: "k_sor_tb"}
+                KERNEL_SOR_TB: "k_sor_tbr"}
 OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y = range(4)
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
