@@ -70,6 +70,7 @@
 #define ORC_PERIODIC 1
 #define ORC_SOR 0
 #define ORC_PCG 1
+#define ORC_SOR_MP 2
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -309,6 +310,80 @@ static int poisson_sor(const orc_ctx *c, const double *vb, double *x, double ome
     return ORC_NOT_CONVERGED;
 }
 
+/* Mixed precision: red-black SOR with single-precision sweeps and
+ * double-precision refinement.  Every check interval of m iterations solves
+ * the correction equation A e = r of the current residual r = vb - A x with
+ * m SOR iterations from e = 0 in single precision (coefficients, right-hand
+ * side and e rounded to float, float arithmetic), then x += e and the residual
+ * and the stop test are evaluated in double precision.  SOR is a stationary
+ * iteration, so in exact arithmetic restarting it on the correction equation
+ * reproduces the double-precision iterates; rounding is relative to the size
+ * of the correction, which shrinks as x converges.  Single-precision SOR alone
+ * stalls where its rounding error reaches the residual (set refine = 0 to run
+ * it without refinement, x += e once at the end). */
+static void sor_colour_f32(const orc_ctx *c, float *e, const float *r32, float omega, int colour) {
+    const int nx = c->nx, ny = c->ny;
+#pragma omp parallel for schedule(static) if (c->nx * c->ny >= ORC_OMP_MIN_CELLS)
+    for (int j = 0; j < ny; ++j)
+        for (int i = (j + colour) & 1; i < nx; i += 2) {
+            float s = 0.0f, d = 0.0f, a;
+            if (i < nx - 1) { a = (float)(c->dy[j] / c->dxu[i + 1]); s += a * e[ic(c, i + 1, j)]; d += a; }
+            else { d += (float)(c->dy[j] / c->dxu[nx]); }
+            if (i > 0) { a = (float)(c->dy[j] / c->dxu[i]); s += a * e[ic(c, i - 1, j)]; d += a; }
+            if (j < ny - 1) { a = (float)(c->dx[i] / c->dyv[j + 1]); s += a * e[ic(c, i, j + 1)]; d += a; }
+            if (j > 0) { a = (float)(c->dx[i] / c->dyv[j]); s += a * e[ic(c, i, j - 1)]; d += a; }
+            float g = (s - r32[ic(c, i, j)]) / d;
+            e[ic(c, i, j)] = (1.0f - omega) * e[ic(c, i, j)] + omega * g;
+        }
+}
+
+static int poisson_sor_mp(const orc_ctx *c, const double *vb, double *x, double omega, double tol,
+                          int max_iter, int check, int fixed, int refine, orc_solve_stats *st) {
+    const size_t n = (size_t)c->nx * c->ny;
+    double *r = c->w0;
+    float *e = (float *)c->w1, *r32 = (float *)c->w2;
+    const float om = (float)omega;
+    double bn = sqrt(sumsq(vb, n));
+    st->iters = 0; st->r0_rel = 0.0; st->rel = 0.0; st->status = ORC_OK;
+    if (!isfinite(bn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+    if (bn == 0.0) { memset(x, 0, n * sizeof(double)); return ORC_OK; }
+    if (fixed > 0) { max_iter = fixed; tol = -1.0; }
+    if (check < 1) check = 1;
+    double rn = poisson_resid_norm(c, x, vb, r);
+    st->r0_rel = rn / bn; st->rel = rn / bn;
+    if (!isfinite(rn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+    if (rn <= tol * bn) return ORC_OK;
+    int it = 0;
+    if (!refine) {
+        for (size_t k = 0; k < n; ++k) { r32[k] = (float)r[k]; e[k] = 0.0f; }
+        for (; it < max_iter; ++it) {
+            sor_colour_f32(c, e, r32, om, 0);
+            sor_colour_f32(c, e, r32, om, 1);
+        }
+        for (size_t k = 0; k < n; ++k) x[k] += (double)e[k];
+        rn = poisson_resid_norm(c, x, vb, r);
+        st->iters = it; st->rel = rn / bn;
+        return ORC_OK;
+    }
+    while (it < max_iter) {
+        int m = check < max_iter - it ? check : max_iter - it;
+        for (size_t k = 0; k < n; ++k) { r32[k] = (float)r[k]; e[k] = 0.0f; }
+        for (int k = 0; k < m; ++k) {
+            sor_colour_f32(c, e, r32, om, 0);
+            sor_colour_f32(c, e, r32, om, 1);
+        }
+        for (size_t k = 0; k < n; ++k) x[k] += (double)e[k];
+        it += m;
+        rn = poisson_resid_norm(c, x, vb, r);
+        st->iters = it; st->rel = rn / bn;
+        if (!isfinite(rn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+        if (rn <= tol * bn) return ORC_OK;
+    }
+    if (fixed > 0) return ORC_OK;
+    st->status = ORC_NOT_CONVERGED;
+    return ORC_NOT_CONVERGED;
+}
+
 /* Jacobi-preconditioned conjugate gradients on M x = c with M = -A (SPD in
  * channel mode), c = -vb; the preconditioner is diag(M) = sum of the
  * neighbour coefficients plus the outlet term.  The stop test uses the
@@ -376,8 +451,10 @@ static int poisson_pcg(const orc_ctx *c, const double *vb, double *x, double tol
 static int poisson_solve_vb(orc_ctx *c, double *vb, double *x, int method, double omega, double tol,
                             int max_iter, int check, int fixed, orc_solve_stats *st) {
     int rc;
+    if (method == ORC_SOR_MP && c->per) return ORC_ERR_INVALID;  /* channel operator only */
     if (c->per) periodic_project_rhs(c, vb);
     if (method == ORC_PCG) rc = poisson_pcg(c, vb, x, tol, max_iter, fixed, st);
+    else if (method == ORC_SOR_MP) rc = poisson_sor_mp(c, vb, x, omega, tol, max_iter, check, fixed, 1, st);
     else rc = poisson_sor(c, vb, x, omega, tol, max_iter, check, fixed, st);
     if (c->per && rc >= 0) periodic_zero_mean(c, x);
     return rc;
@@ -393,6 +470,17 @@ int orc_poisson_solve(orc_ctx *c, const double *b, double *x, int method, double
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * b[ic(c, i, j)];
     return poisson_solve_vb(c, vb, x, method, omega, tol, max_iter, check, fixed, st);
+}
+
+/* Single-precision SOR without refinement (the stall that refinement
+ * removes): `iters` float iterations on the correction of x, then x += e. */
+int orc_poisson_sor_f32(orc_ctx *c, const double *b, double *x, double omega, int iters, orc_solve_stats *st) {
+    const int nx = c->nx, ny = c->ny;
+    double *vb = c->vb;
+    if (c->per || iters < 1) return ORC_ERR_INVALID;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * b[ic(c, i, j)];
+    return poisson_sor_mp(c, vb, x, omega, -1.0, iters, iters, iters, 0, st);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "ibm_oracle.c")
 _LIB = os.path.join(_HERE, "libibm_oracle.so")
 
 CHANNEL, PERIODIC = 0, 1
-SOR, PCG = 0, 1
+SOR, PCG, SOR_MP = 0, 1, 2   # SOR_MP: single-precision sweeps, double-precision refinement
 OK, NOT_CONVERGED, ERR_INVALID, ERR_NAN = 0, 1, -1, -5
 
 
@@ -90,6 +90,8 @@ def lib():
         L.orc_poisson_solve.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_double, C.c_double,
                                         C.c_int, C.c_int, C.c_int, C.POINTER(SolveStats)]
         L.orc_poisson_solve.restype = C.c_int
+        L.orc_poisson_sor_f32.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int, C.POINTER(SolveStats)]
+        L.orc_poisson_sor_f32.restype = C.c_int
         L.orc_momentum_terms.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp]
         L.orc_divergence.argtypes = [C.c_void_p, dp]
         ub = C.POINTER(C.c_ubyte)
@@ -225,6 +227,16 @@ class Oracle:
         st = SolveStats()
         rc = lib().orc_poisson_solve(self._h, _dp(b), _dp(x), method, omega, tol, max_iter,
                                      check, fixed, C.byref(st))
+        return x, {"iters": st.iters, "r0_rel": st.r0_rel, "rel": st.rel, "status": st.status}, rc
+
+    def poisson_sor_f32(self, b, x0=None, omega=1.8, iters=1000):
+        """Single-precision SOR on the correction of x without refinement
+        (iters float iterations, then x += e); returns (x, stats dict, status)."""
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(self.ny, self.nx)
+        x = (np.zeros_like(b) if x0 is None
+             else np.array(x0, dtype=np.float64, copy=True).reshape(self.ny, self.nx))
+        st = SolveStats()
+        rc = lib().orc_poisson_sor_f32(self._h, _dp(b), _dp(x), omega, iters, C.byref(st))
         return x, {"iters": st.iters, "r0_rel": st.r0_rel, "rel": st.rel, "status": st.status}, rc
 
     def momentum_terms(self):
