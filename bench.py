@@ -182,6 +182,11 @@ def main():
     ap.add_argument("--solver", choices=("sor", "pcg"), default="sor",
                     help="pressure solver of the headline leg")
     ap.add_argument("--pcg-steps", type=int, default=4, help="timed steps of the PCG leg (0: skip)")
+    ap.add_argument("--mp-steps", type=int, default=2,
+                    help="timed steps of the mixed-precision SOR leg (float sweeps, double refinement; 0: skip)")
+    ap.add_argument("--c3-iters", type=int, default=20000,
+                    help="Poisson iterations per solve of the capped 2048x1536 comparison of double and "
+                         "mixed-precision SOR (0: skip)")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="bracket every n-th launch of each timed kernel with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -226,6 +231,19 @@ def main():
     if args.solver == "sor" and args.pcg_steps > 0:
         pcg_leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, args.profile_every,
                           args.max_poisson_iters)
+
+    mp_leg = None
+    if args.solver == "sor" and args.mp_steps > 0:
+        mp_leg = gpu_leg(case, ibm.RBSOR_MP, args.mp_steps, args.warmup, args.profile_every,
+                         args.max_poisson_iters)
+    c3 = None
+    if args.solver == "sor" and args.c3_iters > 0:
+        case3 = W.plunging_2048x1536()
+        c3 = {}
+        for name, m in (("f64", ibm.RBSOR), ("mixed", ibm.RBSOR_MP)):
+            leg = gpu_leg(case3, m, 1, 0, args.profile_every, args.c3_iters)
+            c3[name] = {"s_per_step": round(leg["wall"], 4), "poisson_iters": leg["iters"][0],
+                        "us_per_iteration": round(1e6 * leg["wall"] / max(leg["iters"][0], 1), 3)}
 
     # dominant kernel of the headline leg: the most total sampled time
     cands = ((ibm.KERNEL_SOR_TB, ibm.KERNEL_SOR_SWEEP) if method == ibm.RBSOR
@@ -273,6 +291,28 @@ def main():
                       "cell_updates_per_s": round(pcg_leg["cell_updates_per_s"], 1),
                       "kernels_avg_us": {ibm.KERNEL_NAMES[k]: round(pcg_leg["prof"][k]["avg_ms"] * 1e3, 3)
                                          for k in (ibm.KERNEL_PCG_DIR_SPMV, ibm.KERNEL_PCG_UPDATE)}}
+    if mp_leg is not None:
+        mp_steps = args.mp_steps
+        kern = {}
+        for k in (ibm.KERNEL_SOR_MP, ibm.KERNEL_SOR_MP_REFINE):
+            q = mp_leg["prof"][k]
+            if q["avg_ms"] > 0:
+                kern[ibm.KERNEL_NAMES[k]] = {
+                    "avg_us": round(q["avg_ms"] * 1e3, 3),
+                    "achieved_GBps": round(q["bytes_per_launch"] / (q["avg_ms"] * 1e-3) / 1e9, 1)}
+        mp_s = mp_leg["wall"] / mp_steps
+        out["mixed_precision"] = {
+            "solver": "red-black SOR omega 1.8, float sweeps on the correction, double residual, update and "
+                      "stop test every 10 iterations, tol 1e-8",
+            "s_per_time_step": round(mp_s, 6),
+            "poisson_iters_per_step": mp_leg["iters"],
+            "speedup_vs_f64_sor": round((main_leg["wall"] / steps) / mp_s, 3) if mp_s > 0 else None,
+            "kernels": kern}
+    if c3 is not None:
+        out["c3_capped"] = dict(c3, workload="plunging ellipse 2048x1536, Re 1000, h 0.6, f 0.5; first step, "
+                                             f"Poisson solve capped at {args.c3_iters} iterations",
+                                speedup_per_iteration=round(c3["f64"]["us_per_iteration"] /
+                                                            max(c3["mixed"]["us_per_iteration"], 1e-9), 3))
     if args.stress:
         out["stress_hbm"] = stress_leg()
     if args.cpu_seconds > 0:

@@ -64,6 +64,13 @@ extern "C" {
 /* pressure solvers */
 #define IBM_SOLVER_RBSOR 0 /* red-black SOR, red = (i+j) even updated first */
 #define IBM_SOLVER_PCG 1   /* conjugate gradients on -A, Jacobi preconditioner */
+/* Red-black SOR with single-precision sweeps and double-precision refinement:
+ * each check interval solves the correction equation A e = r (r the double
+ * residual, rounded to float) by float SOR sweeps from e = 0, then phi += e
+ * and the residual and stop test are evaluated in double.  Same omega, stop
+ * test and check interval as IBM_SOLVER_RBSOR; it uses the blocked sweep's
+ * tile shape (IBM_OPT_TB_*). */
+#define IBM_SOLVER_RBSOR_MP 2
 
 /* initial guess of the pressure correction at each step */
 #define IBM_INIT_ZERO 0
@@ -84,7 +91,7 @@ typedef struct ibm_params {
     double thickness;        /* thickness / chord (minor axis = thickness * chord) */
     double x0, y0;           /* centre of the ellipse at rest position */
     double amp, freq, phase; /* plunge y_c = y0 + amp sin(2 pi freq t + phase) (Eqs. 1-2, k = 2 pi freq) */
-    int32_t p_method;        /* IBM_SOLVER_RBSOR or IBM_SOLVER_PCG */
+    int32_t p_method;        /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG or IBM_SOLVER_RBSOR_MP */
     int32_t p_max_iter;      /* iteration limit of one pressure solve, >= 1 */
     int32_t p_check_every;   /* SOR: residual tested every this many iterations, >= 1 */
     int32_t p_init;          /* IBM_INIT_ZERO or IBM_INIT_PREVIOUS */
@@ -116,7 +123,7 @@ typedef struct ibm_step_stats {
 
 /* Options of a stand-alone Poisson solve. */
 typedef struct ibm_solve_opts {
-    int32_t method;       /* IBM_SOLVER_RBSOR or IBM_SOLVER_PCG */
+    int32_t method;       /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG or IBM_SOLVER_RBSOR_MP */
     int32_t max_iter;     /* iteration limit, >= 1 */
     int32_t check_every;  /* SOR residual test interval, >= 1 (PCG tests every iteration) */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations, tol ignored */
@@ -217,7 +224,9 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
 #define IBM_KERNEL_PCG_DIR_SPMV 2   /* p = z + beta p, q = M p: 32 B per cell (z, p in; p, q out) */
 #define IBM_KERNEL_PCG_UPDATE 3     /* x, r, z = r/d: 64 B per cell (x, r, p, q, d in; x, r, z out) */
 #define IBM_KERNEL_SOR_TB 4         /* blocked SOR (either variant): 24 B per cell and iteration */
-#define IBM_KERNEL_COUNT 5
+#define IBM_KERNEL_SOR_MP 5         /* mixed-precision sweeps: 12 B per cell and iteration (float e, r) */
+#define IBM_KERNEL_SOR_MP_REFINE 6  /* the same plus the refinement: + 32 B per cell (phi, e, V b -> phi, r) */
+#define IBM_KERNEL_COUNT 7
 int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
 int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
                           double* bytes_per_launch);
@@ -231,7 +240,7 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
  *                       per colour sweep;
  *   IBM_OPT_TB_SWEEPS   iterations per blocked launch, 1..8 (default 5);
  *   IBM_OPT_TB_TILE_X   interior tile width, even (default 104);
- *   IBM_OPT_TB_TILE_Y   interior tile height (default 32).
+ *   IBM_OPT_TB_TILE_Y   interior tile height, even (default 32).
  * The loaded tile (interior plus a halo of 2 S + 2 on each side, clamped to
  * the grid) must fit 128 x 64 cells.
  * IBM_ERR_INVALID for an unknown option or a tile shape whose halo does not

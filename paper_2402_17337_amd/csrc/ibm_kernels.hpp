@@ -95,6 +95,21 @@ __device__ inline double sor_update(double x, double sum, double b, double rd, d
     return __fma_rn(omega, gs, (1.0 - omega) * x);
 }
 
+// The same three operations in single precision (the mixed-precision sweeps).
+__device__ inline float rb_sum(float aE, float xE, float aW, float xW, float aN, float xN, float aS, float xS) {
+    float sum = aE * xE;
+    sum = __fmaf_rn(aW, xW, sum);
+    sum = __fmaf_rn(aN, xN, sum);
+    return __fmaf_rn(aS, xS, sum);
+}
+__device__ inline float rb_diag(float aE, float aD, float aW, float aN, float aS) {
+    return (((aE + aD) + aW) + aN) + aS;
+}
+__device__ inline float sor_update(float x, float sum, float b, float rd, float omega) {
+    const float gs = (sum - b) * rd;
+    return __fmaf_rn(omega, gs, (1.0f - omega) * x);
+}
+
 // Neighbour sum and diagonal of row (i, j) of A, reading the other colour
 // (split index k of the cell, s = its position parity in the row).
 __device__ inline double rb_row(const Grid& g, const double* __restrict__ other, int i, int j, size_t k, int s,
@@ -430,7 +445,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
 //     same lane or in the adjacent lane (a cross-lane move; lanes 0 and 63
 //     read zero, the ghost value at a domain edge).
 // ---------------------------------------------------------------------------
-// Cross-lane moves of a double over the whole wave: lane l receives lane l-1
+// Cross-lane moves over the whole wave: lane l receives lane l-1
 // (from_lower_lane) or lane l+1 (from_upper_lane); the lane without a source
 // receives 0.
 template <int CTRL>
@@ -440,21 +455,73 @@ __device__ inline double dpp_move(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ inline double from_lower_lane(double v) { return dpp_move<0x138>(v); }  // wave_shr:1
-__device__ inline double from_upper_lane(double v) { return dpp_move<0x130>(v); }  // wave_shl:1
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <class T>
+__device__ inline T from_lower_lane(T v) { return dpp_move<0x138>(v); }  // wave_shr:1
+template <class T>
+__device__ inline T from_upper_lane(T v) { return dpp_move<0x130>(v); }  // wave_shl:1
 
 constexpr int kTrSlots = 2 * kTbWaves + 2;  // edge rows: zero, (first, last) per wave, zero
 
+// The helpers below take the position parity P of the strip's first row as a
+// template argument (the kernels use even tile heights, so P = 0): every index
+// into the thread's small arrays is then a constant and the arrays stay in
+// registers.
+
+// 1/d of the thread's cells: colour c of row r sits at position parity
+// (P + r + c) & 1; rows or lanes without cells get 0.
+template <int P, class T>
+__device__ inline void tbr_rdiag(T (&rd)[2][kTbRows], const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
+                                 const T (&cD)[2], const T (&rdy)[kTbRows], const T (&rpn)[kTbRows],
+                                 const T (&rps)[kTbRows], int nlive, bool col) {
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int q = (P + r + c) & 1;
+            const T d = rb_diag(rdy[r] * cE[q], rdy[r] * cD[q], rdy[r] * cW[q], cdx[q] * rpn[r], cdx[q] * rps[r]);
+            rd[c][r] = (col && r < nlive) ? T(1) / d : T(0);
+        }
+    }
+}
+
+// Pins the values of a thread's per-cell array in registers at this point, so
+// that their computation is not sunk past the barrier that follows (it then
+// overlaps the latency of the tile's loads).
+template <class T>
+__device__ inline void tbr_pin(T (&v)[2][kTbRows]) {
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) asm volatile("" : "+v"(v[0][r]), "+v"(v[1][r]));
+}
+
+// Stores the interior cells of v (colour 0 to o0, colour 1 to o1); row r of
+// the strip is at split index kg0 + r nh.
+template <int P, class T, class U>
+__device__ inline void tbr_store(const T (&v)[2][kTbRows], U* __restrict__ o0, U* __restrict__ o1, size_t kg0,
+                                 size_t nh, const int (&dq)[2], const int (&rdist)[kTbRows]) {
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        if (rdist[r] != 0) continue;  // rows of the interior only
+        const int s0 = (P + r) & 1;   // position parity of the colour-0 cell
+        if (dq[s0] == 0) o0[kg0 + r * nh] = v[0][r];
+        if (dq[s0 ^ 1] == 0) o1[kg0 + r * nh] = v[1][r];
+    }
+}
+
 // Sum of the neighbours of the colour-C cell of row r (position parity
 // s = (P + r + C) & 1) in the thread's registers; xS0 / xNR are the other
-// colour's rows below the strip and above it.
-template <int C, int P, int R>
-__device__ inline double tbr_sum(const double (&x)[2][kTbRows], double xS0, double xNR, const double (&cdx)[2],
-                                 const double (&cE)[2], const double (&cW)[2], double dy, double pn, double ps) {
+// colour's rows below the strip and above it.  T = double, or float for the
+// single-precision sweeps of the mixed-precision solve.
+template <int C, int P, int R, class T>
+__device__ inline T tbr_sum(const T (&x)[2][kTbRows], T xS0, T xNR, const T (&cdx)[2], const T (&cE)[2],
+                            const T (&cW)[2], T dy, T pn, T ps) {
     constexpr int O = 1 - C;
     constexpr int s = (P + R + C) & 1;
-    const double xo = x[O][R];
-    double xE, xW;
+    const T xo = x[O][R];
+    T xE, xW;
     if (s) {
         xE = from_upper_lane(xo);
         xW = xo;
@@ -462,41 +529,98 @@ __device__ inline double tbr_sum(const double (&x)[2][kTbRows], double xS0, doub
         xE = xo;
         xW = from_lower_lane(xo);
     }
-    const double xN = (R + 1 < kTbRows) ? x[O][R + 1 < kTbRows ? R + 1 : R] : xNR;
-    const double xS = (R > 0) ? x[O][R > 0 ? R - 1 : 0] : xS0;
-    const double aE = dy * cE[s], aW = dy * cW[s];
-    const double aN = cdx[s] * pn, aS = cdx[s] * ps;
+    const T xN = (R + 1 < kTbRows) ? x[O][R + 1 < kTbRows ? R + 1 : R] : xNR;
+    const T xS = (R > 0) ? x[O][R > 0 ? R - 1 : 0] : xS0;
+    const T aE = dy * cE[s], aW = dy * cW[s];
+    const T aN = cdx[s] * pn, aS = cdx[s] * ps;
     return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
 
-template <int C, int P, int R>
-__device__ inline void tbr_row(double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
-                               const double (&rd)[2][kTbRows], double xS0, double xNR, const double (&cdx)[2],
-                               const double (&cE)[2], const double (&cW)[2], const int (&dq)[2],
-                               const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
-                               const double (&rps)[kTbRows], const int (&rdist)[kTbRows], int e, double omega) {
+template <int C, int P, int R, class T>
+__device__ inline void tbr_row(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows], T xS0,
+                               T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2], const int (&dq)[2],
+                               const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
+                               const int (&rdist)[kTbRows], int e, T omega) {
     if (rdist[R] > e) return;  // wave-uniform
     constexpr int s = (P + R + C) & 1;
-    const double sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
-    const double xn = sor_update(x[C][R], sum, b[C][R], rd[C][R], omega);
+    const T sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
+    const T xn = sor_update(x[C][R], sum, b[C][R], rd[C][R], omega);
     x[C][R] = dq[s] <= e ? xn : x[C][R];
 }
 
-template <int C, int P>
-__device__ inline void tbr_half(double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
-                                const double (&rd)[2][kTbRows], double xS0, double xNR, double (&cdx)[2],
-                                double (&cE)[2], double (&cW)[2], const int (&dq)[2],
-                                const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
-                                const double (&rps)[kTbRows], const int (&rdist)[kTbRows], int e, double omega) {
+template <int C, int P, class T>
+__device__ inline void tbr_half(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows], T xS0,
+                                T xNR, T (&cdx)[2], T (&cE)[2], T (&cW)[2], const int (&dq)[2],
+                                const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
+                                const int (&rdist)[kTbRows], int e, T omega) {
     static_assert(kTbRows == 4, "rows of a strip are unrolled by hand");
     // Keep the east/west coefficient products inside the sweep loop: all
     // four products hoisted out of it would need 64 more registers per
-    // thread; the north/south ones (32 registers) may be hoisted.
+    // thread in double precision; the north/south ones may be hoisted.
     asm volatile("" : "+v"(cE[0]), "+v"(cE[1]), "+v"(cW[0]), "+v"(cW[1]));
     tbr_row<C, P, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
     tbr_row<C, P, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
     tbr_row<C, P, 2>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
     tbr_row<C, P, 3>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+}
+
+// S red-black iterations on the thread's registers with the shrinking update
+// region (e = 2 S - h + extra at half-sweep h), exchanging the strip-end rows
+// through `edge` after each half-sweep.  On entry `edge` holds both colours.
+template <int P, class T>
+__device__ inline void tbr_sweeps(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows],
+                                  T (&cdx)[2], T (&cE)[2], T (&cW)[2], const int (&dq)[2], const T (&rdy)[kTbRows],
+                                  const T (&rpn)[kTbRows], const T (&rps)[kTbRows], const int (&rdist)[kTbRows],
+                                  T (&edge)[2][kTrSlots][kWave], int w, int lane, int nsweep, int extra, T omega) {
+    for (int it = 0; it < nsweep; ++it) {
+        {   // red half-sweep h = 2 it + 1: cells within e of the interior
+            const int e = 2 * nsweep - (2 * it + 1) + extra;
+            const T xS0 = edge[1][2 * w][lane], xNR = edge[1][2 * w + 3][lane];
+            tbr_half<0, P>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            edge[0][2 * w + 1][lane] = x[0][0];
+            edge[0][2 * w + 2][lane] = x[0][kTbRows - 1];
+            __syncthreads();
+        }
+        {   // black half-sweep h = 2 it + 2
+            const int e = 2 * nsweep - (2 * it + 2) + extra;
+            const T xS0 = edge[0][2 * w][lane], xNR = edge[0][2 * w + 3][lane];
+            tbr_half<1, P>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            edge[1][2 * w + 1][lane] = x[1][0];
+            edge[1][2 * w + 2][lane] = x[1][kTbRows - 1];
+            __syncthreads();
+        }
+    }
+}
+
+// Writes both colours' strip-end rows (and, from wave 0, the zero slots).
+template <class T>
+__device__ inline void tbr_edges(const T (&x)[2][kTbRows], T (&edge)[2][kTrSlots][kWave], int w, int lane) {
+    if (w == 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            edge[c][0][lane] = T(0);
+            edge[c][kTrSlots - 1][lane] = T(0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        edge[c][2 * w + 1][lane] = x[c][0];
+        edge[c][2 * w + 2][lane] = x[c][kTbRows - 1];
+    }
+}
+
+// Residual b - (sum - d x) of the colour-C cell of row R, with d from the
+// lane's coefficients.
+template <int C, int P, int R>
+__device__ inline double tbr_rvalue(const double (&x)[2][kTbRows], double bv, double xS0, double xNR,
+                                    const double (&cdx)[2], const double (&cE)[2], const double (&cW)[2],
+                                    const double (&cD)[2], const double (&rdy)[kTbRows],
+                                    const double (&rpn)[kTbRows], const double (&rps)[kTbRows]) {
+    constexpr int s = (P + R + C) & 1;
+    const double sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
+    const double dy = rdy[R];
+    const double d = rb_diag(dy * cE[s], dy * cD[s], dy * cW[s], cdx[s] * rpn[R], cdx[s] * rps[R]);
+    return bv - (sum - d * x[C][R]);
 }
 
 // Residual contribution of the colour-C cell of row R (interior cells only).
@@ -508,12 +632,9 @@ __device__ inline void tbr_resid(const double (&x)[2][kTbRows], const double (&b
                                  const int (&rdist)[kTbRows], double (&acc)[2]) {
     if (rdist[R] != 0) return;
     constexpr int s = (P + R + C) & 1;
-    const double sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
+    const double rres = tbr_rvalue<C, P, R>(x, b[C][R], xS0, xNR, cdx, cE, cW, cD, rdy, rpn, rps);
     if (dq[s] != 0) return;
-    const double dy = rdy[R];
-    const double d = rb_diag(dy * cE[s], dy * cD[s], dy * cW[s], cdx[s] * rpn[R], cdx[s] * rps[R]);
     const double bb = b[C][R];
-    const double rres = bb - (sum - d * x[C][R]);
     acc[0] += rres * rres;
     acc[1] += bb * bb;
 }
@@ -558,7 +679,9 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave index, uniform
     const bool col = lane < lxh;
     const int jw = kTbRows * w;       // first tile row of the wave's strip
-    const int P = (ya + jw) & 1;      // position parity of colour C in row r: (P + r + C) & 1
+    // position parity of colour C in row r of the strip: (P + r + C) & 1; the
+    // tile height is even, so the strip's first row ya + 4 w is even
+    constexpr int P = 0;
 
     // x coefficients and distance from the interior of the lane's two cells,
     // by position parity q (cell i = ic + q)
@@ -594,72 +717,224 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
             x[1][r] = black[kg];
             b[0][r] = bred[kg];
             b[1][r] = bblack[kg];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int q = (P + r + c) & 1;
-                const double d = rb_diag(rdy[r] * cE[q], rdy[r] * cD[q], rdy[r] * cW[q], cdx[q] * rpn[r],
-                                         cdx[q] * rps[r]);
-                rd[c][r] = 1.0 / d;
-            }
         }
     }
+    const int nlive = min(kTbRows, ly - jw);
+    tbr_rdiag<P>(rd, cdx, cE, cW, cD, rdy, rpn, rps, nlive, col);
+    tbr_pin(rd);
     // The stop test comes after the tile's loads are issued, so that its
     // latency overlaps theirs (a finished solve only wastes the loads).
     if (tb_begin(ctl, chk, lds, &s_flag)) return;
     // edge rows of both colours; slots 0 and kTrSlots-1 stay zero
-    if (w == 0) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            edge[c][0][lane] = 0.0;
-            edge[c][kTrSlots - 1][lane] = 0.0;
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        edge[c][2 * w + 1][lane] = x[c][0];
-        edge[c][2 * w + 2][lane] = x[c][kTbRows - 1];
-    }
+    tbr_edges(x, edge, w, lane);
     __syncthreads();
-
-    const int extra = residual ? 1 : 0;
-    for (int it = 0; it < nsweep; ++it) {
-        {   // red half-sweep h = 2 it + 1: cells within e of the interior
-            const int e = 2 * nsweep - (2 * it + 1) + extra;
-            const double xS0 = edge[1][2 * w][lane], xNR = edge[1][2 * w + 3][lane];
-            if (P) tbr_half<0, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-            else tbr_half<0, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-            edge[0][2 * w + 1][lane] = x[0][0];
-            edge[0][2 * w + 2][lane] = x[0][kTbRows - 1];
-            __syncthreads();
-        }
-        {   // black half-sweep h = 2 it + 2
-            const int e = 2 * nsweep - (2 * it + 2) + extra;
-            const double xS0 = edge[0][2 * w][lane], xNR = edge[0][2 * w + 3][lane];
-            if (P) tbr_half<1, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-            else tbr_half<1, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-            edge[1][2 * w + 1][lane] = x[1][0];
-            edge[1][2 * w + 2][lane] = x[1][kTbRows - 1];
-            __syncthreads();
-        }
-    }
+    tbr_sweeps<P>(x, b, rd, cdx, cE, cW, dq, rdy, rpn, rps, rdist, edge, w, lane, nsweep, residual ? 1 : 0, omega);
 
     // interior back to global memory (both colours), and its residual
-#pragma unroll
-    for (int r = 0; r < kTbRows; ++r) {
-        if (rdist[r] != 0) continue;  // rows of the interior only
-        const size_t kg = (size_t)(ya + jw + r) * g.nh + m0 + lane;
-        const int s0 = (P + r) & 1;   // position parity of the red cell
-        if (dq[s0] == 0) ored[kg] = x[0][r];
-        if (dq[s0 ^ 1] == 0) oblack[kg] = x[1][r];
-    }
+    const size_t kg0 = (size_t)(ya + jw) * g.nh + m0 + lane;
+    tbr_store<P>(x, ored, oblack, kg0, (size_t)g.nh, dq, rdist);
     if (residual) {
         double acc[2] = {0.0, 0.0};
         const double xS0[2] = {edge[0][2 * w][lane], edge[1][2 * w][lane]};
         const double xNR[2] = {edge[0][2 * w + 3][lane], edge[1][2 * w + 3][lane]};
-        if (P) tbr_residual<1>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-        else tbr_residual<0>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+        tbr_residual<P>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
         block_partials(acc, partials, nt, t, lds);
     }
+    tb_end(ctl, chk);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision red-black SOR (single-precision sweeps on the correction
+// equation, double-precision refinement), on the register-resident tiles of
+// k_sor_tbr.  A check interval of K iterations solves A e = r32 from e = 0
+// (e_zero on its first launch) in single precision, where r32 is the float
+// rounding of the double residual at the interval's start.  Its last launch
+// (refine) then forms, for the tile interior,
+//   x = phi + e   (double; written to the other phi pair),
+//   r = V b - A x (double; summed into the stop-test partials, and rounded to
+//                  float as the next interval's r32, into the other r32 pair),
+// which needs e one ring beyond the interior: that launch keeps the extra
+// ring exact, as the fused residual of k_sor_tbr does.  A launch with
+// nsweep = 0 and e_zero refines phi itself (the residual of the initial
+// guess).  SOR is a stationary iteration, so these iterates equal the
+// double-precision ones up to rounding relative to the correction.  The
+// single-precision coefficients are products of the float-rounded 1-D arrays,
+// and 1/d a float division.
+// ---------------------------------------------------------------------------
+// Residual of the colour-C cell of row R of x (rows of the interior): rounded
+// to float into r32, and (interior cells) its square and (V b)^2 added to acc.
+template <int C, int P, int R>
+__device__ inline void tbr_refine_cell(const double (&x)[2][kTbRows], const double* __restrict__ vb, size_t k,
+                                       bool live, double xS0, double xNR, const double (&cdx)[2],
+                                       const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
+                                       const int (&dq)[2], const double (&rdy)[kTbRows],
+                                       const double (&rpn)[kTbRows], const double (&rps)[kTbRows],
+                                       const int (&rdist)[kTbRows], float (&r32)[2][kTbRows], double (&acc)[2]) {
+    if (rdist[R] != 0) return;  // interior rows only (wave-uniform)
+    constexpr int s = (P + R + C) & 1;
+    const double bv = live ? vb[k] : 0.0;
+    const double rres = tbr_rvalue<C, P, R>(x, bv, xS0, xNR, cdx, cE, cW, cD, rdy, rpn, rps);
+    r32[C][R] = (float)rres;
+    if (rdist[R] == 0 && dq[s] == 0) {
+        acc[0] += rres * rres;
+        acc[1] += bv * bv;
+    }
+}
+
+template <int P>
+__device__ inline void tbr_refine(const double (&x)[2][kTbRows], const double* __restrict__ vbr,
+                                  const double* __restrict__ vbb, const size_t (&rowk)[kTbRows], int nlive, bool col,
+                                  const double (&xS0)[2], const double (&xNR)[2], const double (&cdx)[2],
+                                  const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
+                                  const int (&dq)[2], const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
+                                  const double (&rps)[kTbRows], const int (&rdist)[kTbRows],
+                                  float (&r32)[2][kTbRows], double (&acc)[2]) {
+    // colour 0 reads the black rows beyond the strip, colour 1 the red ones;
+    // row r of the strip holds cells only if r < nlive
+#define IBM_REFINE_ROW(R)                                                                                     \
+    tbr_refine_cell<0, P, R>(x, vbr, rowk[R], col && R < nlive, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn,    \
+                             rps, rdist, r32, acc);                                                           \
+    tbr_refine_cell<1, P, R>(x, vbb, rowk[R], col && R < nlive, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn,    \
+                             rps, rdist, r32, acc);
+    IBM_REFINE_ROW(0)
+    IBM_REFINE_ROW(1)
+    IBM_REFINE_ROW(2)
+    IBM_REFINE_ROW(3)
+#undef IBM_REFINE_ROW
+}
+
+struct MpArrays {
+    const double *phr, *phb;  // phi in
+    double *ophr, *ophb;      // phi out (refine)
+    const float *er, *eb;     // e in (unless e_zero)
+    float *oer, *oeb;         // e out (unless refine)
+    const double *vbr, *vbb;  // V b
+    const float *rr, *rb;     // r32 in (nsweep > 0)
+    float *orr, *orb;         // r32 out (refine)
+};
+
+__global__ __launch_bounds__(kTbThreads) void k_sor_mp(Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk,
+                                                       TbShape ts, int nsweep, int e_zero, int refine,
+                                                       double* __restrict__ partials) {
+    __shared__ float edge32[2][kTrSlots][kWave];
+    __shared__ double edge64[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
+    const int nt = ts.ntx * ts.nty;
+    const int t = tb_tile(ts);
+    if (t >= nt) return;
+    const int txi = t % ts.ntx, tyi = t / ts.ntx;
+    const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
+    const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
+    const int H = ts.halo;
+    const int xa = max(0, X0 - H), xb = min(g.nx, X1 + H);
+    const int ya = max(0, Y0 - H), yb = min(g.ny, Y1 + H);
+    const int lxh = (xb - xa) >> 1, ly = yb - ya;
+    const int m0 = xa >> 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave index, uniform
+    const bool col = lane < lxh;
+    const int jw = kTbRows * w;
+    constexpr int P = 0;  // even tile height: the strip starts on an even row
+    const int ic = 2 * (m0 + lane);
+    const int ii0 = col ? ic : 0, ii1 = col ? ic + 1 : 0;
+    // split index of the lane's cells in row r of the strip, clamped to the
+    // grid so that no address leaves the arrays (accesses outside the tile are
+    // predicated off)
+    const size_t mcl = (size_t)min(m0 + lane, g.nh - 1);
+    size_t rowk[kTbRows];  // row offsets (wave-uniform) plus the lane's column
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const size_t row = (size_t)__builtin_amdgcn_readfirstlane(min(ya + jw + r, g.ny - 1)) * g.nh;
+        rowk[r] = row + mcl;
+    }
+
+    int dq[2];  // distance of the lane's cells i = ic + q from the interior
+#pragma unroll
+    for (int q = 0; q < 2; ++q) dq[q] = col ? max(max(X0 - (ic + q), (ic + q) - (X1 - 1)), 0) : (1 << 20);
+    int rdist[kTbRows];
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = jw + r;
+        rdist[r] = jl < ly ? max(max(Y0 - (ya + jl), (ya + jl) - (Y1 - 1)), 0) : (1 << 20);
+    }
+    // single-precision state and operator
+    float e[2][kTbRows], b32[2][kTbRows], rd[2][kTbRows];
+    float fdx[2] = {(float)g.dx[ii0], (float)g.dx[ii1]};
+    float fE[2] = {(float)g.pcE[ii0], (float)g.pcE[ii1]};
+    float fW[2] = {(float)g.pcW[ii0], (float)g.pcW[ii1]};
+    const float fD[2] = {(float)g.pcD[ii0], (float)g.pcD[ii1]};
+    float fdy[kTbRows], fpn[kTbRows], fps[kTbRows];
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = jw + r;
+        const int j = min(ya + jl, g.ny - 1);
+        const bool live = jl < ly && col;
+        fdy[r] = (float)g.dy[j];
+        fpn[r] = (float)g.pcN[j];
+        fps[r] = (float)g.pcS[j];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) e[c][r] = b32[c][r] = 0.0f;
+        if (live) {
+            const size_t k = rowk[r];
+            if (!e_zero) {
+                e[0][r] = a.er[k];
+                e[1][r] = a.eb[k];
+            }
+            if (nsweep > 0) {
+                b32[0][r] = a.rr[k];
+                b32[1][r] = a.rb[k];
+            }
+        }
+    }
+    const int nlive = min(kTbRows, ly - jw);
+    tbr_rdiag<P>(rd, fdx, fE, fW, fD, fdy, fpn, fps, nlive, col);
+    tbr_pin(rd);
+    if (tb_begin(ctl, chk, lds, &s_flag)) return;
+    if (nsweep > 0) {
+        tbr_edges(e, edge32, w, lane);
+        __syncthreads();
+        tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, refine ? 1 : 0,
+                      (float)omega);
+    }
+    const size_t kg0 = rowk[0];  // rows of the interior lie inside the grid: rowk[r] = kg0 + r nh there
+    if (!refine) {
+        tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
+        tb_end(ctl, chk);
+        return;
+    }
+
+    // refinement in double precision
+    const double cdx[2] = {g.dx[ii0], g.dx[ii1]}, cE[2] = {g.pcE[ii0], g.pcE[ii1]};
+    const double cW[2] = {g.pcW[ii0], g.pcW[ii1]}, cD[2] = {g.pcD[ii0], g.pcD[ii1]};
+    double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
+    double x[2][kTbRows];
+#pragma unroll
+    for (int r = 0; r < kTbRows; ++r) {
+        const int jl = jw + r;
+        const int j = min(ya + jl, g.ny - 1);
+        rdy[r] = g.dy[j];
+        rpn[r] = g.pcN[j];
+        rps[r] = g.pcS[j];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) x[c][r] = 0.0;
+        // the residual of the interior needs x on the interior and one ring
+        if (rdist[r] <= 1 && col) {
+            const size_t k = rowk[r];
+            const int q = (P + r) & 1;  // position parity of the colour-0 cell
+            if (dq[q] <= 1) x[0][r] = a.phr[k] + (double)e[0][r];
+            if (dq[q ^ 1] <= 1) x[1][r] = a.phb[k] + (double)e[1][r];
+        }
+    }
+    tbr_edges(x, edge64, w, lane);
+    __syncthreads();
+    const double xS0[2] = {edge64[0][2 * w][lane], edge64[1][2 * w][lane]};
+    const double xNR[2] = {edge64[0][2 * w + 3][lane], edge64[1][2 * w + 3][lane]};
+    double acc[2] = {0.0, 0.0};
+    tbr_refine<P>(x, a.vbr, a.vbb, rowk, nlive, col, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, b32, acc);
+    tbr_store<P>(x, a.ophr, a.ophb, kg0, (size_t)g.nh, dq, rdist);
+    tbr_store<P>(b32, a.orr, a.orb, kg0, (size_t)g.nh, dq, rdist);
+    block_partials(acc, partials, nt, t, lds);
     tb_end(ctl, chk);
 }
 

@@ -32,6 +32,8 @@ namespace {
 
 constexpr int kSlots = 256;       // host-mapped check slots (ring)
 constexpr int kAheadSor = 24;     // SOR chunks in flight before the host waits
+constexpr int kFoldMax = 512;     // blocked launches carry the stop test up to this many tiles (every
+                                  // block reads all tile partials); beyond it a k_check runs instead
 constexpr int kAheadHelm = 3;     // implicit velocity iterations in flight
 constexpr int kAheadPcg = 48;     // PCG iterations in flight
 constexpr int kMaxSamples = 8192; // event pairs kept per timed kernel
@@ -54,7 +56,7 @@ struct Layout {
 
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
-    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2;
+    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2, mpf;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -86,6 +88,7 @@ Offsets layout_for(int nx, int ny) {
     o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
     o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
     o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
+    o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
     // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
@@ -116,7 +119,8 @@ const char* validate(const ibm_params* P, const double* xf, const double* yf) {
     if (P->bc_mode != IBM_BC_CHANNEL) return "only IBM_BC_CHANNEL is supported";
     if (P->precision != IBM_PREC_FP64 || P->reserved != 0) return "unsupported precision";
     if (!(P->dt > 0.0) || !(P->re > 0.0) || !std::isfinite(P->u_inf)) return "dt and re must be > 0";
-    if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG) return "unknown p_method";
+    if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG && P->p_method != IBM_SOLVER_RBSOR_MP)
+        return "unknown p_method";
     if (!(P->p_omega > 0.0 && P->p_omega < 2.0) || !(P->uv_omega > 0.0 && P->uv_omega < 2.0))
         return "relaxation factors must lie in (0, 2)";
     if (P->p_max_iter < 1 || P->p_check_every < 1 || P->uv_max_iter < 1) return "iteration limits must be >= 1";
@@ -157,6 +161,7 @@ struct ibm_ctx {
     double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pp2, *pq, *phr, *phb, *vbr, *vbb;
     double *pz, *dn;    // PCG: z = r / diag(M), and diag(M) (natural layout)
     double *phr2, *phb2;  // second pair of split phi arrays (blocked sweeps alternate)
+    float* mpf;           // mixed-precision SOR: e pairs (4 NH), then r32 pairs (4 NH)
     double *f_u, *f_v, *coef, *partials;
     Ctl* ctl;
     int *list_u, *list_v, *counts;
@@ -333,7 +338,7 @@ inline int red_blocks(size_t n) {
 // when the loaded tile would not fit the LDS budget or the per-thread
 // position registers.
 bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts) {
-    if (S < 1 || S > 8 || tx < 2 || (tx & 1) || ty < 1) return false;
+    if (S < 1 || S > 8 || tx < 2 || (tx & 1) || ty < 2 || (ty & 1)) return false;
     const int H = 2 * S + 2;
     const int lx = std::min(c->nx, tx + 2 * H), ly = std::min(c->ny, ty + 2 * H);
     // one lane per split column, kTbRows rows per wave
@@ -436,10 +441,15 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                     ++nlaunch;
                     it += n;
                     if (resid) {
-                        carry.partials = part;
-                        carry.nb = ntiles;
-                        carry.it = it;
-                        carry_nl = nlaunch;
+                        if (ntiles <= kFoldMax) {
+                            carry.partials = part;
+                            carry.nb = ntiles;
+                            carry.it = it;
+                            carry_nl = nlaunch;
+                        } else {
+                            rc = check(1, it, ntiles, part, nlaunch);
+                            if (rc) return rc;
+                        }
                     }
                 } else {
                     const int itk = it + 1;
@@ -491,6 +501,157 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
         if (it >= max_e && pending.empty()) break;  // max_e == 0: only the first check
     }
     if (done_launches & 1) {  // the result is in the second pair
+        std::swap(c->phr, c->phr2);
+        std::swap(c->phb, c->phb2);
+    }
+    out->status = sn.status;
+    out->iters = sn.iters;
+    out->rn = sn.rn;
+    prune_samples(c, sn.iters);
+    return IBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision red-black SOR on A x = vb (split storage): k_sor_mp
+// launches.  A refining launch without sweeps forms the residual of the
+// initial phi (tested by a k_check, phase 0); each check interval then runs
+// its sweeps on the correction from e = 0 and refines phi at its end; the
+// first launch of the next interval tests that refinement (the last one, a
+// k_check).  phi pairs alternate per refinement, e pairs per launch and r32
+// pairs per refinement; the pair that holds the result follows from the
+// number of refinements enqueued before the finishing test.  On return
+// phr/phb hold the result.
+// ---------------------------------------------------------------------------
+int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
+    Ctl* ctl = c->ctl + CTL_P;
+    const dim3 bl(kBlock);
+    const bool fixed_mode = fixed >= 0;
+    const double tol_e = fixed_mode ? -1.0 : tol;
+    const int max_e = fixed_mode ? fixed : max_iter;
+    TbShape ts;
+    if (!tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts)) {
+        c->err = "the blocked-sweep tile shape does not fit this grid";
+        return IBM_ERR_INVALID;
+    }
+    const int S = c->tb_sweeps;
+    const int ntiles = ts.ntx * ts.nty;
+    const int tb_blocks = 8 * ts.per;
+    const size_t NH = (size_t)c->nh * c->ny;
+    double* part[2] = {c->partials, c->partials + 2 * (size_t)ntiles};
+    double* cur[2] = {c->phr, c->phb};
+    double* alt[2] = {c->phr2, c->phb2};
+    float* ecur[2] = {c->mpf, c->mpf + NH};
+    float* ealt[2] = {c->mpf + 2 * NH, c->mpf + 3 * NH};
+    float* rcur[2] = {c->mpf + 4 * NH, c->mpf + 5 * NH};
+    float* ralt[2] = {c->mpf + 6 * NH, c->mpf + 7 * NH};
+    int32_t rc = reset_ctl(c, CTL_P);
+    if (rc) return rc;
+    ++c->solve_id;
+    std::deque<std::pair<int, long>> pending;  // (slot, refinements before the test)
+    long nref = 0;
+    TbCheck carry = {nullptr, 0, 0, max_e, (int)fixed_mode, tol_e, nullptr};
+    long carry_nl = 0;
+    auto check = [&](int phase, int it, const double* prt, long nl) -> int32_t {
+        const int s = next_slot(c);
+        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, prt, ntiles, phase, it, max_e, tol_e,
+                           (int)fixed_mode, 0, c->dslots + s);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+        pending.emplace_back(s, nl);
+        return IBM_OK;
+    };
+    // one k_sor_mp launch; refine: phi + e into the other phi pair, r32 into
+    // the other r32 pair, residual partials
+    auto launch = [&](int n, int e_zero, int refine, int kid, int it_after) -> int32_t {
+        TbCheck chk = carry;
+        int cs = -1;
+        if (chk.nb > 0) {
+            cs = next_slot(c);
+            chk.slot = c->dslots + cs;
+        }
+        MpArrays a;
+        a.phr = cur[0]; a.phb = cur[1]; a.ophr = alt[0]; a.ophb = alt[1];
+        a.er = ecur[0]; a.eb = ecur[1]; a.oer = ealt[0]; a.oeb = ealt[1];
+        a.vbr = c->vbr; a.vbb = c->vbb;
+        a.rr = rcur[0]; a.rb = rcur[1]; a.orr = ralt[0]; a.orb = ralt[1];
+        double* prt = part[nref & 1];
+        auto go = [&](hipEvent_t ea, hipEvent_t eb) {
+            LAUNCH_EV(ea, eb, k_sor_mp, dim3(tb_blocks), dim3(kTbThreads), 0, c->g, a, omega, ctl, chk, ts, n, e_zero,
+                      refine, prt);
+        };
+        if (kid >= 0 && n == S) timed(c, kid, it_after, go);
+        else go(nullptr, nullptr);
+        LAUNCH_CHECK();
+        if (cs >= 0) {
+            HIP_TRY(hipEventRecord(c->ev[cs], c->stream));
+            pending.emplace_back(cs, carry_nl);
+            carry.nb = 0;
+        }
+        if (refine) {
+            std::swap(cur, alt);
+            std::swap(rcur, ralt);
+            ++nref;
+            carry.partials = prt;
+            carry.nb = ntiles;
+            carry.it = it_after;
+            carry_nl = nref;
+            if (ntiles > kFoldMax && it_after > 0) {  // test it now (the first one is phase 0)
+                carry.nb = 0;
+                return check(1, it_after, prt, nref);
+            }
+        } else {
+            std::swap(ecur, ealt);
+        }
+        return IBM_OK;
+    };
+    // residual of the initial guess (phase-0 test)
+    rc = launch(0, 1, 1, -1, 0);
+    if (rc) return rc;
+    carry.nb = 0;
+    rc = check(0, 0, part[0], nref);
+    if (rc) return rc;
+    Slot sn;
+    bool first = true;
+    int it = 0;
+    long done_refs = 0;
+    for (;;) {
+        if (it < max_e) {
+            const int next = std::min(it + K, max_e);
+            bool start = true;
+            while (it < next) {
+                const int n = std::min(S, next - it);
+                const int last = (it + n == next) ? 1 : 0;
+                rc = launch(n, start ? 1 : 0, last, last ? IBM_KERNEL_SOR_MP_REFINE : IBM_KERNEL_SOR_MP, it + n);
+                if (rc) return rc;
+                start = false;
+                it += n;
+            }
+            if ((int)pending.size() < kAheadSor && it < max_e) continue;
+        }
+        if (it >= max_e && carry.nb > 0) {  // the last refinement's test
+            rc = check(1, carry.it, carry.partials, carry_nl);
+            if (rc) return rc;
+            carry.nb = 0;
+        }
+        if (pending.empty()) {
+            c->err = "mixed-precision SOR loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int s = pending.front().first;
+        done_refs = pending.front().second;
+        pending.pop_front();
+        rc = wait_slot(c, s, &sn);
+        if (rc) return rc;
+        if (first) {
+            out->bn = sn.bn;
+            out->r0 = sn.r0;
+            out->zero_rhs = sn.zero_rhs;
+            first = false;
+        }
+        if (sn.done) break;
+        if (it >= max_e && pending.empty()) break;
+    }
+    if (done_refs & 1) {  // the result is in the second pair
         std::swap(c->phr, c->phr2);
         std::swap(c->phb, c->phb2);
     }
@@ -708,7 +869,9 @@ int32_t pressure_solve(ibm_ctx* c, int fixed, LoopOut* out) {
     hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
     hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
     LAUNCH_CHECK();
-    int32_t rc = sor_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out);
+    int32_t rc = P.p_method == IBM_SOLVER_RBSOR_MP
+                     ? mp_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out)
+                     : sor_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out);
     if (rc) return rc;
     if (out->zero_rhs) return fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
     hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb, c->phi);
@@ -952,6 +1115,7 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     c->phr = D(off.phr); c->phb = D(off.phb); c->vbr = D(off.vbr); c->vbb = D(off.vbb);
     c->pz = D(off.pz); c->dn = D(off.dn);
     c->phr2 = D(off.phr2); c->phb2 = D(off.phb2);
+    c->mpf = (float*)(w + off.mpf);
     c->f_u = D(off.f_u); c->f_v = D(off.f_v); c->coef = D(off.coef); c->partials = D(off.partials);
     c->ctl = (Ctl*)(w + off.ctl);
     c->list_u = (int*)(w + off.list_u); c->list_v = (int*)(w + off.list_v); c->counts = (int*)(w + off.counts);
@@ -1041,8 +1205,8 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
                           ibm_solve_stats* st) {
     if (!c) return IBM_ERR_INVALID;
     if (!rhs_dev || !x_dev || !o || o->max_iter < 1 || o->check_every < 1 || o->fixed_iters < 0 ||
-        (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG) ||
-        (o->method == IBM_SOLVER_RBSOR && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol)) {
+        (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG && o->method != IBM_SOLVER_RBSOR_MP) ||
+        (o->method != IBM_SOLVER_PCG && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol)) {
         c->err = "invalid solve options";
         return IBM_ERR_INVALID;
     }
@@ -1069,7 +1233,8 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
         hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)x_dev, c->phr, c->phb, 0);
         hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
         LAUNCH_CHECK();
-        rc = sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo);
+        rc = o->method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo)
+                                              : sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo);
         if (rc) return rc;
         if (lo.zero_rhs) {
             rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
@@ -1254,8 +1419,9 @@ int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* s
     }
     const size_t n = c->samples[kernel].size();
     const double cells = (double)c->nx * c->ny;
+    const double S = c->tb_sweeps;
     const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 64.0 * cells,
-                                            24.0 * cells * c->tb_sweeps};
+                                            24.0 * cells * S, 12.0 * cells * S, (12.0 * S + 32.0) * cells};
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (samples) *samples = (int64_t)n;
     if (launches) *launches = c->launches[kernel];

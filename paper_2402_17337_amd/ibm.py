@@ -20,14 +20,15 @@ LIB_PATH = os.path.join(HERE, "libibm_hip.so")
 
 OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, -5
 BC_CHANNEL = 0
-RBSOR, PCG = 0, 1
+RBSOR, PCG, RBSOR_MP = 0, 1, 2   # RBSOR_MP: float sweeps on the correction, double refinement
 INIT_ZERO, INIT_PREVIOUS = 0, 1
-KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB = range(5)
+(KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB, KERNEL_SOR_MP,
+ KERNEL_SOR_MP_REFINE) = range(7)
 # KERNEL_SOR_TB times whichever blocked sweep runs; named for the default one
 # (k_sor_tb is the LDS-tile variant).
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
-                KERNEL_SOR_TB: "k_sor_tbr"}
+                KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_sor_mp(refine)"}
 OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y = range(4)
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
