@@ -225,7 +225,7 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
 #define IBM_KERNEL_PCG_UPDATE 3     /* x, r, z = r/d: 64 B per cell (x, r, p, q, d in; x, r, z out) */
 #define IBM_KERNEL_SOR_TB 4         /* blocked SOR (either variant): 24 B per cell and iteration */
 #define IBM_KERNEL_SOR_MP 5         /* mixed-precision sweeps: 12 B per cell and iteration (float e, r) */
-#define IBM_KERNEL_SOR_MP_REFINE 6  /* the same plus the refinement: + 32 B per cell (phi, e, V b -> phi, r) */
+#define IBM_KERNEL_SOR_MP_REFINE 6  /* its refinement: 32 B per cell (phi, e, V b in; phi, r out) */
 #define IBM_KERNEL_COUNT 7
 int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
 int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,

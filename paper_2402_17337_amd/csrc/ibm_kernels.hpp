@@ -744,80 +744,29 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision red-black SOR (single-precision sweeps on the correction
-// equation, double-precision refinement), on the register-resident tiles of
-// k_sor_tbr.  A check interval of K iterations solves A e = r32 from e = 0
-// (e_zero on its first launch) in single precision, where r32 is the float
-// rounding of the double residual at the interval's start.  Its last launch
-// (refine) then forms, for the tile interior,
+// Mixed-precision red-black SOR: single-precision sweeps on the correction
+// equation, double-precision refinement.  A check interval of K iterations
+// solves A e = r32 from e = 0 (e_zero on its first launch) with k_sor_mp,
+// where r32 is the float rounding of the double residual at the interval's
+// start; then k_mp_refine forms
 //   x = phi + e   (double; written to the other phi pair),
 //   r = V b - A x (double; summed into the stop-test partials, and rounded to
-//                  float as the next interval's r32, into the other r32 pair),
-// which needs e one ring beyond the interior: that launch keeps the extra
-// ring exact, as the fused residual of k_sor_tbr does.  A launch with
-// nsweep = 0 and e_zero refines phi itself (the residual of the initial
-// guess).  SOR is a stationary iteration, so these iterates equal the
-// double-precision ones up to rounding relative to the correction.  The
-// single-precision coefficients are products of the float-rounded 1-D arrays,
-// and 1/d a float division.
+//                  float as the next interval's r32, into the other r32 pair).
+// SOR is a stationary iteration, so these iterates equal the double-precision
+// ones up to rounding relative to the correction.  The single-precision
+// coefficients are products of the float-rounded 1-D arrays, and 1/d a float
+// division.  The sweep kernel holds 8 waves per SIMD (two blocks per compute
+// unit), so that one block's loads overlap another's sweeps.
 // ---------------------------------------------------------------------------
-// Residual of the colour-C cell of row R of x (rows of the interior): rounded
-// to float into r32, and (interior cells) its square and (V b)^2 added to acc.
-template <int C, int P, int R>
-__device__ inline void tbr_refine_cell(const double (&x)[2][kTbRows], const double* __restrict__ vb, size_t k,
-                                       bool live, double xS0, double xNR, const double (&cdx)[2],
-                                       const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
-                                       const int (&dq)[2], const double (&rdy)[kTbRows],
-                                       const double (&rpn)[kTbRows], const double (&rps)[kTbRows],
-                                       const int (&rdist)[kTbRows], float (&r32)[2][kTbRows], double (&acc)[2]) {
-    if (rdist[R] != 0) return;  // interior rows only (wave-uniform)
-    constexpr int s = (P + R + C) & 1;
-    const double bv = live ? vb[k] : 0.0;
-    const double rres = tbr_rvalue<C, P, R>(x, bv, xS0, xNR, cdx, cE, cW, cD, rdy, rpn, rps);
-    r32[C][R] = (float)rres;
-    if (rdist[R] == 0 && dq[s] == 0) {
-        acc[0] += rres * rres;
-        acc[1] += bv * bv;
-    }
-}
-
-template <int P>
-__device__ inline void tbr_refine(const double (&x)[2][kTbRows], const double* __restrict__ vbr,
-                                  const double* __restrict__ vbb, const size_t (&rowk)[kTbRows], int nlive, bool col,
-                                  const double (&xS0)[2], const double (&xNR)[2], const double (&cdx)[2],
-                                  const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
-                                  const int (&dq)[2], const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
-                                  const double (&rps)[kTbRows], const int (&rdist)[kTbRows],
-                                  float (&r32)[2][kTbRows], double (&acc)[2]) {
-    // colour 0 reads the black rows beyond the strip, colour 1 the red ones;
-    // row r of the strip holds cells only if r < nlive
-#define IBM_REFINE_ROW(R)                                                                                     \
-    tbr_refine_cell<0, P, R>(x, vbr, rowk[R], col && R < nlive, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn,    \
-                             rps, rdist, r32, acc);                                                           \
-    tbr_refine_cell<1, P, R>(x, vbb, rowk[R], col && R < nlive, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn,    \
-                             rps, rdist, r32, acc);
-    IBM_REFINE_ROW(0)
-    IBM_REFINE_ROW(1)
-    IBM_REFINE_ROW(2)
-    IBM_REFINE_ROW(3)
-#undef IBM_REFINE_ROW
-}
-
 struct MpArrays {
-    const double *phr, *phb;  // phi in
-    double *ophr, *ophb;      // phi out (refine)
-    const float *er, *eb;     // e in (unless e_zero)
-    float *oer, *oeb;         // e out (unless refine)
-    const double *vbr, *vbb;  // V b
-    const float *rr, *rb;     // r32 in (nsweep > 0)
-    float *orr, *orb;         // r32 out (refine)
+    const float *er, *eb;  // e in (unless e_zero)
+    float *oer, *oeb;      // e out
+    const float *rr, *rb;  // r32 in
 };
 
-__global__ __launch_bounds__(kTbThreads) void k_sor_mp(Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk,
-                                                       TbShape ts, int nsweep, int e_zero, int refine,
-                                                       double* __restrict__ partials) {
+__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp(
+    Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk, TbShape ts, int nsweep, int e_zero) {
     __shared__ float edge32[2][kTrSlots][kWave];
-    __shared__ double edge64[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];
     __shared__ int s_flag;
     const int nt = ts.ntx * ts.nty;
@@ -838,27 +787,12 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_mp(Grid g, MpArrays a, doubl
     constexpr int P = 0;  // even tile height: the strip starts on an even row
     const int ic = 2 * (m0 + lane);
     const int ii0 = col ? ic : 0, ii1 = col ? ic + 1 : 0;
-    // split index of the lane's cells in row r of the strip, clamped to the
-    // grid so that no address leaves the arrays (accesses outside the tile are
-    // predicated off)
-    const size_t mcl = (size_t)min(m0 + lane, g.nh - 1);
-    size_t rowk[kTbRows];  // row offsets (wave-uniform) plus the lane's column
-#pragma unroll
-    for (int r = 0; r < kTbRows; ++r) {
-        const size_t row = (size_t)__builtin_amdgcn_readfirstlane(min(ya + jw + r, g.ny - 1)) * g.nh;
-        rowk[r] = row + mcl;
-    }
+    const size_t kg0 = (size_t)(ya + jw) * g.nh + m0 + lane;  // row r of the strip: kg0 + r nh
 
     int dq[2];  // distance of the lane's cells i = ic + q from the interior
 #pragma unroll
     for (int q = 0; q < 2; ++q) dq[q] = col ? max(max(X0 - (ic + q), (ic + q) - (X1 - 1)), 0) : (1 << 20);
     int rdist[kTbRows];
-#pragma unroll
-    for (int r = 0; r < kTbRows; ++r) {
-        const int jl = jw + r;
-        rdist[r] = jl < ly ? max(max(Y0 - (ya + jl), (ya + jl) - (Y1 - 1)), 0) : (1 << 20);
-    }
-    // single-precision state and operator
     float e[2][kTbRows], b32[2][kTbRows], rd[2][kTbRows];
     float fdx[2] = {(float)g.dx[ii0], (float)g.dx[ii1]};
     float fE[2] = {(float)g.pcE[ii0], (float)g.pcE[ii1]};
@@ -869,73 +803,86 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_mp(Grid g, MpArrays a, doubl
     for (int r = 0; r < kTbRows; ++r) {
         const int jl = jw + r;
         const int j = min(ya + jl, g.ny - 1);
-        const bool live = jl < ly && col;
+        rdist[r] = jl < ly ? max(max(Y0 - (ya + jl), (ya + jl) - (Y1 - 1)), 0) : (1 << 20);
         fdy[r] = (float)g.dy[j];
         fpn[r] = (float)g.pcN[j];
         fps[r] = (float)g.pcS[j];
 #pragma unroll
         for (int c = 0; c < 2; ++c) e[c][r] = b32[c][r] = 0.0f;
-        if (live) {
-            const size_t k = rowk[r];
+        if (jl < ly && col) {
+            const size_t k = kg0 + (size_t)r * g.nh;
             if (!e_zero) {
                 e[0][r] = a.er[k];
                 e[1][r] = a.eb[k];
             }
-            if (nsweep > 0) {
-                b32[0][r] = a.rr[k];
-                b32[1][r] = a.rb[k];
-            }
+            b32[0][r] = a.rr[k];
+            b32[1][r] = a.rb[k];
         }
     }
-    const int nlive = min(kTbRows, ly - jw);
-    tbr_rdiag<P>(rd, fdx, fE, fW, fD, fdy, fpn, fps, nlive, col);
+    tbr_rdiag<P>(rd, fdx, fE, fW, fD, fdy, fpn, fps, min(kTbRows, ly - jw), col);
     tbr_pin(rd);
     if (tb_begin(ctl, chk, lds, &s_flag)) return;
-    if (nsweep > 0) {
-        tbr_edges(e, edge32, w, lane);
-        __syncthreads();
-        tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, refine ? 1 : 0,
-                      (float)omega);
-    }
-    const size_t kg0 = rowk[0];  // rows of the interior lie inside the grid: rowk[r] = kg0 + r nh there
-    if (!refine) {
-        tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
-        tb_end(ctl, chk);
-        return;
-    }
+    tbr_edges(e, edge32, w, lane);
+    __syncthreads();
+    tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, 0, (float)omega);
+    tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
+    tb_end(ctl, chk);
+}
 
-    // refinement in double precision
-    const double cdx[2] = {g.dx[ii0], g.dx[ii1]}, cE[2] = {g.pcE[ii0], g.pcE[ii1]};
-    const double cW[2] = {g.pcW[ii0], g.pcW[ii1]}, cD[2] = {g.pcD[ii0], g.pcD[ii1]};
-    double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
-    double x[2][kTbRows];
+// Refinement of a mixed-precision interval: x = phi + e (e = 0 with e_zero)
+// into ophi, r = V b - A x rounded to float into or32; per-block partials of
+// r^2 and (V b)^2 in double.  Block b takes a contiguous range of rows (so the
+// rows above and below are mostly in its XCD's L2); the neighbours' x is
+// formed the same way where it is read.
+__device__ inline double mp_x(const double* __restrict__ ph, const float* __restrict__ e, size_t k, int e_zero) {
+    return e_zero ? ph[k] : ph[k] + (double)e[k];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
+                                                           const double* __restrict__ phb,
+                                                           const float* __restrict__ er,
+                                                           const float* __restrict__ eb, int e_zero,
+                                                           const double* __restrict__ vbr,
+                                                           const double* __restrict__ vbb,
+                                                           double* __restrict__ ophr, double* __restrict__ ophb,
+                                                           float* __restrict__ orr, float* __restrict__ orb,
+                                                           const Ctl* __restrict__ ctl, double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    if (ctl->done) return;
+    double acc[2] = {0.0, 0.0};
+    const int rows = (g.ny + gridDim.x - 1) / gridDim.x;
+    const int j0 = blockIdx.x * rows, j1 = min(g.ny, j0 + rows);
+    const int npos = (j1 - j0) * g.nh;  // split positions of the block's rows
+    for (int q = threadIdx.x; q < npos; q += blockDim.x) {
+        const int jr = q / g.nh, m = q - jr * g.nh;
+        const int j = j0 + jr;
+        const size_t k = (size_t)j * g.nh + m;
 #pragma unroll
-    for (int r = 0; r < kTbRows; ++r) {
-        const int jl = jw + r;
-        const int j = min(ya + jl, g.ny - 1);
-        rdy[r] = g.dy[j];
-        rpn[r] = g.pcN[j];
-        rps[r] = g.pcS[j];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) x[c][r] = 0.0;
-        // the residual of the interior needs x on the interior and one ring
-        if (rdist[r] <= 1 && col) {
-            const size_t k = rowk[r];
-            const int q = (P + r) & 1;  // position parity of the colour-0 cell
-            if (dq[q] <= 1) x[0][r] = a.phr[k] + (double)e[0][r];
-            if (dq[q ^ 1] <= 1) x[1][r] = a.phb[k] + (double)e[1][r];
+        for (int c = 0; c < 2; ++c) {
+            const double* ps = c ? phb : phr;
+            const double* po = c ? phr : phb;
+            const float* es = c ? eb : er;
+            const float* eo = c ? er : eb;
+            const int s = (j + c) & 1, i = 2 * m + s;
+            const double dyj = g.dy[j], dxi = g.dx[i];
+            const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+            const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+            const double x = mp_x(ps, es, k, e_zero);
+            const double xE = i < g.nx - 1 ? mp_x(po, eo, k + s, e_zero) : 0.0;
+            const double xW = i > 0 ? mp_x(po, eo, k + s - 1, e_zero) : 0.0;
+            const double xN = j < g.ny - 1 ? mp_x(po, eo, k + g.nh, e_zero) : 0.0;
+            const double xS = j > 0 ? mp_x(po, eo, k - g.nh, e_zero) : 0.0;
+            const double d = rb_diag(aE, aD, aW, aN, aS);
+            const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+            const double bv = (c ? vbb : vbr)[k];
+            const double r = bv - (sum - d * x);
+            (c ? ophb : ophr)[k] = x;
+            (c ? orb : orr)[k] = (float)r;
+            acc[0] += r * r;
+            acc[1] += bv * bv;
         }
     }
-    tbr_edges(x, edge64, w, lane);
-    __syncthreads();
-    const double xS0[2] = {edge64[0][2 * w][lane], edge64[1][2 * w][lane]};
-    const double xNR[2] = {edge64[0][2 * w + 3][lane], edge64[1][2 * w + 3][lane]};
-    double acc[2] = {0.0, 0.0};
-    tbr_refine<P>(x, a.vbr, a.vbb, rowk, nlive, col, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, b32, acc);
-    tbr_store<P>(x, a.ophr, a.ophb, kg0, (size_t)g.nh, dq, rdist);
-    tbr_store<P>(b32, a.orr, a.orb, kg0, (size_t)g.nh, dq, rdist);
-    block_partials(acc, partials, nt, t, lds);
-    tb_end(ctl, chk);
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -512,15 +512,14 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision red-black SOR on A x = vb (split storage): k_sor_mp
-// launches.  A refining launch without sweeps forms the residual of the
-// initial phi (tested by a k_check, phase 0); each check interval then runs
-// its sweeps on the correction from e = 0 and refines phi at its end; the
-// first launch of the next interval tests that refinement (the last one, a
-// k_check).  phi pairs alternate per refinement, e pairs per launch and r32
-// pairs per refinement; the pair that holds the result follows from the
-// number of refinements enqueued before the finishing test.  On return
-// phr/phb hold the result.
+// Mixed-precision red-black SOR on A x = vb (split storage).  A refinement
+// without a correction forms the residual of the initial phi (tested by a
+// k_check, phase 0); each check interval then runs k_sor_mp launches on the
+// correction from e = 0 and a k_mp_refine; the first launch of the next
+// interval tests that refinement (the last one, a k_check).  phi and r32
+// pairs alternate per refinement, e pairs per sweep launch; the phi pair that
+// holds the result follows from the number of refinements enqueued before the
+// finishing test.  On return phr/phb hold the result.
 // ---------------------------------------------------------------------------
 int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
@@ -534,10 +533,10 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
         return IBM_ERR_INVALID;
     }
     const int S = c->tb_sweeps;
-    const int ntiles = ts.ntx * ts.nty;
     const int tb_blocks = 8 * ts.per;
     const size_t NH = (size_t)c->nh * c->ny;
-    double* part[2] = {c->partials, c->partials + 2 * (size_t)ntiles};
+    const int nbr = red_blocks(NH);
+    double* part[2] = {c->partials, c->partials + 2 * (size_t)kRedMax};
     double* cur[2] = {c->phr, c->phb};
     double* alt[2] = {c->phr2, c->phb2};
     float* ecur[2] = {c->mpf, c->mpf + NH};
@@ -553,16 +552,34 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     long carry_nl = 0;
     auto check = [&](int phase, int it, const double* prt, long nl) -> int32_t {
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, prt, ntiles, phase, it, max_e, tol_e,
+        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, prt, nbr, phase, it, max_e, tol_e,
                            (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
         pending.emplace_back(s, nl);
         return IBM_OK;
     };
-    // one k_sor_mp launch; refine: phi + e into the other phi pair, r32 into
-    // the other r32 pair, residual partials
-    auto launch = [&](int n, int e_zero, int refine, int kid, int it_after) -> int32_t {
+    // phi + e and its residual into the other pairs
+    auto refine = [&](int e_zero, int it_after) -> int32_t {
+        double* prt = part[nref & 1];
+        timed(c, IBM_KERNEL_SOR_MP_REFINE, it_after, [&](hipEvent_t ea, hipEvent_t eb) {
+            LAUNCH_EV(ea, eb, k_mp_refine, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)cur[0],
+                      (const double*)cur[1], (const float*)ecur[0], (const float*)ecur[1], e_zero,
+                      (const double*)c->vbr, (const double*)c->vbb, alt[0], alt[1], ralt[0], ralt[1],
+                      (const Ctl*)ctl, prt);
+        });
+        LAUNCH_CHECK();
+        std::swap(cur, alt);
+        std::swap(rcur, ralt);
+        ++nref;
+        carry.partials = prt;
+        carry.nb = nbr;
+        carry.it = it_after;
+        carry_nl = nref;
+        return IBM_OK;
+    };
+    // one sweep launch (carrying the pending test, if any)
+    auto sweep = [&](int n, int e_zero, int it_after) -> int32_t {
         TbCheck chk = carry;
         int cs = -1;
         if (chk.nb > 0) {
@@ -570,16 +587,13 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
             chk.slot = c->dslots + cs;
         }
         MpArrays a;
-        a.phr = cur[0]; a.phb = cur[1]; a.ophr = alt[0]; a.ophb = alt[1];
         a.er = ecur[0]; a.eb = ecur[1]; a.oer = ealt[0]; a.oeb = ealt[1];
-        a.vbr = c->vbr; a.vbb = c->vbb;
-        a.rr = rcur[0]; a.rb = rcur[1]; a.orr = ralt[0]; a.orb = ralt[1];
-        double* prt = part[nref & 1];
+        a.rr = rcur[0]; a.rb = rcur[1];
         auto go = [&](hipEvent_t ea, hipEvent_t eb) {
-            LAUNCH_EV(ea, eb, k_sor_mp, dim3(tb_blocks), dim3(kTbThreads), 0, c->g, a, omega, ctl, chk, ts, n, e_zero,
-                      refine, prt);
+            LAUNCH_EV(ea, eb, k_sor_mp, dim3(tb_blocks), dim3(kTbThreads), 0, c->g, a, omega, ctl, chk, ts, n,
+                      e_zero);
         };
-        if (kid >= 0 && n == S) timed(c, kid, it_after, go);
+        if (n == S) timed(c, IBM_KERNEL_SOR_MP, it_after, go);
         else go(nullptr, nullptr);
         LAUNCH_CHECK();
         if (cs >= 0) {
@@ -587,25 +601,11 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
             pending.emplace_back(cs, carry_nl);
             carry.nb = 0;
         }
-        if (refine) {
-            std::swap(cur, alt);
-            std::swap(rcur, ralt);
-            ++nref;
-            carry.partials = prt;
-            carry.nb = ntiles;
-            carry.it = it_after;
-            carry_nl = nref;
-            if (ntiles > kFoldMax && it_after > 0) {  // test it now (the first one is phase 0)
-                carry.nb = 0;
-                return check(1, it_after, prt, nref);
-            }
-        } else {
-            std::swap(ecur, ealt);
-        }
+        std::swap(ecur, ealt);
         return IBM_OK;
     };
     // residual of the initial guess (phase-0 test)
-    rc = launch(0, 1, 1, -1, 0);
+    rc = refine(1, 0);
     if (rc) return rc;
     carry.nb = 0;
     rc = check(0, 0, part[0], nref);
@@ -620,12 +620,13 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
             bool start = true;
             while (it < next) {
                 const int n = std::min(S, next - it);
-                const int last = (it + n == next) ? 1 : 0;
-                rc = launch(n, start ? 1 : 0, last, last ? IBM_KERNEL_SOR_MP_REFINE : IBM_KERNEL_SOR_MP, it + n);
+                rc = sweep(n, start ? 1 : 0, it + n);
                 if (rc) return rc;
                 start = false;
                 it += n;
             }
+            rc = refine(0, it);
+            if (rc) return rc;
             if ((int)pending.size() < kAheadSor && it < max_e) continue;
         }
         if (it >= max_e && carry.nb > 0) {  // the last refinement's test
@@ -1421,7 +1422,7 @@ int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* s
     const double cells = (double)c->nx * c->ny;
     const double S = c->tb_sweeps;
     const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 64.0 * cells,
-                                            24.0 * cells * S, 12.0 * cells * S, (12.0 * S + 32.0) * cells};
+                                            24.0 * cells * S, 12.0 * cells * S, 32.0 * cells};
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (samples) *samples = (int64_t)n;
     if (launches) *launches = c->launches[kernel];

@@ -28,7 +28,7 @@ INIT_ZERO, INIT_PREVIOUS = 0, 1
 # (k_sor_tb is the LDS-tile variant).
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
-                KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_sor_mp(refine)"}
+                KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_mp_refine"}
 OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y = range(4)
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
