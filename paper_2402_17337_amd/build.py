@@ -8,9 +8,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libibm_hip.so")
-SOURCES = [os.path.join(CSRC, "ibm_lib.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("ibm_device.hpp", "ibm_kernels.hpp")] + [
-    os.path.join(ROOT, "include", "ibm.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("ibm_lib.hip", "unet_lib.hip")]
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("ibm_device.hpp", "ibm_kernels.hpp", "unet_kernels.hpp", "unet_internal.hpp")] + [
+    os.path.join(ROOT, "include", f) for f in ("ibm.h", "ibm_unet.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
