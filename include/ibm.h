@@ -75,6 +75,11 @@ extern "C" {
 /* initial guess of the pressure correction at each step */
 #define IBM_INIT_ZERO 0
 #define IBM_INIT_PREVIOUS 1
+/* Learned warm start (an extension; the paper starts from the previous
+ * solution): phi^n plus the prediction of the network attached with
+ * ibm_set_warm_start.  The solve still runs to p_tol, so the guess changes
+ * the iteration count, never the stop test. */
+#define IBM_INIT_LEARNED 2
 
 /* arithmetic of the sweeps */
 #define IBM_PREC_FP64 0
@@ -94,7 +99,7 @@ typedef struct ibm_params {
     int32_t p_method;        /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG or IBM_SOLVER_RBSOR_MP */
     int32_t p_max_iter;      /* iteration limit of one pressure solve, >= 1 */
     int32_t p_check_every;   /* SOR: residual tested every this many iterations, >= 1 */
-    int32_t p_init;          /* IBM_INIT_ZERO or IBM_INIT_PREVIOUS */
+    int32_t p_init;          /* IBM_INIT_ZERO, IBM_INIT_PREVIOUS or IBM_INIT_LEARNED */
     double p_omega;          /* SOR relaxation factor, 0 < omega < 2 */
     double p_tol;            /* stop when ||V b - A phi||_2 <= p_tol ||V b||_2 */
     double uv_omega;         /* relaxation factor of the implicit velocity solves */
@@ -210,6 +215,30 @@ int32_t ibm_set_state(ibm_ctx* ctx, const void* host, size_t bytes);
  * iteration sequence of a reference run.  n = 0 clears the schedule.  host
  * array, copied. */
 int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
+
+/* Learned warm start of the pressure solve (an extension of the method; the
+ * network is declared in ibm_unet.h).  The network sees three maps of the
+ * step's Poisson problem, each divided by its RMS over the grid:
+ *   0: r0 = V b - A phi^n, the residual of the previous correction;
+ *   1: phi^n;
+ *   2: 1 for cells whose centre lies inside the body at t^{n+1}, else 0;
+ * and predicts the change of phi in units of out_scale * RMS(r0), so that with
+ * IBM_INIT_LEARNED the solve starts from
+ *   phi = phi^n + out_scale * RMS(r0) * net(maps).
+ * ibm_set_warm_start attaches a network (borrowed; NULL detaches) whose
+ * image shape is (ny, nx) and whose stream is the context's stream.
+ * IBM_ERR_INVALID otherwise, or for out_scale <= 0.  A step with
+ * IBM_INIT_LEARNED and no network returns IBM_ERR_STATE before anything is
+ * enqueued. */
+typedef struct ibm_unet ibm_unet;
+int32_t ibm_set_warm_start(ibm_ctx* ctx, ibm_unet* net, double out_scale);
+
+/* Training snapshots: while set, every step writes the maps above for its
+ * pressure solve into feat_dev (device float, (3, ny, nx)) and, after the
+ * solve, the target (phi^{n+1} - phi^n) / (out_scale * RMS(r0)) into
+ * target_dev (device float, (ny, nx)), whatever the initial guess.  Both
+ * pointers are borrowed until they are replaced or cleared (both NULL). */
+int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, double out_scale);
 
 /* Kernel timing with HIP events on the context stream.  sample_every > 0
  * brackets every sample_every-th launch of each timed kernel with a pair of

@@ -1696,4 +1696,76 @@ __global__ void k_scatter_forcing(const int* __restrict__ list, const int* __res
     if (n < counts[which]) full[list[n]] = f[n];
 }
 
+// ---------------------------------------------------------------------------
+// Learned warm start of the pressure solve (an extension of the method): the
+// network sees r0 = V b - A phi (the residual of the previous correction),
+// phi and the body mask, each scaled to unit RMS, and predicts the change of
+// phi in units of s_r = RMS(r0).
+// ---------------------------------------------------------------------------
+// Partials of sum r0^2 and sum phi^2.
+__global__ __launch_bounds__(kRedThreads) void k_ws_stats(Grid g, const double* __restrict__ phi,
+                                                          const double* __restrict__ vb, double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    double acc[2] = {0.0, 0.0};
+    for (CellWalk c(g); c.ok(); c.next()) {
+        double d;
+        const double sum = nat_row(g, phi, c.i, c.j, c.k, d);
+        const double r = vb[c.k] - (sum - d * phi[c.k]);
+        acc[0] += r * r;
+        acc[1] += phi[c.k] * phi[c.k];
+    }
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// Feature maps (3, ny, nx) in float: r0 / s_r, phi / s_phi, 1 inside the body
+// at the new time level.  Every block sums the partials; block 0 stores
+// (s_r, s_phi) in scale (a zero RMS is replaced by 1).
+__global__ __launch_bounds__(kRedThreads) void k_ws_features(Grid g, Body B, const double* __restrict__ phi,
+                                                             const double* __restrict__ vb,
+                                                             const double* __restrict__ partials, int nb,
+                                                             double* __restrict__ scale, float* __restrict__ feat) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    __shared__ double s_inv[2];
+    double acc[2];
+    sum_partials(acc, partials, nb, lds);
+    const size_t n = (size_t)g.nx * g.ny;
+    if (threadIdx.x == 0) {
+        const double sr = sqrt(acc[0] / (double)n), sp = sqrt(acc[1] / (double)n);
+        const double a = sr > 0.0 ? sr : 1.0, b = sp > 0.0 ? sp : 1.0;
+        s_inv[0] = 1.0 / a;
+        s_inv[1] = 1.0 / b;
+        if (blockIdx.x == 0) {
+            scale[0] = a;
+            scale[1] = b;
+        }
+    }
+    __syncthreads();
+    const double ir = s_inv[0], ip = s_inv[1];
+    for (CellWalk c(g); c.ok(); c.next()) {
+        double d;
+        const double sum = nat_row(g, phi, c.i, c.j, c.k, d);
+        const double r = vb[c.k] - (sum - d * phi[c.k]);
+        feat[c.k] = (float)(r * ir);
+        feat[n + c.k] = (float)(phi[c.k] * ip);
+        feat[2 * n + c.k] = (B.present && inside(g.xc[c.i], g.yc[c.j], B)) ? 1.0f : 0.0f;
+    }
+}
+
+// phi += out_scale s_r y (y: the network's output, (ny, nx) float).
+__global__ __launch_bounds__(kRedThreads) void k_ws_apply(Grid g, const float* __restrict__ y,
+                                                          const double* __restrict__ scale, double out_scale,
+                                                          double* __restrict__ phi) {
+    const double f = out_scale * scale[0];
+    for (CellWalk c(g); c.ok(); c.next()) phi[c.k] += f * (double)y[c.k];
+}
+
+// Training target of the step: (phi_new - phi_old) / (out_scale s_r).
+__global__ __launch_bounds__(kRedThreads) void k_ws_target(Grid g, const double* __restrict__ phi,
+                                                           const double* __restrict__ phi_old,
+                                                           const double* __restrict__ scale, double out_scale,
+                                                           float* __restrict__ t) {
+    const double f = 1.0 / (out_scale * scale[0]);
+    for (CellWalk c(g); c.ok(); c.next()) t[c.k] = (float)((phi[c.k] - phi_old[c.k]) * f);
+}
+
 }  // namespace ibm

@@ -25,6 +25,7 @@
 
 #include "ibm.h"
 #include "ibm_kernels.hpp"
+#include "unet_internal.hpp"
 
 using namespace ibm;
 
@@ -56,7 +57,7 @@ struct Layout {
 
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
-    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2, mpf;
+    size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2, mpf, phi0, wsf, wscale;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -89,6 +90,9 @@ Offsets layout_for(int nx, int ny) {
     o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
     o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
     o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
+    o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step, features and
+    o.wsf = L.take<float>(4 * NC);  // the network output (3 + 1 maps), RMS scales
+    o.wscale = L.take<double>(2);
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
     // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
@@ -124,7 +128,8 @@ const char* validate(const ibm_params* P, const double* xf, const double* yf) {
     if (!(P->p_omega > 0.0 && P->p_omega < 2.0) || !(P->uv_omega > 0.0 && P->uv_omega < 2.0))
         return "relaxation factors must lie in (0, 2)";
     if (P->p_max_iter < 1 || P->p_check_every < 1 || P->uv_max_iter < 1) return "iteration limits must be >= 1";
-    if (P->p_init != IBM_INIT_ZERO && P->p_init != IBM_INIT_PREVIOUS) return "unknown p_init";
+    if (P->p_init != IBM_INIT_ZERO && P->p_init != IBM_INIT_PREVIOUS && P->p_init != IBM_INIT_LEARNED)
+        return "unknown p_init";
     if (!(P->alpha_max >= 0.0) || !std::isfinite(P->p_tol) || !std::isfinite(P->uv_tol)) return "invalid tolerances";
     if (!xf || !yf) return "face arrays are NULL";
     for (int i = 0; i < P->nx; ++i)
@@ -162,6 +167,12 @@ struct ibm_ctx {
     double *pz, *dn;    // PCG: z = r / diag(M), and diag(M) (natural layout)
     double *phr2, *phb2;  // second pair of split phi arrays (blocked sweeps alternate)
     float* mpf;           // mixed-precision SOR: e pairs (4 NH), then r32 pairs (4 NH)
+    double *phi0, *wscale;  // learned warm start: phi before the solve, (s_r, s_phi)
+    float* wsf;             // its features (3 maps) and network output (1 map)
+    ibm_unet* net = nullptr;  // warm-start network (borrowed) and its output scale
+    double net_scale = 1.0;
+    float *snap_feat = nullptr, *snap_target = nullptr;  // training snapshots (borrowed)
+    double snap_scale = 1.0;
     double *f_u, *f_v, *coef, *partials;
     Ctl* ctl;
     int *list_u, *list_v, *counts;
@@ -880,6 +891,44 @@ int32_t pressure_solve(ibm_ctx* c, int fixed, LoopOut* out) {
     return IBM_OK;
 }
 
+// Initial guess of the step's pressure solve from phi^n (natural layout):
+// zero, phi^n itself, or phi^n plus the warm-start network's prediction.  The
+// network's features are also computed when training snapshots are recorded
+// (they always describe phi^n, whatever the initial guess).
+int32_t warm_start(ibm_ctx* c, const Body& B) {
+    const ibm_params& P = c->P;
+    const size_t n = (size_t)c->nx * c->ny;
+    if (P.p_init == IBM_INIT_LEARNED && !c->net) {
+        c->err = "p_init is IBM_INIT_LEARNED but no network is attached (ibm_set_warm_start)";
+        return IBM_ERR_STATE;
+    }
+    if (P.p_init == IBM_INIT_LEARNED || c->snap_feat) {
+        const int nb = red_blocks(n);
+        double* part = c->partials;
+        hipLaunchKernelGGL(k_ws_stats, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, (const double*)c->phi,
+                           (const double*)c->vb, part);
+        hipLaunchKernelGGL(k_ws_features, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, B,
+                           (const double*)c->phi, (const double*)c->vb, (const double*)part, nb, c->wscale, c->wsf);
+        LAUNCH_CHECK();
+        if (c->snap_feat) {
+            HIP_TRY(hipMemcpyAsync(c->snap_feat, c->wsf, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->phi0, c->phi, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    if (P.p_init == IBM_INIT_ZERO) return fill(c, c->phi, n, 0.0);
+    if (P.p_init == IBM_INIT_LEARNED) {
+        const int32_t rc = ibm_unet_forward(c->net, c->wsf, c->wsf + 3 * n, 1);
+        if (rc) {
+            c->err = std::string("warm-start network: ") + ibm_unet_last_error(c->net);
+            return rc;
+        }
+        hipLaunchKernelGGL(k_ws_apply, dim3(red_blocks(n)), dim3(kRedThreads), 0, c->stream, c->g,
+                           (const float*)(c->wsf + 3 * n), (const double*)c->wscale, c->net_scale, c->phi);
+        LAUNCH_CHECK();
+    }
+    return IBM_OK;
+}
+
 int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
     const ibm_params& P = c->P;
     const int nx = c->nx, ny = c->ny;
@@ -928,15 +977,19 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
                        (const double*)c->v, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
                        (const uint8_t*)c->msrc, B.vb, dt, P.q_mode, c->vb);
     LAUNCH_CHECK();
-    if (P.p_init == IBM_INIT_ZERO) {
-        rc = fill(c, c->phi, (size_t)nx * ny, 0.0);
-        if (rc) return rc;
-    }
+    rc = warm_start(c, B);
+    if (rc) return rc;
     int fixed = -1;
     if (c->sched_pos < c->schedule.size()) fixed = c->schedule[c->sched_pos++];
     LoopOut po;
     rc = pressure_solve(c, fixed, &po);
     if (rc) return rc;
+    if (c->snap_target) {
+        hipLaunchKernelGGL(k_ws_target, dim3(red_blocks((size_t)nx * ny)), dim3(kRedThreads), 0, c->stream, c->g,
+                           (const double*)c->phi, (const double*)c->phi0, (const double*)c->wscale, c->snap_scale,
+                           c->snap_target);
+        LAUNCH_CHECK();
+    }
     st->p_iters = po.iters;
     st->p_r0 = po.bn > 0.0 ? po.r0 / po.bn : 0.0;
     st->p_rel = po.bn > 0.0 ? po.rn / po.bn : 0.0;
@@ -1117,6 +1170,9 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     c->pz = D(off.pz); c->dn = D(off.dn);
     c->phr2 = D(off.phr2); c->phb2 = D(off.phb2);
     c->mpf = (float*)(w + off.mpf);
+    c->phi0 = D(off.phi0);
+    c->wscale = D(off.wscale);
+    c->wsf = (float*)(w + off.wsf);
     c->f_u = D(off.f_u); c->f_v = D(off.f_v); c->coef = D(off.coef); c->partials = D(off.partials);
     c->ctl = (Ctl*)(w + off.ctl);
     c->list_u = (int*)(w + off.list_u); c->list_v = (int*)(w + off.list_v); c->counts = (int*)(w + off.counts);
@@ -1187,6 +1243,10 @@ int32_t ibm_step(ibm_ctx* c, int32_t nsteps, ibm_step_stats* last) {
         return IBM_ERR_INVALID;
     }
     c->err.clear();
+    if (c->P.p_init == IBM_INIT_LEARNED && !c->net) {  // checked before anything is enqueued
+        c->err = "p_init is IBM_INIT_LEARNED but no network is attached (ibm_set_warm_start)";
+        return IBM_ERR_STATE;
+    }
     const auto w0 = std::chrono::steady_clock::now();
     int32_t status = IBM_OK;
     ibm_step_stats st;
@@ -1363,6 +1423,43 @@ int32_t ibm_set_poisson_schedule(ibm_ctx* c, const int32_t* iters, int32_t n) {
         if (iters[k] < 0) return IBM_ERR_INVALID;
     c->schedule.assign(iters, iters + n);
     c->sched_pos = 0;
+    return IBM_OK;
+}
+
+int32_t ibm_set_warm_start(ibm_ctx* c, ibm_unet* net, double out_scale) {
+    if (!c) return IBM_ERR_INVALID;
+    if (!net) {
+        c->net = nullptr;
+        return IBM_OK;
+    }
+    int mb, h, w;
+    ibm::unet::net_shape(net, &mb, &h, &w);
+    if (h != c->ny || w != c->nx || mb < 1) {
+        c->err = "the network's image shape must be (ny, nx)";
+        return IBM_ERR_INVALID;
+    }
+    if (ibm::unet::net_stream(net) != c->stream) {
+        c->err = "the network must run on the context's stream";
+        return IBM_ERR_INVALID;
+    }
+    if (!(out_scale > 0.0) || !std::isfinite(out_scale)) {
+        c->err = "out_scale must be finite and > 0";
+        return IBM_ERR_INVALID;
+    }
+    c->net = net;
+    c->net_scale = out_scale;
+    return IBM_OK;
+}
+
+int32_t ibm_set_snapshot(ibm_ctx* c, float* feat_dev, float* target_dev, double out_scale) {
+    if (!c) return IBM_ERR_INVALID;
+    if ((feat_dev == nullptr) != (target_dev == nullptr) || !(out_scale > 0.0) || !std::isfinite(out_scale)) {
+        c->err = "feat_dev and target_dev must both be set or both be NULL; out_scale > 0";
+        return IBM_ERR_INVALID;
+    }
+    c->snap_feat = feat_dev;
+    c->snap_target = target_dev;
+    c->snap_scale = out_scale;
     return IBM_OK;
 }
 

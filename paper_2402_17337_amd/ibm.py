@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libibm_hip.so")
 OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, -5
 BC_CHANNEL = 0
 RBSOR, PCG, RBSOR_MP = 0, 1, 2   # RBSOR_MP: float sweeps on the correction, double refinement
-INIT_ZERO, INIT_PREVIOUS = 0, 1
+INIT_ZERO, INIT_PREVIOUS, INIT_LEARNED = 0, 1, 2
 (KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB, KERNEL_SOR_MP,
  KERNEL_SOR_MP_REFINE) = range(7)
 # KERNEL_SOR_TB times whichever blocked sweep runs; named for the default one
@@ -34,7 +34,7 @@ SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
-            "ibm_set_poisson_schedule", "ibm_set_option", "ibm_profile", "ibm_profile_query",
+            "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot", "ibm_profile", "ibm_profile_query",
             "ibm_destroy",
             "ibm_status_string", "ibm_last_error")
 
@@ -109,6 +109,10 @@ def lib():
         L.ibm_set_state.restype = C.c_int32
         L.ibm_set_poisson_schedule.argtypes = [vp, ip, C.c_int32]
         L.ibm_set_poisson_schedule.restype = C.c_int32
+        L.ibm_set_warm_start.argtypes = [vp, vp, C.c_double]
+        L.ibm_set_warm_start.restype = C.c_int32
+        L.ibm_set_snapshot.argtypes = [vp, vp, vp, C.c_double]
+        L.ibm_set_snapshot.restype = C.c_int32
         L.ibm_set_option.argtypes = [vp, C.c_int32, C.c_int64]
         L.ibm_set_option.restype = C.c_int32
         L.ibm_profile.argtypes = [vp, C.c_int32]
@@ -278,6 +282,30 @@ class Solver:
         rc = lib().ibm_set_poisson_schedule(self._h, a, len(iters))
         if rc != OK:
             self._err("ibm_set_poisson_schedule", rc)
+
+    def set_warm_start(self, net, out_scale: float):
+        """Attach a warm-start network (paper_2402_17337_amd.unet.UNet of shape
+        (ny, nx) on this solver's stream), or detach with net=None."""
+        self._ws_net = net  # keep it alive while attached
+        rc = lib().ibm_set_warm_start(self._h, net.handle if net is not None else None, out_scale)
+        if rc:
+            self._err("ibm_set_warm_start", rc)
+
+    def set_snapshot(self, feat=None, target=None, out_scale: float = 1.0):
+        """Record each step's network maps into feat (3, ny, nx) and its target
+        into target (ny, nx), float32 device tensors; None clears."""
+        ptrs = []
+        for t, shp in ((feat, (3, self.ny, self.nx)), (target, (self.ny, self.nx))):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if t.dtype != self.torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+                raise ValueError(f"snapshot buffers: contiguous float32 device tensors of shape {shp}")
+            ptrs.append(C.c_void_p(t.data_ptr()))
+        self._snap = (feat, target)
+        rc = lib().ibm_set_snapshot(self._h, ptrs[0], ptrs[1], out_scale)
+        if rc:
+            self._err("ibm_set_snapshot", rc)
 
     def set_option(self, option: int, value: int) -> int:
         """Tuning option (launch shape of the SOR sweeps); returns the status."""

@@ -1,0 +1,129 @@
+"""Learned warm start of the pressure solve: training data from the solver,
+training of the U-Net on the GPU, and its use as the initial guess.
+
+Orchestration only: the snapshots are written by the solver library's kernels
+(ibm_set_snapshot), training steps and inference run in the network's BF16
+matrix-core kernels (ibm_unet_*), and the solve with the learned guess is the
+library's own time step (IBM_INIT_LEARNED).  PyTorch holds the snapshot
+tensors and cuts the training crops out of them.
+
+The network predicts phi^{n+1} - phi^n from the maps of the step's Poisson
+problem (residual of phi^n, phi^n, body mask), in units of out_scale times the
+RMS of that residual; out_scale is the RMS of the targets over the training
+set, so the network's targets have unit RMS.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import ibm
+from . import unet as U
+from . import workloads as W
+
+
+def solver_for(wl: dict, **over):
+    prm = dict(wl["params"])
+    prm.update(over)
+    return ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **prm)
+
+
+def collect(wl: dict, cases, steps: int, keep_from: int = 1, method=ibm.PCG):
+    """Run each case (a dict of parameter overrides of the workload) for
+    `steps` steps with snapshots on; keep the snapshots of steps >= keep_from
+    (1-based).  Returns float32 device tensors feats (N, 3, ny, nx) and
+    targets (N, 1, ny, nx), targets in units of RMS(r0), and the solver
+    seconds spent."""
+    import torch
+    ny, nx = wl["ny"], wl["nx"]
+    feats, targets = [], []
+    t0 = time.perf_counter()
+    for case in cases:
+        s = solver_for(wl, p_method=method, p_init_prev=ibm.INIT_PREVIOUS, **case)
+        f = torch.empty((3, ny, nx), dtype=torch.float32, device=s.device)
+        t = torch.empty((ny, nx), dtype=torch.float32, device=s.device)
+        s.set_snapshot(f, t, 1.0)
+        for k in range(1, steps + 1):
+            st = s.step(1)
+            if st["rc"] < 0:
+                raise ibm.IbmError(f"snapshot run failed at step {k}: {ibm.status_string(st['rc'])}")
+            if k >= keep_from:
+                feats.append(f.clone())
+                targets.append(t.clone().unsqueeze(0))
+        s.set_snapshot(None, None)
+        s.close()
+    torch.cuda.synchronize()
+    return torch.stack(feats), torch.stack(targets), time.perf_counter() - t0
+
+
+def plunge_cases(n: int, seed: int):
+    """n plunge settings drawn from a seeded generator: amplitude in [0.3, 0.7]
+    (chords), frequency in [0.3, 0.5], phase in [0.5, 2 pi - 0.5] (clear of the
+    evaluation case's phase), Reynolds number in {300, 500, 1000}."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        ph = rng.uniform(0.5, 2.0 * math.pi - 0.5)
+        out.append(dict(amp=float(rng.uniform(0.3, 0.7)), freq=float(rng.uniform(0.3, 0.5)),
+                        phase=float(ph), re=float(rng.choice([300.0, 500.0, 1000.0]))))
+    return out
+
+
+def crops(feats, targets, batch: int, size_y: int, size_x: int, rng):
+    """A batch of random crops, offsets multiples of 8 (the network's pooling
+    grid stays aligned with the full image's)."""
+    import torch
+    n, _, ny, nx = feats.shape
+    idx = rng.integers(0, n, size=batch)
+    ys = rng.integers(0, (ny - size_y) // 8 + 1, size=batch) * 8
+    xs = rng.integers(0, (nx - size_x) // 8 + 1, size=batch) * 8
+    x = torch.stack([feats[i, :, y:y + size_y, xx:xx + size_x] for i, y, xx in zip(idx, ys, xs)]).contiguous()
+    t = torch.stack([targets[i, :, y:y + size_y, xx:xx + size_x] for i, y, xx in zip(idx, ys, xs)]).contiguous()
+    return x, t
+
+
+def train(net: U.UNet, feats, targets, iters: int, lr: float = 1e-3, lr_end: float = 1e-4, seed: int = 0,
+          log_every: int = 0):
+    """Adam on random crops of the snapshots (crop shape = the network's
+    shape); cosine learning-rate decay from lr to lr_end.  Returns the loss
+    history (every log_every iterations, and the last)."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    for k in range(iters):
+        x, t = crops(feats, targets, net.max_batch, net.h, net.w, rng)
+        a = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / max(iters - 1, 1)))
+        want = (log_every and k % log_every == 0) or k == iters - 1
+        loss = net.train_step(x, t, a, want_loss=bool(want))
+        if want:
+            hist.append((k, loss))
+    return hist
+
+
+def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, method=ibm.RBSOR,
+             warm_method=ibm.PCG, eval_steps: int = 1, modes=(ibm.INIT_ZERO, ibm.INIT_PREVIOUS, ibm.INIT_LEARNED)):
+    """Advance the workload warm_steps steps (warm_method), then run
+    eval_steps steps from that same state with each initial guess of `modes`;
+    returns {mode: [step statistics]} (iterations, initial and final relative
+    residuals, seconds of the whole step including the network)."""
+    base = solver_for(wl, p_method=warm_method, p_init_prev=ibm.INIT_PREVIOUS)
+    for _ in range(warm_steps):
+        base.step(1)
+    blob = base.get_state()
+    base.close()
+    out = {}
+    net = None
+    for mode in modes:
+        s = solver_for(wl, p_method=method, p_init_prev=mode)
+        s.set_state(blob)
+        if mode == ibm.INIT_LEARNED:
+            net = U.UNet(1, wl["ny"], wl["nx"], device=s.device, stream=s.stream)
+            net.set_params(params)
+            s.set_warm_start(net, out_scale)
+        out[mode] = [s.step(1) for _ in range(eval_steps)]
+        s.close()
+    return out
+
+
+MODE_NAMES = {ibm.INIT_ZERO: "zero", ibm.INIT_PREVIOUS: "previous", ibm.INIT_LEARNED: "learned"}

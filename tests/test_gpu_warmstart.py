@@ -1,0 +1,148 @@
+"""The learned warm start inside the GPU time step: the snapshot maps and
+targets against their definitions (recomputed from the fields and the oracle's
+operator A), the zero network reproducing the previous-step guess bit for bit,
+and a learned guess still converging to the same tolerance."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import unet as OU
+
+pytestmark = pytest.mark.gpu
+
+
+def _wl():
+    from paper_2402_17337_amd import workloads as W
+    return W.small_plunging(128, 96)
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(wl, **over):
+    from paper_2402_17337_amd import warmstart as WS
+    return WS.solver_for(wl, **over)
+
+
+def test_snapshot_maps_and_target_follow_their_definitions():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _wl()
+    nx, ny = wl["nx"], wl["ny"]
+    s = _solver(wl, p_method=ibm.PCG)
+    s.step(3)
+    f = torch.empty((3, ny, nx), dtype=torch.float32, device="cuda:0")
+    t = torch.empty((ny, nx), dtype=torch.float32, device="cuda:0")
+    s.set_snapshot(f, t, 1.0)
+    phi_old = s.fields()[3]
+    st = s.step(1)
+    phi_new = s.fields()[3]
+    f, t = f.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    # map 1: phi^n over its RMS
+    ref1 = phi_old / np.sqrt(np.mean(phi_old ** 2))
+    assert np.max(np.abs(f[1] - ref1)) <= 1e-6 * np.max(np.abs(ref1))
+    # map 2: cell centres strictly inside the ellipse at t^{n+1}
+    orc = O.Oracle(nx, ny, wl["xf"], wl["yf"], **wl["params"])
+    yb, _, _ = orc.kinematics(st["t"])
+    P = wl["params"]
+    xc = 0.5 * (wl["xf"][1:] + wl["xf"][:-1])
+    yc = 0.5 * (wl["yf"][1:] + wl["yf"][:-1])
+    a, b = 0.5 * P["chord"], 0.5 * P["chord"] * P["thick"]
+    X, Y = np.meshgrid(xc, yc)
+    inside = ((X - P["x0"]) / a) ** 2 + ((Y - yb) / b) ** 2 < 1.0
+    assert inside.sum() > 10
+    assert np.array_equal(f[2] > 0.5, inside)
+    # target: the change of phi over the solve, in units of RMS(r0)
+    d = phi_new - phi_old
+    scale = np.sum(d * t) / np.sum(t * t)
+    assert np.linalg.norm(d - scale * t) <= 1e-6 * np.linalg.norm(d)
+    # map 0: r0 / RMS(r0), and A (phi^{n+1} - phi^n) = r0 up to the solve's
+    # tolerance, so A(target) (oracle operator) must reproduce map 0
+    At = orc.apply_A(t)
+    assert np.linalg.norm(At - f[0]) <= 1e-4 * np.linalg.norm(f[0]), np.linalg.norm(At - f[0]) / np.linalg.norm(f[0])
+    assert abs(np.sqrt(np.mean(f[0] ** 2)) - 1.0) < 1e-5
+
+
+def test_zero_network_reproduces_the_previous_step_guess_bitwise():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    net = U.UNet(1, wl["ny"], wl["nx"], stream=b.stream)
+    net.set_params(np.zeros(U.param_count(), np.float32))
+    b.set_warm_start(net, 1.0)
+    for _ in range(3):
+        sa, sb = a.step(1), b.step(1)
+        assert sa["p_iters"] == sb["p_iters"]
+    fa, fb = a.fields(), b.fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+
+
+def test_learned_guess_without_network_is_a_state_error():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _wl()
+    s = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    with pytest.raises(ibm.IbmError, match="no network is attached"):
+        s.step(1)
+    # refused before anything ran: the state is still the initial one
+    u, v, p, phi = s.fields()
+    assert np.array_equal(p, np.zeros_like(p)) and np.array_equal(u[:, 1:], wl["u0"][:, 1:])
+
+
+def test_network_shape_and_stream_are_checked():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    s = _solver(wl)
+    with pytest.raises(ibm.IbmError):
+        s.set_warm_start(U.UNet(1, wl["ny"], 64), 1.0)
+    other = torch.cuda.Stream()
+    with pytest.raises(ibm.IbmError):
+        s.set_warm_start(U.UNet(1, wl["ny"], wl["nx"], stream=other), 1.0)
+    with pytest.raises(ibm.IbmError):
+        s.set_warm_start(U.UNet(1, wl["ny"], wl["nx"]), 0.0)
+
+
+def test_random_network_guess_still_converges_to_the_same_solution():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    net = U.UNet(1, wl["ny"], wl["nx"], stream=b.stream)
+    net.set_params(U.flatten_params(OU.init_params(7)))
+    b.set_warm_start(net, 1.0)
+    for _ in range(3):
+        sa, sb = a.step(1), b.step(1)
+        assert sb["rc"] == ibm.OK and sb["p_rel"] <= wl["params"]["p_tol"]
+    ua, va, pa, _ = a.fields()
+    ub, vb, pb, _ = b.fields()
+    for x, y in ((ua, ub), (va, vb)):
+        assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_collect_and_train_pipeline_reduces_the_loss():
+    _need_gpu()
+    from paper_2402_17337_amd import unet as U
+    from paper_2402_17337_amd import warmstart as WS
+    wl = _wl()
+    feats, targets, _ = WS.collect(wl, [dict(), dict(phase=1.0)], steps=4, keep_from=2)
+    assert feats.shape == (6, 3, wl["ny"], wl["nx"]) and targets.shape == (6, 1, wl["ny"], wl["nx"])
+    c = float(targets.pow(2).mean().sqrt())
+    net = U.UNet(4, 32, 64)
+    net.set_params(U.flatten_params(OU.init_params(0)))
+    hist = WS.train(net, feats, targets / c, iters=40, lr=2e-3, lr_end=2e-3, log_every=1)
+    first = np.mean([l for _, l in hist[:5]])
+    last = np.mean([l for _, l in hist[-5:]])
+    assert np.isfinite(last) and last < first, (first, last)
