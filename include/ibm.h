@@ -118,12 +118,13 @@ typedef struct ibm_step_stats {
     int32_t u_iters, v_iters;         /* implicit velocity iterations */
     int32_t n_forced_u, n_forced_v;   /* forced u and v nodes */
     int32_t n_msrc;                   /* cells with a forced face */
-    int32_t reserved;
+    int32_t n_net;                    /* network guesses and corrections applied */
     double p_r0;                      /* initial residual / ||V b|| of the pressure solve */
     double p_rel;                     /* final residual / ||V b|| */
     double cd, cl;                    /* drag and lift coefficients */
     double t;                         /* time reached */
     double seconds;                   /* host wall time of the whole ibm_step call */
+    double net_step;                  /* mean step a of those (see ibm_set_warm_start) */
 } ibm_step_stats;
 
 /* Options of a stand-alone Poisson solve. */
@@ -216,28 +217,41 @@ int32_t ibm_set_state(ibm_ctx* ctx, const void* host, size_t bytes);
  * array, copied. */
 int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
 
-/* Learned warm start of the pressure solve (an extension of the method; the
- * network is declared in ibm_unet.h).  The network sees three maps of the
- * step's Poisson problem, each divided by its RMS over the grid:
- *   0: r0 = V b - A phi^n, the residual of the previous correction;
- *   1: phi^n;
- *   2: 1 for cells whose centre lies inside the body at t^{n+1}, else 0;
- * and predicts the change of phi in units of out_scale * RMS(r0), so that with
- * IBM_INIT_LEARNED the solve starts from
- *   phi = phi^n + out_scale * RMS(r0) * net(maps).
+/* Learned guess and correction of the pressure solve (an extension of the
+ * method; the network is declared in ibm_unet.h).  The network works on the
+ * grid coarsened by F = IBM_OPT_NET_FACTOR in both directions: coarse cell
+ * (I, J) averages the fine cells [F I, F I + F) x [F J, F J + F).  For the
+ * current phi it sees three coarse maps, each divided by its RMS over the
+ * coarse grid:
+ *   0: r = V b - A phi, the residual of phi;
+ *   1: phi;
+ *   2: the fraction of the block's cell centres inside the body at t^{n+1};
+ * and predicts the coarse average of the remaining change of phi in units of
+ * out_scale * s_r, s_r = RMS(map 0 before scaling); every fine cell of a
+ * coarse cell receives its block's value:
+ *   phi <- phi + out_scale * s_r * net(maps).
+ * It is applied to phi^n before the solve when p_init is IBM_INIT_LEARNED
+ * (the learned warm start), and, with IBM_OPT_NET_EVERY = M > 0, after every
+ * M red-black SOR iterations that did not meet the stop test (the learned
+ * correction; SOR and mixed-precision SOR only).  Every SOR segment ends on
+ * the method's own stop test, so the network never decides convergence.
  * ibm_set_warm_start attaches a network (borrowed; NULL detaches) whose
- * image shape is (ny, nx) and whose stream is the context's stream.
- * IBM_ERR_INVALID otherwise, or for out_scale <= 0.  A step with
- * IBM_INIT_LEARNED and no network returns IBM_ERR_STATE before anything is
- * enqueued. */
+ * image shape is (ny / F, nx / F) and whose stream is the context's stream;
+ * IBM_ERR_INVALID otherwise, or for out_scale <= 0.  A step that would use a
+ * network while none (or one of another shape) is attached returns
+ * IBM_ERR_STATE before anything is enqueued. */
 typedef struct ibm_unet ibm_unet;
 int32_t ibm_set_warm_start(ibm_ctx* ctx, ibm_unet* net, double out_scale);
 
-/* Training snapshots: while set, every step writes the maps above for its
- * pressure solve into feat_dev (device float, (3, ny, nx)) and, after the
- * solve, the target (phi^{n+1} - phi^n) / (out_scale * RMS(r0)) into
- * target_dev (device float, (ny, nx)), whatever the initial guess.  Both
- * pointers are borrowed until they are replaced or cleared (both NULL). */
+/* Training snapshots: while set, every step writes the maps above into
+ * feat_dev (device float, (3, ny / F, nx / F)) and, after the solve, the
+ * target: the coarse average of (phi^{n+1} - phi_s) / (out_scale * s_r) into
+ * target_dev (device float, (ny / F, nx / F)).  phi_s is phi^n when
+ * IBM_OPT_SNAPSHOT_ITER is 0, whatever the initial guess; with
+ * IBM_OPT_SNAPSHOT_ITER = k > 0 (SOR methods) it is the iterate after k SOR
+ * iterations from the step's initial guess, after which PCG completes the
+ * solve.  Both pointers are borrowed until they are replaced or cleared
+ * (both NULL). */
 int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, double out_scale);
 
 /* Kernel timing with HIP events on the context stream.  sample_every > 0
@@ -278,6 +292,27 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
 #define IBM_OPT_TB_SWEEPS 1
 #define IBM_OPT_TB_TILE_X 2
 #define IBM_OPT_TB_TILE_Y 3
+/* Options of the learned guess and correction (see ibm_set_warm_start):
+ *   IBM_OPT_NET_FACTOR     coarsening factor F of the network's grid: 1, 2,
+ *                          4, 8 or 16, dividing nx and ny (default 1);
+ *   IBM_OPT_NET_EVERY      SOR iterations between network corrections, a
+ *                          multiple of p_check_every; 0 (default): none;
+ *   IBM_OPT_SNAPSHOT_ITER  SOR iterations before the snapshot, a multiple of
+ *                          p_check_every; 0 (default): at the start. */
+#define IBM_OPT_NET_FACTOR 4
+#define IBM_OPT_NET_EVERY 5
+#define IBM_OPT_SNAPSHOT_ITER 6
+#define IBM_OPT_NET_SMOOTH 7  /* binomial [1 2 1]/4 passes (x then y) over the
+                                 network output on the coarse grid, 0..16 (default 4) */
+#define IBM_OPT_NET_STEP 8    /* step rule of a guess or correction e (default ENERGY):
+   IBM_NET_STEP_ENERGY     a = min(1, 2 alpha), alpha = e.r / e.(A e) the step
+                           minimising the energy norm of the error: the full
+                           step unless it would increase that norm;
+   IBM_NET_STEP_BACKTRACK  a = 1, halved whenever an SOR segment ends with a
+                           larger residual than the previous one; below 1/64
+                           the solve continues as plain SOR. */
+#define IBM_NET_STEP_ENERGY 0
+#define IBM_NET_STEP_BACKTRACK 1
 #define IBM_SOR_TEMPORAL 0
 #define IBM_SOR_PER_COLOUR 1
 #define IBM_SOR_TEMPORAL_LDS 2

@@ -80,10 +80,13 @@ int32_t ibm_unet_get_grads(ibm_unet* net, float* host, size_t n);
 int32_t ibm_unet_forward(ibm_unet* net, const float* x_dev, float* y_dev, int32_t batch);
 
 /* Forward, mean squared error against target (batch, 1, height, width) and
- * backward: the parameter gradient is kept in the network.  loss (host,
- * nullable): the loss, which synchronizes the stream; NULL enqueues only. */
-int32_t ibm_unet_loss_grad(ibm_unet* net, const float* x_dev, const float* target_dev, int32_t batch,
-                           float* loss);
+ * backward: the parameter gradient is kept in the network.  weight_dev
+ * (device, batch floats, nullable = all 1) weights each image's squared
+ * errors: loss = sum_b weight[b] sum_p (y - target)^2 / (batch height width).
+ * loss (host, nullable): the loss, which synchronizes the stream; NULL
+ * enqueues only. */
+int32_t ibm_unet_loss_grad(ibm_unet* net, const float* x_dev, const float* target_dev, const float* weight_dev,
+                           int32_t batch, float* loss);
 
 /* One Adam update with the kept gradient: m = b1 m + (1 - b1) g,
  * v = b2 v + (1 - b2) g^2, w -= lr (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps)
@@ -91,8 +94,8 @@ int32_t ibm_unet_loss_grad(ibm_unet* net, const float* x_dev, const float* targe
 int32_t ibm_unet_adam_step(ibm_unet* net, float lr, float beta1, float beta2, float eps);
 
 /* ibm_unet_loss_grad then ibm_unet_adam_step(lr, 0.9, 0.999, 1e-8). */
-int32_t ibm_unet_train_step(ibm_unet* net, const float* x_dev, const float* target_dev, int32_t batch,
-                            float lr, float* loss);
+int32_t ibm_unet_train_step(ibm_unet* net, const float* x_dev, const float* target_dev, const float* weight_dev,
+                            int32_t batch, float lr, float* loss);
 
 void ibm_unet_destroy(ibm_unet* net);
 const char* ibm_unet_last_error(const ibm_unet* net);

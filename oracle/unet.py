@@ -74,14 +74,18 @@ def forward(params, x):
     return _conv(d0, p, "out", False)
 
 
-def loss_and_grads(params, x, target):
+def loss_and_grads(params, x, target, weight=None):
     """Mean squared error over all outputs and its gradient with respect to
-    every parameter (autograd), all in float64."""
+    every parameter (autograd), all in float64.  weight (per image, optional)
+    multiplies each image's squared errors before the mean."""
     p = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in params.items()}
     xt = torch.as_tensor(np.asarray(x, dtype=np.float64))
     tt = torch.as_tensor(np.asarray(target, dtype=np.float64))
     y = forward(p, xt)
-    loss = torch.mean((y - tt) ** 2)
+    sq = (y - tt) ** 2
+    if weight is not None:
+        sq = sq * torch.as_tensor(np.asarray(weight, dtype=np.float64)).reshape(-1, 1, 1, 1)
+    loss = torch.mean(sq)
     loss.backward()
     return loss.item(), {k: v.grad.numpy().copy() for k, v in p.items()}, y.detach().numpy()
 

@@ -1697,75 +1697,213 @@ __global__ void k_scatter_forcing(const int* __restrict__ list, const int* __res
 }
 
 // ---------------------------------------------------------------------------
-// Learned warm start of the pressure solve (an extension of the method): the
-// network sees r0 = V b - A phi (the residual of the previous correction),
-// phi and the body mask, each scaled to unit RMS, and predicts the change of
-// phi in units of s_r = RMS(r0).
+// Learned guess and correction of the pressure solve (an extension of the
+// method).  The network works on a grid coarsened by a factor F in both
+// directions (F = 1: the grid itself): coarse cell (I, J) averages the fine
+// cells i in [F I, F I + F), j in [F J, F J + F).  It sees r = V b - A phi (the
+// residual of the current phi), phi and the body mask, each averaged and
+// scaled to unit RMS over the coarse grid, and predicts the coarse average of
+// the remaining change of phi in units of s_r = RMS(coarse r); the fine cells
+// of a coarse cell all receive its value.
 // ---------------------------------------------------------------------------
-// Partials of sum r0^2 and sum phi^2.
-__global__ __launch_bounds__(kRedThreads) void k_ws_stats(Grid g, const double* __restrict__ phi,
-                                                          const double* __restrict__ vb, double* partials) {
-    __shared__ double lds[2 * kRedThreads / kWave];
-    double acc[2] = {0.0, 0.0};
-    for (CellWalk c(g); c.ok(); c.next()) {
+struct Coarse {
+    int f, ncx, ncy;
+};
+
+__device__ inline double cell_resid(const Grid& g, const double* __restrict__ phi, const double* __restrict__ vb,
+                                    int i, int j) {
+    const size_t k = (size_t)j * g.nx + i;
+    double d;
+    const double sum = nat_row(g, phi, i, j, k, d);
+    return vb[k] - (sum - d * phi[k]);
+}
+
+// Unscaled coarse maps, one fine cell per thread: the F^2 fine cells of a
+// coarse cell are F^2 consecutive threads of a block of kWsThreads (F <= 16),
+// summed by a tree reduction in LDS.  raw: (3, ncy, ncx) float averages of r,
+// phi and the inside indicator; partials of sum r_c^2 and sum phi_c^2.
+constexpr int kWsThreads = 256;
+__global__ __launch_bounds__(kWsThreads) void k_ws_coarse(Grid g, Coarse cg, Body B, const double* __restrict__ phi,
+                                                         const double* __restrict__ vb, float* __restrict__ raw,
+                                                         double* partials) {
+    __shared__ double sr[kWsThreads], sp[kWsThreads];
+    __shared__ int sm[kWsThreads];
+    __shared__ double lds[2 * kWsThreads / kWave];
+    const int f2 = cg.f * cg.f;
+    const int per = kWsThreads / f2;  // coarse cells per block
+    const int t = threadIdx.x, l = t % f2;
+    const size_t nc = (size_t)cg.ncx * cg.ncy;
+    const size_t q = (size_t)blockIdx.x * per + t / f2;
+    double r = 0.0, p = 0.0;
+    int in = 0;
+    if (q < nc) {
+        const int I = (int)(q % cg.ncx), J = (int)(q / cg.ncx);
+        const int i = I * cg.f + l % cg.f, j = J * cg.f + l / cg.f;
+        const size_t k = (size_t)j * g.nx + i;
         double d;
-        const double sum = nat_row(g, phi, c.i, c.j, c.k, d);
-        const double r = vb[c.k] - (sum - d * phi[c.k]);
-        acc[0] += r * r;
-        acc[1] += phi[c.k] * phi[c.k];
+        const double sum = nat_row(g, phi, i, j, k, d);
+        r = vb[k] - (sum - d * phi[k]);
+        p = phi[k];
+        in = (B.present && inside(g.xc[i], g.yc[j], B)) ? 1 : 0;
+    }
+    sr[t] = r;
+    sp[t] = p;
+    sm[t] = in;
+    __syncthreads();
+    for (int o = f2 / 2; o > 0; o >>= 1) {
+        if (l < o) {
+            sr[t] += sr[t + o];
+            sp[t] += sp[t + o];
+            sm[t] += sm[t + o];
+        }
+        __syncthreads();
+    }
+    double acc[2] = {0.0, 0.0};
+    if (l == 0 && q < nc) {
+        const double w = 1.0 / (double)f2;
+        const double rc = sr[t] * w, pc = sp[t] * w;
+        raw[q] = (float)rc;
+        raw[nc + q] = (float)pc;
+        raw[2 * nc + q] = (float)sm[t] / (float)f2;
+        acc[0] = rc * rc;
+        acc[1] = pc * pc;
     }
     block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
 }
 
-// Feature maps (3, ny, nx) in float: r0 / s_r, phi / s_phi, 1 inside the body
-// at the new time level.  Every block sums the partials; block 0 stores
-// (s_r, s_phi) in scale (a zero RMS is replaced by 1).
-__global__ __launch_bounds__(kRedThreads) void k_ws_features(Grid g, Body B, const double* __restrict__ phi,
-                                                             const double* __restrict__ vb,
-                                                             const double* __restrict__ partials, int nb,
-                                                             double* __restrict__ scale, float* __restrict__ feat) {
+// Scale maps 0 and 1 to unit RMS in place (every block sums the partials;
+// block 0 stores (s_r, s_phi) in scale, a zero RMS replaced by 1).
+__global__ __launch_bounds__(kRedThreads) void k_ws_normalize(Coarse cg, const double* __restrict__ partials, int nb,
+                                                              double* __restrict__ scale, float* __restrict__ feat) {
     __shared__ double lds[2 * kRedThreads / kWave];
-    __shared__ double s_inv[2];
+    __shared__ float s_inv[2];
     double acc[2];
     sum_partials(acc, partials, nb, lds);
-    const size_t n = (size_t)g.nx * g.ny;
+    const size_t nc = (size_t)cg.ncx * cg.ncy;
     if (threadIdx.x == 0) {
-        const double sr = sqrt(acc[0] / (double)n), sp = sqrt(acc[1] / (double)n);
+        const double sr = sqrt(acc[0] / (double)nc), sp = sqrt(acc[1] / (double)nc);
         const double a = sr > 0.0 ? sr : 1.0, b = sp > 0.0 ? sp : 1.0;
-        s_inv[0] = 1.0 / a;
-        s_inv[1] = 1.0 / b;
+        s_inv[0] = (float)(1.0 / a);
+        s_inv[1] = (float)(1.0 / b);
         if (blockIdx.x == 0) {
             scale[0] = a;
             scale[1] = b;
         }
     }
     __syncthreads();
-    const double ir = s_inv[0], ip = s_inv[1];
-    for (CellWalk c(g); c.ok(); c.next()) {
-        double d;
-        const double sum = nat_row(g, phi, c.i, c.j, c.k, d);
-        const double r = vb[c.k] - (sum - d * phi[c.k]);
-        feat[c.k] = (float)(r * ir);
-        feat[n + c.k] = (float)(phi[c.k] * ip);
-        feat[2 * n + c.k] = (B.present && inside(g.xc[c.i], g.yc[c.j], B)) ? 1.0f : 0.0f;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += (size_t)gridDim.x * blockDim.x) {
+        feat[q] *= s_inv[0];
+        feat[nc + q] *= s_inv[1];
     }
 }
 
-// phi += out_scale s_r y (y: the network's output, (ny, nx) float).
-__global__ __launch_bounds__(kRedThreads) void k_ws_apply(Grid g, const float* __restrict__ y,
-                                                          const double* __restrict__ scale, double out_scale,
-                                                          double* __restrict__ phi) {
-    const double f = out_scale * scale[0];
-    for (CellWalk c(g); c.ok(); c.next()) phi[c.k] += f * (double)y[c.k];
+// One pass of the binomial filter [1 2 1] / 4 in x, then in y, over the coarse
+// map (edge values mirrored): damps the shortest coarse wavelengths of the
+// network output (a wavelength of 2 coarse cells vanishes, 4 halves) while
+// leaving the smooth part it predicts nearly unchanged.  One thread per
+// coarse cell; tmp holds the x pass.
+__global__ void k_ws_smooth_x(Coarse cg, const float* __restrict__ y, float* __restrict__ tmp) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cg.ncx * cg.ncy) return;
+    const int I = q % cg.ncx;
+    const float c = y[q], w = I > 0 ? y[q - 1] : c, e = I < cg.ncx - 1 ? y[q + 1] : c;
+    tmp[q] = 0.25f * (w + e) + 0.5f * c;
+}
+__global__ void k_ws_smooth_y(Coarse cg, const float* __restrict__ tmp, float* __restrict__ y) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cg.ncx * cg.ncy) return;
+    const int J = q / cg.ncx;
+    const float c = tmp[q], s = J > 0 ? tmp[q - cg.ncx] : c, n = J < cg.ncy - 1 ? tmp[q + cg.ncx] : c;
+    y[q] = 0.25f * (s + n) + 0.5f * c;
 }
 
-// Training target of the step: (phi_new - phi_old) / (out_scale s_r).
-__global__ __launch_bounds__(kRedThreads) void k_ws_target(Grid g, const double* __restrict__ phi,
+// Bilinear interpolation of the coarse map y (cell centres of the coarse
+// grid) at the centre of fine cell (i, j), in index space; constant beyond the
+// outermost coarse centres.
+__device__ inline double coarse_interp(const Coarse& cg, const float* __restrict__ y, int i, int j) {
+    const double fx = ((double)i - 0.5 * (cg.f - 1)) / cg.f, fy = ((double)j - 0.5 * (cg.f - 1)) / cg.f;
+    const double cx = fmin(fmax(fx, 0.0), (double)(cg.ncx - 1)), cy = fmin(fmax(fy, 0.0), (double)(cg.ncy - 1));
+    const int I0 = min((int)cx, max(cg.ncx - 2, 0)), J0 = min((int)cy, max(cg.ncy - 2, 0));
+    const int I1 = min(I0 + 1, cg.ncx - 1), J1 = min(J0 + 1, cg.ncy - 1);
+    const double wx = cx - I0, wy = cy - J0;
+    const double y00 = y[(size_t)J0 * cg.ncx + I0], y10 = y[(size_t)J0 * cg.ncx + I1];
+    const double y01 = y[(size_t)J1 * cg.ncx + I0], y11 = y[(size_t)J1 * cg.ncx + I1];
+    return (1.0 - wy) * ((1.0 - wx) * y00 + wx * y10) + wy * ((1.0 - wx) * y01 + wx * y11);
+}
+
+// The network's correction on the fine grid: e = out_scale s_r P y, P the
+// bilinear interpolation (y: the network output, (ncy, ncx) float).
+__global__ __launch_bounds__(kRedThreads) void k_ws_expand(Grid g, Coarse cg, const float* __restrict__ y,
+                                                           const double* __restrict__ scale, double out_scale,
+                                                           double* __restrict__ e) {
+    const double f = out_scale * scale[0];
+    for (CellWalk c(g); c.ok(); c.next()) e[c.k] = f * coarse_interp(cg, y, c.i, c.j);
+}
+
+// Partials of e.r and e.(A e), r = V b - A phi: the step alpha = e.r / e.A e
+// minimises the energy norm (the norm of -A) of the error of phi + alpha e,
+// and every step in [0, 2 alpha] leaves that norm no larger than at 0.
+__global__ __launch_bounds__(kRedThreads) void k_ws_dots(Grid g, const double* __restrict__ phi,
+                                                         const double* __restrict__ vb,
+                                                         const double* __restrict__ e, double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    double acc[2] = {0.0, 0.0};
+    for (CellWalk c(g); c.ok(); c.next()) {
+        double d;
+        const double sp = nat_row(g, phi, c.i, c.j, c.k, d);
+        const double r = vb[c.k] - (sp - d * phi[c.k]);
+        const double se = nat_row(g, e, c.i, c.j, c.k, d);
+        const double ae = se - d * e[c.k];
+        acc[0] += e[c.k] * r;
+        acc[1] += e[c.k] * ae;
+    }
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// phi += a e.  With step < 0: a = min(1, 2 alpha), alpha the energy-optimal
+// step from the partials (every block sums them): the full correction
+// whenever it does not increase the error's energy norm, else the largest
+// step that does not (a = 0 when the denominator is not negative or alpha is
+// not finite); SOR itself never increases that norm, so such corrections
+// cannot make the iteration diverge.  With step >= 0: a = step.  Block 0
+// records a in scale[2] and adds it to scale[3].
+__global__ __launch_bounds__(kRedThreads) void k_ws_apply(Grid g, const double* __restrict__ e,
+                                                          const double* __restrict__ partials, int nb, double step,
+                                                          double* __restrict__ scale, double* __restrict__ phi) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    __shared__ double s_alpha;
+    double acc[2] = {0.0, 0.0};
+    if (step < 0.0) sum_partials(acc, partials, nb, lds);
+    if (threadIdx.x == 0) {
+        const double opt = acc[1] < 0.0 ? acc[0] / acc[1] : 0.0;
+        s_alpha = step >= 0.0 ? step : (isfinite(opt) ? fmin(1.0, fmax(0.0, 2.0 * opt)) : 0.0);
+        if (blockIdx.x == 0) {
+            scale[2] = s_alpha;
+            scale[3] += s_alpha;
+        }
+    }
+    __syncthreads();
+    const double a = s_alpha;
+    for (CellWalk c(g); c.ok(); c.next()) phi[c.k] += a * e[c.k];
+}
+
+// Training target: coarse average of (phi_new - phi_old) / (out_scale s_r).
+__global__ __launch_bounds__(kRedThreads) void k_ws_target(Grid g, Coarse cg, const double* __restrict__ phi,
                                                            const double* __restrict__ phi_old,
                                                            const double* __restrict__ scale, double out_scale,
                                                            float* __restrict__ t) {
-    const double f = 1.0 / (out_scale * scale[0]);
-    for (CellWalk c(g); c.ok(); c.next()) t[c.k] = (float)((phi[c.k] - phi_old[c.k]) * f);
+    const double f = 1.0 / (out_scale * scale[0] * (double)cg.f * cg.f);
+    const size_t nc = (size_t)cg.ncx * cg.ncy;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += (size_t)gridDim.x * blockDim.x) {
+        const int I = (int)(q % cg.ncx), J = (int)(q / cg.ncx);
+        double s = 0.0;
+        for (int dj = 0; dj < cg.f; ++dj)
+            for (int di = 0; di < cg.f; ++di) {
+                const size_t k = (size_t)(J * cg.f + dj) * g.nx + I * cg.f + di;
+                s += phi[k] - phi_old[k];
+            }
+        t[q] = (float)(s * f);
+    }
 }
 
 }  // namespace ibm

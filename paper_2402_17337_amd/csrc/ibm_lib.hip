@@ -92,7 +92,7 @@ Offsets layout_for(int nx, int ny) {
     o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
     o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step, features and
     o.wsf = L.take<float>(4 * NC);  // the network output (3 + 1 maps), RMS scales
-    o.wscale = L.take<double>(2);
+    o.wscale = L.take<double>(4);  // s_r, s_phi, alpha of the last correction
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
     // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
@@ -173,6 +173,12 @@ struct ibm_ctx {
     double net_scale = 1.0;
     float *snap_feat = nullptr, *snap_target = nullptr;  // training snapshots (borrowed)
     double snap_scale = 1.0;
+    int net_f = 1;       // coarsening factor of the network's grid
+    int net_every = 0;   // SOR iterations between network corrections (0: none)
+    int snap_iter = 0;   // SOR iterations before the snapshot is taken
+    int net_smooth = 4;  // binomial passes over the network output
+    int net_rule = IBM_NET_STEP_ENERGY;
+    double net_step = 1.0;  // IBM_NET_STEP_BACKTRACK: current step
     double *f_u, *f_v, *coef, *partials;
     Ctl* ctl;
     int *list_u, *list_v, *counts;
@@ -183,7 +189,8 @@ struct ibm_ctx {
     Slot* dslots = nullptr;
     long slot_seq = 0;
     hipEvent_t ev[kSlots];
-    double* hstage = nullptr;  // pinned: coef[2], counts[3]
+    double* hstage = nullptr;  // pinned: coef[2], counts[3], sum of the network steps
+    int n_net = 0;             // network guesses and corrections of the current step
     // time stepping
     int have_hist = 0;
     long step = 0;
@@ -868,8 +875,102 @@ Body body_at(const ibm_ctx* c, double t) {
     return B;
 }
 
+Coarse coarse_of(const ibm_ctx* c) { return Coarse{c->net_f, c->nx / c->net_f, c->ny / c->net_f}; }
+
+// The network's maps of the current phi (natural layout) into wsf, and the
+// RMS scales into wscale.
+int32_t net_maps(ibm_ctx* c, const Body& B) {
+    const Coarse cg = coarse_of(c);
+    const size_t nc = (size_t)cg.ncx * cg.ncy;
+    const int per = kWsThreads / (cg.f * cg.f);
+    const int nb = (int)((nc + per - 1) / per);
+    hipLaunchKernelGGL(k_ws_coarse, dim3(nb), dim3(kWsThreads), 0, c->stream, c->g, cg, B, (const double*)c->phi,
+                       (const double*)c->vb, c->wsf, c->partials);
+    hipLaunchKernelGGL(k_ws_normalize, dim3(red_blocks(nc)), dim3(kRedThreads), 0, c->stream, cg,
+                       (const double*)c->partials, nb, c->wscale, c->wsf);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+// phi += a e: e the network's prediction from the maps in wsf, smoothed on
+// the coarse grid and interpolated to the fine grid (into pr, free outside
+// PCG), a the step of the context's rule.
+int32_t net_apply(ibm_ctx* c) {
+    const Coarse cg = coarse_of(c);
+    const size_t nc = (size_t)cg.ncx * cg.ncy, n = (size_t)c->nx * c->ny;
+    const int32_t rc = ibm_unet_forward(c->net, c->wsf, c->wsf + 3 * nc, 1);
+    if (rc) {
+        c->err = std::string("warm-start network: ") + ibm_unet_last_error(c->net);
+        return rc;
+    }
+    float* y = c->wsf + 3 * nc;
+    for (int k = 0; k < c->net_smooth; ++k) {
+        const unsigned gb = (unsigned)((nc + 255) / 256);
+        hipLaunchKernelGGL(k_ws_smooth_x, dim3(gb), dim3(256), 0, c->stream, cg, (const float*)y, y + nc);
+        hipLaunchKernelGGL(k_ws_smooth_y, dim3(gb), dim3(256), 0, c->stream, cg, (const float*)(y + nc), y);
+    }
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_ws_expand, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, cg, (const float*)y,
+                       (const double*)c->wscale, c->net_scale, c->pr);
+    const bool energy = c->net_rule == IBM_NET_STEP_ENERGY;
+    if (energy)
+        hipLaunchKernelGGL(k_ws_dots, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, (const double*)c->phi,
+                           (const double*)c->vb, (const double*)c->pr, c->partials);
+    hipLaunchKernelGGL(k_ws_apply, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, (const double*)c->pr,
+                       (const double*)c->partials, nb, energy ? -1.0 : c->net_step, c->wscale, c->phi);
+    LAUNCH_CHECK();
+    c->n_net += 1;
+    return IBM_OK;
+}
+
+// Record the maps of the current phi as the snapshot and keep phi for its
+// target.
+int32_t snapshot_maps(ibm_ctx* c, const Body& B) {
+    int32_t rc = net_maps(c, B);
+    if (rc) return rc;
+    const Coarse cg = coarse_of(c);
+    const size_t nc = (size_t)cg.ncx * cg.ncy, n = (size_t)c->nx * c->ny;
+    HIP_TRY(hipMemcpyAsync(c->snap_feat, c->wsf, 3 * nc * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->phi0, c->phi, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return IBM_OK;
+}
+
+bool snapshot_mid_solve(const ibm_ctx* c) {
+    return c->snap_feat && c->snap_iter > 0 && c->P.p_method != IBM_SOLVER_PCG;
+}
+
+// Initial guess of the step's pressure solve from phi^n (natural layout):
+// zero, phi^n itself, or phi^n plus the network's prediction.  Snapshots taken
+// at the start of the solve describe phi^n, whatever the initial guess.
+int32_t warm_start(ibm_ctx* c, const Body& B) {
+    const ibm_params& P = c->P;
+    const size_t n = (size_t)c->nx * c->ny;
+    if (P.p_init == IBM_INIT_LEARNED && !c->net) {
+        c->err = "p_init is IBM_INIT_LEARNED but no network is attached (ibm_set_warm_start)";
+        return IBM_ERR_STATE;
+    }
+    int32_t rc;
+    if (c->snap_feat && !snapshot_mid_solve(c)) {
+        rc = snapshot_maps(c, B);
+        if (rc) return rc;
+    }
+    if (P.p_init == IBM_INIT_ZERO) return fill(c, c->phi, n, 0.0);
+    if (P.p_init == IBM_INIT_LEARNED) {
+        if (!c->snap_feat || snapshot_mid_solve(c)) {
+            rc = net_maps(c, B);
+            if (rc) return rc;
+        }
+        return net_apply(c);
+    }
+    return IBM_OK;
+}
+
 // Pressure solve of the time step on phi (natural) with vb (natural, V b).
-int32_t pressure_solve(ibm_ctx* c, int fixed, LoopOut* out) {
+// SOR runs in segments when a network corrects phi every net_every
+// iterations, or when the snapshot is taken snap_iter iterations into the
+// solve (then PCG finishes the solve for the snapshot's target).  Every
+// segment ends on SOR's own stop test, so the last one decides convergence.
+int32_t pressure_solve(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
     const ibm_params& P = c->P;
     if (P.p_method == IBM_SOLVER_PCG) {
         int32_t rc = pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out);
@@ -878,54 +979,84 @@ int32_t pressure_solve(ibm_ctx* c, int fixed, LoopOut* out) {
         return IBM_OK;
     }
     const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
-    hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
+    auto split_phi = [&]() {
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
+    };
+    auto merge_phi = [&]() {
+        hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb,
+                           c->phi);
+    };
+    auto run = [&](int max_iter, int fx, LoopOut* o) {
+        return P.p_method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, P.p_omega, P.p_tol, max_iter, P.p_check_every, fx, o)
+                                                 : sor_loop(c, P.p_omega, P.p_tol, max_iter, P.p_check_every, fx, o);
+    };
+    split_phi();
     hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
     LAUNCH_CHECK();
-    int32_t rc = P.p_method == IBM_SOLVER_RBSOR_MP
-                     ? mp_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out)
-                     : sor_loop(c, P.p_omega, P.p_tol, P.p_max_iter, P.p_check_every, fixed, out);
-    if (rc) return rc;
+    const bool snap_mid = fixed < 0 && snapshot_mid_solve(c);
+    const bool correct = fixed < 0 && c->net && c->net_every > 0;
+    int32_t rc;
+    if (!snap_mid && !correct) {
+        rc = run(P.p_max_iter, fixed, out);
+        if (rc) return rc;
+    } else {
+        int done = 0;
+        double rn_prev = -1.0;  // residual at the end of the previous segment
+        bool corrections = correct;
+        for (int seg = 0;; ++seg) {
+            int lim = P.p_max_iter - done;
+            if (corrections) lim = std::min(lim, c->net_every);
+            if (snap_mid) lim = std::min(lim, c->snap_iter - done);
+            LoopOut so;
+            rc = run(lim, -1, &so);
+            if (rc) return rc;
+            if (seg == 0) {
+                out->bn = so.bn;
+                out->r0 = so.r0;
+                out->zero_rhs = so.zero_rhs;
+            }
+            done += so.iters;
+            out->iters = done;
+            out->rn = so.rn;
+            out->status = so.status;
+            if (so.zero_rhs) break;
+            const bool finished = so.status != kStNotConverged || done >= P.p_max_iter;
+            merge_phi();
+            LAUNCH_CHECK();
+            if (snap_mid && (finished || done >= c->snap_iter)) {
+                rc = snapshot_maps(c, B);
+                if (rc) return rc;
+                if (finished) return IBM_OK;
+                LoopOut po;
+                rc = pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, -1, &po);
+                if (rc) return rc;
+                out->iters = done + po.iters;
+                out->rn = po.rn;
+                out->status = po.status;
+                return IBM_OK;
+            }
+            if (finished) return IBM_OK;
+            if (corrections && c->net_rule == IBM_NET_STEP_BACKTRACK) {
+                // the last correction left a larger residual after a whole
+                // segment of SOR than the segment before it ended with: halve;
+                // below 1/64 the rest of the solve is plain SOR
+                if (rn_prev >= 0.0 && so.rn > rn_prev) c->net_step *= 0.5;
+                rn_prev = so.rn;
+                if (c->net_step < 1.0 / 64) corrections = false;
+            }
+            if (corrections) {
+                rc = net_maps(c, B);
+                if (rc) return rc;
+                rc = net_apply(c);
+                if (rc) return rc;
+                split_phi();
+                LAUNCH_CHECK();
+            }
+        }
+    }
     if (out->zero_rhs) return fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
-    hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb, c->phi);
+    merge_phi();
     LAUNCH_CHECK();
-    return IBM_OK;
-}
-
-// Initial guess of the step's pressure solve from phi^n (natural layout):
-// zero, phi^n itself, or phi^n plus the warm-start network's prediction.  The
-// network's features are also computed when training snapshots are recorded
-// (they always describe phi^n, whatever the initial guess).
-int32_t warm_start(ibm_ctx* c, const Body& B) {
-    const ibm_params& P = c->P;
-    const size_t n = (size_t)c->nx * c->ny;
-    if (P.p_init == IBM_INIT_LEARNED && !c->net) {
-        c->err = "p_init is IBM_INIT_LEARNED but no network is attached (ibm_set_warm_start)";
-        return IBM_ERR_STATE;
-    }
-    if (P.p_init == IBM_INIT_LEARNED || c->snap_feat) {
-        const int nb = red_blocks(n);
-        double* part = c->partials;
-        hipLaunchKernelGGL(k_ws_stats, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, (const double*)c->phi,
-                           (const double*)c->vb, part);
-        hipLaunchKernelGGL(k_ws_features, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, B,
-                           (const double*)c->phi, (const double*)c->vb, (const double*)part, nb, c->wscale, c->wsf);
-        LAUNCH_CHECK();
-        if (c->snap_feat) {
-            HIP_TRY(hipMemcpyAsync(c->snap_feat, c->wsf, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(c->phi0, c->phi, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        }
-    }
-    if (P.p_init == IBM_INIT_ZERO) return fill(c, c->phi, n, 0.0);
-    if (P.p_init == IBM_INIT_LEARNED) {
-        const int32_t rc = ibm_unet_forward(c->net, c->wsf, c->wsf + 3 * n, 1);
-        if (rc) {
-            c->err = std::string("warm-start network: ") + ibm_unet_last_error(c->net);
-            return rc;
-        }
-        hipLaunchKernelGGL(k_ws_apply, dim3(red_blocks(n)), dim3(kRedThreads), 0, c->stream, c->g,
-                           (const float*)(c->wsf + 3 * n), (const double*)c->wscale, c->net_scale, c->phi);
-        LAUNCH_CHECK();
-    }
     return IBM_OK;
 }
 
@@ -977,17 +1108,21 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
                        (const double*)c->v, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
                        (const uint8_t*)c->msrc, B.vb, dt, P.q_mode, c->vb);
     LAUNCH_CHECK();
+    c->n_net = 0;
+    c->net_step = 1.0;
+    if (c->net) HIP_TRY(hipMemsetAsync(c->wscale + 3, 0, sizeof(double), c->stream));
     rc = warm_start(c, B);
     if (rc) return rc;
     int fixed = -1;
     if (c->sched_pos < c->schedule.size()) fixed = c->schedule[c->sched_pos++];
     LoopOut po;
-    rc = pressure_solve(c, fixed, &po);
+    rc = pressure_solve(c, B, fixed, &po);
     if (rc) return rc;
     if (c->snap_target) {
-        hipLaunchKernelGGL(k_ws_target, dim3(red_blocks((size_t)nx * ny)), dim3(kRedThreads), 0, c->stream, c->g,
-                           (const double*)c->phi, (const double*)c->phi0, (const double*)c->wscale, c->snap_scale,
-                           c->snap_target);
+        const Coarse cg = coarse_of(c);
+        hipLaunchKernelGGL(k_ws_target, dim3(red_blocks((size_t)cg.ncx * cg.ncy)), dim3(kRedThreads), 0, c->stream,
+                           c->g, cg, (const double*)c->phi, (const double*)c->phi0, (const double*)c->wscale,
+                           c->snap_scale, c->snap_target);
         LAUNCH_CHECK();
     }
     st->p_iters = po.iters;
@@ -1008,6 +1143,7 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
     // statistics of the step
     HIP_TRY(hipMemcpyAsync(c->hstage, c->coef, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync((int*)(c->hstage + 2), c->counts, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (c->n_net) HIP_TRY(hipMemcpyAsync(c->hstage + 4, c->wscale + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->cd = c->hstage[0];
     c->cl = c->hstage[1];
@@ -1015,6 +1151,8 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
     st->n_forced_u = cnt[0];
     st->n_forced_v = cnt[1];
     st->n_msrc = cnt[2];
+    st->n_net = c->n_net;
+    st->net_step = c->n_net ? c->hstage[4] / c->n_net : 0.0;
     c->step += 1;
     c->t = t1;
     st->cd = c->cd;
@@ -1247,6 +1385,14 @@ int32_t ibm_step(ibm_ctx* c, int32_t nsteps, ibm_step_stats* last) {
         c->err = "p_init is IBM_INIT_LEARNED but no network is attached (ibm_set_warm_start)";
         return IBM_ERR_STATE;
     }
+    if (c->net) {
+        int mb, h, w;
+        ibm::unet::net_shape(c->net, &mb, &h, &w);
+        if (h * c->net_f != c->ny || w * c->net_f != c->nx) {
+            c->err = "the attached network's shape does not match IBM_OPT_NET_FACTOR";
+            return IBM_ERR_STATE;
+        }
+    }
     const auto w0 = std::chrono::steady_clock::now();
     int32_t status = IBM_OK;
     ibm_step_stats st;
@@ -1434,8 +1580,8 @@ int32_t ibm_set_warm_start(ibm_ctx* c, ibm_unet* net, double out_scale) {
     }
     int mb, h, w;
     ibm::unet::net_shape(net, &mb, &h, &w);
-    if (h != c->ny || w != c->nx || mb < 1) {
-        c->err = "the network's image shape must be (ny, nx)";
+    if (h * c->net_f != c->ny || w * c->net_f != c->nx || mb < 1) {
+        c->err = "the network's image shape must be (ny, nx) / IBM_OPT_NET_FACTOR";
         return IBM_ERR_INVALID;
     }
     if (ibm::unet::net_stream(net) != c->stream) {
@@ -1475,6 +1621,30 @@ int32_t ibm_set_option(ibm_ctx* c, int32_t option, int64_t value) {
         case IBM_OPT_TB_SWEEPS: S = (int)value; break;
         case IBM_OPT_TB_TILE_X: tx = (int)value; break;
         case IBM_OPT_TB_TILE_Y: ty = (int)value; break;
+        case IBM_OPT_NET_FACTOR:
+            if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) return IBM_ERR_INVALID;
+            if (c->nx % value || c->ny % value) {
+                c->err = "the network's coarsening factor must divide nx and ny";
+                return IBM_ERR_INVALID;
+            }
+            c->net_f = (int)value;
+            return IBM_OK;
+        case IBM_OPT_NET_SMOOTH:
+            if (value < 0 || value > 16) return IBM_ERR_INVALID;
+            c->net_smooth = (int)value;
+            return IBM_OK;
+        case IBM_OPT_NET_STEP:
+            if (value != IBM_NET_STEP_ENERGY && value != IBM_NET_STEP_BACKTRACK) return IBM_ERR_INVALID;
+            c->net_rule = (int)value;
+            return IBM_OK;
+        case IBM_OPT_NET_EVERY:
+        case IBM_OPT_SNAPSHOT_ITER:
+            if (value < 0 || value > (1 << 30) || value % c->P.p_check_every) {
+                c->err = "the interval must be >= 0 and a multiple of p_check_every";
+                return IBM_ERR_INVALID;
+            }
+            (option == IBM_OPT_NET_EVERY ? c->net_every : c->snap_iter) = (int)value;
+            return IBM_OK;
         default: return IBM_ERR_INVALID;
     }
     if (value < 0 || value > (1 << 20)) return IBM_ERR_INVALID;

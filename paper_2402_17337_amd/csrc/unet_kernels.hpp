@@ -287,21 +287,24 @@ __global__ void k_unpack_nhwc(Shape s, int c, const float* __restrict__ x, float
     y[i] = x[(bn * hw + r) * c + ch];
 }
 
-// Mean squared error of out against t over npix values: g = 2 (out - t) / npix
-// as bf16 in channel 0 of an 8-channel NHWC gradient (channels 1..7 zero), and
-// per-block partial sums of (out - t)^2.
-__global__ __launch_bounds__(kEw) void k_mse(int npix, const float* __restrict__ out, const float* __restrict__ t,
+// Mean squared error of out against t over npix values, each image b of hw
+// values weighted by w[b] (w null: 1): g = 2 w (out - t) / npix as bf16 in
+// channel 0 of an 8-channel NHWC gradient (channels 1..7 zero), and per-block
+// partial sums of w (out - t)^2.
+__global__ __launch_bounds__(kEw) void k_mse(int npix, int hw, const float* __restrict__ out,
+                                             const float* __restrict__ t, const float* __restrict__ w,
                                              bf16* __restrict__ g, float* __restrict__ part) {
     __shared__ float red[kEw];
     const int i = blockIdx.x * kEw + threadIdx.x;
-    float d = 0.0f;
+    float d = 0.0f, wi = 0.0f;
     if (i < npix) {
         d = out[i] - t[i];
+        wi = w ? w[i / hw] : 1.0f;
         bf16x8 v = zero8();
-        v[0] = (bf16)(2.0f * d / (float)npix);
+        v[0] = (bf16)(2.0f * wi * d / (float)npix);
         *(bf16x8*)(g + (size_t)i * 8) = v;
     }
-    red[threadIdx.x] = d * d;
+    red[threadIdx.x] = wi * d * d;
     __syncthreads();
     for (int o = kEw / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];

@@ -395,13 +395,14 @@ int32_t ibm_unet_forward(ibm_unet* u, const float* x, float* y, int32_t batch) {
     return IBM_OK;
 }
 
-int32_t ibm_unet_loss_grad(ibm_unet* u, const float* x, const float* target, int32_t batch, float* loss) {
+int32_t ibm_unet_loss_grad(ibm_unet* u, const float* x, const float* target, const float* weight, int32_t batch,
+                           float* loss) {
     if (check_net(u) || !x || !target || batch < 1 || batch > u->max_batch) return IBM_ERR_INVALID;
     int32_t rc = forward(u, x, batch);
     if (rc) return rc;
     const int P = batch * u->h * u->w;
     const int nb = (int)blocks(P);
-    k_mse<<<nb, kEw, 0, u->stream>>>(P, u->y, target, u->gy, u->lpart);
+    k_mse<<<nb, kEw, 0, u->stream>>>(P, u->h * u->w, u->y, target, weight, u->gy, u->lpart);
     k_loss_reduce<<<1, kEw, 0, u->stream>>>(u->lpart, nb, P, u->loss_dev);
     UNET_LAUNCHED();
     rc = backward(u, batch);
@@ -427,9 +428,9 @@ int32_t ibm_unet_adam_step(ibm_unet* u, float lr, float beta1, float beta2, floa
     return IBM_OK;
 }
 
-int32_t ibm_unet_train_step(ibm_unet* u, const float* x, const float* target, int32_t batch, float lr,
-                            float* loss) {
-    const int32_t rc = ibm_unet_loss_grad(u, x, target, batch, loss);
+int32_t ibm_unet_train_step(ibm_unet* u, const float* x, const float* target, const float* weight, int32_t batch,
+                            float lr, float* loss) {
+    const int32_t rc = ibm_unet_loss_grad(u, x, target, weight, batch, loss);
     if (rc) return rc;
     return ibm_unet_adam_step(u, lr, 0.9f, 0.999f, 1e-8f);
 }

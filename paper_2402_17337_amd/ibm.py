@@ -29,7 +29,9 @@ INIT_ZERO, INIT_PREVIOUS, INIT_LEARNED = 0, 1, 2
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
                 KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_mp_refine"}
-OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y = range(4)
+(OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y, OPT_NET_FACTOR, OPT_NET_EVERY, OPT_SNAPSHOT_ITER,
+ OPT_NET_SMOOTH, OPT_NET_STEP) = range(9)
+NET_STEP_ENERGY, NET_STEP_BACKTRACK = 0, 1
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
@@ -58,9 +60,9 @@ class Params(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("p_iters", C.c_int32), ("u_iters", C.c_int32),
                 ("v_iters", C.c_int32), ("n_forced_u", C.c_int32), ("n_forced_v", C.c_int32),
-                ("n_msrc", C.c_int32), ("reserved", C.c_int32),
+                ("n_msrc", C.c_int32), ("n_net", C.c_int32),
                 ("p_r0", C.c_double), ("p_rel", C.c_double), ("cd", C.c_double), ("cl", C.c_double),
-                ("t", C.c_double), ("seconds", C.c_double)]
+                ("t", C.c_double), ("seconds", C.c_double), ("net_step", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -292,10 +294,13 @@ class Solver:
             self._err("ibm_set_warm_start", rc)
 
     def set_snapshot(self, feat=None, target=None, out_scale: float = 1.0):
-        """Record each step's network maps into feat (3, ny, nx) and its target
-        into target (ny, nx), float32 device tensors; None clears."""
+        """Record each step's network maps into feat (3, ny/F, nx/F) and its
+        target into target (ny/F, nx/F), float32 device tensors (F: the
+        network's coarsening factor); None clears."""
         ptrs = []
-        for t, shp in ((feat, (3, self.ny, self.nx)), (target, (self.ny, self.nx))):
+        f = getattr(self, "net_f", 1)
+        ny, nx = self.ny // f, self.nx // f
+        for t, shp in ((feat, (3, ny, nx)), (target, (ny, nx))):
             if t is None:
                 ptrs.append(None)
                 continue
@@ -308,8 +313,12 @@ class Solver:
             self._err("ibm_set_snapshot", rc)
 
     def set_option(self, option: int, value: int) -> int:
-        """Tuning option (launch shape of the SOR sweeps); returns the status."""
-        return lib().ibm_set_option(self._h, option, int(value))
+        """Tuning option (launch shape of the SOR sweeps, the network's grid and
+        correction interval); returns the status."""
+        rc = lib().ibm_set_option(self._h, option, int(value))
+        if rc == OK and option == OPT_NET_FACTOR:
+            self.net_f = int(value)
+        return rc
 
     # -- stand-alone Poisson solve ------------------------------------------
     def poisson_solve(self, rhs, x, method=RBSOR, omega=1.8, tol=1e-8, max_iter=2_000_000,

@@ -47,11 +47,11 @@ def lib():
             getattr(L, f).restype = i32
         L.ibm_unet_forward.argtypes = [vp, vp, vp, i32]
         L.ibm_unet_forward.restype = i32
-        L.ibm_unet_loss_grad.argtypes = [vp, vp, vp, i32, fp]
+        L.ibm_unet_loss_grad.argtypes = [vp, vp, vp, vp, i32, fp]
         L.ibm_unet_loss_grad.restype = i32
         L.ibm_unet_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
         L.ibm_unet_adam_step.restype = i32
-        L.ibm_unet_train_step.argtypes = [vp, vp, vp, i32, C.c_float, fp]
+        L.ibm_unet_train_step.argtypes = [vp, vp, vp, vp, i32, C.c_float, fp]
         L.ibm_unet_train_step.restype = i32
         L.ibm_unet_destroy.argtypes = [vp]
         L.ibm_unet_destroy.restype = None
@@ -173,12 +173,14 @@ class UNet:
             self._err("ibm_unet_forward", rc)
         return y
 
-    def loss_grad(self, x, target) -> float:
+    def loss_grad(self, x, target, weight=None) -> float:
         b = x.shape[0]
         _check_f32_cuda(x, (b, IN_CHANNELS, self.h, self.w), "x")
         _check_f32_cuda(target, (b, 1, self.h, self.w), "target")
+        if weight is not None:
+            _check_f32_cuda(weight, (b,), "weight")
         loss = C.c_float()
-        rc = lib().ibm_unet_loss_grad(self._h, _ptr(x), _ptr(target), b, C.byref(loss))
+        rc = lib().ibm_unet_loss_grad(self._h, _ptr(x), _ptr(target), _ptr(weight), b, C.byref(loss))
         if rc:
             self._err("ibm_unet_loss_grad", rc)
         return float(loss.value)
@@ -188,12 +190,14 @@ class UNet:
         if rc:
             self._err("ibm_unet_adam_step", rc)
 
-    def train_step(self, x, target, lr, want_loss=True):
+    def train_step(self, x, target, lr, want_loss=True, weight=None):
         b = x.shape[0]
         _check_f32_cuda(x, (b, IN_CHANNELS, self.h, self.w), "x")
         _check_f32_cuda(target, (b, 1, self.h, self.w), "target")
+        if weight is not None:
+            _check_f32_cuda(weight, (b,), "weight")
         loss = C.c_float()
-        rc = lib().ibm_unet_train_step(self._h, _ptr(x), _ptr(target), b, lr,
+        rc = lib().ibm_unet_train_step(self._h, _ptr(x), _ptr(target), _ptr(weight), b, lr,
                                        C.byref(loss) if want_loss else None)
         if rc:
             self._err("ibm_unet_train_step", rc)

@@ -30,32 +30,76 @@ def solver_for(wl: dict, **over):
     return ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **prm)
 
 
-def collect(wl: dict, cases, steps: int, keep_from: int = 1, method=ibm.PCG):
-    """Run each case (a dict of parameter overrides of the workload) for
-    `steps` steps with snapshots on; keep the snapshots of steps >= keep_from
-    (1-based).  Returns float32 device tensors feats (N, 3, ny, nx) and
-    targets (N, 1, ny, nx), targets in units of RMS(r0), and the solver
-    seconds spent."""
+def _net_options(s, factor):
+    if s.set_option(ibm.OPT_NET_FACTOR, factor) != ibm.OK:
+        raise ValueError(f"coarsening factor {factor} does not divide the grid")
+
+
+def collect(wl: dict, cases, steps: int, keep_from: int = 1, factor: int = 1, snap_iters=(0,), policy=None):
+    """Snapshots of the network's maps and targets on the grid coarsened by
+    `factor`.  Each case (a dict of parameter overrides of the workload) is
+    advanced `steps` steps by PCG; for every step >= keep_from (1-based) and
+    every k in snap_iters one snapshot is taken: k = 0 at the start of the
+    solve (phi_s = phi^n), k > 0 after k red-black SOR iterations from phi^n
+    (PCG finishes that solve).  With a policy (dict: params, out_scale,
+    every, options) the k > 0 snapshots follow the solve that network guides:
+    learned guess and a correction every `every` iterations, so that the
+    snapshots show the states the network meets in use.  Returns float32
+    device tensors feats
+    (N, 3, ny/F, nx/F) and targets (N, 1, ny/F, nx/F), targets in units of
+    s_r, the k of each snapshot, and the seconds spent."""
     import torch
-    ny, nx = wl["ny"], wl["nx"]
-    feats, targets = [], []
+    ny, nx = wl["ny"] // factor, wl["nx"] // factor
+    feats, targets, ks = [], [], []
     t0 = time.perf_counter()
     for case in cases:
-        s = solver_for(wl, p_method=method, p_init_prev=ibm.INIT_PREVIOUS, **case)
-        f = torch.empty((3, ny, nx), dtype=torch.float32, device=s.device)
-        t = torch.empty((ny, nx), dtype=torch.float32, device=s.device)
-        s.set_snapshot(f, t, 1.0)
-        for k in range(1, steps + 1):
-            st = s.step(1)
+        drv = solver_for(wl, p_method=ibm.PCG, p_init_prev=ibm.INIT_PREVIOUS, **case)
+        _net_options(drv, factor)
+        mid = solver_for(wl, p_method=ibm.RBSOR,
+                         p_init_prev=ibm.INIT_LEARNED if policy else ibm.INIT_PREVIOUS, **case) \
+            if any(k > 0 for k in snap_iters) else None
+        if mid is not None:
+            _net_options(mid, factor)
+            if policy:
+                pnet = U.UNet(1, ny, nx, device=mid.device, stream=mid.stream)
+                pnet.set_params(policy["params"])
+                opts = dict(policy.get("options") or {})
+                opts[ibm.OPT_NET_EVERY] = policy["every"]
+                for opt, val in opts.items():
+                    if mid.set_option(opt, val) != ibm.OK:
+                        raise ValueError(f"option {opt} = {val}")
+                mid.set_warm_start(pnet, policy["out_scale"])
+        f = torch.empty((3, ny, nx), dtype=torch.float32, device=drv.device)
+        t = torch.empty((ny, nx), dtype=torch.float32, device=drv.device)
+        for step in range(1, steps + 1):
+            keep = step >= keep_from
+            blob = drv.get_state() if keep and mid is not None else None
+            drv.set_snapshot(f, t, 1.0) if keep and 0 in snap_iters else drv.set_snapshot(None, None)
+            st = drv.step(1)
             if st["rc"] < 0:
-                raise ibm.IbmError(f"snapshot run failed at step {k}: {ibm.status_string(st['rc'])}")
-            if k >= keep_from:
+                raise ibm.IbmError(f"snapshot run failed at step {step}: {ibm.status_string(st['rc'])}")
+            if keep and 0 in snap_iters:
                 feats.append(f.clone())
                 targets.append(t.clone().unsqueeze(0))
-        s.set_snapshot(None, None)
-        s.close()
+                ks.append(0)
+            for k in snap_iters:
+                if k <= 0 or not keep:
+                    continue
+                mid.set_state(blob)
+                if mid.set_option(ibm.OPT_SNAPSHOT_ITER, k) != ibm.OK:
+                    raise ValueError(f"snapshot iteration {k}: not a multiple of the check interval")
+                mid.set_snapshot(f, t, 1.0)
+                st = mid.step(1)
+                if st["rc"] < 0:
+                    raise ibm.IbmError(f"snapshot run failed at step {step}, k {k}")
+                feats.append(f.clone())
+                targets.append(t.clone().unsqueeze(0))
+                ks.append(k)
+        drv.close()
+        if mid is not None:
+            mid.close()
     torch.cuda.synchronize()
-    return torch.stack(feats), torch.stack(targets), time.perf_counter() - t0
+    return torch.stack(feats), torch.stack(targets), np.array(ks), time.perf_counter() - t0
 
 
 def plunge_cases(n: int, seed: int):
@@ -85,28 +129,33 @@ def crops(feats, targets, batch: int, size_y: int, size_x: int, rng):
 
 
 def train(net: U.UNet, feats, targets, iters: int, lr: float = 1e-3, lr_end: float = 1e-4, seed: int = 0,
-          log_every: int = 0):
+          log_every: int = 0, relative: bool = False):
     """Adam on random crops of the snapshots (crop shape = the network's
-    shape); cosine learning-rate decay from lr to lr_end.  Returns the loss
+    shape); cosine learning-rate decay from lr to lr_end.  relative: each
+    image's squared error is divided by its target's mean square (a relative
+    error per image, for targets whose sizes span decades).  Returns the loss
     history (every log_every iterations, and the last)."""
     rng = np.random.default_rng(seed)
     hist = []
     for k in range(iters):
         x, t = crops(feats, targets, net.max_batch, net.h, net.w, rng)
+        w = 1.0 / t.pow(2).mean(dim=(1, 2, 3)).clamp_min(1e-30) if relative else None
         a = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / max(iters - 1, 1)))
         want = (log_every and k % log_every == 0) or k == iters - 1
-        loss = net.train_step(x, t, a, want_loss=bool(want))
+        loss = net.train_step(x, t, a, want_loss=bool(want), weight=w)
         if want:
             hist.append((k, loss))
     return hist
 
 
 def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, method=ibm.RBSOR,
-             warm_method=ibm.PCG, eval_steps: int = 1, modes=(ibm.INIT_ZERO, ibm.INIT_PREVIOUS, ibm.INIT_LEARNED)):
+             warm_method=ibm.PCG, eval_steps: int = 1, modes=(ibm.INIT_ZERO, ibm.INIT_PREVIOUS, ibm.INIT_LEARNED),
+             factor: int = 1, every: int = 0, options=None):
     """Advance the workload warm_steps steps (warm_method), then run
-    eval_steps steps from that same state with each initial guess of `modes`;
-    returns {mode: [step statistics]} (iterations, initial and final relative
-    residuals, seconds of the whole step including the network)."""
+    eval_steps steps from that same state with each initial guess of `modes`
+    (the learned mode also corrects every `every` SOR iterations when every >
+    0, with the extra solver options given); returns {mode: [step statistics]} (iterations, initial and final
+    relative residuals, seconds of the whole step including the network)."""
     base = solver_for(wl, p_method=warm_method, p_init_prev=ibm.INIT_PREVIOUS)
     for _ in range(warm_steps):
         base.step(1)
@@ -118,7 +167,13 @@ def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, me
         s = solver_for(wl, p_method=method, p_init_prev=mode)
         s.set_state(blob)
         if mode == ibm.INIT_LEARNED:
-            net = U.UNet(1, wl["ny"], wl["nx"], device=s.device, stream=s.stream)
+            _net_options(s, factor)
+            if every and s.set_option(ibm.OPT_NET_EVERY, every) != ibm.OK:
+                raise ValueError(f"correction interval {every}")
+            for opt, val in (options or {}).items():
+                if s.set_option(opt, val) != ibm.OK:
+                    raise ValueError(f"option {opt} = {val}")
+            net = U.UNet(1, wl["ny"] // factor, wl["nx"] // factor, device=s.device, stream=s.stream)
             net.set_params(params)
             s.set_warm_start(net, out_scale)
         out[mode] = [s.step(1) for _ in range(eval_steps)]

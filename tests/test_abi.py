@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
     # field order and sizes of the mirrored structs (the header is the contract)
     import ctypes as C
     assert C.sizeof(ibm.Params) == 4 * 4 + 10 * 8 + 4 * 4 + 4 * 8 + 2 * 4 + 8 + 2 * 4
-    assert C.sizeof(ibm.StepStats) == 8 * 4 + 6 * 8
+    assert C.sizeof(ibm.StepStats) == 8 * 4 + 7 * 8
     assert C.sizeof(ibm.SolveOpts) == 4 * 4 + 2 * 8
     assert C.sizeof(ibm.SolveStats) == 4 * 4 + 3 * 8
 

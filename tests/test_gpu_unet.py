@@ -153,16 +153,17 @@ def test_network_batch_subset_is_bitwise_the_same():
     assert np.array_equal(y1[0], y3[1])
 
 
-def test_network_loss_and_gradients_match_oracle():
+@pytest.mark.parametrize("weight", [None, (0.25, 3.0)])
+def test_network_loss_and_gradients_match_oracle(weight):
     _need_gpu()
     from paper_2402_17337_amd import unet as U
     B, H, W = 2, 16, 64
     p, x, t = _problem(3, B, H, W)
     net = U.UNet(B, H, W)
     net.set_params(p)
-    loss = net.loss_grad(_dev(x), _dev(t))
+    loss = net.loss_grad(_dev(x), _dev(t), None if weight is None else _dev(np.array(weight)))
     g = U.unflatten_params(net.get_grads().astype(np.float64))
-    ref_loss, ref_g, _ = OU.loss_and_grads(_bf_params(p), _bf(x), np.float32(t).astype(np.float64))
+    ref_loss, ref_g, _ = OU.loss_and_grads(_bf_params(p), _bf(x), np.float32(t).astype(np.float64), weight)
     assert abs(loss - ref_loss) <= 3e-2 * ref_loss
     worst = max((_rel(g[k], ref_g[k]), k) for k in ref_g)
     assert worst[0] < 8e-2, worst

@@ -137,7 +137,7 @@ def test_collect_and_train_pipeline_reduces_the_loss():
     from paper_2402_17337_amd import unet as U
     from paper_2402_17337_amd import warmstart as WS
     wl = _wl()
-    feats, targets, _ = WS.collect(wl, [dict(), dict(phase=1.0)], steps=4, keep_from=2)
+    feats, targets, ks, _ = WS.collect(wl, [dict(), dict(phase=1.0)], steps=4, keep_from=2)
     assert feats.shape == (6, 3, wl["ny"], wl["nx"]) and targets.shape == (6, 1, wl["ny"], wl["nx"])
     c = float(targets.pow(2).mean().sqrt())
     net = U.UNet(4, 32, 64)
@@ -146,3 +146,95 @@ def test_collect_and_train_pipeline_reduces_the_loss():
     first = np.mean([l for _, l in hist[:5]])
     last = np.mean([l for _, l in hist[-5:]])
     assert np.isfinite(last) and last < first, (first, last)
+
+
+def test_mid_solve_snapshot_target_matches_its_maps():
+    # k SOR iterations into the solve: map 0 is the residual of the iterate,
+    # the target the rest of the change; A(target) reproduces map 0
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _wl()
+    nx, ny = wl["nx"], wl["ny"]
+    s = _solver(wl, p_method=ibm.RBSOR)
+    s.step(2)
+    assert s.set_option(ibm.OPT_SNAPSHOT_ITER, 200) == ibm.OK
+    assert s.set_option(ibm.OPT_SNAPSHOT_ITER, 205) == ibm.ERR_INVALID  # not a multiple of the check interval
+    f = torch.empty((3, ny, nx), dtype=torch.float32, device="cuda:0")
+    t = torch.empty((ny, nx), dtype=torch.float32, device="cuda:0")
+    s.set_snapshot(f, t, 1.0)
+    st = s.step(1)
+    assert st["rc"] == ibm.OK and st["p_rel"] <= wl["params"]["p_tol"]
+    f, t = f.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    orc = O.Oracle(nx, ny, wl["xf"], wl["yf"], **wl["params"])
+    At = orc.apply_A(t)
+    assert np.linalg.norm(At - f[0]) <= 1e-4 * np.linalg.norm(f[0])
+
+
+def test_coarse_maps_are_block_averages():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _wl()
+    nx, ny, F = wl["nx"], wl["ny"], 2
+    s = _solver(wl, p_method=ibm.PCG)
+    s.step(2)
+    assert s.set_option(ibm.OPT_NET_FACTOR, 3) == ibm.ERR_INVALID
+    assert s.set_option(ibm.OPT_NET_FACTOR, F) == ibm.OK
+    f = torch.empty((3, ny // F, nx // F), dtype=torch.float32, device="cuda:0")
+    t = torch.empty((ny // F, nx // F), dtype=torch.float32, device="cuda:0")
+    s.set_snapshot(f, t, 1.0)
+    phi_old = s.fields()[3]
+    s.step(1)
+    phi_new = s.fields()[3]
+    f, t = f.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+
+    def block(a):
+        return a.reshape(ny // F, F, nx // F, F).mean(axis=(1, 3))
+    pc = block(phi_old)
+    assert np.max(np.abs(f[1] - pc / np.sqrt(np.mean(pc ** 2)))) <= 1e-6 * np.max(np.abs(f[1]))
+    dc = block(phi_new - phi_old)
+    scale = np.sum(dc * t) / np.sum(t * t)
+    assert np.linalg.norm(dc - scale * t) <= 1e-6 * np.linalg.norm(dc)
+    assert np.all((f[2] >= 0) & (f[2] <= 1)) and np.any((f[2] > 0) & (f[2] < 1))
+
+
+def test_zero_network_corrections_reproduce_plain_sor_bitwise():
+    # corrections split the solve into segments; with a zero network each
+    # segment continues the same iterates, so nothing may change
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    assert b.set_option(ibm.OPT_NET_FACTOR, 2) == ibm.OK
+    assert b.set_option(ibm.OPT_NET_EVERY, 100) == ibm.OK
+    net = U.UNet(1, wl["ny"] // 2, wl["nx"] // 2, stream=b.stream)
+    net.set_params(np.zeros(U.param_count(), np.float32))
+    b.set_warm_start(net, 1.0)
+    for _ in range(3):
+        sa, sb = a.step(1), b.step(1)
+        assert sa["p_iters"] == sb["p_iters"] and sa["p_iters"] > 100
+        assert sa["p_r0"] == sb["p_r0"] and sa["p_rel"] == sb["p_rel"]
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+
+
+def test_random_network_corrections_still_converge():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    assert b.set_option(ibm.OPT_NET_FACTOR, 2) == ibm.OK
+    assert b.set_option(ibm.OPT_NET_EVERY, 200) == ibm.OK
+    net = U.UNet(1, wl["ny"] // 2, wl["nx"] // 2, stream=b.stream)
+    net.set_params(U.flatten_params(OU.init_params(8)))
+    b.set_warm_start(net, 0.1)
+    for _ in range(3):
+        sa, sb = a.step(1), b.step(1)
+        assert sb["rc"] == ibm.OK and sb["p_rel"] <= wl["params"]["p_tol"]
+    ua, va, _, _ = a.fields()
+    ub, vb, _, _ = b.fields()
+    for x, y in ((ua, ub), (va, vb)):
+        assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)

@@ -112,3 +112,21 @@ def test_adam_step_by_hand():
     np.testing.assert_allclose(p1, p - 0.1 * np.sign(g), rtol=1e-7)
     np.testing.assert_allclose(m1, 0.1 * g)
     np.testing.assert_allclose(v1, 0.001 * g * g)
+
+
+def test_weighted_loss_is_the_per_image_weighted_mean():
+    # weights (1, 0) keep only the first image: the batch mean over 2 images
+    # is half the mean of that image alone, and so are its gradients
+    rng = np.random.default_rng(9)
+    p = U.init_params(9)
+    x = rng.standard_normal((2, 3, 16, 16))
+    t = rng.standard_normal((2, 1, 16, 16))
+    lw, gw, _ = U.loss_and_grads(p, x, t, weight=(1.0, 0.0))
+    l1, g1, _ = U.loss_and_grads(p, x[:1], t[:1])
+    assert abs(lw - 0.5 * l1) <= 1e-12 * l1
+    for k in g1:
+        np.testing.assert_allclose(gw[k], 0.5 * g1[k], rtol=1e-10, atol=1e-14)
+    lu, _, _ = U.loss_and_grads(p, x, t)
+    lo, _, _ = U.loss_and_grads(p, x, t, weight=(1.0, 1.0))
+    assert lu == lo
+
