@@ -10,7 +10,9 @@ solve to a relative residual of 1e-8, projection and forces.
 
 Reported: Poisson cell-updates/s over the timed steps (nx*ny*iterations /
 wall time; `value`), seconds per time step, the dominant kernel against the
-HBM roofline (HIP events on the solver stream), a Jacobi-PCG leg, and the CPU
+HBM roofline (HIP events on the solver stream), a Jacobi-PCG leg, the
+mixed-precision SOR leg, the learned warm start and correction (network
+trained on the GPU in the run, then the same steps timed with it), and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -69,15 +71,29 @@ def build_if_missing():
         __graft_entry__.build()
 
 
-def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0):
+def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None, net=None, keep_fields=False):
+    """Time `steps` steps after `warmup` untimed ones.  p_init overrides the
+    initial guess; net = (params, out_scale, factor, every, options) attaches
+    a trained warm-start network."""
     import torch
     from paper_2402_17337_amd import ibm
 
     prm = dict(case["params"], p_method=method)
     if max_iters > 0:
         prm["p_max_iter"] = max_iters
+    if p_init is not None:
+        prm["p_init_prev"] = p_init
     g = ibm.Solver(case["nx"], case["ny"], case["xf"], case["yf"], case["u0"], case["v0"], case["p0"],
                    device="cuda:0", **prm)
+    if net is not None:
+        from paper_2402_17337_amd import unet as U
+        params, out_scale, factor, every, opts = net
+        for opt, val in [(ibm.OPT_NET_FACTOR, factor), (ibm.OPT_NET_EVERY, every)] + list(opts.items()):
+            if g.set_option(opt, val) != ibm.OK:
+                raise RuntimeError(f"solver option {opt} = {val} rejected")
+        unet = U.UNet(1, case["ny"] // factor, case["nx"] // factor, stream=g.stream)
+        unet.set_params(params)
+        g.set_warm_start(unet, out_scale)
     for _ in range(warmup):
         st = g.step(1)
         if st["rc"] < 0:
@@ -95,10 +111,63 @@ def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = {k: g.profile_query(k) for k in ibm.KERNEL_NAMES}
+    fields = g.fields() if keep_fields else None
     g.close()
     cells = case["nx"] * case["ny"]
-    return dict(wall=wall, iters=iters, stats=stats, prof=prof,
+    return dict(wall=wall, iters=iters, stats=stats, prof=prof, fields=fields,
                 cell_updates_per_s=cells * sum(iters) / wall if wall > 0 else 0.0)
+
+
+def learned_legs(case, args, sor_leg):
+    """Train the warm-start network on the GPU (two rounds, see
+    paper_2402_17337_amd.warmstart.train_default), then time the same steps as
+    the headline leg with the zero guess, the learned guess alone, and the
+    learned correction every args.learned_every SOR iterations (from the
+    previous step's phi, and from the learned guess); PCG with the learned
+    guess beside PCG's own legs."""
+    import numpy as np
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import warmstart as WS
+
+    F, every = args.learned_factor, args.learned_every
+    t0 = time.perf_counter()
+    params, scale, info = WS.train_default(case, factor=F, every=every, iters=args.learned_train_iters)
+    opts = WS.RECIPE_OPTIONS
+    info["total_s"] = round(time.perf_counter() - t0, 2)
+    base_s = sor_leg["wall"] / args.steps
+    out = {"network": f"4-level U-Net 16/32/64/128, BF16 matrix cores, on the grid coarsened {F}x "
+                      f"({case['nx'] // F}x{case['ny'] // F})",
+           "training": info, "out_scale": scale,
+           "reference": {"initial_guess": "previous phi", "s_per_time_step": round(base_s, 6),
+                         "poisson_iters_per_step": sor_leg["iters"]}}
+    legs = (("zero_guess", ibm.INIT_ZERO, None),
+            ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts)),
+            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts)),
+            ("learned_guess_and_correction", ibm.INIT_LEARNED, (params, scale, F, every, opts)))
+    ref = sor_leg["fields"]
+    for name, p_init, net in legs:
+        leg = gpu_leg(case, ibm.RBSOR, args.steps, args.warmup, 0, p_init=p_init, net=net,
+                      keep_fields=ref is not None)
+        s_step = leg["wall"] / args.steps
+        d = {"s_per_time_step": round(s_step, 6), "poisson_iters_per_step": leg["iters"],
+             "final_rel_residual": [st["p_rel"] for st in leg["stats"]],
+             "speedup_vs_previous_guess": round(base_s / s_step, 3) if s_step > 0 else None}
+        if net is not None:
+            d["network_steps_per_time_step"] = [st["n_net"] for st in leg["stats"]]
+            d["mean_step_length"] = [round(st["net_step"], 4) for st in leg["stats"]]
+            if net[3]:
+                d["correction_every"] = net[3]
+        if ref is not None and leg["fields"] is not None:
+            d["rel_l2_vs_previous_guess_run"] = {
+                k: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+                for k, a, b in zip(("u", "v", "p"), leg["fields"][:3], ref[:3])}
+        out[name] = d
+    if args.pcg_steps > 0:
+        leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, 0, p_init=ibm.INIT_LEARNED,
+                      net=(params, scale, F, 0, opts))
+        out["pcg_learned_guess"] = {"s_per_time_step": round(leg["wall"] / args.pcg_steps, 6),
+                                    "poisson_iters_per_step": leg["iters"]}
+    return out
 
 
 def stress_leg(nx=8192, ny=6144, iters=60):
@@ -196,6 +265,12 @@ def main():
                          "(same kernels and launch shapes; the line is then marked capped)")
     ap.add_argument("--stress", type=int, default=1,
                     help="1: also time the SOR kernels on the HBM-resident 8192x6144 grid")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="1: train the warm-start network on the GPU and time the learned guess and correction")
+    ap.add_argument("--learned-every", type=int, default=4000,
+                    help="SOR iterations between learned corrections")
+    ap.add_argument("--learned-factor", type=int, default=8, help="coarsening factor of the network's grid")
+    ap.add_argument("--learned-train-iters", type=int, default=3000, help="Adam iterations per training round")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of this many MiB, 20 times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -226,7 +301,9 @@ def main():
     case = W.plunging_1024x768()
     tag = "plunging1024x768"
     method = ibm.RBSOR if args.solver == "sor" else ibm.PCG
-    main_leg = gpu_leg(case, method, args.steps, args.warmup, args.profile_every, args.max_poisson_iters)
+    learned = args.learned and args.solver == "sor" and not args.max_poisson_iters
+    main_leg = gpu_leg(case, method, args.steps, args.warmup, args.profile_every, args.max_poisson_iters,
+                       keep_fields=learned)
     pcg_leg = None
     if args.solver == "sor" and args.pcg_steps > 0:
         pcg_leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, args.profile_every,
@@ -313,6 +390,8 @@ def main():
                                              f"Poisson solve capped at {args.c3_iters} iterations",
                                 speedup_per_iteration=round(c3["f64"]["us_per_iteration"] /
                                                             max(c3["mixed"]["us_per_iteration"], 1e-9), 3))
+    if learned:
+        out["learned"] = learned_legs(case, args, main_leg)
     if args.stress:
         out["stress_hbm"] = stress_leg()
     if args.cpu_seconds > 0:

@@ -313,6 +313,9 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
                            the solve continues as plain SOR. */
 #define IBM_NET_STEP_ENERGY 0
 #define IBM_NET_STEP_BACKTRACK 1
+#define IBM_OPT_NET_MAPS 9    /* maps given to the network, bit k = map k, 1..7
+                                 (default 7); the others are zero, also in
+                                 snapshots */
 #define IBM_SOR_TEMPORAL 0
 #define IBM_SOR_PER_COLOUR 1
 #define IBM_SOR_TEMPORAL_LDS 2

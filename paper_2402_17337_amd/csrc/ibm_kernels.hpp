@@ -1772,9 +1772,11 @@ __global__ __launch_bounds__(kWsThreads) void k_ws_coarse(Grid g, Coarse cg, Bod
 }
 
 // Scale maps 0 and 1 to unit RMS in place (every block sums the partials;
-// block 0 stores (s_r, s_phi) in scale, a zero RMS replaced by 1).
+// block 0 stores (s_r, s_phi) in scale, a zero RMS replaced by 1) and zero
+// the maps whose bit is clear in `maps`.
 __global__ __launch_bounds__(kRedThreads) void k_ws_normalize(Coarse cg, const double* __restrict__ partials, int nb,
-                                                              double* __restrict__ scale, float* __restrict__ feat) {
+                                                              int maps, double* __restrict__ scale,
+                                                              float* __restrict__ feat) {
     __shared__ double lds[2 * kRedThreads / kWave];
     __shared__ float s_inv[2];
     double acc[2];
@@ -1783,8 +1785,8 @@ __global__ __launch_bounds__(kRedThreads) void k_ws_normalize(Coarse cg, const d
     if (threadIdx.x == 0) {
         const double sr = sqrt(acc[0] / (double)nc), sp = sqrt(acc[1] / (double)nc);
         const double a = sr > 0.0 ? sr : 1.0, b = sp > 0.0 ? sp : 1.0;
-        s_inv[0] = (float)(1.0 / a);
-        s_inv[1] = (float)(1.0 / b);
+        s_inv[0] = (maps & 1) ? (float)(1.0 / a) : 0.0f;
+        s_inv[1] = (maps & 2) ? (float)(1.0 / b) : 0.0f;
         if (blockIdx.x == 0) {
             scale[0] = a;
             scale[1] = b;
@@ -1794,6 +1796,7 @@ __global__ __launch_bounds__(kRedThreads) void k_ws_normalize(Coarse cg, const d
     for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += (size_t)gridDim.x * blockDim.x) {
         feat[q] *= s_inv[0];
         feat[nc + q] *= s_inv[1];
+        if (!(maps & 4)) feat[2 * nc + q] = 0.0f;
     }
 }
 

@@ -177,6 +177,7 @@ struct ibm_ctx {
     int net_every = 0;   // SOR iterations between network corrections (0: none)
     int snap_iter = 0;   // SOR iterations before the snapshot is taken
     int net_smooth = 4;  // binomial passes over the network output
+    int net_maps = 7;    // maps given to the network (bit k: map k)
     int net_rule = IBM_NET_STEP_ENERGY;
     double net_step = 1.0;  // IBM_NET_STEP_BACKTRACK: current step
     double *f_u, *f_v, *coef, *partials;
@@ -887,7 +888,7 @@ int32_t net_maps(ibm_ctx* c, const Body& B) {
     hipLaunchKernelGGL(k_ws_coarse, dim3(nb), dim3(kWsThreads), 0, c->stream, c->g, cg, B, (const double*)c->phi,
                        (const double*)c->vb, c->wsf, c->partials);
     hipLaunchKernelGGL(k_ws_normalize, dim3(red_blocks(nc)), dim3(kRedThreads), 0, c->stream, cg,
-                       (const double*)c->partials, nb, c->wscale, c->wsf);
+                       (const double*)c->partials, nb, c->net_maps, c->wscale, c->wsf);
     LAUNCH_CHECK();
     return IBM_OK;
 }
@@ -1628,6 +1629,10 @@ int32_t ibm_set_option(ibm_ctx* c, int32_t option, int64_t value) {
                 return IBM_ERR_INVALID;
             }
             c->net_f = (int)value;
+            return IBM_OK;
+        case IBM_OPT_NET_MAPS:
+            if (value < 1 || value > 7) return IBM_ERR_INVALID;
+            c->net_maps = (int)value;
             return IBM_OK;
         case IBM_OPT_NET_SMOOTH:
             if (value < 0 || value > 16) return IBM_ERR_INVALID;

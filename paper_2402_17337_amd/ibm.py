@@ -30,7 +30,7 @@ KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_res
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
                 KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_mp_refine"}
 (OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y, OPT_NET_FACTOR, OPT_NET_EVERY, OPT_SNAPSHOT_ITER,
- OPT_NET_SMOOTH, OPT_NET_STEP) = range(9)
+ OPT_NET_SMOOTH, OPT_NET_STEP, OPT_NET_MAPS) = range(10)
 NET_STEP_ENERGY, NET_STEP_BACKTRACK = 0, 1
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 

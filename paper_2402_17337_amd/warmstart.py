@@ -21,7 +21,6 @@ import numpy as np
 
 from . import ibm
 from . import unet as U
-from . import workloads as W
 
 
 def solver_for(wl: dict, **over):
@@ -30,22 +29,27 @@ def solver_for(wl: dict, **over):
     return ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **prm)
 
 
-def _net_options(s, factor):
+def _net_options(s, factor, options=None):
     if s.set_option(ibm.OPT_NET_FACTOR, factor) != ibm.OK:
         raise ValueError(f"coarsening factor {factor} does not divide the grid")
+    for opt, val in (options or {}).items():
+        if s.set_option(opt, val) != ibm.OK:
+            raise ValueError(f"option {opt} = {val}")
 
 
-def collect(wl: dict, cases, steps: int, keep_from: int = 1, factor: int = 1, snap_iters=(0,), policy=None):
+def collect(wl: dict, cases, steps: int, keep_from: int = 1, factor: int = 1, snap_iters=(0,), policy=None,
+            options=None):
     """Snapshots of the network's maps and targets on the grid coarsened by
     `factor`.  Each case (a dict of parameter overrides of the workload) is
     advanced `steps` steps by PCG; for every step >= keep_from (1-based) and
     every k in snap_iters one snapshot is taken: k = 0 at the start of the
     solve (phi_s = phi^n), k > 0 after k red-black SOR iterations from phi^n
     (PCG finishes that solve).  With a policy (dict: params, out_scale,
-    every, options) the k > 0 snapshots follow the solve that network guides:
-    learned guess and a correction every `every` iterations, so that the
-    snapshots show the states the network meets in use.  Returns float32
-    device tensors feats
+    every, options, guess) the k > 0 snapshots follow the solve that network
+    guides: a correction every `every` iterations (and its guess at the start
+    when guess is true), so that the snapshots show the states the network
+    meets in use.  options: solver options of the network (e.g. its maps) for
+    every solver.  Returns float32 device tensors feats
     (N, 3, ny/F, nx/F) and targets (N, 1, ny/F, nx/F), targets in units of
     s_r, the k of each snapshot, and the seconds spent."""
     import torch
@@ -54,12 +58,13 @@ def collect(wl: dict, cases, steps: int, keep_from: int = 1, factor: int = 1, sn
     t0 = time.perf_counter()
     for case in cases:
         drv = solver_for(wl, p_method=ibm.PCG, p_init_prev=ibm.INIT_PREVIOUS, **case)
-        _net_options(drv, factor)
+        _net_options(drv, factor, options)
         mid = solver_for(wl, p_method=ibm.RBSOR,
-                         p_init_prev=ibm.INIT_LEARNED if policy else ibm.INIT_PREVIOUS, **case) \
+                         p_init_prev=ibm.INIT_LEARNED if policy and policy.get("guess") else ibm.INIT_PREVIOUS,
+                         **case) \
             if any(k > 0 for k in snap_iters) else None
         if mid is not None:
-            _net_options(mid, factor)
+            _net_options(mid, factor, options)
             if policy:
                 pnet = U.UNet(1, ny, nx, device=mid.device, stream=mid.stream)
                 pnet.set_params(policy["params"])
@@ -150,11 +155,12 @@ def train(net: U.UNet, feats, targets, iters: int, lr: float = 1e-3, lr_end: flo
 
 def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, method=ibm.RBSOR,
              warm_method=ibm.PCG, eval_steps: int = 1, modes=(ibm.INIT_ZERO, ibm.INIT_PREVIOUS, ibm.INIT_LEARNED),
-             factor: int = 1, every: int = 0, options=None):
+             factor: int = 1, every: int = 0, options=None, guess: bool = True):
     """Advance the workload warm_steps steps (warm_method), then run
     eval_steps steps from that same state with each initial guess of `modes`
     (the learned mode also corrects every `every` SOR iterations when every >
-    0, with the extra solver options given); returns {mode: [step statistics]} (iterations, initial and final
+    0, with the extra solver options given; guess=False keeps phi^n as its
+    initial guess and uses the network for the corrections only); returns {mode: [step statistics]} (iterations, initial and final
     relative residuals, seconds of the whole step including the network)."""
     base = solver_for(wl, p_method=warm_method, p_init_prev=ibm.INIT_PREVIOUS)
     for _ in range(warm_steps):
@@ -164,7 +170,8 @@ def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, me
     out = {}
     net = None
     for mode in modes:
-        s = solver_for(wl, p_method=method, p_init_prev=mode)
+        s = solver_for(wl, p_method=method,
+                       p_init_prev=ibm.INIT_PREVIOUS if mode == ibm.INIT_LEARNED and not guess else mode)
         s.set_state(blob)
         if mode == ibm.INIT_LEARNED:
             _net_options(s, factor)
@@ -182,3 +189,69 @@ def evaluate(wl: dict, params: np.ndarray, out_scale: float, warm_steps: int, me
 
 
 MODE_NAMES = {ibm.INIT_ZERO: "zero", ibm.INIT_PREVIOUS: "previous", ibm.INIT_LEARNED: "learned"}
+
+
+RECIPE_OPTIONS = {ibm.OPT_NET_MAPS: 5}  # residual and mask maps: no phi (see train_default)
+
+
+def train_default(wl: dict, factor: int = 8, every: int = 4000, cases: int = 16, seed: int = 1,
+                  iters: int = 3000, batch: int = 16, snap_iters=(200, 1000, 4000, 16000),
+                  policy_iters=(4000, 8000, 16000, 32000, 64000), rounds: int = 3, options=None, log=None):
+    """The training recipe of the learned correction, all on the GPU:
+    round 1 on snapshots of plain SOR solves (3 steps of `cases` seeded plunge
+    settings, snapshots at snap_iters); each later round on snapshots along
+    the solve the current network corrects every `every` iterations (one step
+    of `cases` other settings, snapshots at policy_iters), fine-tuning on all
+    snapshots so far.  The start of a solve (k = 0, the raw residual of
+    phi^n) is left out by default: its targets hold detail the coarse grid
+    cannot carry, and with it the relative loss can stall at the zero
+    prediction.  options: the network's solver options for every snapshot and
+    for use (default RECIPE_OPTIONS: without the phi map, whose shape the
+    network otherwise learns to copy on plain SOR iterates, a shortcut that
+    fails on the iterates its own corrections produce).  Returns (parameters,
+    out_scale, info)."""
+    import torch
+    say = log or (lambda *_: None)
+    options = RECIPE_OPTIONS if options is None else options
+    info = {"options": {int(k): int(v) for k, v in options.items()}}
+    ny, nx = wl["ny"] // factor, wl["nx"] // factor
+    f, t, ks, sec = collect(wl, plunge_cases(cases, seed), steps=3, factor=factor, snap_iters=snap_iters,
+                            options=options)
+    rms = t.pow(2).mean(dim=(1, 2, 3)).sqrt().cpu().numpy()
+    out_scale = float(np.median(rms))
+    t /= out_scale
+    net = U.UNet(batch, ny, nx)
+    net.set_params(he_uniform(seed))
+    rounds_info = []
+    for r in range(rounds):
+        if r > 0:
+            policy = dict(params=net.get_params(), out_scale=out_scale, every=every, guess=False,
+                          options=options)
+            f2, t2, _, sec = collect(wl, plunge_cases(cases, seed + r), steps=2, keep_from=2, factor=factor,
+                                     snap_iters=policy_iters, policy=policy, options=options)
+            f, t = torch.cat([f, f2]), torch.cat([t, t2 / out_scale])
+            del f2, t2
+        t0 = time.perf_counter()
+        hist = train(net, f, t, iters, lr=1e-3 if r == 0 else 3e-4, lr_end=1e-5, log_every=max(iters // 3, 1),
+                     relative=True, seed=seed + r)
+        torch.cuda.synchronize()
+        rounds_info.append({"snapshots": int(f.shape[0]), "collect_s": round(sec, 2),
+                            "train_s": round(time.perf_counter() - t0, 2),
+                            "loss": [(k, round(l, 5)) for k, l in hist]})
+        say(f"round {r + 1}: {rounds_info[-1]}")
+    info["rounds"] = rounds_info
+    params = net.get_params()
+    net.close()
+    return params, out_scale, info
+
+
+def he_uniform(seed: int) -> np.ndarray:
+    """Initial parameters: He-uniform weights (bound sqrt(6 / fan_in)) and
+    zero biases from a seeded generator, in the parameter-vector layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, ci, co, _ in U.LAYERS:
+        bound = math.sqrt(6.0 / (ci * 9))
+        parts.append(rng.uniform(-bound, bound, size=co * ci * 9).astype(np.float32))
+        parts.append(np.zeros(co, np.float32))
+    return np.concatenate(parts)

@@ -160,6 +160,17 @@ def plunging_2048x1536():
                  grid_info=dict(x=ix, y=iy), re=1000.0, dt=5e-4, amp=0.6, freq=0.5)
 
 
+def plunging_stretched(nx: int, ny: int, core_h: float):
+    """The 1024x768 plunging case (h = 0.5, f = 0.4, Re 500, dt 5e-4) on another
+    grid of the same construction: uniform spacing core_h on the core
+    [3, 5.5] x [5.2, 6.8], stretched geometrically outward."""
+    xf, ix = stretched_faces(nx, 16.0, 3.0, 5.5, core_h)
+    yf, iy = stretched_faces(ny, 12.0, 5.2, 6.8, core_h)
+    u0, v0, p0 = initial_fields(nx, ny, 1.0)
+    return _pack(f"plunging ellipse {nx}x{ny}, Re 500", nx, ny, xf, yf, u0, v0, p0, 2000,
+                 grid_info=dict(x=ix, y=iy), re=500.0, dt=5e-4, amp=0.5, freq=0.4)
+
+
 def small_plunging(nx=64, ny=48, seed=0):
     """A small plunging case (uniform grid, visible body) for quick checks."""
     xf, yf = uniform_faces(nx, 8.0), uniform_faces(ny, 6.0)
