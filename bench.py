@@ -63,6 +63,11 @@ def read_traffic(kernel: str, workload_tag: str):
         return None
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def build_if_missing():
     from paper_2402_17337_amd import ibm
     from oracle import oracle as O
@@ -110,6 +115,8 @@ def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None
         stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"{case['nx']}x{case['ny']} method {method} p_init {prm.get('p_init_prev')} "
+        f"net {'yes' if net is not None else 'no'}: {steps} steps in {wall:.2f} s, iterations {iters}")
     prof = {k: g.profile_query(k) for k in ibm.KERNEL_NAMES}
     fields = g.fields() if keep_fields else None
     g.close()
@@ -131,7 +138,7 @@ def learned_legs(case, args, sor_leg):
 
     F, every = args.learned_factor, args.learned_every
     t0 = time.perf_counter()
-    params, scale, info = WS.train_default(case, factor=F, every=every, iters=args.learned_train_iters)
+    params, scale, info = WS.train_default(case, factor=F, every=every, iters=args.learned_train_iters, log=log)
     opts = WS.RECIPE_OPTIONS
     info["total_s"] = round(time.perf_counter() - t0, 2)
     base_s = sor_leg["wall"] / args.steps

@@ -138,13 +138,14 @@ def train(net: U.UNet, feats, targets, iters: int, lr: float = 1e-3, lr_end: flo
     """Adam on random crops of the snapshots (crop shape = the network's
     shape); cosine learning-rate decay from lr to lr_end.  relative: each
     image's squared error is divided by its target's mean square (a relative
-    error per image, for targets whose sizes span decades).  Returns the loss
+    error per image, for targets whose sizes span decades; targets are
+    expected near unit RMS, and weights are capped at 1e6).  Returns the loss
     history (every log_every iterations, and the last)."""
     rng = np.random.default_rng(seed)
     hist = []
     for k in range(iters):
         x, t = crops(feats, targets, net.max_batch, net.h, net.w, rng)
-        w = 1.0 / t.pow(2).mean(dim=(1, 2, 3)).clamp_min(1e-30) if relative else None
+        w = 1.0 / t.pow(2).mean(dim=(1, 2, 3)).clamp_min(1e-6) if relative else None
         a = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / max(iters - 1, 1)))
         want = (log_every and k % log_every == 0) or k == iters - 1
         loss = net.train_step(x, t, a, want_loss=bool(want), weight=w)
@@ -229,7 +230,9 @@ def train_default(wl: dict, factor: int = 8, every: int = 4000, cases: int = 16,
                           options=options)
             f2, t2, _, sec = collect(wl, plunge_cases(cases, seed + r), steps=2, keep_from=2, factor=factor,
                                      snap_iters=policy_iters, policy=policy, options=options)
-            f, t = torch.cat([f, f2]), torch.cat([t, t2 / out_scale])
+            t2 /= out_scale
+            keep = t2.pow(2).mean(dim=(1, 2, 3)).sqrt() > 1e-3  # a solve done before its snapshot: no target
+            f, t = torch.cat([f, f2[keep]]), torch.cat([t, t2[keep]])
             del f2, t2
         t0 = time.perf_counter()
         hist = train(net, f, t, iters, lr=1e-3 if r == 0 else 3e-4, lr_end=1e-5, log_every=max(iters // 3, 1),
