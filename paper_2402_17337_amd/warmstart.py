@@ -258,3 +258,40 @@ def he_uniform(seed: int) -> np.ndarray:
         parts.append(rng.uniform(-bound, bound, size=co * ci * 9).astype(np.float32))
         parts.append(np.zeros(co, np.float32))
     return np.concatenate(parts)
+
+
+def main(argv=None):
+    """Train the learned correction for the plunging 1024x768 workload on the
+    GPU and time the solve it guides against plain SOR from the previous
+    step's phi; prints one JSON line."""
+    import argparse
+    import json
+
+    from . import workloads
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--cases", type=int, default=16, help="plunge settings per training round")
+    ap.add_argument("--iters", type=int, default=3000, help="Adam iterations per round")
+    ap.add_argument("--rounds", type=int, default=3)
+    ap.add_argument("--every", type=int, default=4000, help="SOR iterations between corrections")
+    ap.add_argument("--factor", type=int, default=8, help="coarsening factor of the network's grid")
+    ap.add_argument("--warm-steps", type=int, default=1, help="steps before the timed one")
+    ap.add_argument("--baseline", type=int, default=1, help="1: also time plain SOR from the previous phi")
+    a = ap.parse_args(argv)
+    wl = workloads.plunging_1024x768()
+    t0 = time.perf_counter()
+    params, scale, info = train_default(wl, factor=a.factor, every=a.every, cases=a.cases, iters=a.iters,
+                                        rounds=a.rounds)
+    info["total_s"] = round(time.perf_counter() - t0, 2)
+    modes = (ibm.INIT_PREVIOUS, ibm.INIT_LEARNED) if a.baseline else (ibm.INIT_LEARNED,)
+    res = evaluate(wl, params, scale, warm_steps=a.warm_steps, method=ibm.RBSOR, modes=modes, factor=a.factor,
+                   every=a.every, guess=False, options=RECIPE_OPTIONS)
+    out = {"workload": wl["name"], "training": info,
+           "steps": {("previous_guess" if m == ibm.INIT_PREVIOUS else "learned_correction"):
+                     {k: v[0][k] for k in ("p_iters", "p_rel", "seconds", "n_net", "net_step")}
+                     for m, v in res.items()}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
