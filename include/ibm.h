@@ -254,6 +254,30 @@ int32_t ibm_set_warm_start(ibm_ctx* ctx, ibm_unet* net, double out_scale);
  * (both NULL). */
 int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, double out_scale);
 
+/* Batches: the pressure solves of many independent contexts (cases of
+ * different grids) advanced together, one blocked red-black SOR launch per
+ * IBM_OPT_TB_SWEEPS iterations sweeping the tiles of every case through one
+ * work list, with the stop test of every case taken in one check launch; a
+ * case that has met its stop test skips its tiles while the others go on.
+ * Each case's iterates, iteration counts and results are those of ibm_step on
+ * that context alone (its own tile shape, omega, tolerance and limit).
+ * ibm_batch_create: n >= 1 distinct contexts (borrowed, kept alive by the
+ * caller), all on one stream, all IBM_SOLVER_RBSOR with the register-resident
+ * blocked sweep (IBM_SOR_TEMPORAL), the same IBM_OPT_TB_SWEEPS and
+ * p_check_every, at most 512 tiles each, no network correction or snapshot;
+ * IBM_ERR_INVALID otherwise.  It allocates a small descriptor array on the
+ * device and pinned host memory for the check snapshots.
+ * ibm_batch_step: nsteps time steps of every case; each step runs every
+ * case's steps before and after its pressure solve in turn and one batched
+ * pressure solve between.  last (nullable): n statistics of the last step
+ * (seconds: the whole batched step).  Returns the worst status; after an
+ * error the contexts' states are not usable. */
+typedef struct ibm_batch ibm_batch;
+int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out);
+int32_t ibm_batch_step(ibm_batch* batch, int32_t nsteps, ibm_step_stats* last);
+void ibm_batch_destroy(ibm_batch* batch);
+const char* ibm_batch_last_error(const ibm_batch* batch);
+
 /* Kernel timing with HIP events on the context stream.  sample_every > 0
  * brackets every sample_every-th launch of each timed kernel with a pair of
  * events; 0 switches it off and clears the samples.

@@ -655,18 +655,19 @@ __device__ inline void tbr_residual(const double (&x)[2][kTbRows], const double 
     tbr_resid<1, P, 3>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
 }
 
-__global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __restrict__ red,
-                                                        const double* __restrict__ black, double* __restrict__ ored,
-                                                        double* __restrict__ oblack, const double* __restrict__ bred,
-                                                        const double* __restrict__ bblack,
-                                                        double omega, Ctl* ctl, TbCheck chk, TbShape ts,
-                                                        int nsweep, int residual, double* __restrict__ partials) {
-    __shared__ double edge[2][kTrSlots][kWave];
-    __shared__ double lds[2 * kTbWaves];
-    __shared__ int s_flag;
+// One tile t of the register-resident blocked sweep (the body of k_sor_tbr and
+// of its batched form): loads the tile with its halo, takes the stop test,
+// performs nsweep iterations, stores the interior and, with residual, writes
+// the tile's residual partials (slot t of nt).
+__device__ __forceinline__ void tbr_tile(const Grid& g, const double* __restrict__ red,
+                                         const double* __restrict__ black, double* __restrict__ ored,
+                                         double* __restrict__ oblack, const double* __restrict__ bred,
+                                         const double* __restrict__ bblack, double omega, Ctl* ctl,
+                                         const TbCheck& chk, const TbShape& ts, int t, int nsweep, int residual,
+                                         double* __restrict__ partials, double (&edge)[2][kTrSlots][kWave],
+                                         double* lds, int* s_flag_ptr) {
+    int& s_flag = *s_flag_ptr;
     const int nt = ts.ntx * ts.nty;
-    const int t = tb_tile(ts);
-    if (t >= nt) return;
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
@@ -741,6 +742,80 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
         block_partials(acc, partials, nt, t, lds);
     }
     tb_end(ctl, chk);
+}
+
+__global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __restrict__ red,
+                                                        const double* __restrict__ black, double* __restrict__ ored,
+                                                        double* __restrict__ oblack, const double* __restrict__ bred,
+                                                        const double* __restrict__ bblack,
+                                                        double omega, Ctl* ctl, TbCheck chk, TbShape ts,
+                                                        int nsweep, int residual, double* __restrict__ partials) {
+    __shared__ double edge[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
+    const int t = tb_tile(ts);
+    if (t >= ts.ntx * ts.nty) return;
+    tbr_tile(g, red, black, ored, oblack, bred, bblack, omega, ctl, chk, ts, t, nsweep, residual, partials, edge,
+             lds, &s_flag);
+}
+
+// Many independent grids ("cases") swept by one launch: case c's tiles are
+// the global tiles [tile0, tile0 + ntiles) of a work list over all cases,
+// taken by the blocks with the same XCD banding as one grid's tiles.  A case
+// whose control block says it has finished skips its tiles.  Every case uses
+// the pair `flip` of its split phi arrays as input and the other as output,
+// and partial set `pbuf`; the iterates of each case are those of k_sor_tbr on
+// that case alone.
+struct TbCase {
+    Grid g;
+    double* ph[2][2];  // [pair][colour]
+    const double *bred, *bblack;
+    double* partials[2];
+    Ctl* ctl;
+    TbShape ts;
+    double omega, tol;
+    int tile0, ntiles, nb0, max_iter;
+};
+
+__global__ __launch_bounds__(kTbThreads) void k_sor_tbr_batch(const TbCase* __restrict__ cases, int ncase,
+                                                              int ntotal, int per, int flip, int nsweep,
+                                                              int residual, int pbuf) {
+    __shared__ double edge[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= ntotal) return;
+    int lo = 0, hi = ncase - 1;  // last case with tile0 <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cases[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const TbCase& C = cases[__builtin_amdgcn_readfirstlane(lo)];
+    const TbCheck none = {nullptr, 0, 0, 0, 0, 0.0, nullptr};
+    tbr_tile(C.g, C.ph[flip][0], C.ph[flip][1], C.ph[flip ^ 1][0], C.ph[flip ^ 1][1], C.bred, C.bblack, C.omega,
+             C.ctl, none, C.ts, t - C.tile0, nsweep, residual, C.partials[pbuf], edge, lds, &s_flag);
+}
+
+// The stop tests of all cases of a batch, one block per case (blockDim: the
+// block size of the check the single-grid solve would use, so that the sums
+// and decisions are the same): phase 0 sums the nb0 partials of the initial
+// residual, later phases the ntiles partials of set pbuf after `it`
+// iterations.  Finished cases only republish.
+__global__ __launch_bounds__(kTbThreads) void k_check_batch(const TbCase* __restrict__ cases, int phase, int it,
+                                                            int pbuf, Slot* slots) {
+    __shared__ double lds[2 * kTbWaves];
+    const TbCase& C = cases[blockIdx.x];
+    if (C.ctl->done) {
+        if (threadIdx.x == 0) publish(C.ctl, slots + blockIdx.x);
+        return;
+    }
+    double acc[2];
+    sum_partials(acc, phase == 0 ? C.partials[0] : C.partials[pbuf], phase == 0 ? C.nb0 : C.ntiles, lds);
+    if (threadIdx.x == 0) {
+        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, 0, 0);
+        publish(C.ctl, slots + blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------

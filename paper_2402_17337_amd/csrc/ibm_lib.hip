@@ -1061,13 +1061,18 @@ int32_t pressure_solve(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
     return IBM_OK;
 }
 
-int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
+// A time step is step_pre (everything up to the initial guess of the
+// pressure solve), the pressure solve, and step_post (projection, pressure
+// update, statistics).  A batch of contexts runs step_pre and step_post per
+// context around one batched pressure solve.
+int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     const ibm_params& P = c->P;
     const int nx = c->nx, ny = c->ny;
     const double dt = P.dt, re = P.re, beta = dt / (2.0 * re);
     const double t1 = (double)(c->step + 1) * dt;
     std::memset(st, 0, sizeof(*st));
     const Body B = body_at(c, t1);
+    *Bout = B;
     const dim3 bl(kBlock);
 
     // flags and forced-node lists for the body at t^{n+1}
@@ -1114,11 +1119,16 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
     if (c->net) HIP_TRY(hipMemsetAsync(c->wscale + 3, 0, sizeof(double), c->stream));
     rc = warm_start(c, B);
     if (rc) return rc;
-    int fixed = -1;
-    if (c->sched_pos < c->schedule.size()) fixed = c->schedule[c->sched_pos++];
-    LoopOut po;
-    rc = pressure_solve(c, B, fixed, &po);
-    if (rc) return rc;
+    *status_out = status;
+    return IBM_OK;
+}
+
+int32_t step_post(ibm_ctx* c, ibm_step_stats* st, const LoopOut& po, int status) {
+    const ibm_params& P = c->P;
+    const int nx = c->nx, ny = c->ny;
+    const double dt = P.dt, beta = dt / (2.0 * P.re);
+    const double t1 = (double)(c->step + 1) * dt;
+    const dim3 bl(kBlock);
     if (c->snap_target) {
         const Coarse cg = coarse_of(c);
         hipLaunchKernelGGL(k_ws_target, dim3(red_blocks((size_t)cg.ncx * cg.ncy)), dim3(kRedThreads), 0, c->stream,
@@ -1161,6 +1171,20 @@ int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
     st->t = c->t;
     st->status = status;
     return status;
+}
+
+int32_t step_once(ibm_ctx* c, ibm_step_stats* st) {
+    Body B;
+    int status = IBM_OK;
+    int32_t rc = step_pre(c, st, &B, &status);
+    if (rc) return rc;
+    if (status < 0) return status;
+    int fixed = -1;
+    if (c->sched_pos < c->schedule.size()) fixed = c->schedule[c->sched_pos++];
+    LoopOut po;
+    rc = pressure_solve(c, B, fixed, &po);
+    if (rc) return rc;
+    return step_post(c, st, po, status);
 }
 
 // Face metrics and operator coefficients, computed on the host.
@@ -1229,6 +1253,181 @@ Box motion_box(const ibm_params& P, const double* xf, const double* yf) {
     return b;
 }
 
+// ---------------------------------------------------------------------------
+// Batches: many contexts whose red-black SOR pressure solves run as one
+// blocked launch per S iterations over a work list of all their tiles.
+// ---------------------------------------------------------------------------
+constexpr int kBatchRing = kAheadSor + 2;  // check entries in flight
+
+}  // namespace
+
+struct ibm_batch {
+    std::vector<ibm_ctx*> cs;
+    hipStream_t stream = nullptr;
+    int S = 0, K = 0, ntotal = 0, per = 0, max_iter = 0;
+    TbCase* dcases = nullptr;  // device descriptors
+    TbCase* hcases = nullptr;  // pinned staging of the descriptors
+    Slot* hslots = nullptr;    // kBatchRing x n host-mapped snapshots
+    Slot* dslots = nullptr;
+    hipEvent_t ev[kBatchRing] = {};
+    long seq = 0;
+    std::string err;
+};
+
+namespace {
+
+#define BATCH_TRY(expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            b->err = std::string(#expr) + ": " + hipGetErrorString(e_);                        \
+            return IBM_ERR_HIP;                                                                \
+        }                                                                                      \
+    } while (0)
+
+// The descriptors of the current split phi pairs (they swap between solves).
+int32_t batch_upload(ibm_batch* b) {
+    const int n = (int)b->cs.size();
+    int tile0 = 0;
+    for (int k = 0; k < n; ++k) {
+        ibm_ctx* c = b->cs[k];
+        TbCase& d = b->hcases[k];
+        if (!tb_shape(c, b->S, c->tb_tx, c->tb_ty, &d.ts) || d.ts.ntx * d.ts.nty > kFoldMax) {
+            b->err = "case " + std::to_string(k) + ": its tile shape no longer fits the batched sweep";
+            return IBM_ERR_STATE;
+        }
+        d.g = c->g;
+        d.ph[0][0] = c->phr;
+        d.ph[0][1] = c->phb;
+        d.ph[1][0] = c->phr2;
+        d.ph[1][1] = c->phb2;
+        d.bred = c->vbr;
+        d.bblack = c->vbb;
+        d.ntiles = d.ts.ntx * d.ts.nty;
+        d.partials[0] = c->partials;
+        d.partials[1] = c->partials + 2 * (size_t)d.ntiles;
+        d.ctl = c->ctl + CTL_P;
+        d.omega = c->P.p_omega;
+        d.tol = c->P.p_tol;
+        d.max_iter = c->P.p_max_iter;
+        d.tile0 = tile0;
+        d.nb0 = red_blocks((size_t)c->nh * c->ny);
+        tile0 += d.ntiles;
+    }
+    b->ntotal = tile0;
+    b->per = (tile0 + 7) / 8;
+    BATCH_TRY(hipMemcpyAsync(b->dcases, b->hcases, n * sizeof(TbCase), hipMemcpyHostToDevice, b->stream));
+    return IBM_OK;
+}
+
+// The pressure solves of all contexts of the batch (phi and V b natural on
+// entry; on return the solution is in each context's (phr, phb) pair).
+int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
+    const int n = (int)b->cs.size();
+    for (ibm_ctx* c : b->cs) {
+        const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
+        int32_t rc = reset_ctl(c, CTL_P);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sor_residual, dim3(red_blocks((size_t)c->nh * c->ny)), dim3(kRedThreads), 0,
+                           c->stream, c->g, (const double*)c->phr, (const double*)c->phb, (const double*)c->vbr,
+                           (const double*)c->vbb, (const Ctl*)(c->ctl + CTL_P), c->partials);
+        if (hipGetLastError() != hipSuccess) {
+            b->err = "launch failed";
+            return IBM_ERR_HIP;
+        }
+    }
+    int32_t rc = batch_upload(b);
+    if (rc) return rc;
+    std::deque<std::pair<int, long>> pending;  // (ring entry, blocked launches before its test)
+    auto check = [&](int phase, int it, int pbuf, long nl) -> int32_t {
+        const int e = (int)(b->seq++ % kBatchRing);
+        // phase 0 sums the initial residual's partials as the single-grid k_check
+        // does (kBlock threads); later phases as the folded test (kTbThreads)
+        hipLaunchKernelGGL(k_check_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
+                           (const TbCase*)b->dcases, phase, it, pbuf, b->dslots + (size_t)e * n);
+        if (hipGetLastError() != hipSuccess) {
+            b->err = "k_check_batch launch failed";
+            return IBM_ERR_HIP;
+        }
+        BATCH_TRY(hipEventRecord(b->ev[e], b->stream));
+        pending.emplace_back(e, nl);
+        return IBM_OK;
+    };
+    rc = check(0, 0, 0, 0);
+    if (rc) return rc;
+    std::vector<char> finished(n, 0);
+    std::vector<long> done_launches(n, 0);
+    int nfin = 0;
+    bool first = true;
+    long nlaunch = 0;
+    int nint = 0, it = 0;
+    const int max_e = b->max_iter;
+    for (;;) {
+        if (it < max_e) {
+            const int next = std::min(it + b->K, max_e);
+            const int pbuf = nint & 1;
+            while (it < next) {
+                const int ns = std::min(b->S, next - it);
+                const int resid = (it + ns == next) ? 1 : 0;
+                hipLaunchKernelGGL(k_sor_tbr_batch, dim3(8 * b->per), dim3(kTbThreads), 0, b->stream,
+                                   (const TbCase*)b->dcases, n, b->ntotal, b->per, (int)(nlaunch & 1), ns, resid,
+                                   pbuf);
+                ++nlaunch;
+                it += ns;
+            }
+            if (hipGetLastError() != hipSuccess) {
+                b->err = "k_sor_tbr_batch launch failed";
+                return IBM_ERR_HIP;
+            }
+            ++nint;
+            rc = check(1, it, pbuf, nlaunch);
+            if (rc) return rc;
+            if ((int)pending.size() < kAheadSor && it < max_e) continue;
+        }
+        if (pending.empty()) {
+            b->err = "batched SOR loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int e = pending.front().first;
+        const long nl = pending.front().second;
+        pending.pop_front();
+        BATCH_TRY(hipEventSynchronize(b->ev[e]));
+        for (int k = 0; k < n; ++k) {
+            if (finished[k]) continue;
+            volatile Slot* hs = b->hslots + (size_t)e * n + k;
+            if (first) {
+                outs[k].bn = hs->bn;
+                outs[k].r0 = hs->r0;
+                outs[k].zero_rhs = hs->zero_rhs;
+            }
+            if (hs->done) {
+                finished[k] = 1;
+                ++nfin;
+                done_launches[k] = nl;
+                outs[k].status = hs->status;
+                outs[k].iters = hs->iters;
+                outs[k].rn = hs->rn;
+            }
+        }
+        first = false;
+        if (nfin == n) break;
+        if (it >= max_e && pending.empty()) {
+            b->err = "batched SOR loop: a case neither finished nor reached its iteration limit";
+            return IBM_ERR_STATE;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        if (done_launches[k] & 1) {
+            ibm_ctx* c = b->cs[k];
+            std::swap(c->phr, c->phr2);
+            std::swap(c->phb, c->phb2);
+        }
+    }
+    return IBM_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1241,6 +1440,118 @@ size_t ibm_workspace_bytes(const ibm_params* prm) {
     if ((int64_t)(prm->nx + 1) * (prm->ny + 1) > (int64_t)1 << 30) return 0;
     return layout_for(prm->nx, prm->ny).total;
 }
+
+int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out) {
+    if (!out) return IBM_ERR_INVALID;
+    *out = nullptr;
+    if (n < 1 || n > 4096 || !ctxs) return IBM_ERR_INVALID;
+    for (int k = 0; k < n; ++k) {
+        const ibm_ctx* c = ctxs[k];
+        if (!c) return IBM_ERR_INVALID;
+        for (int q = 0; q < k; ++q)
+            if (ctxs[q] == c) return IBM_ERR_INVALID;  // a context appears once
+        if (c->stream != ctxs[0]->stream || c->P.p_method != IBM_SOLVER_RBSOR || c->sor_kernel != IBM_SOR_TEMPORAL ||
+            c->tb_sweeps != ctxs[0]->tb_sweeps || c->P.p_check_every != ctxs[0]->P.p_check_every ||
+            (c->net && c->net_every > 0) || c->snap_feat)
+            return IBM_ERR_INVALID;
+        TbShape ts;
+        if (!tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts) || ts.ntx * ts.nty > kFoldMax) return IBM_ERR_INVALID;
+    }
+    ibm_batch* b = new ibm_batch();
+    b->cs.assign(ctxs, ctxs + n);
+    b->stream = ctxs[0]->stream;
+    b->S = ctxs[0]->tb_sweeps;
+    b->K = ctxs[0]->P.p_check_every;
+    for (int k = 0; k < n; ++k) b->max_iter = std::max(b->max_iter, ctxs[k]->P.p_max_iter);
+    auto fail = [&](int32_t rc) {
+        ibm_batch_destroy(b);
+        return rc;
+    };
+    if (hipMalloc((void**)&b->dcases, n * sizeof(TbCase)) != hipSuccess) return fail(IBM_ERR_HIP);
+    if (hipHostMalloc((void**)&b->hcases, n * sizeof(TbCase), hipHostMallocDefault) != hipSuccess)
+        return fail(IBM_ERR_HIP);
+    if (hipHostMalloc((void**)&b->hslots, sizeof(Slot) * kBatchRing * n,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return fail(IBM_ERR_HIP);
+    if (hipHostGetDevicePointer((void**)&b->dslots, b->hslots, 0) != hipSuccess) return fail(IBM_ERR_HIP);
+    for (int e = 0; e < kBatchRing; ++e)
+        if (hipEventCreateWithFlags(&b->ev[e], hipEventDisableTiming) != hipSuccess) return fail(IBM_ERR_HIP);
+    *out = b;
+    return IBM_OK;
+}
+
+int32_t ibm_batch_step(ibm_batch* b, int32_t nsteps, ibm_step_stats* last) {
+    if (!b || nsteps < 1) return IBM_ERR_INVALID;
+    b->err.clear();
+    const int n = (int)b->cs.size();
+    for (ibm_ctx* c : b->cs) {
+        if (c->sched_pos < c->schedule.size()) {
+            b->err = "a context of the batch has a pending Poisson schedule";
+            return IBM_ERR_STATE;
+        }
+        if (c->P.p_init == IBM_INIT_LEARNED && !c->net) {
+            b->err = "p_init is IBM_INIT_LEARNED but no network is attached";
+            return IBM_ERR_STATE;
+        }
+    }
+    std::vector<ibm_step_stats> st(n);
+    std::vector<int> status(n, IBM_OK);
+    std::vector<double> wall(n, 0.0);
+    int32_t worst_rc = IBM_OK;
+    for (int s = 0; s < nsteps; ++s) {
+        const auto w0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < n; ++k) {
+            Body B;
+            int32_t rc = step_pre(b->cs[k], &st[k], &B, &status[k]);
+            if (rc < 0) {
+                b->err = std::string("case ") + std::to_string(k) + ": " + b->cs[k]->err;
+                return rc;
+            }
+            if (status[k] < 0) {
+                b->err = std::string("case ") + std::to_string(k) + ": velocity solve failed";
+                return status[k];
+            }
+        }
+        std::vector<LoopOut> outs(n);
+        int32_t rc = batch_sor(b, outs);
+        if (rc) return rc;
+        for (int k = 0; k < n; ++k) {
+            ibm_ctx* c = b->cs[k];
+            if (outs[k].zero_rhs) {
+                rc = fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
+            } else {
+                hipLaunchKernelGGL(k_merge, grid2(c->nh, c->ny), dim3(kBlock), 0, c->stream, c->g,
+                                   (const double*)c->phr, (const double*)c->phb, c->phi);
+                rc = hipGetLastError() == hipSuccess ? IBM_OK : IBM_ERR_HIP;
+            }
+            if (rc) return rc;
+            rc = step_post(c, &st[k], outs[k], status[k]);
+            worst_rc = worst(worst_rc, rc);
+            if (rc < 0) {
+                b->err = std::string("case ") + std::to_string(k) + ": " + c->err;
+                return rc;
+            }
+        }
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+        for (int k = 0; k < n; ++k) st[k].seconds = sec;
+    }
+    if (last)
+        for (int k = 0; k < n; ++k) last[k] = st[k];
+    return worst_rc;
+}
+
+void ibm_batch_destroy(ibm_batch* b) {
+    if (!b) return;
+    if (b->stream || !b->cs.empty()) (void)hipStreamSynchronize(b->stream);
+    for (int e = 0; e < kBatchRing; ++e)
+        if (b->ev[e]) (void)hipEventDestroy(b->ev[e]);
+    if (b->dcases) (void)hipFree(b->dcases);
+    if (b->hcases) (void)hipHostFree(b->hcases);
+    if (b->hslots) (void)hipHostFree(b->hslots);
+    delete b;
+}
+
+const char* ibm_batch_last_error(const ibm_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 const char* ibm_status_string(int32_t s) {
     switch (s) {

@@ -36,7 +36,8 @@ SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
-            "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot", "ibm_profile", "ibm_profile_query",
+            "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot",
+            "ibm_batch_create", "ibm_batch_step", "ibm_batch_destroy", "ibm_batch_last_error", "ibm_profile", "ibm_profile_query",
             "ibm_destroy",
             "ibm_status_string", "ibm_last_error")
 
@@ -115,6 +116,14 @@ def lib():
         L.ibm_set_warm_start.restype = C.c_int32
         L.ibm_set_snapshot.argtypes = [vp, vp, vp, C.c_double]
         L.ibm_set_snapshot.restype = C.c_int32
+        L.ibm_batch_create.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp)]
+        L.ibm_batch_create.restype = C.c_int32
+        L.ibm_batch_step.argtypes = [vp, C.c_int32, C.POINTER(StepStats)]
+        L.ibm_batch_step.restype = C.c_int32
+        L.ibm_batch_destroy.argtypes = [vp]
+        L.ibm_batch_destroy.restype = None
+        L.ibm_batch_last_error.argtypes = [vp]
+        L.ibm_batch_last_error.restype = C.c_char_p
         L.ibm_set_option.argtypes = [vp, C.c_int32, C.c_int64]
         L.ibm_set_option.restype = C.c_int32
         L.ibm_profile.argtypes = [vp, C.c_int32]
@@ -368,3 +377,42 @@ def init_status(nx, ny, xf, yf, workspace_ptr=0, workspace_bytes_=None, **params
     nb = workspace_bytes_ if workspace_bytes_ is not None else lib().ibm_workspace_bytes(C.byref(P))
     return lib().ibm_init(C.byref(P), _dp(xf), _dp(yf), None, None, None, C.c_void_p(workspace_ptr),
                           nb, None, C.byref(h))
+
+
+class Batch:
+    """The pressure solves of several solvers advanced by one batched launch
+    per blocked sweep (see ibm_batch_create); the solvers stay usable alone."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        h = C.c_void_p()
+        rc = lib().ibm_batch_create(len(self.solvers), arr, C.byref(h))
+        if rc != OK:
+            raise IbmError(f"ibm_batch_create failed: {status_string(rc)}")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().ibm_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        """n time steps of every case; returns the last step's statistics per case."""
+        st = (StepStats * len(self.solvers))()
+        rc = lib().ibm_batch_step(self._h, n, st)
+        if rc < 0:
+            raise IbmError(f"ibm_batch_step failed: {status_string(rc)} {lib().ibm_batch_last_error(self._h).decode()}")
+        out = []
+        for x in st:
+            d = {k: getattr(x, k) for k, _ in StepStats._fields_}
+            d["rc"] = rc
+            out.append(d)
+        return out

@@ -1,0 +1,74 @@
+"""Batched pressure solves (many cases of different grids, one blocked SOR
+launch per sweep over all their tiles): every case's steps are bit for bit
+those of the same context stepped alone, whatever the mix of grid sizes, tile
+shapes and convergence points."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _cases():
+    from paper_2402_17337_amd import workloads as W
+    return [W.small_plunging(64, 48), W.stationary_128x96(), W.plunging_stretched(256, 192, 0.05),
+            W.small_plunging(96, 64, seed=3)]
+
+
+def _solver(wl, tile=None):
+    from paper_2402_17337_amd import ibm
+    s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **wl["params"])
+    if tile:
+        assert s.set_option(ibm.OPT_TB_TILE_X, tile[0]) == ibm.OK
+        assert s.set_option(ibm.OPT_TB_TILE_Y, tile[1]) == ibm.OK
+    return s
+
+
+TILES = [None, (64, 24), None, (32, 16)]
+
+
+def test_batched_steps_equal_solo_steps_bitwise():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    solo = [_solver(w, t) for w, t in zip(wls, TILES)]
+    batched = [_solver(w, t) for w, t in zip(wls, TILES)]
+    batch = ibm.Batch(batched)
+    for step in range(3):
+        st_b = batch.step(1)
+        for k, s in enumerate(solo):
+            st = s.step(1)
+            assert st["rc"] == ibm.OK and st_b[k]["status"] == ibm.OK
+            assert st["p_iters"] == st_b[k]["p_iters"], (step, k, st["p_iters"], st_b[k]["p_iters"])
+            assert st["p_rel"] == st_b[k]["p_rel"] and st["p_r0"] == st_b[k]["p_r0"]
+            assert st["cd"] == st_b[k]["cd"] and st["cl"] == st_b[k]["cl"]
+    iters = [st["p_iters"] for st in st_b]
+    assert len(set(iters)) > 1  # the cases finish at different iterations
+    for a, b in zip(solo, batched):
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+
+
+def test_batch_validation():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    a = _solver(wls[0])
+    p = ibm.Solver(wls[1]["nx"], wls[1]["ny"], wls[1]["xf"], wls[1]["yf"], **dict(wls[1]["params"], p_method=ibm.PCG))
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([a, p])           # PCG cannot join
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([a, a])           # a context appears once
+    other = torch.cuda.Stream()
+    q = ibm.Solver(wls[1]["nx"], wls[1]["ny"], wls[1]["xf"], wls[1]["yf"], stream=other, **wls[1]["params"])
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([a, q])           # one stream for all
+    b = _solver(wls[2])
+    assert b.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([a, b])           # one sweep count for all
