@@ -177,6 +177,66 @@ def learned_legs(case, args, sor_leg):
     return out
 
 
+def batch_leg(args):
+    """The many-case workload (64 plunging cases, grids 256x192 to 1024x768):
+    one time step of every case with the pressure solves batched (one blocked
+    launch per 5 iterations over all cases' tiles), against the same cases
+    stepped one after another.  Each pressure solve is capped at
+    args.c4_iters iterations (the cases' full solves take up to 1.4 M
+    iterations); tile shapes are tuned per grid size."""
+    import torch
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import workloads as W
+
+    cases = W.batched_plunging(args.c4_cases, 0)
+    cap = args.c4_iters
+
+    def make():
+        return [ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0",
+                           **dict(c["params"], p_max_iter=cap)) for c in cases]
+
+    batched, solo = make(), make()
+    tiles = {}
+    if args.c4_autotune:
+        for k, c in enumerate(cases):
+            key = (c["nx"], c["ny"])
+            if key not in tiles:
+                tiles[key] = batched[k].autotune_tiles()[0]
+    for k, c in enumerate(cases):
+        for s in (batched[k], solo[k]):
+            tx, ty = tiles.get((c["nx"], c["ny"]), (104, 32))
+            s.set_option(ibm.OPT_TB_TILE_X, tx)
+            s.set_option(ibm.OPT_TB_TILE_Y, ty)
+    batch = ibm.Batch(batched)
+    batch.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b = batch.step(1)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    log(f"batched step of {len(cases)} cases: {t_b:.3f} s")
+    for s in solo:
+        s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_s = [s.step(1) for s in solo]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    log(f"the same step case by case: {t_s:.3f} s")
+    same = all(a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"] for a, b in zip(st_b, st_s))
+    cells = [c["nx"] * c["ny"] for c in cases]
+    upd = sum(n * st["p_iters"] for n, st in zip(cells, st_b))
+    batch.close()
+    return {"workload": f"{len(cases)} plunging cases, grids 256x192..1024x768 (seed 0), one time step, "
+                        f"pressure solves capped at {cap} iterations",
+            "cells": sum(cells), "batched_s": round(t_b, 4), "sequential_s": round(t_s, 4),
+            "speedup": round(t_s / t_b, 3) if t_b > 0 else None,
+            "batched_cell_updates_per_s": round(upd / t_b, 1), "sequential_cell_updates_per_s": round(upd / t_s, 1),
+            "poisson_iters": sorted(set(st["p_iters"] for st in st_b)),
+            "identical_to_sequential": same,
+            "tiles": {f"{k[0]}x{k[1]}": f"{v[0]}x{v[1]}" for k, v in tiles.items()}}
+
+
 def stress_leg(nx=8192, ny=6144, iters=60):
     """The Poisson sweep kernels on a grid whose phi and V b (805 MB) exceed
     the last-level cache, so that their traffic is HBM traffic: 60 fixed
@@ -278,6 +338,10 @@ def main():
                     help="SOR iterations between learned corrections")
     ap.add_argument("--learned-factor", type=int, default=8, help="coarsening factor of the network's grid")
     ap.add_argument("--learned-train-iters", type=int, default=3000, help="Adam iterations per training round")
+    ap.add_argument("--c4-cases", type=int, default=64,
+                    help="cases of the batched many-grid leg (0: skip)")
+    ap.add_argument("--c4-iters", type=int, default=2000, help="Poisson iteration cap of the batched leg")
+    ap.add_argument("--c4-autotune", type=int, default=1, help="1: tune the tile shape per grid size")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of this many MiB, 20 times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -399,6 +463,8 @@ def main():
                                                             max(c3["mixed"]["us_per_iteration"], 1e-9), 3))
     if learned:
         out["learned"] = learned_legs(case, args, main_leg)
+    if args.solver == "sor" and args.c4_cases > 0:
+        out["batched_cases"] = batch_leg(args)
     if args.stress:
         out["stress_hbm"] = stress_leg()
     if args.cpu_seconds > 0:

@@ -329,6 +329,29 @@ class Solver:
             self.net_f = int(value)
         return rc
 
+    def autotune_tiles(self, candidates=((104, 32), (64, 32), (64, 24), (48, 16), (32, 16)), iters: int = 200,
+                       seed: int = 0):
+        """Time `iters` fixed SOR iterations of a stand-alone solve (random
+        right-hand side) with each candidate tile shape of the blocked sweep,
+        keep the fastest and return it with the timings (seconds, GPU events).
+        Every shape gives the same iterates; only the speed differs."""
+        torch = self.torch
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        rhs = (torch.rand(self.ny, self.nx, generator=g, dtype=torch.float64) - 0.5).to(self.device)
+        times = {}
+        for tx, ty in candidates:
+            if self.set_option(OPT_TB_TILE_X, tx) != OK or self.set_option(OPT_TB_TILE_Y, ty) != OK:
+                continue
+            x = torch.zeros_like(rhs)
+            self.poisson_solve(rhs, x, fixed_iters=iters)          # warm-up
+            x.zero_()
+            st = self.poisson_solve(rhs, x, fixed_iters=iters)
+            times[(tx, ty)] = st["seconds"]
+        best = min(times, key=times.get)
+        self.set_option(OPT_TB_TILE_X, best[0])
+        self.set_option(OPT_TB_TILE_Y, best[1])
+        return best, times
+
     # -- stand-alone Poisson solve ------------------------------------------
     def poisson_solve(self, rhs, x, method=RBSOR, omega=1.8, tol=1e-8, max_iter=2_000_000,
                       check_every=10, fixed_iters=0):

@@ -171,6 +171,31 @@ def plunging_stretched(nx: int, ny: int, core_h: float):
                  grid_info=dict(x=ix, y=iy), re=500.0, dt=5e-4, amp=0.5, freq=0.4)
 
 
+def batched_plunging(n: int = 64, seed: int = 0):
+    """The many-case workload: n plunging-ellipse cases from a seeded
+    generator, nx uniform on the multiples of 32 in [256, 1024], ny = 3 nx / 4,
+    core spacing 0.01 * 1024 / nx rounded so that the core [3, 5.5] x
+    [5.2, 6.8] holds a whole number of cells in each direction, h uniform in
+    [0.2, 0.8], f uniform in [0.2, 0.6], Re in {100, 300, 500}; dt 5e-4."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nx = 32 * int(rng.integers(8, 33))
+        ny = 3 * nx // 4
+        h0 = 0.01 * 1024 / nx
+        hx = 2.5 / round(2.5 / h0)
+        hy = 1.6 / round(1.6 / h0)
+        amp = float(rng.uniform(0.2, 0.8))
+        freq = float(rng.uniform(0.2, 0.6))
+        re = float(rng.choice([100.0, 300.0, 500.0]))
+        xf, ix = stretched_faces(nx, 16.0, 3.0, 5.5, hx)
+        yf, iy = stretched_faces(ny, 12.0, 5.2, 6.8, hy)
+        u0, v0, p0 = initial_fields(nx, ny, 1.0)
+        out.append(_pack(f"plunging ellipse {nx}x{ny}, h {amp:.3f}, f {freq:.3f}, Re {re:g}", nx, ny, xf, yf,
+                         u0, v0, p0, 1, grid_info=dict(x=ix, y=iy), re=re, dt=5e-4, amp=amp, freq=freq))
+    return out
+
+
 def small_plunging(nx=64, ny=48, seed=0):
     """A small plunging case (uniform grid, visible body) for quick checks."""
     xf, yf = uniform_faces(nx, 8.0), uniform_faces(ny, 6.0)

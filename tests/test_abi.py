@@ -115,3 +115,17 @@ def test_binding_refuses_to_run_without_a_gpu():
     c = W.small_plunging()
     with pytest.raises(RuntimeError):
         ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], **c["params"])
+
+
+def test_batched_workload_recipe():
+    # the many-case workload: seeded, 64 cases, sizes and parameters in range,
+    # core spacing whole in both directions, about 21 M cells in all
+    a = W.batched_plunging(8, 0)
+    b = W.batched_plunging(8, 0)
+    assert [c["nx"] for c in a] == [c["nx"] for c in b]
+    for c in a:
+        assert c["nx"] % 32 == 0 and 256 <= c["nx"] <= 1024 and c["ny"] == 3 * c["nx"] // 4
+        p = c["params"]
+        assert 0.2 <= p["amp"] <= 0.8 and 0.2 <= p["freq"] <= 0.6 and p["re"] in (100.0, 300.0, 500.0)
+        assert len(c["xf"]) == c["nx"] + 1 and np.all(np.diff(c["xf"]) > 0)
+        assert ibm.workspace_bytes(c["nx"], c["ny"]) > 0
