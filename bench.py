@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s per time step + Poisson cell-updates/s at 1024x768; learned/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak of the MI355X
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_17337_amd", "csrc", f)
                   for f in ("ibm_kernels.hpp", "ibm_device.hpp")]
@@ -125,6 +126,41 @@ def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None
                 cell_updates_per_s=cells * sum(iters) / wall if wall > 0 else 0.0)
 
 
+def network_roofline(params, case, factor, reps=20):
+    """The network's matrix-core rate: forward passes at the solve's coarse
+    size and at the full grid, and a training step at the training shape,
+    timed with events on the stream the kernels run on, against the dense
+    BF16 peak.  FLOPs count 2 per multiply-add of the convolutions (the
+    backward pass: twice the forward)."""
+    import torch
+    from paper_2402_17337_amd import unet as U
+    out = {"bound": "mfma", "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    shapes = (("forward_coarse", 1, case["ny"] // factor, case["nx"] // factor, False),
+              ("forward_full_grid", 1, case["ny"], case["nx"], False),
+              ("train_step", 16, case["ny"] // factor, case["nx"] // factor, True))
+    for name, b, h, w, train in shapes:
+        net = U.UNet(b, h, w)
+        net.set_params(params)
+        x = torch.randn(b, 3, h, w, device="cuda:0")
+        t = torch.randn(b, 1, h, w, device="cuda:0")
+        y = torch.empty(b, 1, h, w, device="cuda:0")
+        for _ in range(3):
+            net.train_step(x, t, 0.0, want_loss=False) if train else net.forward(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            net.train_step(x, t, 0.0, want_loss=False) if train else net.forward(x, y)
+        e1.record(net.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flops = U.forward_flops(b, h, w) * (3.0 if train else 1.0)
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"shape": f"{b}x3x{h}x{w}", "ms": round(ms, 4), "gflop": round(flops / 1e9, 3),
+                     "achieved": round(tf, 2), "frac": round(tf / BF16_PEAK_TFLOPS, 5)}
+        net.close()
+    return out
+
+
 def learned_legs(case, args, sor_leg):
     """Train the warm-start network on the GPU (two rounds, see
     paper_2402_17337_amd.warmstart.train_default), then time the same steps as
@@ -169,6 +205,7 @@ def learned_legs(case, args, sor_leg):
                 k: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
                 for k, a, b in zip(("u", "v", "p"), leg["fields"][:3], ref[:3])}
         out[name] = d
+    out["network_roofline"] = network_roofline(params, case, F)
     if args.pcg_steps > 0:
         leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, 0, p_init=ibm.INIT_LEARNED,
                       net=(params, scale, F, 0, opts))

@@ -115,6 +115,89 @@ __global__ __launch_bounds__(kConvWaves * kWave) void k_conv3x3(Shape s, const b
     }
 }
 
+// The same convolution with the block's input tile staged in LDS: a block
+// computes a (8 PB) x 8 tile of output pixels (4 waves, each PB blocks of 16
+// pixels: two rows of 8) for NCO blocks of 16 output channels; the input
+// pixels of the tile and its one-pixel halo, with all cin channels, are
+// loaded once (zero outside the image) and each K slice's input fragment,
+// read from LDS, feeds NCO products.  Grid: (n ceil(h / (8 PB)) ceil(w / 8),
+// cout_pad / (16 NCO)); (8 PB + 2) 10 (cin / 8 + 1) <= kTileVec.
+constexpr int kTile = 8;
+constexpr int kTileVec = 2500;  // 16-byte LDS vectors: 40 000 bytes
+template <bool RELU, bool OUTF32, int NCO, int PB>
+__global__ __launch_bounds__(4 * kWave) void k_conv3x3_tile(Shape s, const bf16* __restrict__ x, int cin,
+                                                           const bf16* __restrict__ wt,
+                                                           const float* __restrict__ bias,
+                                                           void* __restrict__ y, int cout) {
+    constexpr int TH = 8 * PB, TW = kTile;
+    __shared__ bf16x8 tile[kTileVec];  // pixel-major, one 16-byte pad per pixel
+    const int cs = cin / 8 + 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int g = lane >> 4, col = lane & 15;
+    const int tpr = (s.w + TW - 1) / TW, tpc = (s.h + TH - 1) / TH;
+    const int tb = blockIdx.x;
+    const int bn = tb / (tpr * tpc), rem = tb - bn * tpr * tpc;
+    const int y0 = (rem / tpr) * TH, x0 = (rem % tpr) * TW;
+    const int nv = cin / 8;
+    for (int q = threadIdx.x; q < (TH + 2) * (TW + 2) * nv; q += 4 * kWave) {
+        const int pix = q / nv, v = q - pix * nv;
+        const int yy = y0 - 1 + pix / (TW + 2), xx = x0 - 1 + pix % (TW + 2);
+        bf16x8 val = zero8();
+        if (yy >= 0 && yy < s.h && xx >= 0 && xx < s.w)
+            val = *(const bf16x8*)(x + ((size_t)(bn * s.h + yy) * s.w + xx) * cin + 8 * v);
+        tile[pix * cs + v] = val;
+    }
+    __syncthreads();
+    const int lx = col & 7;
+    int ly[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) ly[b] = 2 * (wave * PB + b) + (col >> 3);
+    const int co0 = blockIdx.y * 16 * NCO;
+    const int K = 9 * cin;
+    const int nslice = (K + 31) / 32;
+    f32x4 acc[NCO][PB];
+#pragma unroll
+    for (int j = 0; j < NCO; ++j)
+#pragma unroll
+        for (int b = 0; b < PB; ++b) acc[j][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int sl = 0; sl < nslice; ++sl) {
+        const int k0 = sl * 32 + 8 * g;
+        const bool kin = k0 < K;
+        const int t = kin ? k0 / cin : 0;
+        const int ci0 = k0 - t * cin;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        bf16x8 a[NCO];
+#pragma unroll
+        for (int j = 0; j < NCO; ++j)
+            a[j] = kin ? *(const bf16x8*)(wt + (size_t)(co0 + 16 * j + col) * K + k0) : zero8();
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const bf16x8 v = kin ? tile[((ly[b] + 1 + dy) * (TW + 2) + lx + 1 + dx) * cs + ci0 / 8] : zero8();
+#pragma unroll
+            for (int j = 0; j < NCO; ++j) acc[j][b] = mfma(a[j], v, acc[j][b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+        const int oy = y0 + ly[b], ox = x0 + lx;
+        if (oy >= s.h || ox >= s.w) continue;
+        const size_t p = (size_t)(bn * s.h + oy) * s.w + ox;
+#pragma unroll
+        for (int j = 0; j < NCO; ++j) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int co = co0 + 16 * j + 4 * g + q;
+                if (co >= cout) continue;
+                float v = acc[j][b][q] + (bias ? bias[co] : 0.0f);
+                if (RELU) v = v > 0.0f ? v : 0.0f;
+                if (OUTF32) ((float*)y)[p * cout + co] = v;
+                else ((bf16*)y)[p * cout + co] = (bf16)v;
+            }
+        }
+    }
+}
+
 // Weight-gradient partials of a 3x3 convolution, one per kGradPix pixels:
 //   part[chunk][co][t cin + ci] = sum_{p in chunk} gz[p, co] x[p + off(t), ci]
 // M = co (16 per block), N = (t, ci) (16 per block), K = pixels (32 per
@@ -195,76 +278,102 @@ __global__ void k_bgrad_reduce(const float* __restrict__ part, int nchunk, int c
     gb[co] = acc;
 }
 
-// Gradient through the ReLU: gz = g where the layer's output y is positive.
+// The elementwise kernels below move 8 channels (16 bytes) per thread; every
+// channel count is a multiple of 8.
+__device__ inline bf16x8 ld8(const bf16* p) { return *(const bf16x8*)p; }
+__device__ inline void st8(bf16* p, bf16x8 v) { *(bf16x8*)p = v; }
+
+// Gradient through the ReLU: gz = g where the layer's output y is positive
+// (n elements, a multiple of 8).
 __global__ void k_relu_back(size_t n, const bf16* __restrict__ g, const bf16* __restrict__ y,
                             bf16* __restrict__ gz) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = 8 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
-    gz[i] = (float)y[i] > 0.0f ? g[i] : (bf16)0.0f;
+    const bf16x8 gv = ld8(g + i), yv = ld8(y + i);
+    bf16x8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (float)yv[q] > 0.0f ? gv[q] : (bf16)0.0f;
+    st8(gz + i, o);
 }
 
-// 2x2 average pooling (so: the output shape).
+// 2x2 average pooling (so: the output shape), 8 channels per thread.
 __global__ void k_pool(Shape so, int c, const bf16* __restrict__ x, bf16* __restrict__ y) {
+    const int cv = c / 8;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)so.n * so.h * so.w * c) return;
-    const int ch = (int)(i % c);
-    const size_t p = i / c;
+    if (i >= (size_t)so.n * so.h * so.w * cv) return;
+    const int ch = 8 * (int)(i % cv);
+    const size_t p = i / cv;
     const int xo = (int)(p % so.w), yo = (int)((p / so.w) % so.h), bn = (int)(p / ((size_t)so.w * so.h));
     const int wi = 2 * so.w, hi = 2 * so.h;
     const size_t b0 = ((size_t)(bn * hi + 2 * yo) * wi + 2 * xo) * c + ch;
     const size_t rs = (size_t)wi * c;
-    const float sum = ((float)x[b0] + (float)x[b0 + c]) + ((float)x[b0 + rs] + (float)x[b0 + rs + c]);
-    y[i] = (bf16)(0.25f * sum);
+    const bf16x8 a = ld8(x + b0), b = ld8(x + b0 + c), d = ld8(x + b0 + rs), e = ld8(x + b0 + rs + c);
+    bf16x8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (bf16)(0.25f * (((float)a[q] + (float)b[q]) + ((float)d[q] + (float)e[q])));
+    st8(y + p * c + ch, o);
 }
 
 // Gradient of the pooling added to gx (si: the input shape): gx[p] += g[p / 2] / 4.
 __global__ void k_pool_back_add(Shape si, int c, const bf16* __restrict__ g, bf16* __restrict__ gx) {
+    const int cv = c / 8;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)si.n * si.h * si.w * c) return;
-    const int ch = (int)(i % c);
-    const size_t p = i / c;
+    if (i >= (size_t)si.n * si.h * si.w * cv) return;
+    const int ch = 8 * (int)(i % cv);
+    const size_t p = i / cv;
     const int xi = (int)(p % si.w), yi = (int)((p / si.w) % si.h), bn = (int)(p / ((size_t)si.w * si.h));
     const int wo = si.w / 2, ho = si.h / 2;
-    const float v = 0.25f * (float)g[((size_t)(bn * ho + yi / 2) * wo + xi / 2) * c + ch];
-    gx[i] = (bf16)((float)gx[i] + v);
+    const bf16x8 gv = ld8(g + ((size_t)(bn * ho + yi / 2) * wo + xi / 2) * c + ch);
+    bf16x8 xv = ld8(gx + p * c + ch);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = (bf16)((float)xv[q] + 0.25f * (float)gv[q]);
+    st8(gx + p * c + ch, xv);
 }
 
 // y = concat(nearest 2x up-sampling of a (ca channels), b (cb channels)) on the
-// output shape so.
+// output shape so, 8 channels per thread.
 __global__ void k_up_concat(Shape so, const bf16* __restrict__ a, int ca, const bf16* __restrict__ b, int cb,
                             bf16* __restrict__ y) {
-    const int c = ca + cb;
+    const int c = ca + cb, cv = c / 8;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)so.n * so.h * so.w * c) return;
-    const int ch = (int)(i % c);
-    const size_t p = i / c;
+    if (i >= (size_t)so.n * so.h * so.w * cv) return;
+    const int ch = 8 * (int)(i % cv);
+    const size_t p = i / cv;
+    bf16x8 v;
     if (ch < ca) {
         const int xo = (int)(p % so.w), yo = (int)((p / so.w) % so.h), bn = (int)(p / ((size_t)so.w * so.h));
-        y[i] = a[((size_t)(bn * (so.h / 2) + yo / 2) * (so.w / 2) + xo / 2) * ca + ch];
+        v = ld8(a + ((size_t)(bn * (so.h / 2) + yo / 2) * (so.w / 2) + xo / 2) * ca + ch);
     } else {
-        y[i] = b[p * cb + (ch - ca)];
+        v = ld8(b + p * cb + (ch - ca));
     }
+    st8(y + p * c + ch, v);
 }
 
 // Gradient of k_up_concat: ga[q] = sum of g over the 2x2 block of q (first ca
-// channels), gb = the last cb channels of g.
+// channels), gb = the last cb channels of g.  One thread per 8 channels of
+// the larger of the two outputs.
 __global__ void k_up_concat_back(Shape so, const bf16* __restrict__ g, int ca, int cb, bf16* __restrict__ ga,
                                  bf16* __restrict__ gb) {
     const int c = ca + cb;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t nb = (size_t)so.n * so.h * so.w * cb;
-    if (i < nb) {
-        const size_t p = i / cb;
-        gb[i] = g[p * c + ca + (int)(i % cb)];
+    const int cbv = cb / 8, cav = ca / 8;
+    if (i < (size_t)so.n * so.h * so.w * cbv) {
+        const size_t p = i / cbv;
+        const int ch = 8 * (int)(i % cbv);
+        st8(gb + p * cb + ch, ld8(g + p * c + ca + ch));
     }
     const Shape sa = {so.n, so.h / 2, so.w / 2};
-    if (i < (size_t)sa.n * sa.h * sa.w * ca) {
-        const int ch = (int)(i % ca);
-        const size_t p = i / ca;
+    if (i < (size_t)sa.n * sa.h * sa.w * cav) {
+        const int ch = 8 * (int)(i % cav);
+        const size_t p = i / cav;
         const int xa = (int)(p % sa.w), ya = (int)((p / sa.w) % sa.h), bn = (int)(p / ((size_t)sa.w * sa.h));
         const size_t q0 = ((size_t)(bn * so.h + 2 * ya) * so.w + 2 * xa) * c + ch;
         const size_t rs = (size_t)so.w * c;
-        ga[i] = (bf16)(((float)g[q0] + (float)g[q0 + c]) + ((float)g[q0 + rs] + (float)g[q0 + rs + c]));
+        const bf16x8 a = ld8(g + q0), b = ld8(g + q0 + c), d = ld8(g + q0 + rs), e = ld8(g + q0 + rs + c);
+        bf16x8 o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o[q] = (bf16)(((float)a[q] + (float)b[q]) + ((float)d[q] + (float)e[q]));
+        st8(ga + p * ca + ch, o);
     }
 }
 

@@ -189,14 +189,44 @@ inline unsigned blocks(size_t n, int t = kEw) { return (unsigned)((n + t - 1) / 
         }                                                                 \
     } while (0)
 
+// y = act(conv(x) + b): the LDS-tiled kernel for cin <= kTileCin, sharing
+// each input fragment across up to 4 blocks of 16 output channels; rows16 is
+// the padded number of weight rows (a multiple of 16).
+template <bool RELU, bool OUTF32>
+void launch_conv(Shape s, const bf16* x, int cin, const bf16* wt, const float* bias, void* y, int cout, int rows16,
+                 hipStream_t st) {
+    const int nblk = rows16 / 16;
+    // pixel blocks per wave: as many as the LDS tile holds, up to 4 (a
+    // narrow layer otherwise gives each block too little work)
+    const int cs = cin / 8 + 1;
+    const int pb = (34 * 10 * cs <= kTileVec) ? 4 : (18 * 10 * cs <= kTileVec) ? 2 : (10 * 10 * cs <= kTileVec) ? 1 : 0;
+    if (pb == 0) {
+        k_conv3x3<RELU, OUTF32><<<dim3(blocks(npix(s), kConvPix), nblk), kConvWaves * kWave, 0, st>>>(
+            s, x, cin, wt, bias, y, cout);
+        return;
+    }
+    const int th = 8 * pb;
+    const unsigned tiles = (unsigned)(s.n * ((s.h + th - 1) / th) * ((s.w + kTile - 1) / kTile));
+    const int nco = nblk % 4 == 0 ? 4 : nblk % 2 == 0 ? 2 : 1;
+    const dim3 grid(tiles, nblk / nco), bl(4 * kWave);
+#define CONV_TILE(NCO, PB) k_conv3x3_tile<RELU, OUTF32, NCO, PB><<<grid, bl, 0, st>>>(s, x, cin, wt, bias, y, cout)
+    if (nco == 4) {
+        if (pb == 4) CONV_TILE(4, 4); else if (pb == 2) CONV_TILE(4, 2); else CONV_TILE(4, 1);
+    } else if (nco == 2) {
+        if (pb == 4) CONV_TILE(2, 4); else if (pb == 2) CONV_TILE(2, 2); else CONV_TILE(2, 1);
+    } else {
+        if (pb == 4) CONV_TILE(1, 4); else if (pb == 2) CONV_TILE(1, 2); else CONV_TILE(1, 1);
+    }
+#undef CONV_TILE
+}
+
 // y = act(conv(x) + b) of layer L on shape s (bf16 out, or f32 for the last).
 void conv_forward(ibm_unet* u, const Layer& L, Shape s, const bf16* x, void* y) {
-    const dim3 grid(blocks(npix(s), kConvPix), L.cout16 / 16);
     const float* bias = u->params + L.b_off;
     if (!L.s.relu)
-        k_conv3x3<false, true><<<grid, kConvWaves * kWave, 0, u->stream>>>(s, x, L.cin8, L.wf, bias, y, L.s.cout);
+        launch_conv<false, true>(s, x, L.cin8, L.wf, bias, y, L.s.cout, L.cout16, u->stream);
     else
-        k_conv3x3<true, false><<<grid, kConvWaves * kWave, 0, u->stream>>>(s, x, L.cin8, L.wf, bias, y, L.s.cout);
+        launch_conv<true, false>(s, x, L.cin8, L.wf, bias, y, L.s.cout, L.cout16, u->stream);
 }
 
 // Backward of layer L: g = gradient at its output (cout8 channels), y = its
@@ -207,7 +237,7 @@ void conv_backward(ibm_unet* u, const Layer& L, Shape s, const bf16* x, const bf
     const size_t P = npix(s);
     const bf16* gzv = g;
     if (L.s.relu) {
-        k_relu_back<<<blocks(P * L.cout8), kEw, 0, u->stream>>>(P * L.cout8, g, y, gz);
+        k_relu_back<<<blocks(P * L.cout8 / 8), kEw, 0, u->stream>>>(P * L.cout8, g, y, gz);
         gzv = gz;
     }
     const int nc = nchunk(s);
@@ -218,11 +248,7 @@ void conv_backward(ibm_unet* u, const Layer& L, Shape s, const bf16* x, const bf
                                                       u->grads + L.w_off);
     k_bgrad<<<nc, (L.s.cout + 63) / 64 * 64, 0, u->stream>>>((int)P, gzv, L.cout8, L.s.cout, u->bpart);
     k_bgrad_reduce<<<1, 128, 0, u->stream>>>(u->bpart, nc, L.s.cout, u->grads + L.b_off);
-    if (gx) {
-        const dim3 grid(blocks(P, kConvPix), L.cin16 / 16);
-        k_conv3x3<false, false><<<grid, kConvWaves * kWave, 0, u->stream>>>(s, gzv, L.cout8, L.wt, nullptr, gx,
-                                                                           L.cin8);
-    }
+    if (gx) launch_conv<false, false>(s, gzv, L.cout8, L.wt, nullptr, gx, L.cin8, L.cin16, u->stream);
 }
 
 void pack_weights(ibm_unet* u) {
@@ -242,22 +268,22 @@ int32_t forward(ibm_unet* u, const float* x, int B) {
     k_pack_nchw<<<blocks(npix(S[0]) * 8), kEw, 0, u->stream>>>(S[0], IBM_UNET_IN_CHANNELS, 8, x, u->x0);
     conv_forward(u, L[0], S[0], u->x0, u->a0);
     conv_forward(u, L[1], S[0], u->a0, u->s0);
-    k_pool<<<blocks(npix(S[1]) * 16), kEw, 0, u->stream>>>(S[1], 16, u->s0, u->p0);
+    k_pool<<<blocks(npix(S[1]) * 2), kEw, 0, u->stream>>>(S[1], 16, u->s0, u->p0);
     conv_forward(u, L[2], S[1], u->p0, u->a1);
     conv_forward(u, L[3], S[1], u->a1, u->s1);
-    k_pool<<<blocks(npix(S[2]) * 32), kEw, 0, u->stream>>>(S[2], 32, u->s1, u->p1);
+    k_pool<<<blocks(npix(S[2]) * 4), kEw, 0, u->stream>>>(S[2], 32, u->s1, u->p1);
     conv_forward(u, L[4], S[2], u->p1, u->a2);
     conv_forward(u, L[5], S[2], u->a2, u->s2);
-    k_pool<<<blocks(npix(S[3]) * 64), kEw, 0, u->stream>>>(S[3], 64, u->s2, u->p2);
+    k_pool<<<blocks(npix(S[3]) * 8), kEw, 0, u->stream>>>(S[3], 64, u->s2, u->p2);
     conv_forward(u, L[6], S[3], u->p2, u->am);
     conv_forward(u, L[7], S[3], u->am, u->mm);
-    k_up_concat<<<blocks(npix(S[2]) * 192), kEw, 0, u->stream>>>(S[2], u->mm, 128, u->s2, 64, u->c2);
+    k_up_concat<<<blocks(npix(S[2]) * 24), kEw, 0, u->stream>>>(S[2], u->mm, 128, u->s2, 64, u->c2);
     conv_forward(u, L[8], S[2], u->c2, u->b2);
     conv_forward(u, L[9], S[2], u->b2, u->d2);
-    k_up_concat<<<blocks(npix(S[1]) * 96), kEw, 0, u->stream>>>(S[1], u->d2, 64, u->s1, 32, u->c1);
+    k_up_concat<<<blocks(npix(S[1]) * 12), kEw, 0, u->stream>>>(S[1], u->d2, 64, u->s1, 32, u->c1);
     conv_forward(u, L[10], S[1], u->c1, u->b1);
     conv_forward(u, L[11], S[1], u->b1, u->d1);
-    k_up_concat<<<blocks(npix(S[0]) * 48), kEw, 0, u->stream>>>(S[0], u->d1, 32, u->s0, 16, u->c0);
+    k_up_concat<<<blocks(npix(S[0]) * 6), kEw, 0, u->stream>>>(S[0], u->d1, 32, u->s0, 16, u->c0);
     conv_forward(u, L[12], S[0], u->c0, u->b0);
     conv_forward(u, L[13], S[0], u->b0, u->d0);
     conv_forward(u, L[14], S[0], u->d0, u->y);
@@ -274,27 +300,27 @@ int32_t backward(ibm_unet* u, int B) {
     conv_backward(u, L[14], S[0], u->d0, nullptr, u->gy, nullptr, gA[0]);  // g d0 (16)
     conv_backward(u, L[13], S[0], u->b0, u->d0, gA[0], gz[0], gB[0]);     // g b0 (16)
     conv_backward(u, L[12], S[0], u->c0, u->b0, gB[0], gz[0], gA[0]);     // g c0 (48)
-    k_up_concat_back<<<blocks(npix(S[0]) * 16), kEw, 0, u->stream>>>(S[0], gA[0], 32, 16, gA[1], u->gs0);
+    k_up_concat_back<<<blocks(npix(S[0]) * 2), kEw, 0, u->stream>>>(S[0], gA[0], 32, 16, gA[1], u->gs0);
     // level 1, decoder
     conv_backward(u, L[11], S[1], u->b1, u->d1, gA[1], gz[1], gB[1]);     // g b1 (32)
     conv_backward(u, L[10], S[1], u->c1, u->b1, gB[1], gz[1], gA[1]);     // g c1 (96)
-    k_up_concat_back<<<blocks(npix(S[1]) * 32), kEw, 0, u->stream>>>(S[1], gA[1], 64, 32, gA[2], u->gs1);
+    k_up_concat_back<<<blocks(npix(S[1]) * 4), kEw, 0, u->stream>>>(S[1], gA[1], 64, 32, gA[2], u->gs1);
     // level 2, decoder
     conv_backward(u, L[9], S[2], u->b2, u->d2, gA[2], gz[2], gB[2]);      // g b2 (64)
     conv_backward(u, L[8], S[2], u->c2, u->b2, gB[2], gz[2], gA[2]);      // g c2 (192)
-    k_up_concat_back<<<blocks(npix(S[2]) * 64), kEw, 0, u->stream>>>(S[2], gA[2], 128, 64, gA[3], u->gs2);
+    k_up_concat_back<<<blocks(npix(S[2]) * 8), kEw, 0, u->stream>>>(S[2], gA[2], 128, 64, gA[3], u->gs2);
     // level 3
     conv_backward(u, L[7], S[3], u->am, u->mm, gA[3], gz[3], gB[3]);      // g am (128)
     conv_backward(u, L[6], S[3], u->p2, u->am, gB[3], gz[3], gA[3]);      // g p2 (64)
-    k_pool_back_add<<<blocks(npix(S[2]) * 64), kEw, 0, u->stream>>>(S[2], 64, gA[3], u->gs2);
+    k_pool_back_add<<<blocks(npix(S[2]) * 8), kEw, 0, u->stream>>>(S[2], 64, gA[3], u->gs2);
     // level 2, encoder
     conv_backward(u, L[5], S[2], u->a2, u->s2, u->gs2, gz[2], gB[2]);     // g a2 (64)
     conv_backward(u, L[4], S[2], u->p1, u->a2, gB[2], gz[2], gA[2]);      // g p1 (32)
-    k_pool_back_add<<<blocks(npix(S[1]) * 32), kEw, 0, u->stream>>>(S[1], 32, gA[2], u->gs1);
+    k_pool_back_add<<<blocks(npix(S[1]) * 4), kEw, 0, u->stream>>>(S[1], 32, gA[2], u->gs1);
     // level 1, encoder
     conv_backward(u, L[3], S[1], u->a1, u->s1, u->gs1, gz[1], gB[1]);     // g a1 (32)
     conv_backward(u, L[2], S[1], u->p0, u->a1, gB[1], gz[1], gA[1]);      // g p0 (16)
-    k_pool_back_add<<<blocks(npix(S[0]) * 16), kEw, 0, u->stream>>>(S[0], 16, gA[1], u->gs0);
+    k_pool_back_add<<<blocks(npix(S[0]) * 2), kEw, 0, u->stream>>>(S[0], 16, gA[1], u->gs0);
     // level 0, encoder
     conv_backward(u, L[1], S[0], u->a0, u->s0, u->gs0, gz[0], gB[0]);     // g a0 (16)
     conv_backward(u, L[0], S[0], u->x0, u->a0, gB[0], gz[0], nullptr);
@@ -501,13 +527,11 @@ int32_t ibm_unet_conv3x3(int32_t op, int32_t n, int32_t h, int32_t w, int32_t ci
     if (gy) k_pack_nchw<<<blocks(P * co8), kEw, 0, st>>>(s, cout, co8, gy, c.gb);
     if (op == IBM_UNET_CONV_FORWARD) {
         k_pack_weights<<<blocks((size_t)co16 * 9 * ci8), kEw, 0, st>>>(wt, cout, cin, co16, ci8, 0, c.wf);
-        k_conv3x3<false, true><<<dim3(blocks(P, kConvPix), co16 / 16), kConvWaves * kWave, 0, st>>>(
-            s, c.xb, ci8, c.wf, b, c.tmp, cout);
+        launch_conv<false, true>(s, c.xb, ci8, c.wf, b, c.tmp, cout, co16, st);
         k_unpack_nhwc<<<blocks(P * cout), kEw, 0, st>>>(s, cout, c.tmp, out);
     } else if (op == IBM_UNET_CONV_DGRAD) {
         k_pack_weights<<<blocks((size_t)ci16 * 9 * co8), kEw, 0, st>>>(wt, cout, cin, co8, ci16, 1, c.wt);
-        k_conv3x3<false, true><<<dim3(blocks(P, kConvPix), ci16 / 16), kConvWaves * kWave, 0, st>>>(
-            s, c.gb, co8, c.wt, nullptr, c.tmp, cin);
+        launch_conv<false, true>(s, c.gb, co8, c.wt, nullptr, c.tmp, cin, ci16, st);
         k_unpack_nhwc<<<blocks(P * cin), kEw, 0, st>>>(s, cin, c.tmp, out);
     } else {
         const int nc = nchunk(s);

@@ -69,6 +69,17 @@ def param_count() -> int:
     return int(lib().ibm_unet_param_count())
 
 
+def forward_flops(batch: int, h: int, w: int) -> float:
+    """Multiply-add FLOPs (2 per product) of the network's convolutions for
+    one forward pass over batch images h x w (unpadded channel counts)."""
+    lvl = {"enc0": 0, "enc1": 1, "enc2": 2, "mid_": 3, "dec2": 2, "dec1": 1, "dec0": 0, "out": 0}
+    total = 0.0
+    for name, ci, co, _ in LAYERS:
+        l = lvl[name[:4] if name != "out" else "out"]
+        total += 2.0 * 9 * ci * co * batch * (h >> l) * (w >> l)
+    return total
+
+
 def flatten_params(params: dict) -> np.ndarray:
     """Parameter dict {name.w: (co, ci, 3, 3), name.b: (co,)} -> float32 vector."""
     parts = []

@@ -53,7 +53,8 @@ CONV_CASES = [  # n, h, w, cin, cout
     (2, 12, 24, 16, 16),
     (2, 7, 16, 48, 32),    # odd height, K = 432 (14 slices, ragged)
     (2, 24, 48, 32, 64),   # 2304 pixels: three gradient partials, the last ragged
-    (1, 8, 64, 192, 16),   # widest input of the network
+    (1, 8, 64, 192, 16),   # widest input of the network (the LDS tile's limit)
+    (1, 6, 16, 200, 24),   # wider than the LDS tile: the untiled kernel
 ]
 
 
