@@ -260,14 +260,25 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunk, int c
     gw[e] = acc;
 }
 
-// Bias-gradient partials: part[chunk][co] = sum_{p in chunk} gz[p, co].
-__global__ void k_bgrad(int npix, const bf16* __restrict__ gz, int gs, int cout, float* __restrict__ part) {
-    const int co = threadIdx.x;
-    if (co >= cout) return;
+// Bias-gradient partials: part[chunk][co] = sum_{p in chunk} gz[p, co].  The
+// kEw threads of a block split as co = tid % cp (cp: cout rounded up to a power
+// of two, <= kEw) and kEw / cp pixel lanes, each summing every (kEw / cp)-th
+// pixel of the chunk; the lanes' sums are then added in a fixed tree order.
+__global__ __launch_bounds__(kEw) void k_bgrad(int npix, const bf16* __restrict__ gz, int gs, int cout, int cp,
+                                               float* __restrict__ part) {
+    __shared__ float red[kEw];
+    const int co = threadIdx.x % cp, lanes = kEw / cp, l = threadIdx.x / cp;
     const int p0 = blockIdx.x * kGradPix, p1 = min(npix, p0 + kGradPix);
     float acc = 0.0f;
-    for (int p = p0; p < p1; ++p) acc += (float)gz[(size_t)p * gs + co];
-    part[(size_t)blockIdx.x * cout + co] = acc;
+    if (co < cout)
+        for (int p = p0 + l; p < p1; p += lanes) acc += (float)gz[(size_t)p * gs + co];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = lanes / 2; o > 0; o >>= 1) {
+        if (l < o) red[threadIdx.x] += red[threadIdx.x + o * cp];
+        __syncthreads();
+    }
+    if (l == 0 && co < cout) part[(size_t)blockIdx.x * cout + co] = red[threadIdx.x];
 }
 
 __global__ void k_bgrad_reduce(const float* __restrict__ part, int nchunk, int cout, float* __restrict__ gb) {

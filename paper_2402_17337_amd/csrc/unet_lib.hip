@@ -23,6 +23,11 @@ constexpr int kWidths[kLevels] = {16, 32, 64, 128};
 inline int pad8(int c) { return (c + 7) / 8 * 8; }
 inline int pad16(int c) { return (c + 15) / 16 * 16; }
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+inline int pow2_at_least(int c) {
+    int p = 1;
+    while (p < c) p <<= 1;
+    return p;
+}
 
 struct LayerSpec {
     const char* name;
@@ -246,7 +251,7 @@ void conv_backward(ibm_unet* u, const Layer& L, Shape s, const bf16* x, const bf
     const int nw = L.s.cout * L.s.cin * 9;
     k_wgrad_reduce<<<blocks(nw), kEw, 0, u->stream>>>(u->part, nc, L.s.cout, L.cout16, L.cin8, L.s.cin,
                                                       u->grads + L.w_off);
-    k_bgrad<<<nc, (L.s.cout + 63) / 64 * 64, 0, u->stream>>>((int)P, gzv, L.cout8, L.s.cout, u->bpart);
+    k_bgrad<<<nc, kEw, 0, u->stream>>>((int)P, gzv, L.cout8, L.s.cout, pow2_at_least(L.s.cout), u->bpart);
     k_bgrad_reduce<<<1, 128, 0, u->stream>>>(u->bpart, nc, L.s.cout, u->grads + L.b_off);
     if (gx) launch_conv<false, false>(s, gzv, L.cout8, L.wt, nullptr, gx, L.cin8, L.cin16, u->stream);
 }
@@ -538,7 +543,7 @@ int32_t ibm_unet_conv3x3(int32_t op, int32_t n, int32_t h, int32_t w, int32_t ci
         k_wgrad<<<dim3(nc, co16 / 16, (9 * ci8 + 15) / 16), kWave, 0, st>>>(s, c.xb, ci8, c.gb, co8, cout, co16,
                                                                            c.part);
         k_wgrad_reduce<<<blocks((size_t)cout * cin * 9), kEw, 0, st>>>(c.part, nc, cout, co16, ci8, cin, out);
-        k_bgrad<<<nc, (cout + 63) / 64 * 64, 0, st>>>((int)P, c.gb, co8, cout, c.bpart);
+        k_bgrad<<<nc, kEw, 0, st>>>((int)P, c.gb, co8, cout, pow2_at_least(cout), c.bpart);
         k_bgrad_reduce<<<blocks(cout), kEw, 0, st>>>(c.bpart, nc, cout, out + (size_t)cout * cin * 9);
     }
     return hipGetLastError() == hipSuccess ? IBM_OK : IBM_ERR_HIP;
