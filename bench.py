@@ -396,7 +396,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the solver is single-device "
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the solver is single-device "
                                    "(grid sharding is described but not implemented); use --gpus 1"}))
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:

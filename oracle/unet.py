@@ -6,8 +6,8 @@ TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's CPU
 baseline use this module; the GPU path never imports it.
 
 The network (channel widths 16/32/64/128, 3x3 kernels, bias and ReLU after
-every convolution but the last) is this build's design of the warm-start
-network the method is extended with; it is not part of the paper, whose
+every convolution but the last) is the warm-start network this code extends
+the method with; it is not part of the paper, whose
 pressure solve starts from the previous step.  Layout of every tensor:
 (batch, channels, height, width).  Down-sampling is a 2x2 average, up-sampling
 repeats each value over a 2x2 block, skips are concatenated after the

@@ -199,7 +199,7 @@ def train_default(wl: dict, factor: int = 8, every: int = 4000, cases: int = 16,
                   iters: int = 3000, batch: int = 16, snap_iters=(200, 1000, 4000, 16000),
                   policy_iters=(4000, 8000, 16000, 32000, 64000), rounds: int = 3, options=None, log=None):
     """The training recipe of the learned correction, all on the GPU:
-    round 1 on snapshots of plain SOR solves (3 steps of `cases` seeded plunge
+    a first training round on snapshots of plain SOR solves (3 steps of `cases` seeded plunge
     settings, snapshots at snap_iters); each later round on snapshots along
     the solve the current network corrects every `every` iterations (one step
     of `cases` other settings, snapshots at policy_iters), fine-tuning on all

@@ -3,7 +3,7 @@ correction equation, double-precision residual, update and stop test) against
 facts fixed by mathematics.
 
 The method it speeds up is the paper's red-black SOR pressure solve (Sec. 2.2
-and 3.1); the precision split is this build's extension of it.
+and 3.1); the precision split is an extension of it.
 """
 import numpy as np
 import pytest
