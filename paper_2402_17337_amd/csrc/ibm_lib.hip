@@ -90,8 +90,9 @@ Offsets layout_for(int nx, int ny) {
     o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
     o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
     o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
-    o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step, features and
-    o.wsf = L.take<float>(4 * NC);  // the network output (3 + 1 maps), RMS scales
+    o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step; the network's
+    o.wsf = L.take<float>(5 * NC);  // maps, output and smoothing buffer (3 + 1 + 1 coarse maps, at
+                                    // most fine-grid size each); RMS scales
     o.wscale = L.take<double>(4);  // s_r, s_phi, alpha of the last correction
     o.f_u = L.take<double>(NU); o.f_v = L.take<double>(NV);
     o.coef = L.take<double>(4);
@@ -168,7 +169,7 @@ struct ibm_ctx {
     double *phr2, *phb2;  // second pair of split phi arrays (blocked sweeps alternate)
     float* mpf;           // mixed-precision SOR: e pairs (4 NH), then r32 pairs (4 NH)
     double *phi0, *wscale;  // learned warm start: phi before the solve, (s_r, s_phi)
-    float* wsf;             // its features (3 maps) and network output (1 map)
+    float* wsf;             // its maps (3), network output (1) and smoothing buffer (1)
     ibm_unet* net = nullptr;  // warm-start network (borrowed) and its output scale
     double net_scale = 1.0;
     float *snap_feat = nullptr, *snap_target = nullptr;  // training snapshots (borrowed)

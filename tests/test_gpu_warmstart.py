@@ -238,3 +238,24 @@ def test_random_network_corrections_still_converge():
     ub, vb, _, _ = b.fields()
     for x, y in ((ua, ub), (va, vb)):
         assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_full_resolution_network_leaves_other_arrays_alone():
+    # factor 1: the network's maps, output and smoothing buffer are five
+    # fine-grid maps; nothing beyond them (the scales, the forcing values) may
+    # change, so the forcing of a learned step equals that of a plain step
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    assert b.set_option(ibm.OPT_NET_SMOOTH, 4) == ibm.OK
+    net = U.UNet(1, wl["ny"], wl["nx"], stream=b.stream)
+    net.set_params(U.flatten_params(OU.init_params(9)))
+    b.set_warm_start(net, 1.0)
+    a.step(1)
+    b.step(1)
+    ia, ib = a.ibm(), b.ibm()
+    assert np.array_equal(ia["fu"], ib["fu"]) and np.array_equal(ia["fv"], ib["fv"])
+    assert np.count_nonzero(ia["fv"]) > 0
