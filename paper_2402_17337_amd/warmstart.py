@@ -197,7 +197,7 @@ RECIPE_OPTIONS = {ibm.OPT_NET_MAPS: 5}  # residual and mask maps: no phi (see tr
 
 def train_default(wl: dict, factor: int = 8, every: int = 4000, cases: int = 16, seed: int = 1,
                   iters: int = 3000, batch: int = 16, snap_iters=(200, 1000, 4000, 16000),
-                  policy_iters=(4000, 8000, 16000, 32000, 64000), rounds: int = 3, options=None, log=None):
+                  policy_iters=(4000, 8000, 16000, 32000, 64000), rounds: int = 4, options=None, log=None):
     """The training recipe of the learned correction, all on the GPU:
     a first training round on snapshots of plain SOR solves (3 steps of `cases` seeded plunge
     settings, snapshots at snap_iters); each later round on snapshots along
@@ -272,7 +272,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--cases", type=int, default=16, help="plunge settings per training round")
     ap.add_argument("--iters", type=int, default=3000, help="Adam iterations per round")
-    ap.add_argument("--rounds", type=int, default=3)
+    ap.add_argument("--rounds", type=int, default=4)
     ap.add_argument("--every", type=int, default=4000, help="SOR iterations between corrections")
     ap.add_argument("--factor", type=int, default=8, help="coarsening factor of the network's grid")
     ap.add_argument("--warm-steps", type=int, default=1, help="steps before the timed one")
