@@ -161,6 +161,57 @@ def network_roofline(params, case, factor, reps=20):
     return out
 
 
+def c3_learned_leg(params, scale, steps):
+    """Full 2048x1536 steps to the 1e-8 stop test: SOR with the learned
+    correction (the network trained on the 1024x768 workload, on the grid
+    coarsened 16x: again 128x96), with FP64 sweeps and with FP32 sweeps + FP64
+    refinement, from one common state (one PCG step); errors of the mixed
+    form in u, v, p and the force coefficients against the FP64 form."""
+    import numpy as np
+    import torch
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    from paper_2402_17337_amd import workloads as W
+
+    wl = W.plunging_2048x1536()
+    base = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], device="cuda:0",
+                      **dict(wl["params"], p_method=ibm.PCG))
+    base.step(1)
+    blob = base.get_state()
+    base.close()
+    res = {}
+    for name, method in (("f64", ibm.RBSOR), ("mixed", ibm.RBSOR_MP)):
+        s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], device="cuda:0", **dict(wl["params"], p_method=method))
+        s.set_state(blob)
+        for opt, val in ((ibm.OPT_NET_FACTOR, 16), (ibm.OPT_NET_EVERY, 4000), (ibm.OPT_NET_MAPS, 5)):
+            if s.set_option(opt, val) != ibm.OK:
+                raise RuntimeError(f"option {opt} = {val} rejected")
+        net = U.UNet(1, wl["ny"] // 16, wl["nx"] // 16, stream=s.stream)
+        net.set_params(params)
+        s.set_warm_start(net, scale)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [s.step(1) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        log(f"2048x1536 learned {name}: {steps} steps in {wall:.2f} s, iterations {[x['p_iters'] for x in sts]}")
+        res[name] = dict(s_per_step=round(wall / steps, 4), poisson_iters=[x["p_iters"] for x in sts],
+                         final_rel_residual=[x["p_rel"] for x in sts], fields=s.fields()[:3], forces=s.forces())
+        s.close()
+    f, m = res["f64"], res["mixed"]
+    err = {k: float(np.linalg.norm(a - b) / np.linalg.norm(b)) for k, a, b in zip("uvp", m["fields"], f["fields"])}
+    err["cd"] = abs(m["forces"][0] - f["forces"][0]) / abs(f["forces"][0])
+    err["cl"] = abs(m["forces"][1] - f["forces"][1]) / abs(f["forces"][1])
+    for r in res.values():
+        del r["fields"], r["forces"]
+    return {"workload": "plunging ellipse 2048x1536, Re 1000, h 0.6, f 0.5; steps 2.. after one common PCG step, "
+                        "pressure solves to 1e-8 with the learned correction (network trained on 1024x768, "
+                        "coarse grid 128x96)",
+            "f64": res["f64"], "mixed": res["mixed"],
+            "mixed_speedup": round(res["f64"]["s_per_step"] / res["mixed"]["s_per_step"], 3),
+            "mixed_rel_error_vs_f64": err}
+
+
 def learned_legs(case, args, sor_leg):
     """Train the warm-start network on the GPU (two rounds, see
     paper_2402_17337_amd.warmstart.train_default), then time the same steps as
@@ -206,6 +257,8 @@ def learned_legs(case, args, sor_leg):
                 for k, a, b in zip(("u", "v", "p"), leg["fields"][:3], ref[:3])}
         out[name] = d
     out["network_roofline"] = network_roofline(params, case, F)
+    if args.c3_learned_steps > 0:
+        out["c3_full_steps"] = c3_learned_leg(params, scale, args.c3_learned_steps)
     if args.pcg_steps > 0:
         leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, 0, p_init=ibm.INIT_LEARNED,
                       net=(params, scale, F, 0, opts))
@@ -397,6 +450,8 @@ def main():
                     help="1: also time the SOR kernels on the HBM-resident 8192x6144 grid")
     ap.add_argument("--learned", type=int, default=1,
                     help="1: train the warm-start network on the GPU and time the learned guess and correction")
+    ap.add_argument("--c3-learned-steps", type=int, default=2,
+                    help="full 2048x1536 steps with the learned correction, FP64 and mixed sweeps (0: skip)")
     ap.add_argument("--learned-every", type=int, default=4000,
                     help="SOR iterations between learned corrections")
     ap.add_argument("--learned-factor", type=int, default=8, help="coarsening factor of the network's grid")
