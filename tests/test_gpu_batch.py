@@ -72,3 +72,17 @@ def test_batch_validation():
     assert b.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK
     with pytest.raises(ibm.IbmError):
         ibm.Batch([a, b])           # one sweep count for all
+
+
+def test_autotune_picks_a_candidate_and_keeps_the_iterates():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _cases()[2]
+    a, b = _solver(wl), _solver(wl)
+    best, times = b.autotune_tiles(candidates=((104, 32), (48, 16)), iters=50)
+    assert best in times and len(times) == 2 and all(v > 0 for v in times.values())
+    for _ in range(2):
+        sa, sb = a.step(1), b.step(1)
+        assert sa["p_iters"] == sb["p_iters"]
+    for x, y in zip(a.fields()[:3], b.fields()[:3]):
+        assert np.array_equal(x, y)

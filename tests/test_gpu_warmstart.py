@@ -259,3 +259,46 @@ def test_full_resolution_network_leaves_other_arrays_alone():
     ia, ib = a.ibm(), b.ibm()
     assert np.array_equal(ia["fu"], ib["fu"]) and np.array_equal(ia["fv"], ib["fv"])
     assert np.count_nonzero(ia["fv"]) > 0
+
+
+def test_backtracking_step_rule():
+    # IBM_NET_STEP_BACKTRACK: full steps, halved when a segment ends worse; a
+    # zero network changes nothing, a random one still converges
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    a = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    b = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    c = _solver(wl, p_init_prev=ibm.INIT_PREVIOUS)
+    assert b.set_option(ibm.OPT_NET_STEP, 2) == ibm.ERR_INVALID
+    for s, prm in ((b, np.zeros(U.param_count(), np.float32)), (c, U.flatten_params(OU.init_params(11)))):
+        for opt, val in ((ibm.OPT_NET_FACTOR, 2), (ibm.OPT_NET_EVERY, 100), (ibm.OPT_NET_STEP, ibm.NET_STEP_BACKTRACK)):
+            assert s.set_option(opt, val) == ibm.OK
+        net = U.UNet(1, wl["ny"] // 2, wl["nx"] // 2, stream=s.stream)
+        net.set_params(prm)
+        s.set_warm_start(net, 1.0)
+    for _ in range(2):
+        sa, sb, sc = a.step(1), b.step(1), c.step(1)
+        assert sa["p_iters"] == sb["p_iters"] and sb["net_step"] == 1.0
+        assert sc["rc"] == ibm.OK and sc["p_rel"] <= wl["params"]["p_tol"]
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+
+
+def test_map_selection_zeroes_the_dropped_maps():
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wl = _wl()
+    nx, ny = wl["nx"], wl["ny"]
+    s = _solver(wl, p_method=ibm.PCG)
+    s.step(2)
+    assert s.set_option(ibm.OPT_NET_MAPS, 0) == ibm.ERR_INVALID
+    assert s.set_option(ibm.OPT_NET_MAPS, 5) == ibm.OK  # residual and mask
+    f = torch.empty((3, ny, nx), dtype=torch.float32, device="cuda:0")
+    t = torch.empty((ny, nx), dtype=torch.float32, device="cuda:0")
+    s.set_snapshot(f, t, 1.0)
+    s.step(1)
+    f = f.cpu().numpy()
+    assert np.all(f[1] == 0.0) and np.any(f[0] != 0.0) and np.any(f[2] > 0.0)
+    assert abs(np.sqrt(np.mean(f[0].astype(np.float64) ** 2)) - 1.0) < 1e-5
