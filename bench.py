@@ -277,7 +277,9 @@ def batch_leg(args):
     grid size alone (small grids want small tiles to fill the GPU); the batch
     is timed with those and with the largest default shape (104x32) for every
     case, since a batch has parallelism to spare and small tiles cost halo
-    work; the faster of the two is reported as the batched time."""
+    work; the faster of the two is reported as the batched time.  The
+    104x32 batch is also timed replaying stretches of args.c4_graph check
+    intervals from a HIP graph."""
     import torch
     from paper_2402_17337_amd import ibm
     from paper_2402_17337_amd import workloads as W
@@ -305,8 +307,10 @@ def batch_leg(args):
                 tuned[key] = s.autotune_tiles()[0]
                 s.close()
 
-    def timed_batch(solvers):
+    def timed_batch(solvers, graph=0):
         batch = ibm.Batch(solvers)
+        if graph:
+            batch.set_graph(graph)
         batch.step(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -318,6 +322,10 @@ def batch_leg(args):
 
     t_uniform, st_b = timed_batch(make({}))
     log(f"batched step of {len(cases)} cases, 104x32 tiles: {t_uniform:.3f} s")
+    t_graph = None
+    if args.c4_graph:
+        t_graph, st_g = timed_batch(make({}), args.c4_graph)
+        log(f"batched step of {len(cases)} cases, 104x32 tiles, graph of {args.c4_graph} intervals: {t_graph:.3f} s")
     t_tuned = None
     if tuned:
         t_tuned, st_t = timed_batch(make(tuned))
@@ -337,7 +345,9 @@ def batch_leg(args):
                                              for a, b in zip(st_t, st_s))
     same_iters = all(a["p_iters"] == b["p_iters"] and abs(a["p_rel"] - b["p_rel"]) <= 1e-12 * b["p_rel"]
                      for a, b in zip(st_b, st_s))
-    t_b = min(t_uniform, t_tuned) if t_tuned is not None else t_uniform
+    t_b = min(t for t in (t_uniform, t_tuned, t_graph) if t is not None)
+    graph_same = None if t_graph is None else all(
+        a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"] and a["cd"] == b["cd"] for a, b in zip(st_g, st_b))
     cells = [c["nx"] * c["ny"] for c in cases]
     upd = sum(n * st["p_iters"] for n, st in zip(cells, st_b))
     return {"workload": f"{len(cases)} plunging cases, grids 256x192..1024x768 (seed 0), one time step, "
@@ -346,6 +356,9 @@ def batch_leg(args):
             "speedup": round(t_s / t_b, 3) if t_b > 0 else None,
             "batched_s_uniform_104x32": round(t_uniform, 4),
             "batched_s_per_size_tiles": round(t_tuned, 4) if t_tuned is not None else None,
+            "batched_s_uniform_104x32_graph": round(t_graph, 4) if t_graph is not None else None,
+            "graph_intervals": args.c4_graph or None,
+            "graph_batch_bitwise_equal_to_launched": graph_same,
             "batched_cell_updates_per_s": round(upd / t_b, 1), "sequential_cell_updates_per_s": round(upd / t_s, 1),
             "poisson_iters": sorted(set(st["p_iters"] for st in st_b)),
             "per_size_batch_bitwise_equal_to_sequential": same,
@@ -461,6 +474,9 @@ def main():
     ap.add_argument("--c4-iters", type=int, default=2000, help="Poisson iteration cap of the batched leg")
     ap.add_argument("--c4-autotune", type=int, default=1,
                     help="1: tune the tile shape per grid size (for the case-by-case run, and as a batch variant)")
+    ap.add_argument("--c4-graph", type=int, default=10,
+                    help="check intervals per HIP-graph stretch of the batched variant replayed from a graph "
+                         "(even; 0: skip that variant)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of this many MiB, 20 times "
                          "(reference kernel for scaling the HBM byte counters)")

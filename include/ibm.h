@@ -275,6 +275,22 @@ int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, doubl
 typedef struct ibm_batch ibm_batch;
 int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out);
 int32_t ibm_batch_step(ibm_batch* batch, int32_t nsteps, ibm_step_stats* last);
+
+/* Graph replay of the batched pressure solve.  intervals > 0 (even, at most
+ * 1000): the launches of that many check intervals (the blocked sweeps and
+ * the stop tests of all cases) are captured once into a HIP graph, on a
+ * private stream of the batch, and each stretch of the solve replays it on
+ * the contexts' stream after a one-thread launch that sets the stretch's
+ * iteration base; the host waits on one event per stretch instead of one per
+ * interval.  The final intervals that do not fill a stretch (up to the
+ * largest p_max_iter) are launched one by one.  Results, iteration counts
+ * and statuses are bit for bit those without the graph; a case that finishes
+ * inside a stretch leaves the rest of the stretch's launches to skip its
+ * tiles.  The graph is captured at the next ibm_batch_step and again when
+ * the cases' tile counts change.  intervals = 0 (the default): no graph.
+ * IBM_ERR_INVALID for odd or out-of-range counts; IBM_ERR_HIP if the stream
+ * or the 8-byte device cursor cannot be made (then the setting is unchanged). */
+int32_t ibm_batch_set_graph(ibm_batch* batch, int32_t intervals);
 void ibm_batch_destroy(ibm_batch* batch);
 const char* ibm_batch_last_error(const ibm_batch* batch);
 

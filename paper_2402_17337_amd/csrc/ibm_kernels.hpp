@@ -801,10 +801,17 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr_batch(const TbCase* __re
 // block size of the check the single-grid solve would use, so that the sums
 // and decisions are the same): phase 0 sums the nb0 partials of the initial
 // residual, later phases the ntiles partials of set pbuf after `it`
-// iterations.  Finished cases only republish.
+// iterations.  Finished cases only republish.  With a cursor (cur non-null:
+// {iteration base, snapshot entry}, written by k_batch_cursor) `it` counts
+// from the base and the snapshots go to entry cur[1] of the slot ring, so
+// that one captured sequence of launches serves every stretch of the solve.
 __global__ __launch_bounds__(kTbThreads) void k_check_batch(const TbCase* __restrict__ cases, int phase, int it,
-                                                            int pbuf, Slot* slots) {
+                                                            int pbuf, Slot* slots, const int* __restrict__ cur) {
     __shared__ double lds[2 * kTbWaves];
+    if (cur) {
+        it += cur[0];
+        slots += (size_t)cur[1] * gridDim.x;
+    }
     const TbCase& C = cases[blockIdx.x];
     if (C.ctl->done) {
         if (threadIdx.x == 0) publish(C.ctl, slots + blockIdx.x);
@@ -815,6 +822,14 @@ __global__ __launch_bounds__(kTbThreads) void k_check_batch(const TbCase* __rest
     if (threadIdx.x == 0) {
         check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, 0, 0);
         publish(C.ctl, slots + blockIdx.x);
+    }
+}
+
+// Sets the cursor read by the checks of a captured stretch of a batched solve.
+__global__ void k_batch_cursor(int* cur, int base, int entry) {
+    if (threadIdx.x == 0) {
+        cur[0] = base;
+        cur[1] = entry;
     }
 }
 

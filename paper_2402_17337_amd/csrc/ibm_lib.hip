@@ -1259,6 +1259,7 @@ Box motion_box(const ibm_params& P, const double* xf, const double* yf) {
 // blocked launch per S iterations over a work list of all their tiles.
 // ---------------------------------------------------------------------------
 constexpr int kBatchRing = kAheadSor + 2;  // check entries in flight
+constexpr int kMaxGraphIntervals = 1000;   // check intervals in one captured stretch
 
 }  // namespace
 
@@ -1272,6 +1273,12 @@ struct ibm_batch {
     Slot* dslots = nullptr;
     hipEvent_t ev[kBatchRing] = {};
     long seq = 0;
+    // captured stretches: graph_iv check intervals of launches in one HIP graph
+    int graph_iv = 0;                // 0: every launch from the host
+    hipStream_t cap = nullptr;       // private stream the graph is captured on
+    hipGraphExec_t gexec = nullptr;  // instantiated for (g_ntotal, g_per, g_iv)
+    int g_ntotal = -1, g_per = -1, g_iv = 0;
+    int* dcur = nullptr;             // {iteration base, slot entry} read by the captured checks
     std::string err;
 };
 
@@ -1321,6 +1328,62 @@ int32_t batch_upload(ibm_batch* b) {
     return IBM_OK;
 }
 
+// Blocked launches of the batched sweep before the check after `it`
+// iterations: check intervals of K iterations (the last one of a solve may be
+// shorter), each split into launches of at most S iterations.
+long batch_launches_at(const ibm_batch* b, int it) {
+    const long per_iv = (b->K + b->S - 1) / b->S;
+    return (long)(it / b->K) * per_iv + ((it % b->K) + b->S - 1) / b->S;
+}
+
+// Captures graph_iv check intervals of the batched loop (starting after an
+// even number of intervals and launches, so that the pair flips and partial
+// sets repeat from one stretch to the next) into one HIP graph.  The checks
+// take their iteration base and snapshot entry from the cursor.
+int32_t batch_capture(ibm_batch* b) {
+    if (b->gexec && b->g_ntotal == b->ntotal && b->g_per == b->per && b->g_iv == b->graph_iv) return IBM_OK;
+    if (b->gexec) {
+        BATCH_TRY(hipStreamSynchronize(b->stream));  // a replay of the old graph may still run
+        BATCH_TRY(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
+    const int n = (int)b->cs.size();
+    BATCH_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    long nl = 0;
+    for (int j = 0; j < b->graph_iv; ++j) {
+        for (int i = 0; i < b->K;) {
+            const int ns = std::min(b->S, b->K - i);
+            const int resid = (i + ns == b->K) ? 1 : 0;
+            hipLaunchKernelGGL(k_sor_tbr_batch, dim3(8 * b->per), dim3(kTbThreads), 0, b->cap,
+                               (const TbCase*)b->dcases, n, b->ntotal, b->per, (int)(nl & 1), ns, resid, j & 1);
+            ++nl;
+            i += ns;
+        }
+        hipLaunchKernelGGL(k_check_batch, dim3(n), dim3(kTbThreads), 0, b->cap, (const TbCase*)b->dcases, 1,
+                           (j + 1) * b->K, j & 1, b->dslots, (const int*)b->dcur);
+    }
+    const hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        b->err = std::string("capture of the batched sweep failed: ") +
+                 hipGetErrorString(le != hipSuccess ? le : ce);
+        return IBM_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiateWithFlags(&b->gexec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        b->gexec = nullptr;
+        b->err = std::string("hipGraphInstantiateWithFlags: ") + hipGetErrorString(ie);
+        return IBM_ERR_HIP;
+    }
+    b->g_ntotal = b->ntotal;
+    b->g_per = b->per;
+    b->g_iv = b->graph_iv;
+    return IBM_OK;
+}
+
 // The pressure solves of all contexts of the batch (phi and V b natural on
 // entry; on return the solution is in each context's (phr, phb) pair).
 int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
@@ -1341,13 +1404,20 @@ int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
     }
     int32_t rc = batch_upload(b);
     if (rc) return rc;
-    std::deque<std::pair<int, long>> pending;  // (ring entry, blocked launches before its test)
+    if (b->graph_iv > 0) {
+        rc = batch_capture(b);
+        if (rc) return rc;
+    }
+    // (ring entry, blocked launches before its test; -1: a captured stretch,
+    // whose launch count at a case's finish follows from its iteration count)
+    std::deque<std::pair<int, long>> pending;
     auto check = [&](int phase, int it, int pbuf, long nl) -> int32_t {
         const int e = (int)(b->seq++ % kBatchRing);
         // phase 0 sums the initial residual's partials as the single-grid k_check
         // does (kBlock threads); later phases as the folded test (kTbThreads)
         hipLaunchKernelGGL(k_check_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
-                           (const TbCase*)b->dcases, phase, it, pbuf, b->dslots + (size_t)e * n);
+                           (const TbCase*)b->dcases, phase, it, pbuf, b->dslots + (size_t)e * n,
+                           (const int*)nullptr);
         if (hipGetLastError() != hipSuccess) {
             b->err = "k_check_batch launch failed";
             return IBM_ERR_HIP;
@@ -1365,8 +1435,24 @@ int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
     long nlaunch = 0;
     int nint = 0, it = 0;
     const int max_e = b->max_iter;
+    const long stretch = (long)b->graph_iv * b->K;
+    const int ahead = b->graph_iv > 0 ? std::max(2, kAheadSor / b->graph_iv) : kAheadSor;
     for (;;) {
-        if (it < max_e) {
+        if (it < max_e && b->gexec && (nint & 1) == 0 && (nlaunch & 1) == 0 && it + stretch <= max_e) {
+            const int e = (int)(b->seq++ % kBatchRing);
+            hipLaunchKernelGGL(k_batch_cursor, dim3(1), dim3(kWave), 0, b->stream, b->dcur, it, e);
+            if (hipGetLastError() != hipSuccess) {
+                b->err = "k_batch_cursor launch failed";
+                return IBM_ERR_HIP;
+            }
+            BATCH_TRY(hipGraphLaunch(b->gexec, b->stream));
+            BATCH_TRY(hipEventRecord(b->ev[e], b->stream));
+            pending.emplace_back(e, -1L);
+            it += (int)stretch;
+            nint += b->graph_iv;
+            nlaunch += batch_launches_at(b, (int)stretch);
+            if ((int)pending.size() < ahead && it < max_e) continue;
+        } else if (it < max_e) {
             const int next = std::min(it + b->K, max_e);
             const int pbuf = nint & 1;
             while (it < next) {
@@ -1406,7 +1492,7 @@ int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
             if (hs->done) {
                 finished[k] = 1;
                 ++nfin;
-                done_launches[k] = nl;
+                done_launches[k] = nl >= 0 ? nl : batch_launches_at(b, hs->iters);
                 outs[k].status = hs->status;
                 outs[k].iters = hs->iters;
                 outs[k].rn = hs->rn;
@@ -1549,7 +1635,38 @@ void ibm_batch_destroy(ibm_batch* b) {
     if (b->dcases) (void)hipFree(b->dcases);
     if (b->hcases) (void)hipHostFree(b->hcases);
     if (b->hslots) (void)hipHostFree(b->hslots);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->dcur) (void)hipFree(b->dcur);
     delete b;
+}
+
+int32_t ibm_batch_set_graph(ibm_batch* b, int32_t intervals) {
+    if (!b) return IBM_ERR_INVALID;
+    if (intervals != 0 && (intervals < 2 || intervals > kMaxGraphIntervals || (intervals & 1))) return IBM_ERR_INVALID;
+    b->err.clear();
+    if (intervals > 0) {
+        if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+            b->cap = nullptr;
+            b->err = "hipStreamCreateWithFlags failed";
+            return IBM_ERR_HIP;
+        }
+        if (!b->dcur && hipMalloc((void**)&b->dcur, 2 * sizeof(int)) != hipSuccess) {
+            b->dcur = nullptr;
+            b->err = "hipMalloc of the cursor failed";
+            return IBM_ERR_HIP;
+        }
+    }
+    b->graph_iv = intervals;
+    if (intervals == 0 && b->gexec) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) {
+            b->err = "hipStreamSynchronize failed";
+            return IBM_ERR_HIP;
+        }
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return IBM_OK;
 }
 
 const char* ibm_batch_last_error(const ibm_batch* b) { return b ? b->err.c_str() : "null batch"; }

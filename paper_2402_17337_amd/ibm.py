@@ -37,8 +37,8 @@ SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
             "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot",
-            "ibm_batch_create", "ibm_batch_step", "ibm_batch_destroy", "ibm_batch_last_error", "ibm_profile", "ibm_profile_query",
-            "ibm_destroy",
+            "ibm_batch_create", "ibm_batch_step", "ibm_batch_set_graph", "ibm_batch_destroy", "ibm_batch_last_error",
+            "ibm_profile", "ibm_profile_query", "ibm_destroy",
             "ibm_status_string", "ibm_last_error")
 
 
@@ -120,6 +120,8 @@ def lib():
         L.ibm_batch_create.restype = C.c_int32
         L.ibm_batch_step.argtypes = [vp, C.c_int32, C.POINTER(StepStats)]
         L.ibm_batch_step.restype = C.c_int32
+        L.ibm_batch_set_graph.argtypes = [vp, C.c_int32]
+        L.ibm_batch_set_graph.restype = C.c_int32
         L.ibm_batch_destroy.argtypes = [vp]
         L.ibm_batch_destroy.restype = None
         L.ibm_batch_last_error.argtypes = [vp]
@@ -426,6 +428,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_graph(self, intervals: int):
+        """Replay the batched solve from a HIP graph of `intervals` check
+        intervals (even; 0 switches the graph off)."""
+        rc = lib().ibm_batch_set_graph(self._h, intervals)
+        if rc != OK:
+            raise IbmError(f"ibm_batch_set_graph({intervals}) failed: {status_string(rc)}")
 
     def step(self, n: int = 1):
         """n time steps of every case; returns the last step's statistics per case."""

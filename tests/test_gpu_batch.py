@@ -20,9 +20,9 @@ def _cases():
             W.small_plunging(96, 64, seed=3)]
 
 
-def _solver(wl, tile=None):
+def _solver(wl, tile=None, **over):
     from paper_2402_17337_amd import ibm
-    s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **wl["params"])
+    s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"], **dict(wl["params"], **over))
     if tile:
         assert s.set_option(ibm.OPT_TB_TILE_X, tile[0]) == ibm.OK
         assert s.set_option(ibm.OPT_TB_TILE_Y, tile[1]) == ibm.OK
@@ -54,6 +54,40 @@ def test_batched_steps_equal_solo_steps_bitwise():
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("intervals,cap", [(4, None), (6, 1234)])
+def test_graph_replayed_batch_equals_launched_batch_bitwise(intervals, cap):
+    """Stretches of `intervals` check intervals replayed from one HIP graph,
+    with each case's steps around the solve run eagerly between the replays:
+    every step equals the batch launched interval by interval.  With the cap
+    (1234 iterations: 30 stretches of 40 or 20 of 60, then intervals launched
+    one by one, the last of 4 iterations) some solves end at the limit; in
+    the uncapped run the cases finish inside stretches.  The last step runs
+    with the graph switched off again."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    over = {} if cap is None else {"p_max_iter": cap}
+    plain = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
+    graphed = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
+    graphed.set_graph(intervals)
+    for step in range(4):
+        if step == 3:
+            graphed.set_graph(0)
+        st_p, st_g = plain.step(1), graphed.step(1)
+        assert st_p[0]["rc"] == st_g[0]["rc"]
+        for a, b in zip(st_p, st_g):
+            for key in ("status", "p_iters", "p_rel", "p_r0", "cd", "cl"):
+                assert a[key] == b[key], (step, key, a[key], b[key])
+    iters = [st["p_iters"] for st in st_p]
+    if cap is None:
+        assert len(set(iters)) > 1 and any(k % (10 * intervals) for k in iters)
+    else:
+        assert cap in iters
+    for a, b in zip(plain.solvers, graphed.solvers):
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+
+
 def test_batch_validation():
     _need_gpu()
     from paper_2402_17337_amd import ibm
@@ -72,6 +106,12 @@ def test_batch_validation():
     assert b.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK
     with pytest.raises(ibm.IbmError):
         ibm.Batch([a, b])           # one sweep count for all
+    batch = ibm.Batch([a])
+    for bad in (3, -2, 1002):
+        with pytest.raises(ibm.IbmError):
+            batch.set_graph(bad)    # even counts from 2 to 1000, or 0
+    batch.set_graph(2)
+    batch.set_graph(0)
 
 
 def test_autotune_picks_a_candidate_and_keeps_the_iterates():
