@@ -77,14 +77,17 @@ def build_if_missing():
         __graft_entry__.build()
 
 
-def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None, net=None, keep_fields=False):
+def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None, net=None, keep_fields=False,
+            check=None):
     """Time `steps` steps after `warmup` untimed ones.  p_init overrides the
     initial guess; net = (params, out_scale, factor, every, options) attaches
-    a trained warm-start network."""
+    a trained warm-start network; check overrides the stop-test interval."""
     import torch
     from paper_2402_17337_amd import ibm
 
     prm = dict(case["params"], p_method=method)
+    if check is not None:
+        prm["p_check"] = check
     if max_iters > 0:
         prm["p_max_iter"] = max_iters
     if p_init is not None:
@@ -116,7 +119,7 @@ def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None
         stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"{case['nx']}x{case['ny']} method {method} p_init {prm.get('p_init_prev')} "
+    log(f"{case['nx']}x{case['ny']} method {method} p_init {prm.get('p_init_prev')} check {prm.get('p_check', 10)} "
         f"net {'yes' if net is not None else 'no'}: {steps} steps in {wall:.2f} s, iterations {iters}")
     prof = {k: g.profile_query(k) for k in ibm.KERNEL_NAMES}
     fields = g.fields() if keep_fields else None
@@ -161,12 +164,14 @@ def network_roofline(params, case, factor, reps=20):
     return out
 
 
-def c3_learned_leg(params, scale, steps):
+def c3_learned_leg(params, scale, steps, mp_check=10):
     """Full 2048x1536 steps to the 1e-8 stop test: SOR with the learned
     correction (the network trained on the 1024x768 workload, on the grid
-    coarsened 16x: again 128x96), with FP64 sweeps and with FP32 sweeps + FP64
-    refinement, from one common state (one PCG step); errors of the mixed
-    form in u, v, p and the force coefficients against the FP64 form."""
+    coarsened 16x: again 128x96), with FP64 sweeps (stop test every 10
+    iterations, and every mp_check) and with FP32 sweeps + FP64 refinement
+    every mp_check iterations, from one common state (one PCG step); errors
+    of the mixed form in u, v, p and the force coefficients against the FP64
+    form with the 10-iteration test."""
     import numpy as np
     import torch
     from paper_2402_17337_amd import ibm
@@ -180,8 +185,12 @@ def c3_learned_leg(params, scale, steps):
     blob = base.get_state()
     base.close()
     res = {}
-    for name, method in (("f64", ibm.RBSOR), ("mixed", ibm.RBSOR_MP)):
-        s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], device="cuda:0", **dict(wl["params"], p_method=method))
+    forms = [("f64", ibm.RBSOR, 10), ("mixed", ibm.RBSOR_MP, mp_check)]
+    if mp_check != 10:
+        forms.insert(1, ("f64_same_interval", ibm.RBSOR, mp_check))
+    for name, method, check in forms:
+        s = ibm.Solver(wl["nx"], wl["ny"], wl["xf"], wl["yf"], device="cuda:0",
+                       **dict(wl["params"], p_method=method, p_check=check))
         s.set_state(blob)
         for opt, val in ((ibm.OPT_NET_FACTOR, 16), (ibm.OPT_NET_EVERY, 4000), (ibm.OPT_NET_MAPS, 5)):
             if s.set_option(opt, val) != ibm.OK:
@@ -195,7 +204,8 @@ def c3_learned_leg(params, scale, steps):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         log(f"2048x1536 learned {name}: {steps} steps in {wall:.2f} s, iterations {[x['p_iters'] for x in sts]}")
-        res[name] = dict(s_per_step=round(wall / steps, 4), poisson_iters=[x["p_iters"] for x in sts],
+        res[name] = dict(s_per_step=round(wall / steps, 4), check_interval=check,
+                         poisson_iters=[x["p_iters"] for x in sts],
                          final_rel_residual=[x["p_rel"] for x in sts], fields=s.fields()[:3], forces=s.forces())
         s.close()
     f, m = res["f64"], res["mixed"]
@@ -207,8 +217,10 @@ def c3_learned_leg(params, scale, steps):
     return {"workload": "plunging ellipse 2048x1536, Re 1000, h 0.6, f 0.5; steps 2.. after one common PCG step, "
                         "pressure solves to 1e-8 with the learned correction (network trained on 1024x768, "
                         "coarse grid 128x96)",
-            "f64": res["f64"], "mixed": res["mixed"],
+            **res,
             "mixed_speedup": round(res["f64"]["s_per_step"] / res["mixed"]["s_per_step"], 3),
+            "mixed_speedup_same_interval": round(res["f64_same_interval"]["s_per_step"] / res["mixed"]["s_per_step"], 3)
+            if "f64_same_interval" in res else None,
             "mixed_rel_error_vs_f64": err}
 
 
@@ -258,7 +270,8 @@ def learned_legs(case, args, sor_leg):
         out[name] = d
     out["network_roofline"] = network_roofline(params, case, F)
     if args.c3_learned_steps > 0:
-        out["c3_full_steps"] = c3_learned_leg(params, scale, args.c3_learned_steps)
+        out["c3_full_steps"] = c3_learned_leg(params, scale, args.c3_learned_steps,
+                                              args.mp_check if 4000 % args.mp_check == 0 else 10)
     if args.pcg_steps > 0:
         leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, 0, p_init=ibm.INIT_LEARNED,
                       net=(params, scale, F, 0, opts))
@@ -463,6 +476,8 @@ def main():
                     help="1: also time the SOR kernels on the HBM-resident 8192x6144 grid")
     ap.add_argument("--learned", type=int, default=1,
                     help="1: train the warm-start network on the GPU and time the learned guess and correction")
+    ap.add_argument("--mp-check", type=int, default=100,
+                    help="stop-test (= refinement) interval of the FP32-sweep legs; the FP64 legs test every 10")
     ap.add_argument("--c3-learned-steps", type=int, default=2,
                     help="full 2048x1536 steps with the learned correction, FP64 and mixed sweeps (0: skip)")
     ap.add_argument("--learned-every", type=int, default=4000,
@@ -518,13 +533,18 @@ def main():
     mp_leg = None
     if args.solver == "sor" and args.mp_steps > 0:
         mp_leg = gpu_leg(case, ibm.RBSOR_MP, args.mp_steps, args.warmup, args.profile_every,
-                         args.max_poisson_iters)
+                         args.max_poisson_iters, check=args.mp_check)
+    f64_same = None
+    if mp_leg is not None and args.mp_check != 10:
+        f64_same = gpu_leg(case, ibm.RBSOR, args.mp_steps, args.warmup, 0, args.max_poisson_iters,
+                           check=args.mp_check)
     c3 = None
     if args.solver == "sor" and args.c3_iters > 0:
         case3 = W.plunging_2048x1536()
         c3 = {}
         for name, m in (("f64", ibm.RBSOR), ("mixed", ibm.RBSOR_MP)):
-            leg = gpu_leg(case3, m, 1, 0, args.profile_every, args.c3_iters)
+            leg = gpu_leg(case3, m, 1, 0, args.profile_every, args.c3_iters,
+                          check=args.mp_check if m == ibm.RBSOR_MP else None)
             c3[name] = {"s_per_step": round(leg["wall"], 4), "poisson_iters": leg["iters"][0],
                         "us_per_iteration": round(1e6 * leg["wall"] / max(leg["iters"][0], 1), 3)}
 
@@ -584,12 +604,17 @@ def main():
                     "avg_us": round(q["avg_ms"] * 1e3, 3),
                     "achieved_GBps": round(q["bytes_per_launch"] / (q["avg_ms"] * 1e-3) / 1e9, 1)}
         mp_s = mp_leg["wall"] / mp_steps
+        f64_same_s = f64_same["wall"] / mp_steps if f64_same is not None else main_leg["wall"] / steps
         out["mixed_precision"] = {
             "solver": "red-black SOR omega 1.8, float sweeps on the correction, double residual, update and "
-                      "stop test every 10 iterations, tol 1e-8",
+                      f"stop test every {args.mp_check} iterations, tol 1e-8",
+            "check_interval": args.mp_check,
             "s_per_time_step": round(mp_s, 6),
             "poisson_iters_per_step": mp_leg["iters"],
             "speedup_vs_f64_sor": round((main_leg["wall"] / steps) / mp_s, 3) if mp_s > 0 else None,
+            "f64_same_interval": {"s_per_time_step": round(f64_same_s, 6),
+                                  "poisson_iters_per_step": (f64_same or main_leg)["iters"]},
+            "speedup_vs_f64_same_interval": round(f64_same_s / mp_s, 3) if mp_s > 0 else None,
             "kernels": kern}
     if c3 is not None:
         out["c3_capped"] = dict(c3, workload="plunging ellipse 2048x1536, Re 1000, h 0.6, f 0.5; first step, "

@@ -7,8 +7,11 @@ The method accelerates the paper's red-black SOR pressure solve (Sec. 2.2,
 multiply-adds and float-rounded 1-D coefficient arrays on the GPU, plain float
 operations on the oracle's coefficients), so the bar is derived from the
 arithmetic rather than 1e-10:
-  - after one check interval from the same start, the correction agrees to
-    single-precision rounding: |x_gpu - x_oracle| <= 1e-5 |x_oracle - x0|;
+  - after one check interval of K iterations from the same start, the
+    correction agrees to single-precision rounding:
+    |x_gpu - x_oracle| <= max(1e-5, 10 K u) |x_oracle - x0|, u = 2^-24 (the
+    sweeps are contractive, so rounding errors of the K float iterations add
+    at most linearly; K = 10 and the benchmark's K = 100);
   - to tolerance, both stop within one check interval of each other and of
     double SOR, and the GPU result meets the double-precision stop test when
     its residual is recomputed by the oracle's operator;
@@ -28,17 +31,20 @@ def _vb(o, b):
     return b * np.diff(o.xf)[None, :] * np.diff(o.yf)[:, None]
 
 
-@pytest.mark.parametrize("nx,ny,stretched", [(128, 96, False), (200, 150, True), (16, 8, False)])
-def test_one_interval_matches_oracle_to_float_rounding(torch, nx, ny, stretched):
+@pytest.mark.parametrize("nx,ny,stretched,check", [(128, 96, False, 10), (200, 150, True, 10), (16, 8, False, 10),
+                                                   (128, 96, False, 100), (200, 150, True, 100)])
+def test_one_interval_matches_oracle_to_float_rounding(torch, nx, ny, stretched, check):
     o, g = _pair(torch, nx, ny, stretched)
     rng = np.random.default_rng(nx * 3 + ny)
     b = rng.standard_normal((ny, nx))
     x0 = rng.standard_normal((ny, nx))
-    for fixed in (10, 23):
-        xo, so, rco = o.poisson_solve(b, x0=x0, method=O.SOR_MP, omega=1.8, fixed=fixed, check=10)
-        x64, _, _ = o.poisson_solve(b, x0=x0, method=O.SOR, omega=1.8, fixed=fixed, check=10)
+    bar = max(1e-5, 10 * check * 2.0 ** -24)
+    for fixed in (check, 2 * check + 3):
+        xo, so, rco = o.poisson_solve(b, x0=x0, method=O.SOR_MP, omega=1.8, fixed=fixed, check=check)
+        x64, _, _ = o.poisson_solve(b, x0=x0, method=O.SOR, omega=1.8, fixed=fixed, check=check)
         xd = _dev(torch, x0)
-        st = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR_MP, omega=1.8, fixed_iters=fixed, check_every=10)
+        st = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR_MP, omega=1.8, fixed_iters=fixed,
+                             check_every=check)
         xg = xd.cpu().numpy()
         corr = np.linalg.norm(xo - x0)
         d_or = np.linalg.norm(xg - xo) / corr
@@ -46,19 +52,19 @@ def test_one_interval_matches_oracle_to_float_rounding(torch, nx, ny, stretched)
         print(f"{nx}x{ny} fixed={fixed}: |gpu-oracle_mp|/|corr| {d_or:.3e}  |gpu-oracle_f64|/|corr| {d_64:.3e} "
               f"rel {st['rel']:.3e} vs {so['rel']:.3e}", flush=True)
         assert rco == O.OK and st["rc"] == ibm.OK and st["iters"] == fixed
-        assert d_or <= 1e-5 and d_64 <= 1e-5
+        assert d_or <= bar and d_64 <= bar
         assert abs(st["rel"] - so["rel"]) <= 1e-4 * so["rel"]
 
 
-@pytest.mark.parametrize("nx,ny,stretched", [(128, 96, False), (200, 150, True)])
-def test_to_tolerance_meets_the_double_stop_test(torch, nx, ny, stretched):
+@pytest.mark.parametrize("nx,ny,stretched,check", [(128, 96, False, 10), (200, 150, True, 10), (200, 150, True, 100)])
+def test_to_tolerance_meets_the_double_stop_test(torch, nx, ny, stretched, check):
     o, g = _pair(torch, nx, ny, stretched)
     rng = np.random.default_rng(nx + 5)
     b = rng.standard_normal((ny, nx))
-    _, s64, _ = o.poisson_solve(b, method=O.SOR, omega=1.8, tol=1e-8)
-    xo, smp, _ = o.poisson_solve(b, method=O.SOR_MP, omega=1.8, tol=1e-8)
+    _, s64, _ = o.poisson_solve(b, method=O.SOR, omega=1.8, tol=1e-8, check=check)
+    xo, smp, _ = o.poisson_solve(b, method=O.SOR_MP, omega=1.8, tol=1e-8, check=check)
     xd = _dev(torch, np.zeros((ny, nx)))
-    st = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR_MP, omega=1.8, tol=1e-8, check_every=10)
+    st = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR_MP, omega=1.8, tol=1e-8, check_every=check)
     xg = xd.cpu().numpy()
     vb = _vb(o, b)
     r = vb - o.apply_A(xg)
@@ -66,7 +72,7 @@ def test_to_tolerance_meets_the_double_stop_test(torch, nx, ny, stretched):
     print(f"{nx}x{ny}: iters gpu {st['iters']} oracle_mp {smp['iters']} oracle_f64 {s64['iters']}; "
           f"true rel {true_rel:.3e}; |gpu-oracle_mp| {rel_l2(xg, xo):.3e}", flush=True)
     assert st["rc"] == ibm.OK
-    assert abs(st["iters"] - smp["iters"]) <= 10 and abs(st["iters"] - s64["iters"]) <= 10
+    assert abs(st["iters"] - smp["iters"]) <= check and abs(st["iters"] - s64["iters"]) <= check
     assert true_rel <= 1e-8 * (1 + 1e-6)
     assert abs(true_rel - st["rel"]) <= 1e-6 * true_rel + 1e-16
 
