@@ -246,14 +246,19 @@ def learned_legs(case, args, sor_leg):
            "training": info, "out_scale": scale,
            "reference": {"initial_guess": "previous phi", "s_per_time_step": round(base_s, 6),
                          "poisson_iters_per_step": sor_leg["iters"]}}
-    legs = (("zero_guess", ibm.INIT_ZERO, None),
-            ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts)),
-            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts)),
-            ("learned_guess_and_correction", ibm.INIT_LEARNED, (params, scale, F, every, opts)))
+    legs = [("zero_guess", ibm.INIT_ZERO, None, ibm.RBSOR, None),
+            ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts), ibm.RBSOR, None),
+            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR, None),
+            ("learned_guess_and_correction", ibm.INIT_LEARNED, (params, scale, F, every, opts), ibm.RBSOR, None)]
+    if every % args.mp_check == 0:
+        # the learned correction with FP32 sweeps and FP64 refinement (the
+        # refinement interval divides the correction interval)
+        legs.append(("learned_correction_mixed", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR_MP,
+                     args.mp_check))
     ref = sor_leg["fields"]
-    for name, p_init, net in legs:
-        leg = gpu_leg(case, ibm.RBSOR, args.steps, args.warmup, 0, p_init=p_init, net=net,
-                      keep_fields=ref is not None)
+    for name, p_init, net, meth, check in legs:
+        leg = gpu_leg(case, meth, args.steps, args.warmup, 0, p_init=p_init, net=net,
+                      keep_fields=ref is not None, check=check)
         s_step = leg["wall"] / args.steps
         d = {"s_per_time_step": round(s_step, 6), "poisson_iters_per_step": leg["iters"],
              "final_rel_residual": [st["p_rel"] for st in leg["stats"]],
@@ -263,6 +268,8 @@ def learned_legs(case, args, sor_leg):
             d["mean_step_length"] = [round(st["net_step"], 4) for st in leg["stats"]]
             if net[3]:
                 d["correction_every"] = net[3]
+        if check is not None:
+            d["check_interval"] = check
         if ref is not None and leg["fields"] is not None:
             d["rel_l2_vs_previous_guess_run"] = {
                 k: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
