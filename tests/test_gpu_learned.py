@@ -1,8 +1,8 @@
 """What the trained network gains: the learned correction of red-black SOR,
 trained on the GPU by the network's own kernels from solver snapshots, against
 the same SOR started from the previous step's correction, both to the same
-1e-8 residual.  A half-resolution (512x384) version of the plunging workload
-keeps the test to seconds."""
+1e-8 residual; also with FP32 sweeps and FP64 refinement.  A half-resolution
+(512x384) version of the plunging workload keeps the test to seconds."""
 import numpy as np
 import pytest
 import torch
@@ -32,3 +32,11 @@ def test_trained_correction_cuts_sor_iterations():
     print(f"previous guess {prev['p_iters']} iterations, learned {lrn['p_iters']} "
           f"({lrn['n_net']} network steps, mean step {lrn['net_step']:.3f})")
     assert lrn["p_iters"] < 0.67 * prev["p_iters"], (prev["p_iters"], lrn["p_iters"])
+    # the same network correcting the FP32-sweep solve (FP64 refinement and
+    # stop test every 100 iterations, a divisor of the correction interval)
+    wl_mp = dict(wl, params=dict(wl["params"], p_check=100))
+    mp = WS.evaluate(wl_mp, params, scale, warm_steps=2, method=ibm.RBSOR_MP, modes=(ibm.INIT_LEARNED,),
+                     factor=F, every=every, guess=False, options=WS.RECIPE_OPTIONS)[ibm.INIT_LEARNED][0]
+    print(f"learned with FP32 sweeps: {mp['p_iters']} iterations ({mp['n_net']} network steps)")
+    assert mp["rc"] == ibm.OK and mp["p_rel"] <= tol and mp["n_net"] >= 1
+    assert mp["p_iters"] < 0.67 * prev["p_iters"], (prev["p_iters"], mp["p_iters"])
