@@ -129,3 +129,20 @@ def test_batched_workload_recipe():
         assert 0.2 <= p["amp"] <= 0.8 and 0.2 <= p["freq"] <= 0.6 and p["re"] in (100.0, 300.0, 500.0)
         assert len(c["xf"]) == c["nx"] + 1 and np.all(np.diff(c["xf"]) > 0)
         assert ibm.workspace_bytes(c["nx"], c["ny"]) > 0
+
+
+def test_batch_entry_points_reject_null_handles():
+    import ctypes as C
+    L = ibm.lib()
+    assert L.ibm_batch_set_graph(None, 2) == ibm.ERR_INVALID
+    assert L.ibm_batch_step(None, 1, None) == ibm.ERR_INVALID
+    out = C.c_void_p()
+    assert L.ibm_batch_create(0, None, C.byref(out)) == ibm.ERR_INVALID and not out.value
+
+
+def test_benchmark_refuses_more_than_one_gpu():
+    # one GPU only: the refusal comes before anything touches a device
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
