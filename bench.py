@@ -307,11 +307,11 @@ def batch_leg(args):
     cases = W.batched_plunging(args.c4_cases, 0)
     cap = args.c4_iters
 
-    def make(tiles):
+    def make(tiles, **over):
         out = []
         for c in cases:
             s = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0",
-                           **dict(c["params"], p_max_iter=cap))
+                           **dict(c["params"], p_max_iter=cap, **over))
             tx, ty = tiles.get((c["nx"], c["ny"]), (104, 32))
             s.set_option(ibm.OPT_TB_TILE_X, tx)
             s.set_option(ibm.OPT_TB_TILE_Y, ty)
@@ -365,7 +365,32 @@ def batch_leg(args):
                                              for a, b in zip(st_t, st_s))
     same_iters = all(a["p_iters"] == b["p_iters"] and abs(a["p_rel"] - b["p_rel"]) <= 1e-12 * b["p_rel"]
                      for a, b in zip(st_b, st_s))
+    mixed = None
+    if args.c4_mixed:
+        # FP32 sweeps with FP64 refinement every args.mp_check iterations:
+        # batched (104x32 tiles) and case by case (per-size tiles; the tile
+        # shape does not change the float iterates, nor the refinement's sums)
+        over = dict(p_method=ibm.RBSOR_MP, p_check=args.mp_check)
+        t_mb, st_mb = timed_batch(make({}, **over))
+        log(f"mixed-precision batched step of {len(cases)} cases: {t_mb:.3f} s")
+        solo_mp = make(tuned, **over)
+        for s in solo_mp:
+            s.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_ms = [s.step(1) for s in solo_mp]
+        torch.cuda.synchronize()
+        t_ms = time.perf_counter() - t0
+        for s in solo_mp:
+            s.close()
+        log(f"the same mixed-precision step case by case: {t_ms:.3f} s")
+        mixed = {"check_interval": args.mp_check, "batched_s": round(t_mb, 4), "sequential_s": round(t_ms, 4),
+                 "speedup": round(t_ms / t_mb, 3),
+                 "bitwise_equal_to_sequential": all(a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"]
+                                                    and a["cd"] == b["cd"] for a, b in zip(st_mb, st_ms))}
     t_b = min(t for t in (t_uniform, t_tuned, t_graph) if t is not None)
+    if mixed is not None:
+        mixed["speedup_vs_f64_batch"] = round(t_b / mixed["batched_s"], 3)
     graph_same = None if t_graph is None else all(
         a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"] and a["cd"] == b["cd"] for a, b in zip(st_g, st_b))
     cells = [c["nx"] * c["ny"] for c in cases]
@@ -383,7 +408,8 @@ def batch_leg(args):
             "poisson_iters": sorted(set(st["p_iters"] for st in st_b)),
             "per_size_batch_bitwise_equal_to_sequential": same,
             "uniform_batch_same_iterations_as_sequential": same_iters,
-            "per_size_tiles": {f"{k[0]}x{k[1]}": f"{v[0]}x{v[1]}" for k, v in tuned.items()}}
+            "per_size_tiles": {f"{k[0]}x{k[1]}": f"{v[0]}x{v[1]}" for k, v in tuned.items()},
+            "mixed_precision": mixed}
 
 
 def stress_leg(nx=8192, ny=6144, iters=60):
@@ -496,6 +522,8 @@ def main():
     ap.add_argument("--c4-iters", type=int, default=2000, help="Poisson iteration cap of the batched leg")
     ap.add_argument("--c4-autotune", type=int, default=1,
                     help="1: tune the tile shape per grid size (for the case-by-case run, and as a batch variant)")
+    ap.add_argument("--c4-mixed", type=int, default=1,
+                    help="1: also time the batched leg with FP32 sweeps and FP64 refinement (--mp-check)")
     ap.add_argument("--c4-graph", type=int, default=10,
                     help="check intervals per HIP-graph stretch of the batched variant replayed from a graph "
                          "(even; 0: skip that variant)")

@@ -262,11 +262,14 @@ int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, doubl
  * Each case's iterates, iteration counts and results are those of ibm_step on
  * that context alone (its own tile shape, omega, tolerance and limit).
  * ibm_batch_create: n >= 1 distinct contexts (borrowed, kept alive by the
- * caller), all on one stream, all IBM_SOLVER_RBSOR with the register-resident
- * blocked sweep (IBM_SOR_TEMPORAL), the same IBM_OPT_TB_SWEEPS and
- * p_check_every, at most 512 tiles each, no network correction or snapshot;
- * IBM_ERR_INVALID otherwise.  It allocates a small descriptor array on the
- * device and pinned host memory for the check snapshots.
+ * caller), all on one stream, either all IBM_SOLVER_RBSOR with the
+ * register-resident blocked sweep (IBM_SOR_TEMPORAL) or all
+ * IBM_SOLVER_RBSOR_MP (then each refinement runs as one launch over the row
+ * blocks of every case, and the float sweeps as one launch over all their
+ * tiles), the same IBM_OPT_TB_SWEEPS and p_check_every, at most 512 tiles
+ * each, no network correction or snapshot; IBM_ERR_INVALID otherwise.  It
+ * allocates a small descriptor array on the device and pinned host memory for
+ * the check snapshots.
  * ibm_batch_step: nsteps time steps of every case; each step runs every
  * case's steps before and after its pressure solve in turn and one batched
  * pressure solve between.  last (nullable): n statistics of the last step
@@ -288,7 +291,8 @@ int32_t ibm_batch_step(ibm_batch* batch, int32_t nsteps, ibm_step_stats* last);
  * inside a stretch leaves the rest of the stretch's launches to skip its
  * tiles.  The graph is captured at the next ibm_batch_step and again when
  * the cases' tile counts change.  intervals = 0 (the default): no graph.
- * IBM_ERR_INVALID for odd or out-of-range counts; IBM_ERR_HIP if the stream
+ * IBM_ERR_INVALID for odd or out-of-range counts and for a batch of
+ * IBM_SOLVER_RBSOR_MP contexts (no graph form); IBM_ERR_HIP if the stream
  * or the 8-byte device cursor cannot be made (then the setting is unchanged). */
 int32_t ibm_batch_set_graph(ibm_batch* batch, int32_t intervals);
 void ibm_batch_destroy(ibm_batch* batch);

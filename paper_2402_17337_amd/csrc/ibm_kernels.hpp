@@ -854,14 +854,10 @@ struct MpArrays {
     const float *rr, *rb;  // r32 in
 };
 
-__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp(
-    Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk, TbShape ts, int nsweep, int e_zero) {
-    __shared__ float edge32[2][kTrSlots][kWave];
-    __shared__ double lds[2 * kTbWaves];
-    __shared__ int s_flag;
-    const int nt = ts.ntx * ts.nty;
-    const int t = tb_tile(ts);
-    if (t >= nt) return;
+// Tile t of the float sweeps (S iterations on A e = r32).
+__device__ __forceinline__ void mp_tile(const Grid& g, const MpArrays& a, double omega, Ctl* ctl, const TbCheck& chk,
+                                        const TbShape& ts, int t, int nsweep, int e_zero,
+                                        float (&edge32)[2][kTrSlots][kWave], double* lds, int* s_flag) {
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
@@ -911,12 +907,22 @@ __global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8
     }
     tbr_rdiag<P>(rd, fdx, fE, fW, fD, fdy, fpn, fps, min(kTbRows, ly - jw), col);
     tbr_pin(rd);
-    if (tb_begin(ctl, chk, lds, &s_flag)) return;
+    if (tb_begin(ctl, chk, lds, s_flag)) return;
     tbr_edges(e, edge32, w, lane);
     __syncthreads();
     tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, 0, (float)omega);
     tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
     tb_end(ctl, chk);
+}
+
+__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp(
+    Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk, TbShape ts, int nsweep, int e_zero) {
+    __shared__ float edge32[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
+    const int t = tb_tile(ts);
+    if (t >= ts.ntx * ts.nty) return;
+    mp_tile(g, a, omega, ctl, chk, ts, t, nsweep, e_zero, edge32, lds, &s_flag);
 }
 
 // Refinement of a mixed-precision interval: x = phi + e (e = 0 with e_zero)
@@ -928,20 +934,17 @@ __device__ inline double mp_x(const double* __restrict__ ph, const float* __rest
     return e_zero ? ph[k] : ph[k] + (double)e[k];
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
-                                                           const double* __restrict__ phb,
-                                                           const float* __restrict__ er,
-                                                           const float* __restrict__ eb, int e_zero,
-                                                           const double* __restrict__ vbr,
-                                                           const double* __restrict__ vbb,
-                                                           double* __restrict__ ophr, double* __restrict__ ophb,
-                                                           float* __restrict__ orr, float* __restrict__ orb,
-                                                           const Ctl* __restrict__ ctl, double* partials) {
-    __shared__ double lds[2 * kRedThreads / kWave];
-    if (ctl->done) return;
+// Block blk of nblk: its rows' refinement and its partials.
+__device__ __forceinline__ void mp_refine_rows(const Grid& g, const double* __restrict__ phr,
+                                               const double* __restrict__ phb, const float* __restrict__ er,
+                                               const float* __restrict__ eb, int e_zero,
+                                               const double* __restrict__ vbr, const double* __restrict__ vbb,
+                                               double* __restrict__ ophr, double* __restrict__ ophb,
+                                               float* __restrict__ orr, float* __restrict__ orb, int blk, int nblk,
+                                               double* partials, double* lds) {
     double acc[2] = {0.0, 0.0};
-    const int rows = (g.ny + gridDim.x - 1) / gridDim.x;
-    const int j0 = blockIdx.x * rows, j1 = min(g.ny, j0 + rows);
+    const int rows = (g.ny + nblk - 1) / nblk;
+    const int j0 = blk * rows, j1 = min(g.ny, j0 + rows);
     const int npos = (j1 - j0) * g.nh;  // split positions of the block's rows
     for (int q = threadIdx.x; q < npos; q += blockDim.x) {
         const int jr = q / g.nh, m = q - jr * g.nh;
@@ -972,7 +975,104 @@ __global__ __launch_bounds__(kRedThreads) void k_mp_refine(Grid g, const double*
             acc[1] += bv * bv;
         }
     }
-    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+    block_partials(acc, partials, nblk, blk, lds);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
+                                                           const double* __restrict__ phb,
+                                                           const float* __restrict__ er,
+                                                           const float* __restrict__ eb, int e_zero,
+                                                           const double* __restrict__ vbr,
+                                                           const double* __restrict__ vbb,
+                                                           double* __restrict__ ophr, double* __restrict__ ophb,
+                                                           float* __restrict__ orr, float* __restrict__ orb,
+                                                           const Ctl* __restrict__ ctl, double* partials) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    if (ctl->done) return;
+    mp_refine_rows(g, phr, phb, er, eb, e_zero, vbr, vbb, ophr, ophb, orr, orb, blockIdx.x, gridDim.x, partials, lds);
+}
+
+// Many cases of the mixed-precision solve in one launch per step of the
+// solve, as the double-precision batch: the float sweeps over a work list of
+// all cases' tiles, the refinement over a list of all cases' row blocks (case
+// c's nbr blocks from rblk0, the split of its single-grid refinement), and
+// the stop tests one block per case.  Pair selectors are global: every case
+// advances in lockstep until it finishes, after which its launches return.
+struct MpCase {
+    Grid g;
+    double* ph[2][2];  // phi [pair][colour]
+    float* e[2][2];    // corrections [pair][colour]
+    float* r[2][2];    // float residuals [pair][colour]
+    const double *bred, *bblack;
+    double* partials[2];
+    Ctl* ctl;
+    TbShape ts;
+    double omega, tol;
+    int tile0, ntiles, rblk0, nbr, max_iter;
+};
+
+template <class CaseT>
+__device__ inline int batch_case(const CaseT* __restrict__ cases, int ncase, int item, int CaseT::*start) {
+    int lo = 0, hi = ncase - 1;  // last case whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cases[mid].*start <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Sweeps: e pair `eflip` in, the other out; float residual pair rsel.
+__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp_batch(
+    const MpCase* __restrict__ cases, int ncase, int ntotal, int per, int eflip, int rsel, int nsweep, int e_zero) {
+    __shared__ float edge32[2][kTrSlots][kWave];
+    __shared__ double lds[2 * kTbWaves];
+    __shared__ int s_flag;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= ntotal) return;
+    const MpCase& C = cases[batch_case(cases, ncase, t, &MpCase::tile0)];
+    MpArrays a;
+    a.er = C.e[eflip][0];
+    a.eb = C.e[eflip][1];
+    a.oer = C.e[eflip ^ 1][0];
+    a.oeb = C.e[eflip ^ 1][1];
+    a.rr = C.r[rsel][0];
+    a.rb = C.r[rsel][1];
+    const TbCheck none = {nullptr, 0, 0, 0, 0, 0.0, nullptr};
+    mp_tile(C.g, a, C.omega, C.ctl, none, C.ts, t - C.tile0, nsweep, e_zero, edge32, lds, &s_flag);
+}
+
+// Refinement: phi pair `pin` plus e pair `ein` into the other phi pair, the
+// float residual into pair rout, partials into set pbuf.
+__global__ __launch_bounds__(kRedThreads) void k_mp_refine_batch(const MpCase* __restrict__ cases, int ncase,
+                                                                 int nblocks, int pin, int ein, int e_zero, int rout,
+                                                                 int pbuf) {
+    __shared__ double lds[2 * kRedThreads / kWave];
+    if ((int)blockIdx.x >= nblocks) return;
+    const MpCase& C = cases[batch_case(cases, ncase, (int)blockIdx.x, &MpCase::rblk0)];
+    if (C.ctl->done) return;
+    mp_refine_rows(C.g, C.ph[pin][0], C.ph[pin][1], C.e[ein][0], C.e[ein][1], e_zero, C.bred, C.bblack,
+                   C.ph[pin ^ 1][0], C.ph[pin ^ 1][1], C.r[rout][0], C.r[rout][1], (int)blockIdx.x - C.rblk0, C.nbr,
+                   C.partials[pbuf], lds);
+}
+
+// Stop tests after a refinement, one block per case: the nbr partials of set
+// pbuf (phase 0: the initial residual).  At most kRedMax partials, so every
+// block size sums them in the same order as the single-grid tests.
+__global__ __launch_bounds__(kTbThreads) void k_check_mp_batch(const MpCase* __restrict__ cases, int phase, int it,
+                                                               int pbuf, Slot* slots) {
+    __shared__ double lds[2 * kTbWaves];
+    const MpCase& C = cases[blockIdx.x];
+    if (C.ctl->done) {
+        if (threadIdx.x == 0) publish(C.ctl, slots + blockIdx.x);
+        return;
+    }
+    double acc[2];
+    sum_partials(acc, C.partials[pbuf], C.nbr, lds);
+    if (threadIdx.x == 0) {
+        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, 0, 0);
+        publish(C.ctl, slots + blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -1279,6 +1279,11 @@ struct ibm_batch {
     hipGraphExec_t gexec = nullptr;  // instantiated for (g_ntotal, g_per, g_iv)
     int g_ntotal = -1, g_per = -1, g_iv = 0;
     int* dcur = nullptr;             // {iteration base, slot entry} read by the captured checks
+    // mixed-precision batches (every context IBM_SOLVER_RBSOR_MP)
+    bool mp = false;
+    MpCase* dmp = nullptr;  // device descriptors
+    MpCase* hmp = nullptr;  // pinned staging
+    int nrblk = 0;          // refinement blocks of all cases
     std::string err;
 };
 
@@ -1384,9 +1389,174 @@ int32_t batch_capture(ibm_batch* b) {
     return IBM_OK;
 }
 
+// The descriptors of the mixed-precision cases (current phi pairs).
+int32_t batch_upload_mp(ibm_batch* b) {
+    const int n = (int)b->cs.size();
+    int tile0 = 0, rblk0 = 0;
+    for (int k = 0; k < n; ++k) {
+        ibm_ctx* c = b->cs[k];
+        MpCase& d = b->hmp[k];
+        if (!tb_shape(c, b->S, c->tb_tx, c->tb_ty, &d.ts)) {
+            b->err = "case " + std::to_string(k) + ": its tile shape no longer fits the batched sweep";
+            return IBM_ERR_STATE;
+        }
+        const size_t NH = (size_t)c->nh * c->ny;
+        d.g = c->g;
+        d.ph[0][0] = c->phr;
+        d.ph[0][1] = c->phb;
+        d.ph[1][0] = c->phr2;
+        d.ph[1][1] = c->phb2;
+        for (int q = 0; q < 2; ++q)
+            for (int col = 0; col < 2; ++col) {
+                d.e[q][col] = c->mpf + (2 * q + col) * NH;
+                d.r[q][col] = c->mpf + (4 + 2 * q + col) * NH;
+            }
+        d.bred = c->vbr;
+        d.bblack = c->vbb;
+        d.partials[0] = c->partials;
+        d.partials[1] = c->partials + 2 * (size_t)kRedMax;
+        d.ctl = c->ctl + CTL_P;
+        d.omega = c->P.p_omega;
+        d.tol = c->P.p_tol;
+        d.max_iter = c->P.p_max_iter;
+        d.tile0 = tile0;
+        d.ntiles = d.ts.ntx * d.ts.nty;
+        d.rblk0 = rblk0;
+        d.nbr = red_blocks(NH);
+        tile0 += d.ntiles;
+        rblk0 += d.nbr;
+    }
+    b->ntotal = tile0;
+    b->per = (tile0 + 7) / 8;
+    b->nrblk = rblk0;
+    BATCH_TRY(hipMemcpyAsync(b->dmp, b->hmp, n * sizeof(MpCase), hipMemcpyHostToDevice, b->stream));
+    return IBM_OK;
+}
+
+// The mixed-precision pressure solves of all contexts of the batch, in the
+// single-grid order: a refinement of the initial phi (phase-0 test), then per
+// check interval the float sweeps from e = 0, a refinement and the test.
+// Pair selectors advance with the global counts of sweeps and refinements;
+// the phi pair holding a case's result follows from the refinements before
+// its finishing test.
+int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
+    const int n = (int)b->cs.size();
+    for (ibm_ctx* c : b->cs) {
+        const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->phi, c->phr, c->phb, 0);
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
+        int32_t rc = reset_ctl(c, CTL_P);
+        if (rc) return rc;
+        if (hipGetLastError() != hipSuccess) {
+            b->err = "launch failed";
+            return IBM_ERR_HIP;
+        }
+    }
+    int32_t rc = batch_upload_mp(b);
+    if (rc) return rc;
+    long nref = 0, nsw = 0;
+    auto refine = [&](int e_zero) -> int32_t {
+        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kRedThreads), 0, b->stream, (const MpCase*)b->dmp,
+                           n, b->nrblk, (int)(nref & 1), (int)(nsw & 1), e_zero, (int)((nref + 1) & 1),
+                           (int)(nref & 1));
+        if (hipGetLastError() != hipSuccess) {
+            b->err = "k_mp_refine_batch launch failed";
+            return IBM_ERR_HIP;
+        }
+        ++nref;
+        return IBM_OK;
+    };
+    std::deque<std::pair<int, long>> pending;  // (ring entry, refinements before its test)
+    auto check = [&](int phase, int it) -> int32_t {
+        const int e = (int)(b->seq++ % kBatchRing);
+        hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
+                           (const MpCase*)b->dmp, phase, it, (int)((nref - 1) & 1), b->dslots + (size_t)e * n);
+        if (hipGetLastError() != hipSuccess) {
+            b->err = "k_check_mp_batch launch failed";
+            return IBM_ERR_HIP;
+        }
+        BATCH_TRY(hipEventRecord(b->ev[e], b->stream));
+        pending.emplace_back(e, nref);
+        return IBM_OK;
+    };
+    rc = refine(1);
+    if (rc) return rc;
+    rc = check(0, 0);
+    if (rc) return rc;
+    std::vector<char> finished(n, 0);
+    std::vector<long> done_refs(n, 0);
+    int nfin = 0, it = 0;
+    bool first = true;
+    const int max_e = b->max_iter;
+    for (;;) {
+        if (it < max_e) {
+            const int next = std::min(it + b->K, max_e);
+            int e_zero = 1;
+            while (it < next) {
+                const int ns = std::min(b->S, next - it);
+                hipLaunchKernelGGL(k_sor_mp_batch, dim3(8 * b->per), dim3(kTbThreads), 0, b->stream,
+                                   (const MpCase*)b->dmp, n, b->ntotal, b->per, (int)(nsw & 1), (int)(nref & 1), ns,
+                                   e_zero);
+                ++nsw;
+                e_zero = 0;
+                it += ns;
+            }
+            if (hipGetLastError() != hipSuccess) {
+                b->err = "k_sor_mp_batch launch failed";
+                return IBM_ERR_HIP;
+            }
+            rc = refine(0);
+            if (rc) return rc;
+            rc = check(1, it);
+            if (rc) return rc;
+            if ((int)pending.size() < kAheadSor && it < max_e) continue;
+        }
+        if (pending.empty()) {
+            b->err = "batched mixed-precision loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        const int e = pending.front().first;
+        const long nr = pending.front().second;
+        pending.pop_front();
+        BATCH_TRY(hipEventSynchronize(b->ev[e]));
+        for (int k = 0; k < n; ++k) {
+            if (finished[k]) continue;
+            volatile Slot* hs = b->hslots + (size_t)e * n + k;
+            if (first) {
+                outs[k].bn = hs->bn;
+                outs[k].r0 = hs->r0;
+                outs[k].zero_rhs = hs->zero_rhs;
+            }
+            if (hs->done) {
+                finished[k] = 1;
+                ++nfin;
+                done_refs[k] = nr;
+                outs[k].status = hs->status;
+                outs[k].iters = hs->iters;
+                outs[k].rn = hs->rn;
+            }
+        }
+        first = false;
+        if (nfin == n) break;
+        if (it >= max_e && pending.empty()) {
+            b->err = "batched mixed-precision loop: a case neither finished nor reached its iteration limit";
+            return IBM_ERR_STATE;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        if (done_refs[k] & 1) {
+            ibm_ctx* c = b->cs[k];
+            std::swap(c->phr, c->phr2);
+            std::swap(c->phb, c->phb2);
+        }
+    }
+    return IBM_OK;
+}
+
 // The pressure solves of all contexts of the batch (phi and V b natural on
 // entry; on return the solution is in each context's (phr, phb) pair).
 int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
+    if (b->mp) return batch_sor_mp(b, outs);
     const int n = (int)b->cs.size();
     for (ibm_ctx* c : b->cs) {
         const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
@@ -1537,7 +1707,10 @@ int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out) {
         if (!c) return IBM_ERR_INVALID;
         for (int q = 0; q < k; ++q)
             if (ctxs[q] == c) return IBM_ERR_INVALID;  // a context appears once
-        if (c->stream != ctxs[0]->stream || c->P.p_method != IBM_SOLVER_RBSOR || c->sor_kernel != IBM_SOR_TEMPORAL ||
+        const bool method_ok = c->P.p_method == ctxs[0]->P.p_method &&
+                               ((c->P.p_method == IBM_SOLVER_RBSOR && c->sor_kernel == IBM_SOR_TEMPORAL) ||
+                                c->P.p_method == IBM_SOLVER_RBSOR_MP);
+        if (c->stream != ctxs[0]->stream || !method_ok ||
             c->tb_sweeps != ctxs[0]->tb_sweeps || c->P.p_check_every != ctxs[0]->P.p_check_every ||
             (c->net && c->net_every > 0) || c->snap_feat)
             return IBM_ERR_INVALID;
@@ -1554,9 +1727,16 @@ int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out) {
         ibm_batch_destroy(b);
         return rc;
     };
-    if (hipMalloc((void**)&b->dcases, n * sizeof(TbCase)) != hipSuccess) return fail(IBM_ERR_HIP);
-    if (hipHostMalloc((void**)&b->hcases, n * sizeof(TbCase), hipHostMallocDefault) != hipSuccess)
-        return fail(IBM_ERR_HIP);
+    b->mp = ctxs[0]->P.p_method == IBM_SOLVER_RBSOR_MP;
+    if (b->mp) {
+        if (hipMalloc((void**)&b->dmp, n * sizeof(MpCase)) != hipSuccess) return fail(IBM_ERR_HIP);
+        if (hipHostMalloc((void**)&b->hmp, n * sizeof(MpCase), hipHostMallocDefault) != hipSuccess)
+            return fail(IBM_ERR_HIP);
+    } else {
+        if (hipMalloc((void**)&b->dcases, n * sizeof(TbCase)) != hipSuccess) return fail(IBM_ERR_HIP);
+        if (hipHostMalloc((void**)&b->hcases, n * sizeof(TbCase), hipHostMallocDefault) != hipSuccess)
+            return fail(IBM_ERR_HIP);
+    }
     if (hipHostMalloc((void**)&b->hslots, sizeof(Slot) * kBatchRing * n,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(IBM_ERR_HIP);
@@ -1634,6 +1814,8 @@ void ibm_batch_destroy(ibm_batch* b) {
         if (b->ev[e]) (void)hipEventDestroy(b->ev[e]);
     if (b->dcases) (void)hipFree(b->dcases);
     if (b->hcases) (void)hipHostFree(b->hcases);
+    if (b->dmp) (void)hipFree(b->dmp);
+    if (b->hmp) (void)hipHostFree(b->hmp);
     if (b->hslots) (void)hipHostFree(b->hslots);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -1644,6 +1826,10 @@ void ibm_batch_destroy(ibm_batch* b) {
 int32_t ibm_batch_set_graph(ibm_batch* b, int32_t intervals) {
     if (!b) return IBM_ERR_INVALID;
     if (intervals != 0 && (intervals < 2 || intervals > kMaxGraphIntervals || (intervals & 1))) return IBM_ERR_INVALID;
+    if (intervals != 0 && b->mp) {
+        b->err = "graph replay is for double-precision batches";
+        return IBM_ERR_INVALID;
+    }
     b->err.clear();
     if (intervals > 0) {
         if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {

@@ -54,6 +54,31 @@ def test_batched_steps_equal_solo_steps_bitwise():
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("check", [10, 100])
+def test_mixed_precision_batch_equals_solo_steps_bitwise(check):
+    """FP32 sweeps with FP64 refinement: the batched refinements, sweeps and
+    stop tests give every case the steps of its context stepped alone."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    over = dict(p_method=ibm.RBSOR_MP, p_check=check)
+    solo = [_solver(w, t, **over) for w, t in zip(wls, TILES)]
+    batch = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
+    with pytest.raises(ibm.IbmError):
+        batch.set_graph(2)  # no graph form of the mixed-precision batch
+    for step in range(3):
+        st_b = batch.step(1)
+        for k, s in enumerate(solo):
+            st = s.step(1)
+            assert st["rc"] == ibm.OK and st_b[k]["status"] == ibm.OK
+            for key in ("p_iters", "p_rel", "p_r0", "cd", "cl"):
+                assert st[key] == st_b[k][key], (step, k, key, st[key], st_b[k][key])
+    assert len(set(st["p_iters"] for st in st_b)) > 1
+    for a, b in zip(solo, batch.solvers):
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("intervals,cap", [(4, None), (6, 1234)])
 def test_graph_replayed_batch_equals_launched_batch_bitwise(intervals, cap):
     """Stretches of `intervals` check intervals replayed from one HIP graph,
@@ -96,6 +121,10 @@ def test_batch_validation():
     p = ibm.Solver(wls[1]["nx"], wls[1]["ny"], wls[1]["xf"], wls[1]["yf"], **dict(wls[1]["params"], p_method=ibm.PCG))
     with pytest.raises(ibm.IbmError):
         ibm.Batch([a, p])           # PCG cannot join
+    m = ibm.Solver(wls[1]["nx"], wls[1]["ny"], wls[1]["xf"], wls[1]["yf"],
+                   **dict(wls[1]["params"], p_method=ibm.RBSOR_MP))
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([a, m])           # one method for all
     with pytest.raises(ibm.IbmError):
         ibm.Batch([a, a])           # a context appears once
     other = torch.cuda.Stream()
