@@ -171,3 +171,31 @@ def test_many_tiles_test_the_residual_outside_the_sweep(torch):
     print(f"many tiles: iters {a[3]['iters']} {c[3]['iters']}", flush=True)
     assert np.array_equal(a[0], c[0])
     assert a[3]["iters"] == c[3]["iters"] and np.array_equal(a[2], c[2])
+
+
+@pytest.mark.parametrize("which", ["plunging_1024x768", "plunging_2048x1536"])
+def test_full_size_grids_in_the_benchmark_configuration(torch, which):
+    """The stretched grids of the 1024x768 and 2048x1536 workloads with the
+    benchmark's refinement interval (100 iterations): one full interval and a
+    partial one (130 iterations) from the same start against the oracle's
+    mixed and double-precision solves, to the one-interval bar."""
+    from paper_2402_17337_amd import workloads as W
+    c = getattr(W, which)()
+    nx, ny = c["nx"], c["ny"]
+    o, g = _pair(torch, nx, ny, faces=(c["xf"], c["yf"]))
+    rng = np.random.default_rng(nx + 17)
+    b = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    check, fixed = 100, 130
+    xo, so, rco = o.poisson_solve(b, x0=x0, method=O.SOR_MP, omega=1.8, fixed=fixed, check=check)
+    x64, _, _ = o.poisson_solve(b, x0=x0, method=O.SOR, omega=1.8, fixed=fixed, check=check)
+    xd = _dev(torch, x0)
+    st = g.poisson_solve(_dev(torch, b), xd, method=ibm.RBSOR_MP, omega=1.8, fixed_iters=fixed, check_every=check)
+    xg = xd.cpu().numpy()
+    corr = np.linalg.norm(xo - x0)
+    d_or, d_64 = np.linalg.norm(xg - xo) / corr, np.linalg.norm(xg - x64) / corr
+    print(f"{which}: |gpu-oracle_mp|/|corr| {d_or:.3e} |gpu-oracle_f64|/|corr| {d_64:.3e}", flush=True)
+    bar = 10 * check * 2.0 ** -24
+    assert rco == O.OK and st["rc"] == ibm.OK and st["iters"] == fixed
+    assert d_or <= bar and d_64 <= bar
+    assert abs(st["rel"] - so["rel"]) <= 1e-4 * so["rel"]
