@@ -155,3 +155,35 @@ def test_autotune_picks_a_candidate_and_keeps_the_iterates():
         assert sa["p_iters"] == sb["p_iters"]
     for x, y in zip(a.fields()[:3], b.fields()[:3]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_full_batched_workload_equals_case_by_case_bitwise(mixed):
+    """The 64-case workload (grids 256x192 to 1024x768, 21.1 M cells) in the
+    benchmark's launch configuration (104x32 tiles, solves capped; FP32 sweeps
+    refined every 100 iterations for the mixed form): one batched step equals
+    the same contexts stepped one by one, bit for bit, for every case."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import workloads as W
+    cases = W.batched_plunging(64, 0)
+    over = dict(p_max_iter=300)
+    if mixed:
+        over.update(p_method=ibm.RBSOR_MP, p_check=100)
+
+    def make():
+        return [ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"],
+                           **dict(c["params"], **over)) for c in cases]
+    solo = make()
+    batch = ibm.Batch(make())
+    st_b = batch.step(1)
+    for k, s in enumerate(solo):
+        st = s.step(1)
+        for key in ("status", "p_iters", "p_rel", "cd", "cl"):
+            assert st[key] == st_b[k][key], (k, key, st[key], st_b[k][key])
+        if k % 16 == 0:  # fields of a sample of the cases
+            for x, y in zip(s.fields(), batch.solvers[k].fields()):
+                assert np.array_equal(x, y)
+    batch.close()  # the batch borrows its contexts: release it first
+    for s in solo + batch.solvers:
+        s.close()
