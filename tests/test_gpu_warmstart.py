@@ -302,3 +302,35 @@ def test_map_selection_zeroes_the_dropped_maps():
     f = f.cpu().numpy()
     assert np.all(f[1] == 0.0) and np.any(f[0] != 0.0) and np.any(f[2] > 0.0)
     assert abs(np.sqrt(np.mean(f[0].astype(np.float64) ** 2)) - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_zero_network_corrections_at_full_size(mixed):
+    """The benchmark's configuration of the learned correction on the
+    1024x768 workload (factor-8 maps with the recipe's options, a correction
+    every 4000 iterations; FP64 sweeps, or FP32 sweeps refined every 100
+    iterations), with a zero network and the solve capped at 12000
+    iterations: the segmented solve with its (zero) corrections reproduces
+    the plain solve bit for bit."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    from paper_2402_17337_amd import warmstart as WS
+    from paper_2402_17337_amd import workloads as W
+    wl = W.plunging_1024x768()
+    over = dict(p_init_prev=ibm.INIT_PREVIOUS, p_max_iter=12000)
+    if mixed:
+        over.update(p_method=ibm.RBSOR_MP, p_check=100)
+    a, b = _solver(wl, **over), _solver(wl, **over)
+    opts = {ibm.OPT_NET_FACTOR: 8, ibm.OPT_NET_EVERY: 4000, **WS.RECIPE_OPTIONS}
+    for opt, val in opts.items():
+        assert b.set_option(opt, val) == ibm.OK
+    net = U.UNet(1, wl["ny"] // 8, wl["nx"] // 8, stream=b.stream)
+    net.set_params(np.zeros(U.param_count(), np.float32))
+    b.set_warm_start(net, 1.0)
+    sa, sb = a.step(1), b.step(1)
+    assert sa["p_iters"] == sb["p_iters"] == 12000 and sb["n_net"] >= 2
+    for key in ("status", "p_r0", "p_rel", "cd", "cl"):
+        assert sa[key] == sb[key], (key, sa[key], sb[key])
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
