@@ -44,8 +44,10 @@
  *             f = (V - u~)/dt.  Cells with a forced face carry the mass
  *             source q = divergence of (u^ - body velocity) over their forced
  *             faces, so D(u^) - q is the divergence with forced faces moving
- *             with the body (leaving the whole cut-cell divergence
- *             uncorrected instead lets mass appear there and is unstable).
+ *             with the body (q_mode 1).  q_mode 2 keeps the other reading for
+ *             comparison: q = D(u^) in cells with at least one forced and one
+ *             free face, so their Poisson source vanishes (it lets mass
+ *             appear in the cut cells and is unstable); q_mode 0: q = 0.
  *   pressure  incremental: A phi = V (D(u^) - q)/dt, A = V D G (5-point FV),
  *             u^{n+1} = u^ - dt G phi, p^{n+1} = p^n + phi - dt/(2Re) L phi.
  *   Poisson   red-black SOR, red = (i+j) even first, stop when
@@ -706,6 +708,12 @@ static int in_v(const orc_ctx *c, const body_pos *bp, int i, int j) {
     return inside(c->xc[i], c->yf[j], bp->xb, bp->yb, bp->a, bp->b);
 }
 
+/* Number of forced faces of cell (i, j) under the current flags. */
+static int forced_faces(const orc_ctx *c, int i, int j) {
+    return (c->flu[iu(c, i, j)] != 0) + (c->flu[iu(c, i + 1, j)] != 0) + (c->flv[iv(c, i, j)] != 0) +
+           (c->flv[iv(c, i, j + 1)] != 0);
+}
+
 /* Flag every u and v unknown (fluid / forcing / deep) and every cell (mass
  * source or not) for the body at bp.  Forcing = inside with at least one of
  * its four same-component neighbours outside; deep = all four inside; a
@@ -732,12 +740,8 @@ static void classify(orc_ctx *c, const body_pos *bp, int *nfu, int *nfv, int *nm
             ++*nfv;
         }
     for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            int f[4] = {c->flu[iu(c, i, j)] != 0, c->flu[iu(c, i + 1, j)] != 0, c->flv[iv(c, i, j)] != 0,
-                        c->flv[iv(c, i, j + 1)] != 0};
-            int nf = f[0] + f[1] + f[2] + f[3];
-            if (nf > 0) { c->msrc[ic(c, i, j)] = 1; ++*nms; }
-        }
+        for (int i = 0; i < nx; ++i)
+            if (forced_faces(c, i, j) > 0) { c->msrc[ic(c, i, j)] = 1; ++*nms; }
 }
 
 /* Interpolation weight along one grid line: the forced node sits d_f inside
@@ -831,6 +835,15 @@ static int worst(int a, int b) {
     return a > b ? a : b;
 }
 
+/* Convective outflow (channel mode): the outlet velocity of row j advected
+ * with the free-stream speed, u* = u^n - dt U (u^n_nx - u^n_{nx-1}) / dx_{nx-1}
+ * (a first-order upwind step of du/dt + U du/dx = 0 at the outlet face). */
+static double outlet_predictor(const orc_ctx *c, int j) {
+    const int nx = c->nx;
+    double uo = U(c, nx, j), ui = U(c, nx - 1, j);
+    return uo - c->P.dt * c->P.uinf * (uo - ui) / c->dx[nx - 1];
+}
+
 static int step_once(orc_ctx *c, orc_step_stats *st) {
     const int nx = c->nx, ny = c->ny, per = c->per;
     const double dt = c->P.dt, re = c->P.re, beta = dt / (2.0 * re);
@@ -881,10 +894,7 @@ static int step_once(orc_ctx *c, orc_step_stats *st) {
 
     /* convective outlet: u* = u^n - dt U (u^n_nx - u^n_{nx-1}) / dx_{nx-1} */
     if (!per) {
-        for (int j = 0; j < ny; ++j) {
-            double uo = U(c, nx, j), ui = U(c, nx - 1, j);
-            c->ut[iu(c, nx, j)] = uo - dt * c->P.uinf * (uo - ui) / c->dx[nx - 1];
-        }
+        for (int j = 0; j < ny; ++j) c->ut[iu(c, nx, j)] = outlet_predictor(c, j);
         for (int j = 0; j < ny; ++j) c->u[iu(c, nx, j)] = c->ut[iu(c, nx, j)];
     }
 
@@ -924,12 +934,17 @@ static int step_once(orc_ctx *c, orc_step_stats *st) {
         for (int i = 0; i < nx; ++i) {
             double d = div_at(c, i, j);
             double q = 0.0;
-            if (c->P.q_mode && c->msrc[ic(c, i, j)]) {
+            if (c->P.q_mode == 1 && c->msrc[ic(c, i, j)]) {
                 double fe = c->flu[iu(c, i + 1, j)] ? U(c, i + 1, j) - 0.0 : 0.0;
                 double fw = c->flu[iu(c, i, j)] ? U(c, i, j) - 0.0 : 0.0;
                 double fn = c->flv[iv(c, i, j + 1)] ? V(c, i, j + 1) - vbody : 0.0;
                 double fs = c->flv[iv(c, i, j)] ? V(c, i, j) - vbody : 0.0;
                 q = (fe - fw) / c->dx[i] + (fn - fs) / c->dy[j];
+            } else if (c->P.q_mode == 2 && c->msrc[ic(c, i, j)] && forced_faces(c, i, j) < 4) {
+                /* the alternative reading kept for comparison: q is the whole
+                 * divergence of a cut cell (at least one forced and one free
+                 * face), so the Poisson source vanishes there */
+                q = d;
             }
             c->vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * ((d - q) / dt);
         }
@@ -1013,6 +1028,7 @@ int orc_create(const orc_params *P, const double *xf, const double *yf, const do
     if (!P || P->nx < 4 || P->ny < 4 || (P->nx & 1) || (P->ny & 1) || !(P->dt > 0.0) || !(P->re > 0.0))
         return ORC_ERR_INVALID;
     if (P->bc != ORC_CHANNEL && P->bc != ORC_PERIODIC) return ORC_ERR_INVALID;
+    if (P->q_mode < 0 || P->q_mode > 2) return ORC_ERR_INVALID;
     const int nx = P->nx, ny = P->ny;
     for (int i = 0; i < nx; ++i) if (!(xf[i + 1] > xf[i])) return ORC_ERR_INVALID;
     for (int j = 0; j < ny; ++j) if (!(yf[j + 1] > yf[j])) return ORC_ERR_INVALID;
@@ -1150,6 +1166,24 @@ void orc_targets_at(orc_ctx *c, double t, const double *ut, const double *vt, do
             if (c->flv[k] == FL_FLUID) continue;
             Vv[k] = c->flv[k] == FL_DEEP ? vbody : target_v(c, &bp, vt, i, j, vbody);
         }
+}
+
+/* Implicit viscous solve of one component (0: u, 1: v) on the current
+ * fields: (I - beta L) x = rhs by the step's red-black SOR, in place from the
+ * current u or v, boundary values held fixed.  rhs has the shape of u or v
+ * (entries off the unknowns are ignored).  Returns the status; *iters the
+ * iterations taken. */
+int orc_helm_solve(orc_ctx *c, int comp, const double *rhs, double beta, int *iters) {
+    if (comp != 0 && comp != 1) return ORC_ERR_INVALID;
+    return helm_solve(c, comp, rhs, beta, iters);
+}
+
+/* Convective-outlet predictor u* of every row for the current fields
+ * (channel mode; out[ny]). */
+int orc_outlet_predictor(const orc_ctx *c, double *out) {
+    if (c->per) return ORC_ERR_INVALID;
+    for (int j = 0; j < c->ny; ++j) out[j] = outlet_predictor(c, j);
+    return ORC_OK;
 }
 
 /* Body centre height, velocity and acceleration at time t (Eqs. 1-2). */

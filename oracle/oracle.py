@@ -99,6 +99,10 @@ def lib():
         L.orc_classify_at.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_int32)]
         L.orc_targets_at.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp]
         L.orc_forces.argtypes = [C.c_void_p, dp, dp]
+        L.orc_helm_solve.argtypes = [C.c_void_p, C.c_int, dp, C.c_double, C.POINTER(C.c_int)]
+        L.orc_helm_solve.restype = C.c_int
+        L.orc_outlet_predictor.argtypes = [C.c_void_p, dp]
+        L.orc_outlet_predictor.restype = C.c_int
         L.orc_kinematics.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
         L.orc_time.argtypes = [C.c_void_p]
         L.orc_time.restype = C.c_double
@@ -244,6 +248,24 @@ class Oracle:
         a = [np.zeros((ny, nx + 1)) for _ in range(3)] + [np.zeros((ny + 1, nx)) for _ in range(3)]
         lib().orc_momentum_terms(self._h, *[_dp(x) for x in a])
         return dict(Nu=a[0], Gu=a[1], Lu=a[2], Nv=a[3], Gv=a[4], Lv=a[5])
+
+    def helm_solve(self, comp, rhs, beta):
+        """(I - beta L) x = rhs for component comp (0: u, 1: v) by the step's
+        red-black SOR, from the current field; returns (x, iters, status)."""
+        shp = (self.ny, self.nx + 1) if comp == 0 else (self.ny + 1, self.nx)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        assert rhs.shape == shp
+        it = C.c_int()
+        rc = lib().orc_helm_solve(self._h, comp, _dp(rhs), beta, C.byref(it))
+        u, v, _, _ = self.fields()
+        return (u if comp == 0 else v), it.value, rc
+
+    def outlet_predictor(self):
+        """Convective-outlet predictor u* of every row for the current fields."""
+        out = np.empty(self.ny)
+        rc = lib().orc_outlet_predictor(self._h, _dp(out))
+        assert rc == OK
+        return out
 
     def divergence(self):
         d = np.empty((self.ny, self.nx))
