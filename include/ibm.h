@@ -149,10 +149,16 @@ typedef struct ibm_solve_stats {
 typedef struct ibm_ctx ibm_ctx;
 
 /* Device workspace a context needs for prm, in bytes (0 if prm is invalid).
- * Pure function; no GPU call. */
+ * Paper: the fields and solver arrays of the staggered-grid method of
+ * Sec. 2.2 on the grid of Sec. 2.3, held resident on the device (Sec. 3.4.4,
+ * data management).  Pure function; no GPU call. */
 size_t ibm_workspace_bytes(const ibm_params* prm);
 
 /* Create a context.
+ * Paper: the problem of Sec. 2.1 (rigid ellipse, thickness/chord 0.12,
+ * plunge y = h sin(k t), Eqs. 1-2) in the domain of Sec. 2.3 (Cartesian grid
+ * uniform around the body, stretched outward; channel boundary conditions),
+ * with the flow parameters of Sec. 4.1 (Re, plunge amplitude and frequency).
  *   xf[nx+1], yf[ny+1]     host; strictly increasing face coordinates;
  *   u0[(nx+1)*ny], v0[nx*(ny+1)], p0[nx*ny]
  *                          host initial fields, or NULL for u = u_inf, v = 0,
@@ -172,7 +178,12 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
                  const double* v0, const double* p0, void* workspace, size_t workspace_bytes,
                  void* hip_stream, ibm_ctx** out);
 
-/* Advance nsteps (>= 1) time steps.  Each step: classification at
+/* Advance nsteps (>= 1) time steps.
+ * Paper: one time-marching step of Sec. 2.2 (Eqs. 3-4: momentum forcing f and
+ * mass source q; semi-implicit fractional step with Adams-Bashforth and
+ * Crank-Nicolson terms; fluid/solid flagging at the start of every step;
+ * red-black SOR for the velocity and pressure equations), whose four hot
+ * spots are those of Table 1 (Sec. 3.4.1).  Each step: classification at
  * t^{n+1}, momentum predictor, forcing, implicit velocity solves, pressure
  * Poisson solve (p_method, from zero or the previous phi), projection,
  * pressure update, forces.  Returns the worst status; IBM_NOT_CONVERGED is
@@ -182,6 +193,9 @@ int32_t ibm_step(ibm_ctx* ctx, int32_t nsteps, ibm_step_stats* last);
 
 /* Solve the cell-centred Poisson problem (D G) x = rhs on the context's grid
  * and boundary conditions (the pressure-correction operator A / V).
+ * Paper: the pressure-correction equation of the fractional step (Sec. 2.2)
+ * and its red-black SOR solver (Sec. 2.2, Sec. 3.1), the "P iterative
+ * solver" of Table 1 (54.7 % of the serial step).
  *   rhs_dev[nx*ny]  device, per unit volume, natural layout; read only;
  *   x_dev[nx*ny]    device; initial guess on entry, solution on exit.
  * Stream-ordered; returns after the solve has finished.  rhs = 0 gives
@@ -190,20 +204,29 @@ int32_t ibm_poisson_solve(ibm_ctx* ctx, const double* rhs_dev, double* x_dev, co
                           ibm_solve_stats* stats);
 
 /* Drag and lift coefficients of the last completed step (0 before the
- * first).  Synchronizes the context stream. */
+ * first).  Paper: the aerodynamic force coefficients of Sec. 4.1 (Fig. 4);
+ * the force is the reaction of the forcing f of Eq. 3 plus the inertia of the
+ * fluid inside the rigid body.  Synchronizes the context stream. */
 int32_t ibm_forces(ibm_ctx* ctx, double* cd, double* cl);
 
 /* Host copies of the current fields; each pointer is nullable.
+ * Paper: the velocity and pressure of Eqs. 3-4 on the staggered grid of
+ * Sec. 2.2.
  * u[(nx+1)*ny], v[nx*(ny+1)], p[nx*ny], phi[nx*ny].  Synchronizes. */
 int32_t ibm_get_fields(ibm_ctx* ctx, double* u, double* v, double* p, double* phi);
 
-/* Immersed-boundary data of the last step (each pointer nullable):
+/* Immersed-boundary data of the last step (each pointer nullable).
+ * Paper: the solid/fluid flags of Sec. 2.2 (Table 1, "fluid/solid
+ * flagging"), the cells of the mass source q (Eq. 4) and the forcing f
+ * (Eq. 3; Table 1, "body force interpolation"):
  * flu[(nx+1)*ny], flv[nx*(ny+1)] (0 fluid, 1 forcing, 2 deep),
  * msrc[nx*ny] (1 = cell with a forced face), fu, fv (forcing f, full-size
  * arrays, zero away from forced nodes).  Synchronizes. */
 int32_t ibm_get_ibm(ibm_ctx* ctx, uint8_t* flu, uint8_t* flv, uint8_t* msrc, double* fu, double* fv);
 
 /* Checkpoint: bytes needed, then a host copy of the complete state (fields,
+ * the time-stepping state of Sec. 2.2; checkpointing itself is not in the
+ * paper),
  * phi, convection history, time, step count, forces) and its restore.  A run
  * restored from a checkpoint continues bit for bit as the uninterrupted run.
  * IBM_ERR_INVALID if bytes is too small or the blob does not match the grid. */
@@ -211,14 +234,18 @@ size_t ibm_state_bytes(const ibm_ctx* ctx);
 int32_t ibm_get_state(ibm_ctx* ctx, void* host, size_t bytes);
 int32_t ibm_set_state(ibm_ctx* ctx, const void* host, size_t bytes);
 
-/* Replay schedule of pressure iterations: the next n steps each run exactly
+/* Replay schedule of pressure iterations (a test aid, not in the paper:
+ * the stop test of Sec. 2.2's SOR is reproduced iteration for iteration):
+ * the next n steps each run exactly
  * iters[k] pressure iterations (tolerance ignored), e.g. to reproduce the
  * iteration sequence of a reference run.  n = 0 clears the schedule.  host
  * array, copied. */
 int32_t ibm_set_poisson_schedule(ibm_ctx* ctx, const int32_t* iters, int32_t n);
 
 /* Learned guess and correction of the pressure solve (an extension of the
- * method; the network is declared in ibm_unet.h).  The network works on the
+ * method, not in the paper; it changes only the initial guess and iterates
+ * of the Sec. 2.2 pressure solve, whose stop test still decides; the network
+ * is declared in ibm_unet.h).  The network works on the
  * grid coarsened by F = IBM_OPT_NET_FACTOR in both directions: coarse cell
  * (I, J) averages the fine cells [F I, F I + F) x [F J, F J + F).  For the
  * current phi it sees three coarse maps, each divided by its RMS over the
@@ -254,7 +281,9 @@ int32_t ibm_set_warm_start(ibm_ctx* ctx, ibm_unet* net, double out_scale);
  * (both NULL). */
 int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, double out_scale);
 
-/* Batches: the pressure solves of many independent contexts (cases of
+/* Batches (an extension, not in the paper: many plunging-foil problems of
+ * Sec. 2.1 on their own grids of Sec. 2.3 at once): the pressure solves of
+ * many independent contexts (cases of
  * different grids) advanced together, one blocked red-black SOR launch per
  * IBM_OPT_TB_SWEEPS iterations sweeping the tiles of every case through one
  * work list, with the stop test of every case taken in one check launch; a
@@ -267,7 +296,10 @@ int32_t ibm_set_snapshot(ibm_ctx* ctx, float* feat_dev, float* target_dev, doubl
  * IBM_SOLVER_RBSOR_MP (then each refinement runs as one launch over the row
  * blocks of every case, and the float sweeps as one launch over all their
  * tiles), the same IBM_OPT_TB_SWEEPS and p_check_every, at most 512 tiles
- * each, no network correction or snapshot; IBM_ERR_INVALID otherwise.  It
+ * each, no network correction or snapshot, and either one p_max_iter shared
+ * by all contexts or limits that are all multiples of p_check_every (the
+ * batch advances in whole check intervals, so only then does every case stop
+ * at its own limit); IBM_ERR_INVALID otherwise.  It
  * allocates a small descriptor array on the device and pinned host memory for
  * the check snapshots.
  * ibm_batch_step: nsteps time steps of every case; each step runs every
@@ -298,7 +330,8 @@ int32_t ibm_batch_set_graph(ibm_batch* batch, int32_t intervals);
 void ibm_batch_destroy(ibm_batch* batch);
 const char* ibm_batch_last_error(const ibm_batch* batch);
 
-/* Kernel timing with HIP events on the context stream.  sample_every > 0
+/* Kernel timing with HIP events on the context stream (the per-kernel view
+ * of the profiling of Sec. 3.4.1).  sample_every > 0
  * brackets every sample_every-th launch of each timed kernel with a pair of
  * events; 0 switches it off and clears the samples.
  * ibm_profile_query: kernel id (IBM_KERNEL_*), average duration of the
@@ -318,7 +351,8 @@ int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
 int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
                           double* bytes_per_launch);
 
-/* Tuning options of the red-black SOR sweeps (they change the launch shape,
+/* Tuning options (not in the paper) of the red-black SOR sweeps of
+ * Sec. 2.2 (they change the launch shape,
  * never the arithmetic: every choice gives bit-identical iterates).
  *   IBM_OPT_SOR_KERNEL  IBM_SOR_TEMPORAL (default): one launch performs
  *                       IBM_OPT_TB_SWEEPS iterations on a tile with halos

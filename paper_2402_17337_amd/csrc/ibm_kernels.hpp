@@ -775,6 +775,7 @@ struct TbCase {
     TbShape ts;
     double omega, tol;
     int tile0, ntiles, nb0, max_iter;
+    int fixed;  // 1: max_iter is a replayed iteration count (tolerance ignored)
 };
 
 __global__ __launch_bounds__(kTbThreads) void k_sor_tbr_batch(const TbCase* __restrict__ cases, int ncase,
@@ -820,7 +821,7 @@ __global__ __launch_bounds__(kTbThreads) void k_check_batch(const TbCase* __rest
     double acc[2];
     sum_partials(acc, phase == 0 ? C.partials[0] : C.partials[pbuf], phase == 0 ? C.nb0 : C.ntiles, lds);
     if (threadIdx.x == 0) {
-        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, 0, 0);
+        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, C.fixed, 0);
         publish(C.ctl, slots + blockIdx.x);
     }
 }
@@ -1009,6 +1010,7 @@ struct MpCase {
     TbShape ts;
     double omega, tol;
     int tile0, ntiles, rblk0, nbr, max_iter;
+    int fixed;  // 1: max_iter is a replayed iteration count (tolerance ignored)
 };
 
 template <class CaseT>
@@ -1070,7 +1072,7 @@ __global__ __launch_bounds__(kTbThreads) void k_check_mp_batch(const MpCase* __r
     double acc[2];
     sum_partials(acc, C.partials[pbuf], C.nbr, lds);
     if (threadIdx.x == 0) {
-        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, 0, 0);
+        check_finish(C.ctl, acc[0], acc[1], phase, it, C.max_iter, C.tol, C.fixed, 0);
         publish(C.ctl, slots + blockIdx.x);
     }
 }

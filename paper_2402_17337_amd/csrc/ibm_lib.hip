@@ -199,6 +199,7 @@ struct ibm_ctx {
     double t = 0.0, cd = 0.0, cl = 0.0;
     std::vector<int> schedule;
     size_t sched_pos = 0;
+    int batch_fixed = -1;  // replayed iteration count of this step's batched solve (-1: none)
     // profiling
     int prof_every = 0;
     long launches[IBM_KERNEL_COUNT] = {};
@@ -1302,6 +1303,7 @@ namespace {
 int32_t batch_upload(ibm_batch* b) {
     const int n = (int)b->cs.size();
     int tile0 = 0;
+    b->max_iter = 0;
     for (int k = 0; k < n; ++k) {
         ibm_ctx* c = b->cs[k];
         TbCase& d = b->hcases[k];
@@ -1321,8 +1323,10 @@ int32_t batch_upload(ibm_batch* b) {
         d.partials[1] = c->partials + 2 * (size_t)d.ntiles;
         d.ctl = c->ctl + CTL_P;
         d.omega = c->P.p_omega;
-        d.tol = c->P.p_tol;
-        d.max_iter = c->P.p_max_iter;
+        d.tol = c->batch_fixed >= 0 ? -1.0 : c->P.p_tol;
+        d.max_iter = c->batch_fixed >= 0 ? c->batch_fixed : c->P.p_max_iter;
+        d.fixed = c->batch_fixed >= 0 ? 1 : 0;
+        b->max_iter = std::max(b->max_iter, d.max_iter);
         d.tile0 = tile0;
         d.nb0 = red_blocks((size_t)c->nh * c->ny);
         tile0 += d.ntiles;
@@ -1392,6 +1396,7 @@ int32_t batch_capture(ibm_batch* b) {
 // The descriptors of the mixed-precision cases (current phi pairs).
 int32_t batch_upload_mp(ibm_batch* b) {
     const int n = (int)b->cs.size();
+    b->max_iter = 0;
     int tile0 = 0, rblk0 = 0;
     for (int k = 0; k < n; ++k) {
         ibm_ctx* c = b->cs[k];
@@ -1417,8 +1422,10 @@ int32_t batch_upload_mp(ibm_batch* b) {
         d.partials[1] = c->partials + 2 * (size_t)kRedMax;
         d.ctl = c->ctl + CTL_P;
         d.omega = c->P.p_omega;
-        d.tol = c->P.p_tol;
-        d.max_iter = c->P.p_max_iter;
+        d.tol = c->batch_fixed >= 0 ? -1.0 : c->P.p_tol;
+        d.max_iter = c->batch_fixed >= 0 ? c->batch_fixed : c->P.p_max_iter;
+        d.fixed = c->batch_fixed >= 0 ? 1 : 0;
+        b->max_iter = std::max(b->max_iter, d.max_iter);
         d.tile0 = tile0;
         d.ntiles = d.ts.ntx * d.ts.nty;
         d.rblk0 = rblk0;
@@ -1717,6 +1724,15 @@ int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out) {
         TbShape ts;
         if (!tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts) || ts.ntx * ts.nty > kFoldMax) return IBM_ERR_INVALID;
     }
+    // The batched loop advances every case in whole check intervals; a case
+    // stops at its own limit only when that limit falls on an interval's end
+    // (or when all cases share it, so the last interval is shortened for all).
+    bool same_limit = true, limits_on_checks = true;
+    for (int k = 0; k < n; ++k) {
+        same_limit = same_limit && ctxs[k]->P.p_max_iter == ctxs[0]->P.p_max_iter;
+        limits_on_checks = limits_on_checks && ctxs[k]->P.p_max_iter % ctxs[0]->P.p_check_every == 0;
+    }
+    if (!same_limit && !limits_on_checks) return IBM_ERR_INVALID;
     ibm_batch* b = new ibm_batch();
     b->cs.assign(ctxs, ctxs + n);
     b->stream = ctxs[0]->stream;
@@ -1752,10 +1768,6 @@ int32_t ibm_batch_step(ibm_batch* b, int32_t nsteps, ibm_step_stats* last) {
     b->err.clear();
     const int n = (int)b->cs.size();
     for (ibm_ctx* c : b->cs) {
-        if (c->sched_pos < c->schedule.size()) {
-            b->err = "a context of the batch has a pending Poisson schedule";
-            return IBM_ERR_STATE;
-        }
         if (c->P.p_init == IBM_INIT_LEARNED && !c->net) {
             b->err = "p_init is IBM_INIT_LEARNED but no network is attached";
             return IBM_ERR_STATE;
@@ -1767,6 +1779,27 @@ int32_t ibm_batch_step(ibm_batch* b, int32_t nsteps, ibm_step_stats* last) {
     int32_t worst_rc = IBM_OK;
     for (int s = 0; s < nsteps; ++s) {
         const auto w0 = std::chrono::steady_clock::now();
+        // replayed iteration counts (ibm_set_poisson_schedule) of this step:
+        // every case stops at its own count only if the counts fall on check
+        // intervals or are all the same (as for the contexts' limits)
+        {
+            bool any = false, same = true, on_checks = true;
+            int first = -1;
+            for (int k = 0; k < n; ++k) {
+                const ibm_ctx* c = b->cs[k];
+                const int lim = c->sched_pos < c->schedule.size() ? c->schedule[c->sched_pos] : c->P.p_max_iter;
+                any = any || c->sched_pos < c->schedule.size();
+                if (first < 0) first = lim;
+                same = same && lim == first;
+                on_checks = on_checks && lim % b->K == 0;
+            }
+            if (any && !same && !on_checks) {
+                b->err = "replayed iteration counts of a batch must be multiples of p_check_every or all equal";
+                return IBM_ERR_STATE;
+            }
+            for (ibm_ctx* c : b->cs)
+                c->batch_fixed = c->sched_pos < c->schedule.size() ? c->schedule[c->sched_pos++] : -1;
+        }
         for (int k = 0; k < n; ++k) {
             Body B;
             int32_t rc = step_pre(b->cs[k], &st[k], &B, &status[k]);

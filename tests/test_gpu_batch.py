@@ -187,3 +187,82 @@ def test_full_batched_workload_equals_case_by_case_bitwise(mixed):
     batch.close()  # the batch borrows its contexts: release it first
     for s in solo + batch.solvers:
         s.close()
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_steps_match_the_oracle(mixed):
+    """Four cases of different grids stepped as one batch against the FP64
+    oracle stepping each case alone (Sec. 2.2 time steps, Eqs. 1-4): each case
+    replays its oracle iteration counts (the stop test compares a residual
+    whose last digits depend on rounding order), and u, v, p agree to the
+    FP64 bar of 1e-10 (relative L2).  Mixed form: FP32 sweeps refined every
+    100 iterations against the oracle's mixed-precision solve, to the bar of
+    the single-grid mixed test (the two sides round the float sweeps
+    differently): u, v within 1e-8, p within 1e-6; the distance to the FP64
+    oracle is printed."""
+    _need_gpu()
+    from oracle import oracle as O
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    nsteps = 3
+    over_o = dict(p_method=O.SOR_MP, p_check=100) if mixed else {}
+    over_g = dict(p_method=ibm.RBSOR_MP, p_check=100) if mixed else {}
+    orcs, iters = [], []
+    for w in wls:
+        o = O.Oracle(w["nx"], w["ny"], w["xf"], w["yf"], w["u0"], w["v0"], w["p0"], **dict(w["params"], **over_o))
+        rc, so = o.step(nsteps)
+        assert rc == O.OK, so
+        orcs.append(o)
+        iters.append([s["p_iters"] for s in so])
+    solvers = [_solver(w, t, **over_g) for w, t in zip(wls, TILES)]
+    for s, it in zip(solvers, iters):
+        s.set_poisson_schedule(it)
+    batch = ibm.Batch(solvers)
+    for step in range(nsteps):
+        st_b = batch.step(1)
+        for k in range(len(wls)):
+            assert st_b[k]["status"] == ibm.OK and st_b[k]["p_iters"] == iters[k][step], (step, k, st_b[k])
+    for k, (s, o) in enumerate(zip(solvers, orcs)):
+        ug, vg, pg, _ = s.fields()
+        uo, vo, po, _ = o.fields()
+        e = (_rel_l2(ug, uo), _rel_l2(vg, vo), _rel_l2(pg, po))
+        print(f"case {k} ({wls[k]['nx']}x{wls[k]['ny']}) iters {iters[k]}: u {e[0]:.2e} v {e[1]:.2e} p {e[2]:.2e}",
+              flush=True)
+        if mixed:
+            assert e[0] <= 1e-8 and e[1] <= 1e-8 and e[2] <= 1e-6, (k, e)
+        else:
+            assert max(e) <= 1e-10, (k, e)
+    assert len({tuple(i) for i in iters}) > 1
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_per_case_limits_must_fall_on_check_intervals():
+    """A batch advances in whole check intervals: contexts with different
+    iteration limits are accepted when every limit is a multiple of the check
+    interval (each case then stops at its own limit, bit for bit as when
+    stepped alone), and rejected otherwise."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    wls = _cases()
+    with pytest.raises(ibm.IbmError):
+        ibm.Batch([_solver(wls[0], p_max_iter=35), _solver(wls[1], p_max_iter=50)])
+    limits = [30, 50, 70, 40]
+    solo = [_solver(w, t, p_max_iter=m) for w, t, m in zip(wls, TILES, limits)]
+    batch = ibm.Batch([_solver(w, t, p_max_iter=m) for w, t, m in zip(wls, TILES, limits)])
+    for step in range(2):
+        st_b = batch.step(1)
+        for k, s in enumerate(solo):
+            st = s.step(1)
+            assert st["p_iters"] == limits[k] == st_b[k]["p_iters"]
+            assert st["rc"] == ibm.NOT_CONVERGED and st_b[k]["status"] == ibm.NOT_CONVERGED
+            assert st["p_rel"] == st_b[k]["p_rel"]
+    for a, b in zip(solo, batch.solvers):
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+    batch.close()
