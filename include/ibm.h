@@ -203,6 +203,28 @@ int32_t ibm_step(ibm_ctx* ctx, int32_t nsteps, ibm_step_stats* last);
 int32_t ibm_poisson_solve(ibm_ctx* ctx, const double* rhs_dev, double* x_dev, const ibm_solve_opts* opts,
                           ibm_solve_stats* stats);
 
+/* Allocation-free variant of ibm_poisson_solve, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, iterates, stop test,
+ * statistics and results as ibm_poisson_solve with opts->method =
+ * IBM_SOLVER_RBSOR (bit for bit: the same kernels in the same launch shape),
+ * but the solve's working arrays (the red/black split copies of x and of
+ * V rhs, the residual partials and the control block) live in a static array
+ * of the library's own device memory instead of the context's workspace:
+ * 6 * 393216 + 33792 doubles plus 256 bytes (about 19.2 MB), one copy per
+ * device, held until the process ends, its address resolved by ibm_init.
+ * The call allocates no device memory and creates no events (kernel timing
+ * with ibm_profile is suspended for its duration).  Limits: nx * ny <=
+ * 1024 * 768 cells and at most 8192 tiles of the blocked sweep
+ * (IBM_OPT_TB_TILE_X / _Y); IBM_ERR_INVALID beyond them, for another method
+ * or invalid options, with nothing enqueued; IBM_ERR_HIP if the runtime could
+ * not resolve the array on this device.  Every call on a device shares that
+ * device's array and leaves its contents behind (each call rewrites what it
+ * reads before reading it): calls that overlap on one device, from two
+ * contexts or two threads, race and give wrong results. */
+int32_t ibm_poisson_solve_noalloc(ibm_ctx* ctx, const double* rhs_dev, double* x_dev, const ibm_solve_opts* opts,
+                                  ibm_solve_stats* stats);
+
 /* Drag and lift coefficients of the last completed step (0 before the
  * first).  Paper: the aerodynamic force coefficients of Sec. 4.1 (Fig. 4);
  * the force is the reaction of the forcing f of Eq. 3 plus the inertia of the

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -28,6 +29,27 @@
 #include "unet_internal.hpp"
 
 using namespace ibm;
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free Poisson solve
+// (ibm_poisson_solve_noalloc): the working arrays of its red-black SOR solve
+// live in this fixed array of the library's own device memory, one copy per
+// device, held until the process ends.  Layout, in doubles: six split
+// half-arrays of up to kNoAllocCells / 2 cells each (phi, its second pair,
+// V b), the residual partials, then the control blocks.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress returns for the
+// current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocCells = (size_t)1024 * 768;  // at most nx * ny cells
+constexpr size_t kNoAllocTiles = 8192;                // at most this many blocked-sweep tiles
+constexpr size_t kNoAllocHalf = ((kNoAllocCells / 2 + 31) / 32) * 32;  // doubles per split array (256-byte multiple)
+constexpr size_t kNoAllocPartials = 4 * (size_t)kRedMax + 4 * kNoAllocTiles;
+constexpr size_t kNoAllocCtlDoubles = 4 * sizeof(Ctl) / sizeof(double);
+constexpr size_t kNoAllocDoubles = 6 * kNoAllocHalf + kNoAllocPartials + kNoAllocCtlDoubles;
+}  // namespace
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 namespace {
 
@@ -212,6 +234,9 @@ struct ibm_ctx {
     int sor_kernel = IBM_SOR_TEMPORAL;
     int tb_sweeps = 5;
     int tb_tx = 104, tb_ty = 32;
+    // device address of this device's static scratch array (the
+    // allocation-free solve), resolved at ibm_init; nullptr if unavailable
+    double* noalloc = nullptr;
 };
 
 namespace {
@@ -308,6 +333,44 @@ void prune_samples(ibm_ctx* c, int last_it) {
         }
         v.resize(w);
     }
+}
+
+// Device address of the static scratch on the device that holds
+// device_ptr, resolved once per device with that device current (every
+// device holds its own copy of the array at its own address); nullptr if the
+// runtime cannot resolve it.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+double* noalloc_scratch(const void* device_ptr) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, device_ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const int dev = attr.device;
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[dev]) return g_noalloc_ptr[dev];
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_noalloc_ptr[dev] = (double*)ptr;
+    return g_noalloc_ptr[dev];
 }
 
 int32_t reset_ctl(ibm_ctx* c, int which) {
@@ -1694,6 +1757,45 @@ int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
 
 }  // namespace
 
+namespace {
+
+// Red-black SOR solve of a stand-alone right-hand side: x and V rhs into the
+// split arrays, the solve, the result back into x (x = 0 for rhs = 0).
+int32_t split_sor_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, const ibm_solve_opts* o, int fixed,
+                        LoopOut* lo) {
+    const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+    hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)x_dev, c->phr, c->phb, 0);
+    hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
+    LAUNCH_CHECK();
+    int32_t rc = o->method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo)
+                                                  : sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo);
+    if (rc) return rc;
+    if (lo->zero_rhs) return fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
+    hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb, x_dev);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+// Statistics of a stand-alone solve (GPU time between the context's t0 and
+// t1 events) and its status.
+int32_t solve_stats(ibm_ctx* c, const LoopOut& lo, ibm_solve_stats* st) {
+    HIP_TRY(hipEventRecord(c->t1, c->stream));
+    HIP_TRY(hipEventSynchronize(c->t1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->t0, c->t1));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->status = map_status(lo.status);
+        st->iters = lo.iters;
+        st->r0_rel = lo.bn > 0.0 ? lo.r0 / lo.bn : 0.0;
+        st->rel = lo.bn > 0.0 ? lo.rn / lo.bn : 0.0;
+        st->seconds = 1e-3 * ms;
+    }
+    return map_status(lo.status);
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1979,6 +2081,7 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     for (int s = 0; s < kSlots; ++s)
         if (hipEventCreateWithFlags(&c->ev[s], hipEventDisableTiming) != hipSuccess) return fail(IBM_ERR_HIP);
     if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess) return fail(IBM_ERR_HIP);
+    c->noalloc = noalloc_scratch(workspace);  // the allocation-free solve reports its absence
 
     // metrics
     std::vector<std::vector<double>> A;
@@ -2085,35 +2188,71 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
             if (rc) return rc;
         }
     } else {
-        const dim3 gr = grid2(c->nh, c->ny);
-        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)x_dev, c->phr, c->phb, 0);
-        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
-        LAUNCH_CHECK();
-        rc = o->method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo)
-                                              : sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, &lo);
+        rc = split_sor_solve(c, rhs_dev, x_dev, o, fixed, &lo);
         if (rc) return rc;
-        if (lo.zero_rhs) {
-            rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
-            if (rc) return rc;
-        } else {
-            hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb,
-                               x_dev);
-            LAUNCH_CHECK();
-        }
     }
-    HIP_TRY(hipEventRecord(c->t1, c->stream));
-    HIP_TRY(hipEventSynchronize(c->t1));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->t0, c->t1));
-    if (st) {
-        std::memset(st, 0, sizeof(*st));
-        st->status = map_status(lo.status);
-        st->iters = lo.iters;
-        st->r0_rel = lo.bn > 0.0 ? lo.r0 / lo.bn : 0.0;
-        st->rel = lo.bn > 0.0 ? lo.rn / lo.bn : 0.0;
-        st->seconds = 1e-3 * ms;
+    return solve_stats(c, lo, st);
+}
+
+// Allocation-free variant of ibm_poisson_solve (red-black SOR): the solve's
+// working arrays come from this device's static scratch instead of the
+// context's workspace; the context's own pointers are swapped back before
+// returning, whatever the outcome.
+int32_t ibm_poisson_solve_noalloc(ibm_ctx* c, const double* rhs_dev, double* x_dev, const ibm_solve_opts* o,
+                                  ibm_solve_stats* st) {
+    if (!c) return IBM_ERR_INVALID;
+    if (!rhs_dev || !x_dev || !o || o->method != IBM_SOLVER_RBSOR || o->max_iter < 1 || o->check_every < 1 ||
+        o->fixed_iters < 0 || !(o->omega > 0.0 && o->omega < 2.0) || !std::isfinite(o->tol)) {
+        c->err = "invalid solve options (the allocation-free solve takes IBM_SOLVER_RBSOR only)";
+        return IBM_ERR_INVALID;
     }
-    return map_status(lo.status);
+    if ((size_t)c->nx * c->ny > kNoAllocCells) {
+        c->err = "grid larger than the static scratch of the allocation-free solve (1024*768 cells)";
+        return IBM_ERR_INVALID;
+    }
+    TbShape ts;
+    if (c->sor_kernel != IBM_SOR_PER_COLOUR && tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts) &&
+        (size_t)ts.ntx * ts.nty > kNoAllocTiles) {
+        c->err = "more blocked-sweep tiles than the static scratch of the allocation-free solve holds (8192)";
+        return IBM_ERR_INVALID;
+    }
+    if (!c->noalloc) {
+        c->err = "the static scratch of this device could not be resolved";
+        return IBM_ERR_HIP;
+    }
+    c->err.clear();
+    double* base = c->noalloc;
+    double* saved[] = {c->phr, c->phb, c->phr2, c->phb2, c->vbr, c->vbb, c->partials};
+    Ctl* saved_ctl = c->ctl;
+    const int saved_prof = c->prof_every;
+    c->phr = base;
+    c->phb = base + kNoAllocHalf;
+    c->phr2 = base + 2 * kNoAllocHalf;
+    c->phb2 = base + 3 * kNoAllocHalf;
+    c->vbr = base + 4 * kNoAllocHalf;
+    c->vbb = base + 5 * kNoAllocHalf;
+    c->partials = base + 6 * kNoAllocHalf;
+    c->ctl = (Ctl*)(base + 6 * kNoAllocHalf + kNoAllocPartials);
+    c->prof_every = 0;  // sampled timing would create events
+    const int fixed = o->fixed_iters > 0 ? o->fixed_iters : -1;
+    LoopOut lo;
+    int32_t rc = IBM_OK;
+    if (hipEventRecord(c->t0, c->stream) != hipSuccess) {
+        c->err = "hipEventRecord failed";
+        rc = IBM_ERR_HIP;
+    }
+    if (!rc) rc = split_sor_solve(c, rhs_dev, x_dev, o, fixed, &lo);
+    c->phr = saved[0];
+    c->phb = saved[1];
+    c->phr2 = saved[2];
+    c->phb2 = saved[3];
+    c->vbr = saved[4];
+    c->vbb = saved[5];
+    c->partials = saved[6];
+    c->ctl = saved_ctl;
+    c->prof_every = saved_prof;
+    if (rc) return rc;
+    return solve_stats(c, lo, st);
 }
 
 int32_t ibm_forces(ibm_ctx* c, double* cd, double* cl) {

@@ -34,7 +34,8 @@ KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_res
 NET_STEP_ENERGY, NET_STEP_BACKTRACK = 0, 1
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
-EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_forces",
+EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_poisson_solve_noalloc",
+            "ibm_forces",
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
             "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot",
             "ibm_batch_create", "ibm_batch_step", "ibm_batch_set_graph", "ibm_batch_destroy", "ibm_batch_last_error",
@@ -98,6 +99,8 @@ def lib():
         L.ibm_step.restype = C.c_int32
         L.ibm_poisson_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
         L.ibm_poisson_solve.restype = C.c_int32
+        L.ibm_poisson_solve_noalloc.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
+        L.ibm_poisson_solve_noalloc.restype = C.c_int32
         L.ibm_forces.argtypes = [vp, dp, dp]
         L.ibm_forces.restype = C.c_int32
         L.ibm_get_fields.argtypes = [vp, dp, dp, dp, dp]
@@ -356,8 +359,10 @@ class Solver:
 
     # -- stand-alone Poisson solve ------------------------------------------
     def poisson_solve(self, rhs, x, method=RBSOR, omega=1.8, tol=1e-8, max_iter=2_000_000,
-                      check_every=10, fixed_iters=0):
-        """Solve (D G) x = rhs in place on device tensors (float64, (ny, nx))."""
+                      check_every=10, fixed_iters=0, noalloc=False):
+        """Solve (D G) x = rhs in place on device tensors (float64, (ny, nx)).
+        noalloc=True calls ibm_poisson_solve_noalloc (red-black SOR with the
+        library's static scratch instead of the context's workspace)."""
         torch = self.torch
         for t in (rhs, x):
             if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device \
@@ -365,10 +370,11 @@ class Solver:
                 raise ValueError("rhs and x must be contiguous float64 device tensors of nx*ny")
         o = SolveOpts(method, max_iter, check_every, fixed_iters, omega, tol)
         st = SolveStats()
-        rc = lib().ibm_poisson_solve(self._h, C.c_void_p(rhs.data_ptr()), C.c_void_p(x.data_ptr()),
-                                     C.byref(o), C.byref(st))
+        name = "ibm_poisson_solve_noalloc" if noalloc else "ibm_poisson_solve"
+        rc = getattr(lib(), name)(self._h, C.c_void_p(rhs.data_ptr()), C.c_void_p(x.data_ptr()),
+                                  C.byref(o), C.byref(st))
         if rc < 0 and rc != ERR_NAN:
-            self._err("ibm_poisson_solve", rc)
+            self._err(name, rc)
         d = {k: getattr(st, k) for k, _ in SolveStats._fields_ if not k.startswith("reserved")}
         d["rc"] = rc
         return d

@@ -1,0 +1,123 @@
+"""The allocation-free Poisson solve (ibm_poisson_solve_noalloc) against the
+ordinary entry point (ibm_poisson_solve), through the C ABI.
+
+The two run the same red-black SOR kernels in the same launch shape (the
+pressure-correction solve of the fractional step, Sec. 2.2), so their
+iterates, iteration counts and residuals must agree bit for bit; the
+allocation-free one keeps its working arrays in the library's static device
+scratch, which every call on the device shares and leaves behind.  Two calls
+in a row, the second on a smaller grid, check that nothing of the first
+call's contents leaks into the second."""
+import numpy as np
+import pytest
+
+from paper_2402_17337_amd import ibm
+from paper_2402_17337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+def _solver(nx, ny, stretched):
+    if stretched:
+        s = W.uniform_faces(nx, 1.0)
+        xf = 16.0 * (s - 0.12 * np.sin(2 * np.pi * s) / (2 * np.pi))
+        s = W.uniform_faces(ny, 1.0)
+        yf = 12.0 * (s - 0.10 * np.sin(2 * np.pi * s) / (2 * np.pi))
+    else:
+        xf, yf = W.uniform_faces(nx, 16.0), W.uniform_faces(ny, 12.0)
+    return ibm.Solver(nx, ny, xf, yf, body=0)
+
+
+def _rhs(torch, nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    return dev(b), dev(x0)
+
+
+def _both(torch, g, b, x0, **kw):
+    """The allocation-free call first, then the ordinary one on the same input."""
+    xa = x0.clone()
+    sa = g.poisson_solve(b, xa, noalloc=True, **kw)
+    xb = x0.clone()
+    sb = g.poisson_solve(b, xb, **kw)
+    return xa.cpu().numpy(), sa, xb.cpu().numpy(), sb
+
+
+def _same(xa, sa, xb, sb):
+    assert sa["rc"] == sb["rc"]
+    assert sa["iters"] == sb["iters"]
+    assert sa["rel"] == sb["rel"] and sa["r0_rel"] == sb["r0_rel"]
+    assert np.array_equal(xa, xb), float(np.abs(xa - xb).max())
+
+
+def test_two_calls_in_a_row_the_second_smaller(torch):
+    # 256x192 stretched (several tiles, ragged in x and y), to tolerance;
+    # then 64x48 uniform, whose arrays are a fraction of the first call's
+    g1 = _solver(256, 192, True)
+    b1, x1 = _rhs(torch, 256, 192, 1)
+    xa, sa, xb, sb = _both(torch, g1, b1, x1, tol=1e-8, check_every=10)
+    assert sa["rc"] == ibm.OK and 0 < sa["iters"] < 2_000_000 and sa["rel"] <= 1e-8
+    _same(xa, sa, xb, sb)
+    g2 = _solver(64, 48, False)
+    b2, x2 = _rhs(torch, 64, 48, 2)
+    xa2, sa2, xb2, sb2 = _both(torch, g2, b2, x2, tol=1e-8, check_every=10)
+    assert sa2["rc"] == ibm.OK and sa2["rel"] <= 1e-8
+    _same(xa2, sa2, xb2, sb2)
+    # the scratch now holds the small grid's arrays: the large grid again
+    xa3, sa3, _, _ = _both(torch, g1, b1, x1, tol=1e-8, check_every=10)
+    _same(xa3, sa3, xb, sb)
+    g1.close()
+    g2.close()
+
+
+@pytest.mark.parametrize("kernel", [ibm.SOR_TEMPORAL, ibm.SOR_PER_COLOUR, ibm.SOR_TEMPORAL_LDS])
+def test_every_sweep_kernel_and_fixed_iterations(torch, kernel):
+    g = _solver(200, 150, True)
+    assert g.set_option(ibm.OPT_SOR_KERNEL, kernel) == ibm.OK
+    b, x0 = _rhs(torch, 200, 150, 3)
+    xa, sa, xb, sb = _both(torch, g, b, x0, fixed_iters=53, check_every=10)
+    assert sa["iters"] == 53
+    _same(xa, sa, xb, sb)
+    g.close()
+
+
+def test_full_size_grid_in_the_benchmark_launch_shape(torch):
+    # the 1024x768 plunging grid (the largest the scratch holds), 104x32 tiles
+    c = W.plunging_1024x768()
+    g = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], body=0)
+    b, x0 = _rhs(torch, c["nx"], c["ny"], 4)
+    xa, sa, xb, sb = _both(torch, g, b, x0, fixed_iters=300, check_every=10)
+    _same(xa, sa, xb, sb)
+    # 8x8 tiles: 12288 of them, more than the scratch's partials hold
+    assert g.set_option(ibm.OPT_TB_TILE_X, 8) == ibm.OK and g.set_option(ibm.OPT_TB_TILE_Y, 8) == ibm.OK
+    with pytest.raises(ibm.IbmError, match="tiles"):
+        g.poisson_solve(b, x0.clone(), fixed_iters=10, noalloc=True)
+    g.close()
+
+
+def test_zero_rhs_and_rejections(torch):
+    g = _solver(64, 48, False)
+    z = torch.zeros(48, 64, dtype=torch.float64, device="cuda")
+    x = torch.ones_like(z)
+    st = g.poisson_solve(z, x, noalloc=True)
+    assert st["rc"] == ibm.OK and st["iters"] == 0 and float(x.abs().max()) == 0.0
+    # other methods are not offered by the allocation-free call
+    with pytest.raises(ibm.IbmError):
+        g.poisson_solve(z, x, method=ibm.PCG, noalloc=True)
+    # 1024x776 cells exceed the scratch and are rejected
+    g.close()
+    big = _solver(1024, 776, False)
+    zb = torch.zeros(776, 1024, dtype=torch.float64, device="cuda")
+    with pytest.raises(ibm.IbmError, match="static scratch"):
+        big.poisson_solve(zb, zb.clone(), noalloc=True)
+    big.close()
