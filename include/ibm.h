@@ -60,6 +60,15 @@ extern "C" {
 
 /* boundary conditions */
 #define IBM_BC_CHANNEL 0
+/* Periodic in x and y (the Taylor-Green vortex test of the time integrator;
+ * not a configuration of the paper): no body, the two ends of each direction
+ * are neighbours (centre distance (dx[0] + dx[nx-1]) / 2), u face nx and v
+ * face row ny mirror face 0 and row 0.  The pressure operator is singular:
+ * every Poisson solve uses the zero-sum part of V b and returns the solution
+ * of zero volume-weighted mean.  Red-black SOR runs colour by colour (the
+ * blocked sweeps are for the channel), or PCG; no mixed-precision sweeps, no
+ * learned guess, no batch. */
+#define IBM_BC_PERIODIC 1
 
 /* pressure solvers */
 #define IBM_SOLVER_RBSOR 0 /* red-black SOR, red = (i+j) even updated first */
@@ -87,7 +96,7 @@ extern "C" {
 /* Problem and solver parameters.  Lengths in chords, velocities in u_inf. */
 typedef struct ibm_params {
     int32_t nx, ny;          /* cells in x and y; both even and >= 8 */
-    int32_t bc_mode;         /* IBM_BC_CHANNEL */
+    int32_t bc_mode;         /* IBM_BC_CHANNEL or IBM_BC_PERIODIC */
     int32_t body;            /* 1: ellipse present; 0: no body */
     double re;               /* Reynolds number u_inf c / nu, > 0 */
     double dt;               /* time step, > 0 */
@@ -171,7 +180,8 @@ size_t ibm_workspace_bytes(const ibm_params* prm);
  *   hip_stream             hipStream_t (NULL = the null stream), borrowed.
  * Errors: IBM_ERR_INVALID for odd or too small nx/ny, non-increasing faces,
  * dt <= 0, re <= 0, omega outside (0, 2), a body whose range of motion comes
- * within two cells of the boundary, an unsupported bc_mode or precision, a
+ * within two cells of the boundary, an unknown bc_mode, IBM_BC_PERIODIC with
+ * a body, IBM_SOLVER_RBSOR_MP or IBM_INIT_LEARNED, an unsupported precision, a
  * small or misaligned workspace; IBM_ERR_HIP if the device rejects the setup.
  * Validation happens before any GPU call. */
 int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, const double* u0,

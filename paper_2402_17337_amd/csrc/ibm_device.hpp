@@ -23,8 +23,14 @@ constexpr int kBlockRows = 4;   // rows per block of the 2-D kernels
 //   v node (i, j): L v = vcn[j](vN-vP) + vcs[j](vS-vP) + vce[i](vE-vP) + vcw[i](vW-vP)
 //   with ucn/ucs zero at the slip walls, vce zero at the outlet (zero
 //   gradient) and vcw[0] pointing at v = 0 on the inflow face.
+// Periodic mode (per = 1, both directions periodic, no body): every
+// coefficient is nonzero, the centre distances across the two ends are
+// (dx[nx-1] + dx[0]) / 2 and (dy[ny-1] + dy[0]) / 2, neighbours wrap
+// (cell nx-1's east neighbour is cell 0), u faces 0..nx-1 and v faces
+// 0..ny-1 are the unknowns, and u face nx / v face row ny mirror face 0.
 struct Grid {
     int nx, ny, nh;  // nh = nx / 2 (cells of one colour in a row)
+    int per;         // 0: channel boundaries; 1: periodic
     const double *xf, *yf, *dx, *dy, *xc, *yc, *dxu, *dyv;
     const double *pcE, *pcW, *pcD, *pcN, *pcS;
     const double *uce, *ucw, *ucn, *ucs;

@@ -117,10 +117,14 @@ __device__ inline double rb_row(const Grid& g, const double* __restrict__ other,
     const double dyj = g.dy[j], dxi = g.dx[i];
     const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
     const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
-    const double xE = i < g.nx - 1 ? other[k + s] : 0.0;
-    const double xW = i > 0 ? other[k + s - 1] : 0.0;
-    const double xN = j < g.ny - 1 ? other[k + g.nh] : 0.0;
-    const double xS = j > 0 ? other[k - g.nh] : 0.0;
+    // periodic mode wraps: cell nx-1's east neighbour is position 0 of the
+    // row, cell 0's west neighbour position nh-1, rows ny-1 and 0 are
+    // neighbours (same position: the colours alternate, nx and ny are even)
+    const size_t nh = g.nh, top = (size_t)(g.ny - 1) * g.nh;
+    const double xE = i < g.nx - 1 ? other[k + s] : (g.per ? other[k + 1 - nh] : 0.0);
+    const double xW = i > 0 ? other[k + s - 1] : (g.per ? other[k + nh - 1] : 0.0);
+    const double xN = j < g.ny - 1 ? other[k + nh] : (g.per ? other[k - top] : 0.0);
+    const double xS = j > 0 ? other[k - nh] : (g.per ? other[k + top] : 0.0);
     d = rb_diag(aE, aD, aW, aN, aS);
     return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
@@ -1084,10 +1088,11 @@ __device__ inline double nat_row(const Grid& g, const double* __restrict__ x, in
     const double dyj = g.dy[j], dxi = g.dx[i];
     const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
     const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
-    const double xE = i < g.nx - 1 ? x[k + 1] : 0.0;
-    const double xW = i > 0 ? x[k - 1] : 0.0;
-    const double xN = j < g.ny - 1 ? x[k + g.nx] : 0.0;
-    const double xS = j > 0 ? x[k - g.nx] : 0.0;
+    const size_t W = g.nx, top = (size_t)(g.ny - 1) * g.nx;  // periodic mode wraps
+    const double xE = i < g.nx - 1 ? x[k + 1] : (g.per ? x[k + 1 - W] : 0.0);
+    const double xW = i > 0 ? x[k - 1] : (g.per ? x[k + W - 1] : 0.0);
+    const double xN = j < g.ny - 1 ? x[k + W] : (g.per ? x[k - top] : 0.0);
+    const double xS = j > 0 ? x[k - W] : (g.per ? x[k + top] : 0.0);
     d = rb_diag(aE, aD, aW, aN, aS);
     return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
@@ -1233,7 +1238,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const doub
     if (s_stop) return;
     const double beta = s_beta;
     double pacc[1] = {0.0};
-    const size_t nx = g.nx;
+    const size_t nx = g.nx, top = (size_t)(g.ny - 1) * g.nx;
     for (CellWalk c(g); c.ok(); c.next()) {
         const size_t k = c.k;
         const int i = c.i, j = c.j;
@@ -1242,10 +1247,15 @@ __global__ __launch_bounds__(kRedThreads) void k_pcg_dir_spmv(Grid g, const doub
         const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
         const double d = rb_diag(aE, aD, aW, aN, aS);
         const double pk = pcg_dir(z[k], pold[k], beta);
-        const double pE = i < g.nx - 1 ? pcg_dir(z[k + 1], pold[k + 1], beta) : 0.0;
-        const double pW = i > 0 ? pcg_dir(z[k - 1], pold[k - 1], beta) : 0.0;
-        const double pN = j < g.ny - 1 ? pcg_dir(z[k + nx], pold[k + nx], beta) : 0.0;
-        const double pS = j > 0 ? pcg_dir(z[k - nx], pold[k - nx], beta) : 0.0;
+        // neighbours (periodic mode wraps; channel mode has none beyond the ends)
+        const bool hE = i < g.nx - 1 || g.per, hW = i > 0 || g.per;
+        const bool hN = j < g.ny - 1 || g.per, hS = j > 0 || g.per;
+        const size_t kE = i < g.nx - 1 ? k + 1 : k + 1 - nx, kW = i > 0 ? k - 1 : k + nx - 1;
+        const size_t kN = j < g.ny - 1 ? k + nx : k - top, kS = j > 0 ? k - nx : k + top;
+        const double pE = hE ? pcg_dir(z[kE], pold[kE], beta) : 0.0;
+        const double pW = hW ? pcg_dir(z[kW], pold[kW], beta) : 0.0;
+        const double pN = hN ? pcg_dir(z[kN], pold[kN], beta) : 0.0;
+        const double pS = hS ? pcg_dir(z[kS], pold[kS], beta) : 0.0;
         const double sum = rb_sum(aE, pE, aW, pW, aN, pN, aS, pS);
         const double qk = d * pk - sum;  // M p = -A p
         pnew[k] = pk;
@@ -1335,6 +1345,40 @@ __global__ __launch_bounds__(kBlock) void k_pcg_confirm(Ctl* ctl, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// Periodic (singular) Poisson problem: the right-hand side V b is made to sum
+// to zero and the solution to have zero volume-weighted mean.
+// k_per_sums: per-block partials of sum a (weighted = 0) or sum V a
+// (weighted = 1), and of sum V; k_per_shift: every block sums them and
+// subtracts m V (by_volume = 1) or m from every cell, m = (first sum) / (sum V).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRedThreads) void k_per_sums(Grid g, const double* __restrict__ a, int weighted,
+                                                          double* partials) {
+#pragma clang fp contract(off)
+    __shared__ double lds[2 * kRedThreads / kWave];
+    double acc[2] = {0.0, 0.0};
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const double vol = g.dx[c.i] * g.dy[c.j];
+        acc[0] += weighted ? vol * a[c.k] : a[c.k];
+        acc[1] += vol;
+    }
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_per_shift(Grid g, double* __restrict__ a,
+                                                           const double* __restrict__ partials, int nb,
+                                                           int by_volume) {
+#pragma clang fp contract(off)
+    __shared__ double lds[2 * kRedThreads / kWave];
+    __shared__ double s_m;
+    double acc[2];
+    sum_partials(acc, partials, nb, lds);
+    if (threadIdx.x == 0) s_m = acc[0] / acc[1];
+    __syncthreads();
+    const double m = s_m;
+    for (CellWalk c(g); c.ok(); c.next()) a[c.k] -= by_volume ? m * (g.dx[c.i] * g.dy[c.j]) : m;
+}
+
+// ---------------------------------------------------------------------------
 // Implicit viscous half: (I - beta L) x = rhs by red-black SOR, natural layout
 // ---------------------------------------------------------------------------
 template <int COLOR>
@@ -1346,20 +1390,23 @@ __global__ __launch_bounds__(kBlock) void k_helm_u_sweep(Grid g, double* __restr
     const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
     const int i = 2 * m + ((j + COLOR) & 1);
-    if (j >= g.ny || i < 1 || i > g.nx - 1) return;
+    if (j >= g.ny || i < (g.per ? 0 : 1) || i > g.nx - 1) return;
     const int W = g.nx + 1;
-    const size_t k = (size_t)j * W + i;
+    const size_t k = (size_t)j * W + i, top = (size_t)(g.ny - 1) * W;
     const double ce = g.uce[i], cw = g.ucw[i];
-    double s = ce * u[k + 1] + cw * u[k - 1];
+    // periodic mode wraps (face nx mirrors face 0; rows ny-1 and 0 are neighbours)
+    const double uE = (g.per && i == g.nx - 1) ? u[k + 1 - g.nx] : u[k + 1];
+    const double uW = (g.per && i == 0) ? u[k + g.nx - 1] : u[k - 1];
+    double s = ce * uE + cw * uW;
     double cs = ce + cw;
-    if (j < g.ny - 1) {
+    if (j < g.ny - 1 || g.per) {
         const double a = g.ucn[j];
-        s += a * u[k + W];
+        s += a * u[j < g.ny - 1 ? k + W : k - top];
         cs += a;
     }
-    if (j > 0) {
+    if (j > 0 || g.per) {
         const double a = g.ucs[j];
-        s += a * u[k - W];
+        s += a * u[j > 0 ? k - W : k + top];
         cs += a;
     }
     const double gs = (rhs[k] + beta * s) / (1.0 + beta * cs);
@@ -1375,20 +1422,23 @@ __global__ __launch_bounds__(kBlock) void k_helm_v_sweep(Grid g, double* __restr
     const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
     const int i = 2 * m + ((j + COLOR) & 1);
-    if (j < 1 || j > g.ny - 1 || i > g.nx - 1) return;
+    if (j < (g.per ? 0 : 1) || j > g.ny - 1 || i > g.nx - 1) return;
     const int W = g.nx;
-    const size_t k = (size_t)j * W + i;
+    const size_t k = (size_t)j * W + i, top = (size_t)(g.ny - 1) * W;
     const double cn = g.vcn[j], cso = g.vcs[j];
-    double s = cn * v[k + W] + cso * v[k - W];
+    // periodic mode wraps (face row ny mirrors row 0; columns nx-1 and 0 are neighbours)
+    const double vN = (g.per && j == g.ny - 1) ? v[k - top] : v[k + W];
+    const double vS = (g.per && j == 0) ? v[k + top] : v[k - W];
+    double s = cn * vN + cso * vS;
     double cs = cn + cso;
-    if (i < g.nx - 1) {
+    if (i < g.nx - 1 || g.per) {
         const double a = g.vce[i];
-        s += a * v[k + 1];
+        s += a * v[i < g.nx - 1 ? k + 1 : k + 1 - W];
         cs += a;
     }
-    if (i > 0) {
+    if (i > 0 || g.per) {
         const double a = g.vcw[i];
-        s += a * v[k - 1];
+        s += a * v[i > 0 ? k - 1 : k + W - 1];
         cs += a;
     } else {
         const double a = g.vcw[0];
@@ -1402,22 +1452,30 @@ __global__ __launch_bounds__(kBlock) void k_helm_v_sweep(Grid g, double* __restr
 __device__ inline double lap_u(const Grid& g, const double* __restrict__ u, int i, int j) {
 #pragma clang fp contract(off)
     const int W = g.nx + 1;
-    const size_t k = (size_t)j * W + i;
+    const size_t k = (size_t)j * W + i, top = (size_t)(g.ny - 1) * W;
     const double uP = u[k];
-    double L = (u[k + 1] - uP) / (g.dx[i] * g.dxu[i]) + (u[k - 1] - uP) / (g.dx[i - 1] * g.dxu[i]);
-    if (j < g.ny - 1) L += (u[k + W] - uP) / (g.dyv[j + 1] * g.dy[j]);
-    if (j > 0) L += (u[k - W] - uP) / (g.dyv[j] * g.dy[j]);
+    // periodic mode wraps (face nx mirrors face 0)
+    const double uE = (g.per && i == g.nx - 1) ? u[k + 1 - g.nx] : u[k + 1];
+    const double uW = (g.per && i == 0) ? u[k + g.nx - 1] : u[k - 1];
+    const int im1 = (g.per && i == 0) ? g.nx - 1 : i - 1;
+    double L = (uE - uP) / (g.dx[i] * g.dxu[i]) + (uW - uP) / (g.dx[im1] * g.dxu[i]);
+    if (j < g.ny - 1 || g.per) L += (u[j < g.ny - 1 ? k + W : k - top] - uP) / (g.dyv[j + 1] * g.dy[j]);
+    if (j > 0 || g.per) L += (u[j > 0 ? k - W : k + top] - uP) / (g.dyv[j] * g.dy[j]);
     return L;
 }
 
 __device__ inline double lap_v(const Grid& g, const double* __restrict__ v, int i, int j) {
 #pragma clang fp contract(off)
     const int W = g.nx;
-    const size_t k = (size_t)j * W + i;
+    const size_t k = (size_t)j * W + i, top = (size_t)(g.ny - 1) * W;
     const double vP = v[k];
-    double L = (v[k + W] - vP) / (g.dy[j] * g.dyv[j]) + (v[k - W] - vP) / (g.dy[j - 1] * g.dyv[j]);
-    if (i < g.nx - 1) L += (v[k + 1] - vP) / (g.dxu[i + 1] * g.dx[i]);
-    if (i > 0) L += (v[k - 1] - vP) / (g.dxu[i] * g.dx[i]);
+    // periodic mode wraps (face row ny mirrors row 0)
+    const double vN = (g.per && j == g.ny - 1) ? v[k - top] : v[k + W];
+    const double vS = (g.per && j == 0) ? v[k + top] : v[k - W];
+    const int jm1 = (g.per && j == 0) ? g.ny - 1 : j - 1;
+    double L = (vN - vP) / (g.dy[j] * g.dyv[j]) + (vS - vP) / (g.dy[jm1] * g.dyv[j]);
+    if (i < g.nx - 1 || g.per) L += (v[i < g.nx - 1 ? k + 1 : k + 1 - W] - vP) / (g.dxu[i + 1] * g.dx[i]);
+    if (i > 0 || g.per) L += (v[i > 0 ? k - 1 : k + W - 1] - vP) / (g.dxu[i] * g.dx[i]);
     else L += (0.0 - vP) / (g.dxu[0] * g.dx[0]);
     return L;
 }
@@ -1431,20 +1489,22 @@ __global__ __launch_bounds__(kRedThreads) void k_helm_residual(Grid g, int comp,
 #pragma clang fp contract(off)
     __shared__ double lds[2 * kRedThreads / kWave];
     if (ctl->done) return;
-    const int w = comp == 0 ? g.nx - 1 : g.nx;   // unknowns per row
-    const int h = comp == 0 ? g.ny : g.ny - 1;   // rows of unknowns
+    const int i0 = (comp == 0 && !g.per) ? 1 : 0;  // first unknown face in x
+    const int j0 = (comp == 1 && !g.per) ? 1 : 0;  // first unknown row
+    const int w = comp == 0 ? g.nx - i0 : g.nx;   // unknowns per row
+    const int h = comp == 0 ? g.ny : g.ny - j0;   // rows of unknowns
     const size_t n = (size_t)w * h;
     double acc[2] = {0.0, 0.0};
     for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
         const int jr = (int)(q / w), ir = (int)(q - (size_t)jr * w);
         if (comp == 0) {
-            const int i = ir + 1, j = jr;
+            const int i = ir + i0, j = jr;
             const size_t k = (size_t)j * (g.nx + 1) + i;
             const double r = rhs[k] - (x[k] - beta * lap_u(g, x, i, j));
             acc[0] += r * r;
             acc[1] += rhs[k] * rhs[k];
         } else {
-            const int i = ir, j = jr + 1;
+            const int i = ir, j = jr + j0;
             const size_t k = (size_t)j * g.nx + i;
             const double r = rhs[k] - (x[k] - beta * lap_v(g, x, i, j));
             acc[0] += r * r;
@@ -1466,32 +1526,38 @@ __global__ __launch_bounds__(kBlock) void k_momentum_u(Grid g, const double* __r
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (i < 1 || i > g.nx || j >= g.ny) return;
-    const int nx = g.nx, W = nx + 1;
+    // unknown faces: 1..nx-1 and the outlet nx (channel); 0..nx-1 (periodic)
+    if (i < (g.per ? 0 : 1) || i > (g.per ? g.nx - 1 : g.nx) || j >= g.ny) return;
+    const int nx = g.nx, ny = g.ny, W = nx + 1;
     const size_t k = (size_t)j * W + i;
     if (i == nx) {  // convective outlet, kept in the R array until committed
         const double uo = u[k], ui = u[k - 1];
         ru[k] = uo - dt * uinf * (uo - ui) / g.dx[nx - 1];
         return;
     }
+    // neighbours; periodic mode wraps (face nx mirrors face 0, row ny row 0)
+    const int im1 = (g.per && i == 0) ? nx - 1 : i - 1;
+    const int jp1 = j < ny - 1 ? j + 1 : 0, jm1 = j > 0 ? j - 1 : ny - 1;
     const double uP = u[k];
-    const double ue = 0.5 * (uP + u[k + 1]);
-    const double uw = 0.5 * (u[k - 1] + uP);
+    const double uE = (g.per && i == nx - 1) ? u[k + 1 - nx] : u[k + 1];
+    const double uW = u[(size_t)j * W + im1];
+    const double ue = 0.5 * (uP + uE);
+    const double uw = 0.5 * (uW + uP);
     const double nxp = (ue * ue - uw * uw) / g.dxu[i];
     double fn = 0.0, fs = 0.0;
-    if (j < g.ny - 1) {
-        const double vc = 0.5 * (v[(size_t)(j + 1) * nx + i - 1] + v[(size_t)(j + 1) * nx + i]);
-        const double uc = 0.5 * (uP + u[k + W]);
+    if (j < ny - 1 || g.per) {
+        const double vc = 0.5 * (v[(size_t)jp1 * nx + im1] + v[(size_t)jp1 * nx + i]);
+        const double uc = 0.5 * (uP + u[(size_t)jp1 * W + i]);
         fn = vc * uc;
     }
-    if (j > 0) {
-        const double vc = 0.5 * (v[(size_t)j * nx + i - 1] + v[(size_t)j * nx + i]);
-        const double uc = 0.5 * (u[k - W] + uP);
+    if (j > 0 || g.per) {
+        const double vc = 0.5 * (v[(size_t)j * nx + im1] + v[(size_t)j * nx + i]);
+        const double uc = 0.5 * (u[(size_t)jm1 * W + i] + uP);
         fs = vc * uc;
     }
     const double N = nxp + (fn - fs) / g.dy[j];
     const double L = lap_u(g, u, i, j);
-    const double G = (p[(size_t)j * nx + i] - p[(size_t)j * nx + i - 1]) / g.dxu[i];
+    const double G = (p[(size_t)j * nx + i] - p[(size_t)j * nx + im1]) / g.dxu[i];
     const double Nold = have_hist ? nu[k] : N;
     ru[k] = uP + dt * (-(1.5 * N - 0.5 * Nold) - G + (0.5 / re) * L);
     nu[k] = N;
@@ -1504,20 +1570,26 @@ __global__ __launch_bounds__(kBlock) void k_momentum_v(Grid g, const double* __r
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (i >= g.nx || j < 1 || j > g.ny - 1) return;
-    const int nx = g.nx, W = nx + 1;
+    // unknown rows: 1..ny-1 (channel); 0..ny-1 (periodic)
+    if (i >= g.nx || j < (g.per ? 0 : 1) || j > g.ny - 1) return;
+    const int nx = g.nx, ny = g.ny, W = nx + 1;
     const size_t k = (size_t)j * nx + i;
+    // neighbours; periodic mode wraps (row ny mirrors row 0, face nx face 0)
+    const int jm1 = (g.per && j == 0) ? ny - 1 : j - 1;
+    const int ip1 = (g.per && i == nx - 1) ? 0 : i + 1;
     const double vP = v[k];
-    const double vn = 0.5 * (vP + v[k + nx]);
-    const double vs = 0.5 * (v[k - nx] + vP);
+    const double vNv = (g.per && j == ny - 1) ? v[i] : v[k + nx];
+    const double vSv = v[(size_t)jm1 * nx + i];
+    const double vn = 0.5 * (vP + vNv);
+    const double vs = 0.5 * (vSv + vP);
     const double nyp = (vn * vn - vs * vs) / g.dyv[j];
-    const double ue = 0.5 * (u[(size_t)(j - 1) * W + i + 1] + u[(size_t)j * W + i + 1]);
-    const double ve = (i < nx - 1) ? 0.5 * (vP + v[k + 1]) : vP;
-    const double uw = 0.5 * (u[(size_t)(j - 1) * W + i] + u[(size_t)j * W + i]);
-    const double vw = (i > 0) ? 0.5 * (v[k - 1] + vP) : 0.0;
+    const double ue = 0.5 * (u[(size_t)jm1 * W + ip1] + u[(size_t)j * W + ip1]);
+    const double ve = (i < nx - 1 || g.per) ? 0.5 * (vP + v[(size_t)j * nx + ip1]) : vP;
+    const double uw = 0.5 * (u[(size_t)jm1 * W + i] + u[(size_t)j * W + i]);
+    const double vw = (i > 0 || g.per) ? 0.5 * (v[i > 0 ? k - 1 : k + nx - 1] + vP) : 0.0;
     const double N = (ue * ve - uw * vw) / g.dx[i] + nyp;
     const double L = lap_v(g, v, i, j);
-    const double G = (p[(size_t)j * nx + i] - p[(size_t)(j - 1) * nx + i]) / g.dyv[j];
+    const double G = (p[(size_t)j * nx + i] - p[(size_t)jm1 * nx + i]) / g.dyv[j];
     const double Nold = have_hist ? nv[k] : N;
     rv[k] = vP + dt * (-(1.5 * N - 0.5 * Nold) - G + (0.5 / re) * L);
     nv[k] = N;
@@ -1804,7 +1876,10 @@ __global__ __launch_bounds__(kBlock) void k_poisson_rhs(Grid g, const double* __
     if (i >= g.nx || j >= g.ny) return;
     const int nx = g.nx, W = nx + 1;
     const size_t ku = (size_t)j * W + i, kv = (size_t)j * nx + i;
-    const double d = (u[ku + 1] - u[ku]) / g.dx[i] + (v[kv + nx] - v[kv]) / g.dy[j];
+    // periodic mode wraps (face nx mirrors face 0, row ny row 0)
+    const double uE = (g.per && i == nx - 1) ? u[ku + 1 - nx] : u[ku + 1];
+    const double vN = (g.per && j == g.ny - 1) ? v[i] : v[kv + nx];
+    const double d = (uE - u[ku]) / g.dx[i] + (vN - v[kv]) / g.dy[j];
     double q = 0.0;
     if (q_mode && msrc[kv]) {
         const double fe = flu[ku + 1] ? u[ku + 1] - 0.0 : 0.0;
@@ -1823,11 +1898,13 @@ __global__ __launch_bounds__(kBlock) void k_project_u(Grid g, double* __restrict
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (i < 1 || i > g.nx || j >= g.ny) return;
+    // faces 1..nx (channel, nx the outlet); 0..nx-1 (periodic)
+    if (i < (g.per ? 0 : 1) || i > (g.per ? g.nx - 1 : g.nx) || j >= g.ny) return;
     const int nx = g.nx;
     const size_t k = (size_t)j * (nx + 1) + i;
     if (i < nx) {
-        u[k] -= dt * ((phi[(size_t)j * nx + i] - phi[(size_t)j * nx + i - 1]) / g.dxu[i]);
+        const int im1 = (g.per && i == 0) ? nx - 1 : i - 1;
+        u[k] -= dt * ((phi[(size_t)j * nx + i] - phi[(size_t)j * nx + im1]) / g.dxu[i]);
     } else {
         u[k] -= dt * (0.0 - phi[(size_t)j * nx + nx - 1]) / g.dxu[nx];
     }
@@ -1838,10 +1915,19 @@ __global__ __launch_bounds__(kBlock) void k_project_v(Grid g, double* __restrict
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (i >= g.nx || j < 1 || j > g.ny - 1) return;
+    // rows 1..ny-1 (channel); 0..ny-1 (periodic)
+    if (i >= g.nx || j < (g.per ? 0 : 1) || j > g.ny - 1) return;
     const int nx = g.nx;
     const size_t k = (size_t)j * nx + i;
-    v[k] -= dt * ((phi[k] - phi[k - nx]) / g.dyv[j]);
+    const size_t ks = j > 0 ? k - nx : k + (size_t)(g.ny - 1) * nx;
+    v[k] -= dt * ((phi[k] - phi[ks]) / g.dyv[j]);
+}
+
+// Periodic mode: u face nx and v face row ny mirror face 0 / row 0.
+__global__ void k_sync_periodic(int nx, int ny, double* __restrict__ u, double* __restrict__ v) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ny) u[(size_t)t * (nx + 1) + nx] = u[(size_t)t * (nx + 1)];
+    if (t < nx) v[(size_t)ny * nx + t] = v[t];
 }
 
 // p^{n+1} = p^n + phi - dt/(2Re) (A phi)/V, A evaluated as a plain
@@ -1853,28 +1939,29 @@ __global__ __launch_bounds__(kBlock) void k_update_p(Grid g, double* __restrict_
     const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
     if (i >= g.nx || j >= g.ny) return;
     const int nx = g.nx, ny = g.ny;
-    const size_t k = (size_t)j * nx + i;
+    const size_t k = (size_t)j * nx + i, top = (size_t)(ny - 1) * nx;
     double s = 0.0, d = 0.0, a;
-    if (i < nx - 1) {
+    // periodic mode wraps; channel mode: Neumann, phi = 0 on the outlet face
+    if (i < nx - 1 || g.per) {
         a = g.dy[j] / g.dxu[i + 1];
-        s += a * phi[k + 1];
+        s += a * phi[i < nx - 1 ? k + 1 : k + 1 - nx];
         d += a;
     } else {
         d += g.dy[j] / g.dxu[nx];
     }
-    if (i > 0) {
+    if (i > 0 || g.per) {
         a = g.dy[j] / g.dxu[i];
-        s += a * phi[k - 1];
+        s += a * phi[i > 0 ? k - 1 : k + nx - 1];
         d += a;
     }
-    if (j < ny - 1) {
+    if (j < ny - 1 || g.per) {
         a = g.dx[i] / g.dyv[j + 1];
-        s += a * phi[k + nx];
+        s += a * phi[j < ny - 1 ? k + nx : k - top];
         d += a;
     }
-    if (j > 0) {
+    if (j > 0 || g.per) {
         a = g.dx[i] / g.dyv[j];
-        s += a * phi[k - nx];
+        s += a * phi[j > 0 ? k - nx : k + top];
         d += a;
     }
     const double Aphi = s - d * phi[k];

@@ -143,7 +143,10 @@ const char* validate(const ibm_params* P, const double* xf, const double* yf) {
     if (!P) return "params is NULL";
     if (P->nx < 8 || P->ny < 8 || (P->nx & 1) || (P->ny & 1)) return "nx and ny must be even and >= 8";
     if ((int64_t)(P->nx + 1) * (P->ny + 1) > (int64_t)1 << 30) return "grid too large";
-    if (P->bc_mode != IBM_BC_CHANNEL) return "only IBM_BC_CHANNEL is supported";
+    if (P->bc_mode != IBM_BC_CHANNEL && P->bc_mode != IBM_BC_PERIODIC) return "unknown bc_mode";
+    if (P->bc_mode == IBM_BC_PERIODIC &&
+        (P->body || P->p_method == IBM_SOLVER_RBSOR_MP || P->p_init == IBM_INIT_LEARNED))
+        return "periodic mode takes no body, no mixed-precision sweeps and no learned guess";
     if (P->precision != IBM_PREC_FP64 || P->reserved != 0) return "unsupported precision";
     if (!(P->dt > 0.0) || !(P->re > 0.0) || !std::isfinite(P->u_inf)) return "dt and re must be > 0";
     if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG && P->p_method != IBM_SOLVER_RBSOR_MP)
@@ -458,7 +461,10 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     const int max_e = fixed_mode ? fixed : max_iter;
     const int nbr = red_blocks((size_t)c->nh * c->ny);
     TbShape ts;
-    const bool use_tb = c->sor_kernel != IBM_SOR_PER_COLOUR && tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts);
+    // the blocked sweeps treat the domain edge as the end of the grid: periodic
+    // mode sweeps colour by colour
+    const bool use_tb = !c->g.per && c->sor_kernel != IBM_SOR_PER_COLOUR &&
+                        tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts);
     auto* tb_kernel = c->sor_kernel == IBM_SOR_TEMPORAL_LDS ? k_sor_tb : k_sor_tbr;
     const int S = c->tb_sweeps;
     const int ntiles = use_tb ? ts.ntx * ts.nty : 0;
@@ -864,7 +870,8 @@ int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
     double* x = comp == 0 ? c->u : c->v;
     const double* rhs = comp == 0 ? c->ru : c->rv;
     const dim3 gs = grid2(c->nh, c->ny + 1), bl(kBlock);
-    const size_t nunk = comp == 0 ? (size_t)(c->nx - 1) * c->ny : (size_t)c->nx * (c->ny - 1);
+    const size_t nunk = c->g.per ? (size_t)c->nx * c->ny
+                                 : comp == 0 ? (size_t)(c->nx - 1) * c->ny : (size_t)c->nx * (c->ny - 1);
     const int nb = red_blocks(nunk);
     const double omega = c->P.uv_omega, tol = c->P.uv_tol;
     const int max_e = c->P.uv_max_iter;
@@ -1036,7 +1043,42 @@ int32_t warm_start(ibm_ctx* c, const Body& B) {
 // iterations, or when the snapshot is taken snap_iter iterations into the
 // solve (then PCG finishes the solve for the snapshot's target).  Every
 // segment ends on SOR's own stop test, so the last one decides convergence.
+// Periodic (singular) mode: with rhs = 1, V b (natural layout) is made to
+// sum to zero; with rhs = 0, x is shifted to zero volume-weighted mean.
+// Nothing in channel mode.
+int32_t per_project(ibm_ctx* c, double* a, int rhs) {
+    if (!c->g.per) return IBM_OK;
+    const int nb = red_blocks((size_t)c->nx * c->ny);
+    hipLaunchKernelGGL(k_per_sums, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, (const double*)a, rhs ? 0 : 1,
+                       c->partials);
+    hipLaunchKernelGGL(k_per_shift, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, a, (const double*)c->partials,
+                       nb, rhs);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+// Periodic mode: u face nx and v row ny take the values of face 0 and row 0.
+int32_t sync_periodic(ibm_ctx* c) {
+    if (!c->g.per) return IBM_OK;
+    const int n = std::max(c->nx, c->ny);
+    hipLaunchKernelGGL(k_sync_periodic, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->nx, c->ny, c->u, c->v);
+    LAUNCH_CHECK();
+    return IBM_OK;
+}
+
+int32_t pressure_solve_body(ibm_ctx* c, const Body& B, int fixed, LoopOut* out);
+
+// The pressure solve of a step; periodic mode solves the singular problem on
+// the zero-sum part of V b and returns the zero-mean solution.
 int32_t pressure_solve(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
+    int32_t rc = per_project(c, c->vb, 1);
+    if (rc) return rc;
+    rc = pressure_solve_body(c, B, fixed, out);
+    if (rc) return rc;
+    return out->status == kStNan ? IBM_OK : per_project(c, c->phi, 0);
+}
+
+int32_t pressure_solve_body(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
     const ibm_params& P = c->P;
     if (P.p_method == IBM_SOLVER_PCG) {
         int32_t rc = pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out);
@@ -1155,8 +1197,9 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
                        (const double*)c->v, c->ru, c->rv, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
                        (const int*)c->list_u, (const int*)c->list_v, (const int*)c->counts, c->f_u, c->f_v, dt, beta,
                        P.alpha_max, qn, c->coef);
-    hipLaunchKernelGGL(k_outlet_commit, dim3((ny + 255) / 256), dim3(256), 0, c->stream, nx, ny, c->u,
-                       (const double*)c->ru);
+    if (!c->g.per)
+        hipLaunchKernelGGL(k_outlet_commit, dim3((ny + 255) / 256), dim3(256), 0, c->stream, nx, ny, c->u,
+                           (const double*)c->ru);
     LAUNCH_CHECK();
     c->have_hist = 1;
 
@@ -1165,6 +1208,8 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     int32_t rc = helm_loop(c, 0, beta, &hu);
     if (rc) return rc;
     rc = helm_loop(c, 1, beta, &hv);
+    if (rc) return rc;
+    rc = sync_periodic(c);
     if (rc) return rc;
     st->u_iters = hu.iters;
     st->v_iters = hv.iters;
@@ -1215,6 +1260,8 @@ int32_t step_post(ibm_ctx* c, ibm_step_stats* st, const LoopOut& po, int status)
     hipLaunchKernelGGL(k_project_v, grid2(nx, ny + 1), bl, 0, c->stream, c->g, c->v, (const double*)c->phi, dt);
     hipLaunchKernelGGL(k_update_p, grid2(nx, ny), bl, 0, c->stream, c->g, c->p, (const double*)c->phi, beta);
     LAUNCH_CHECK();
+    int32_t rc = sync_periodic(c);
+    if (rc) return rc;
 
     // statistics of the step
     HIP_TRY(hipMemcpyAsync(c->hstage, c->coef, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1260,37 +1307,43 @@ void host_metrics(const ibm_params& P, const double* xf, const double* yf, std::
     for (int j = 0; j < ny; ++j) { dy[j] = yf[j + 1] - yf[j]; yc[j] = 0.5 * (yf[j] + yf[j + 1]); }
     for (int i = 1; i < nx; ++i) dxu[i] = xc[i] - xc[i - 1];
     for (int j = 1; j < ny; ++j) dyv[j] = yc[j] - yc[j - 1];
-    dxu[0] = 0.5 * dx[0];
-    dxu[nx] = 0.5 * dx[nx - 1];
-    dyv[0] = 0.5 * dy[0];
-    dyv[ny] = 0.5 * dy[ny - 1];
+    const bool per = P.bc_mode == IBM_BC_PERIODIC;
+    if (per) {  // the two ends are neighbours
+        dxu[0] = dxu[nx] = 0.5 * (dx[nx - 1] + dx[0]);
+        dyv[0] = dyv[ny] = 0.5 * (dy[ny - 1] + dy[0]);
+    } else {    // half cells at the ends
+        dxu[0] = 0.5 * dx[0];
+        dxu[nx] = 0.5 * dx[nx - 1];
+        dyv[0] = 0.5 * dy[0];
+        dyv[ny] = 0.5 * dy[ny - 1];
+    }
     std::vector<double> pcE(nx, 0.0), pcW(nx, 0.0), pcD(nx, 0.0), pcN(ny, 0.0), pcS(ny, 0.0);
     for (int i = 0; i < nx; ++i) {
-        if (i < nx - 1) pcE[i] = 1.0 / dxu[i + 1];
-        if (i > 0) pcW[i] = 1.0 / dxu[i];
-        if (i == nx - 1) pcD[i] = 1.0 / dxu[nx];
+        if (per || i < nx - 1) pcE[i] = 1.0 / dxu[i + 1];
+        if (per || i > 0) pcW[i] = 1.0 / dxu[i];
+        if (!per && i == nx - 1) pcD[i] = 1.0 / dxu[nx];
     }
     for (int j = 0; j < ny; ++j) {
-        if (j < ny - 1) pcN[j] = 1.0 / dyv[j + 1];
-        if (j > 0) pcS[j] = 1.0 / dyv[j];
+        if (per || j < ny - 1) pcN[j] = 1.0 / dyv[j + 1];
+        if (per || j > 0) pcS[j] = 1.0 / dyv[j];
     }
     std::vector<double> uce(nx + 1, 0.0), ucw(nx + 1, 0.0), ucn(ny, 0.0), ucs(ny, 0.0);
-    for (int i = 1; i < nx; ++i) {
+    for (int i = per ? 0 : 1; i < nx; ++i) {
         uce[i] = 1.0 / (dx[i] * dxu[i]);
-        ucw[i] = 1.0 / (dx[i - 1] * dxu[i]);
+        ucw[i] = 1.0 / (dx[i > 0 ? i - 1 : nx - 1] * dxu[i]);
     }
     for (int j = 0; j < ny; ++j) {
-        if (j < ny - 1) ucn[j] = 1.0 / (dyv[j + 1] * dy[j]);
-        if (j > 0) ucs[j] = 1.0 / (dyv[j] * dy[j]);
+        if (per || j < ny - 1) ucn[j] = 1.0 / (dyv[j + 1] * dy[j]);
+        if (per || j > 0) ucs[j] = 1.0 / (dyv[j] * dy[j]);
     }
     std::vector<double> vce(nx, 0.0), vcw(nx, 0.0), vcn(ny + 1, 0.0), vcs(ny + 1, 0.0);
     for (int i = 0; i < nx; ++i) {
-        if (i < nx - 1) vce[i] = 1.0 / (dxu[i + 1] * dx[i]);
+        if (per || i < nx - 1) vce[i] = 1.0 / (dxu[i + 1] * dx[i]);
         vcw[i] = 1.0 / (dxu[i] * dx[i]);
     }
-    for (int j = 1; j < ny; ++j) {
+    for (int j = per ? 0 : 1; j < ny; ++j) {
         vcn[j] = 1.0 / (dy[j] * dyv[j]);
-        vcs[j] = 1.0 / (dy[j - 1] * dyv[j]);
+        vcs[j] = 1.0 / (dy[j > 0 ? j - 1 : ny - 1] * dyv[j]);
     }
     A = {std::vector<double>(xf, xf + nx + 1), std::vector<double>(yf, yf + ny + 1), dx, dy, xc, yc, dxu, dyv,
          pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs};
@@ -1767,13 +1820,22 @@ int32_t split_sor_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, const 
     hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)x_dev, c->phr, c->phb, 0);
     hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
     LAUNCH_CHECK();
-    int32_t rc = o->method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo)
-                                                  : sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo);
+    int32_t rc;
+    if (c->g.per) {  // singular: the zero-sum part of V rhs (natural layout in vb)
+        hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->vbr, (const double*)c->vbb, c->vb);
+        LAUNCH_CHECK();
+        rc = per_project(c, c->vb, 1);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, (const double*)c->vb, c->vbr, c->vbb, 0);
+        LAUNCH_CHECK();
+    }
+    rc = o->method == IBM_SOLVER_RBSOR_MP ? mp_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo)
+                                          : sor_loop(c, o->omega, o->tol, o->max_iter, o->check_every, fixed, lo);
     if (rc) return rc;
     if (lo->zero_rhs) return fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
     hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->phr, (const double*)c->phb, x_dev);
     LAUNCH_CHECK();
-    return IBM_OK;
+    return lo->status == kStNan ? IBM_OK : per_project(c, x_dev, 0);
 }
 
 // Statistics of a stand-alone solve (GPU time between the context's t0 and
@@ -1821,7 +1883,7 @@ int32_t ibm_batch_create(int32_t n, ibm_ctx* const* ctxs, ibm_batch** out) {
                                 c->P.p_method == IBM_SOLVER_RBSOR_MP);
         if (c->stream != ctxs[0]->stream || !method_ok ||
             c->tb_sweeps != ctxs[0]->tb_sweeps || c->P.p_check_every != ctxs[0]->P.p_check_every ||
-            (c->net && c->net_every > 0) || c->snap_feat)
+            (c->net && c->net_every > 0) || c->snap_feat || c->g.per)
             return IBM_ERR_INVALID;
         TbShape ts;
         if (!tb_shape(c, c->tb_sweeps, c->tb_tx, c->tb_ty, &ts) || ts.ntx * ts.nty > kFoldMax) return IBM_ERR_INVALID;
@@ -2046,6 +2108,7 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     auto D = [&](size_t o) { return (double*)(w + o); };
     Grid& g = c->g;
     g.nx = nx; g.ny = ny; g.nh = c->nh;
+    g.per = prm->bc_mode == IBM_BC_PERIODIC ? 1 : 0;
     g.xf = D(off.xf); g.yf = D(off.yf); g.dx = D(off.dx); g.dy = D(off.dy); g.xc = D(off.xc); g.yc = D(off.yc);
     g.dxu = D(off.dxu); g.dyv = D(off.dyv);
     g.pcE = D(off.pcE); g.pcW = D(off.pcW); g.pcD = D(off.pcD); g.pcN = D(off.pcN); g.pcS = D(off.pcS);
@@ -2098,10 +2161,15 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     for (size_t k = 0; k < NU; ++k) hu[k] = u0 ? u0[k] : prm->u_inf;
     for (size_t k = 0; k < NV; ++k) hv[k] = v0 ? v0[k] : 0.0;
     for (size_t k = 0; k < NC; ++k) hp[k] = p0 ? p0[k] : 0.0;
-    for (int j = 0; j < ny; ++j) hu[(size_t)j * (nx + 1)] = prm->u_inf;
-    for (int i = 0; i < nx; ++i) {
-        hv[i] = 0.0;
-        hv[(size_t)ny * nx + i] = 0.0;
+    if (g.per) {  // face nx and face row ny mirror face 0 and row 0
+        for (int j = 0; j < ny; ++j) hu[(size_t)j * (nx + 1) + nx] = hu[(size_t)j * (nx + 1)];
+        for (int i = 0; i < nx; ++i) hv[(size_t)ny * nx + i] = hv[i];
+    } else {      // inflow u and wall v
+        for (int j = 0; j < ny; ++j) hu[(size_t)j * (nx + 1)] = prm->u_inf;
+        for (int i = 0; i < nx; ++i) {
+            hv[i] = 0.0;
+            hv[(size_t)ny * nx + i] = 0.0;
+        }
     }
     if (hipMemcpyAsync(c->u, hu.data(), NU * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->v, hv.data(), NV * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
@@ -2165,7 +2233,8 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
     if (!c) return IBM_ERR_INVALID;
     if (!rhs_dev || !x_dev || !o || o->max_iter < 1 || o->check_every < 1 || o->fixed_iters < 0 ||
         (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG && o->method != IBM_SOLVER_RBSOR_MP) ||
-        (o->method != IBM_SOLVER_PCG && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol)) {
+        (o->method != IBM_SOLVER_PCG && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol) ||
+        (c->g.per && o->method == IBM_SOLVER_RBSOR_MP)) {
         c->err = "invalid solve options";
         return IBM_ERR_INVALID;
     }
@@ -2181,10 +2250,15 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
         hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
         hipLaunchKernelGGL(k_merge, gr, bl, 0, c->stream, c->g, (const double*)c->vbr, (const double*)c->vbb, c->vb);
         LAUNCH_CHECK();
+        rc = per_project(c, c->vb, 1);
+        if (rc) return rc;
         rc = pcg_loop(c, x_dev, c->vb, o->tol, o->max_iter, fixed, &lo);
         if (rc) return rc;
         if (lo.zero_rhs) {
             rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
+            if (rc) return rc;
+        } else if (lo.status != kStNan) {
+            rc = per_project(c, x_dev, 0);
             if (rc) return rc;
         }
     } else {
@@ -2365,6 +2439,10 @@ int32_t ibm_set_warm_start(ibm_ctx* c, ibm_unet* net, double out_scale) {
     if (!net) {
         c->net = nullptr;
         return IBM_OK;
+    }
+    if (c->g.per) {
+        c->err = "periodic mode takes no learned guess or correction";
+        return IBM_ERR_INVALID;
     }
     int mb, h, w;
     ibm::unet::net_shape(net, &mb, &h, &w);

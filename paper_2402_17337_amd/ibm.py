@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibm_hip.so")
 
 OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, -5
-BC_CHANNEL = 0
+BC_CHANNEL, BC_PERIODIC = 0, 1
 RBSOR, PCG, RBSOR_MP = 0, 1, 2   # RBSOR_MP: float sweeps on the correction, double refinement
 INIT_ZERO, INIT_PREVIOUS, INIT_LEARNED = 0, 1, 2
 (KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB, KERNEL_SOR_MP,

@@ -79,7 +79,9 @@ def test_status_strings():
     dict(dt=0.0), dict(re=-1.0),
     dict(p_omega=2.0), dict(uv_omega=0.0),
     dict(p_max_iter=0), dict(p_check=0),
-    dict(bc=1),                         # periodic is not part of this library
+    dict(bc=1),                         # periodic mode takes no body
+    dict(bc=1, body=0, p_method=2),     # ... and no mixed-precision sweeps
+    dict(bc=2),                         # unknown boundary mode
     dict(y0=0.1),                       # body outside the interior
     dict(amp=5.9),                      # plunge range leaves the domain
     dict(p_method=7),
