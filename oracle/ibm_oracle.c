@@ -73,6 +73,8 @@
 #define ORC_SOR 0
 #define ORC_PCG 1
 #define ORC_SOR_MP 2
+#define ORC_CG1 3     /* Jacobi-PCG with one reduction per iteration */
+#define ORC_PCG_MP 4  /* single-precision CG on the correction, double refinement */
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -97,6 +99,7 @@ typedef struct {
     double uv_omega, uv_tol;
     int32_t uv_max_iter, q_mode;
     double alpha_max;
+    double p_inner_tol;  /* ORC_PCG_MP: relative residual of each inner solve */
 } orc_params;
 
 typedef struct {
@@ -119,7 +122,7 @@ typedef struct orc_ctx {
     int have_hist;
     double *ru, *rv, *ut, *vt, *fu, *fv, *nwu, *nwv;
     unsigned char *flu, *flv, *msrc;
-    double *vb, *w0, *w1, *w2, *w3, *w4;
+    double *vb, *w0, *w1, *w2, *w3, *w4, *w5, *w6;
     long step;
     double t, cd, cl;
 } orc_ctx;
@@ -450,13 +453,217 @@ static int poisson_pcg(const orc_ctx *c, const double *vb, double *x, double tol
     return ORC_NOT_CONVERGED;
 }
 
+/* y = M x = -A x for the Jacobi-PCG solvers. */
+static void apply_M(const orc_ctx *c, const double *x, double *y) {
+    const size_t n = (size_t)c->nx * c->ny;
+    orc_apply_A(c, x, y);
+    for (size_t k = 0; k < n; ++k) y[k] = -y[k];
+}
+
+/* Jacobi-preconditioned CG on M x = -vb (M = -A) in the form with one
+ * reduction per iteration (Chronopoulos and Gear, 1989): besides the
+ * direction p it carries s = M p by its own recurrence, so the two inner
+ * products of an iteration, gamma = (r, u) and delta = (M u, u) with
+ * u = D^-1 r, are taken together:
+ *   beta_i = gamma_i / gamma_{i-1},
+ *   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+ *   p_i = u_i + beta_i p_{i-1},  s_i = M u_i + beta_i s_{i-1},
+ *   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i.
+ * In exact arithmetic its iterates are those of poisson_pcg.  Stop test and
+ * confirmation as there: the recursive residual, then the true one (on a
+ * failed confirmation the recurrences restart from it). */
+static int poisson_cg1(const orc_ctx *c, const double *vb, double *x, double tol, int max_iter, int fixed,
+                       orc_solve_stats *st) {
+    const int nx = c->nx, ny = c->ny;
+    const size_t n = (size_t)nx * ny;
+    double *r = c->w0, *u = c->w1, *w = c->w2, *pp = c->w3, *ss = c->w4, *dg = c->w5, *q = c->w6;
+    double bn = sqrt(sumsq(vb, n));
+    st->iters = 0; st->r0_rel = 0.0; st->rel = 0.0; st->status = ORC_OK;
+    if (!isfinite(bn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+    if (bn == 0.0) { memset(x, 0, n * sizeof(double)); return ORC_OK; }
+    if (fixed > 0) { max_iter = fixed; tol = -1.0; }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) { double d; A_row(c, x, i, j, &d); dg[ic(c, i, j)] = d; }
+    orc_apply_A(c, x, q);
+    for (size_t k = 0; k < n; ++k) r[k] = -vb[k] + q[k];
+    double rn = sqrt(sumsq(r, n));
+    st->r0_rel = rn / bn; st->rel = rn / bn;
+    if (!isfinite(rn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+    if (rn <= tol * bn) return ORC_OK;
+    int it = 0, start = 1;
+    double gamma_old = 0.0, alpha = 0.0;
+    for (;;) {
+        /* u = D^-1 r, w = M u, gamma, delta; then the new direction */
+        for (size_t k = 0; k < n; ++k) u[k] = r[k] / dg[k];
+        apply_M(c, u, w);
+        double gamma = dot(r, u, n), delta = dot(w, u, n);
+        if (start) {
+            alpha = gamma / delta;
+            for (size_t k = 0; k < n; ++k) { pp[k] = u[k]; ss[k] = w[k]; }
+            start = 0;
+        } else {
+            double beta = gamma / gamma_old;
+            alpha = gamma / (delta - beta * gamma / alpha);
+            for (size_t k = 0; k < n; ++k) { pp[k] = u[k] + beta * pp[k]; ss[k] = w[k] + beta * ss[k]; }
+        }
+        gamma_old = gamma;
+        if (it >= max_iter) break;
+        for (size_t k = 0; k < n; ++k) { x[k] += alpha * pp[k]; r[k] -= alpha * ss[k]; }
+        ++it;
+        rn = sqrt(sumsq(r, n));
+        st->iters = it; st->rel = rn / bn;
+        if (!isfinite(rn)) { st->status = ORC_ERR_NAN; return ORC_ERR_NAN; }
+        if (rn <= tol * bn) {
+            orc_apply_A(c, x, q);
+            for (size_t k = 0; k < n; ++k) r[k] = -vb[k] + q[k];
+            rn = sqrt(sumsq(r, n));
+            st->rel = rn / bn;
+            if (rn <= tol * bn) return ORC_OK;
+            start = 1;  /* restart from the true residual */
+        }
+    }
+    if (fixed > 0) {
+        orc_apply_A(c, x, q);
+        for (size_t k = 0; k < n; ++k) r[k] = -vb[k] + q[k];
+        st->rel = sqrt(sumsq(r, n)) / bn;
+        return ORC_OK;
+    }
+    st->status = ORC_NOT_CONVERGED;
+    return ORC_NOT_CONVERGED;
+}
+
+/* y = M x in single precision: M = -A with the coefficients of A rounded to
+ * float, summed in the order E, W, N, S (outlet term with E), float
+ * arithmetic throughout. */
+static void apply_M_f32(const orc_ctx *c, const float *x, float *y) {
+    const int nx = c->nx, ny = c->ny;
+#pragma omp parallel for schedule(static) if (c->nx * c->ny >= ORC_OMP_MIN_CELLS)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            float s = 0.0f, d = 0.0f, a;
+            if (i < nx - 1) { a = (float)(c->dy[j] / c->dxu[i + 1]); s += a * x[ic(c, i + 1, j)]; d += a; }
+            else { d += (float)(c->dy[j] / c->dxu[nx]); }
+            if (i > 0) { a = (float)(c->dy[j] / c->dxu[i]); s += a * x[ic(c, i - 1, j)]; d += a; }
+            if (j < ny - 1) { a = (float)(c->dx[i] / c->dyv[j + 1]); s += a * x[ic(c, i, j + 1)]; d += a; }
+            if (j > 0) { a = (float)(c->dx[i] / c->dyv[j]); s += a * x[ic(c, i, j - 1)]; d += a; }
+            y[ic(c, i, j)] = d * x[ic(c, i, j)] - s;
+        }
+}
+/* Diagonal of the single-precision M. */
+static void diag_M_f32(const orc_ctx *c, float *d) {
+    const int nx = c->nx, ny = c->ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            float dd = 0.0f;
+            if (i < nx - 1) dd += (float)(c->dy[j] / c->dxu[i + 1]);
+            else dd += (float)(c->dy[j] / c->dxu[nx]);
+            if (i > 0) dd += (float)(c->dy[j] / c->dxu[i]);
+            if (j < ny - 1) dd += (float)(c->dx[i] / c->dyv[j + 1]);
+            if (j > 0) dd += (float)(c->dx[i] / c->dyv[j]);
+            d[ic(c, i, j)] = dd;
+        }
+}
+/* Inner product of two float vectors: every product exactly in double
+ * (a float times a float fits), summed in double. */
+static double dot_f32(const float *a, const float *b, size_t n) {
+    double s = 0.0, comp = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+        double x = (double)a[k] * (double)b[k];
+        double t = s + x;
+        if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+        else comp += (x - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+/* Mixed precision Jacobi-PCG: iterative refinement in double around an inner
+ * single-precision CG.  Each cycle takes the double residual r = vb - A x of
+ * the current x, solves the correction equation M e = -r (M = -A) by the
+ * one-reduction CG of poisson_cg1 in single precision (vectors and operator
+ * in float, inner products in double, the scalars rounded to float for the
+ * vector updates) from e = 0 until its recursive residual falls to
+ * inner_tol times its initial one or the cycle reaches `cap` iterations, then
+ * x += e in double and the residual and stop test are evaluated in double.
+ * Iterations count inner CG iterations.  refine = 0 runs a single inner
+ * solve of max_iter iterations and adds its correction (the stall of
+ * single-precision CG that the refinement removes). */
+static int poisson_pcg_mp(const orc_ctx *c, const double *vb, double *x, double tol, int max_iter, int cap,
+                          double inner_tol, int refine, orc_solve_stats *st) {
+    const size_t n = (size_t)c->nx * c->ny;
+    double *r = c->w0;
+    float *fr = calloc(n, sizeof(float)), *fu = calloc(n, sizeof(float)), *fw = calloc(n, sizeof(float));
+    float *fp = calloc(n, sizeof(float)), *fs = calloc(n, sizeof(float)), *fe = calloc(n, sizeof(float));
+    float *fd = calloc(n, sizeof(float));
+    int rc = ORC_OK;
+    double bn = sqrt(sumsq(vb, n));
+    st->iters = 0; st->r0_rel = 0.0; st->rel = 0.0; st->status = ORC_OK;
+    if (!fr || !fu || !fw || !fp || !fs || !fe || !fd) { rc = ORC_ERR_INVALID; goto out; }
+    if (!isfinite(bn)) { st->status = rc = ORC_ERR_NAN; goto out; }
+    if (bn == 0.0) { memset(x, 0, n * sizeof(double)); goto out; }
+    if (cap < 1) cap = max_iter;
+    diag_M_f32(c, fd);
+    double rn = poisson_resid_norm(c, x, vb, r);
+    st->r0_rel = rn / bn; st->rel = rn / bn;
+    if (!isfinite(rn)) { st->status = rc = ORC_ERR_NAN; goto out; }
+    int it = 0;
+    if (refine && rn <= tol * bn) goto out;
+    while (it < max_iter) {
+        /* inner solve of M e = -r from e = 0: its residual starts at -r */
+        const int lim = refine ? (cap < max_iter - it ? cap : max_iter - it) : max_iter;
+        for (size_t k = 0; k < n; ++k) { fr[k] = (float)(-r[k]); fe[k] = 0.0f; }
+        const double r0in = sqrt(dot_f32(fr, fr, n));
+        double gamma_old = 0.0, alpha = 0.0;
+        int start = 1, k_in = 0;
+        for (;;) {
+            for (size_t k = 0; k < n; ++k) fu[k] = fr[k] / fd[k];
+            apply_M_f32(c, fu, fw);
+            double gamma = dot_f32(fr, fu, n), delta = dot_f32(fw, fu, n);
+            if (start) {
+                alpha = gamma / delta;
+                for (size_t k = 0; k < n; ++k) { fp[k] = fu[k]; fs[k] = fw[k]; }
+                start = 0;
+            } else {
+                double beta = gamma / gamma_old;
+                alpha = gamma / (delta - beta * gamma / alpha);
+                const float fb = (float)beta;
+                for (size_t k = 0; k < n; ++k) { fp[k] = fu[k] + fb * fp[k]; fs[k] = fw[k] + fb * fs[k]; }
+            }
+            gamma_old = gamma;
+            if (k_in >= lim) break;
+            const float fa = (float)alpha;
+            for (size_t k = 0; k < n; ++k) { fe[k] += fa * fp[k]; fr[k] -= fa * fs[k]; }
+            ++k_in;
+            double rin = sqrt(dot_f32(fr, fr, n));
+            if (!isfinite(rin)) break;
+            if (refine && rin <= inner_tol * r0in) break;
+        }
+        for (size_t k = 0; k < n; ++k) x[k] += (double)fe[k];
+        it += k_in;
+        rn = poisson_resid_norm(c, x, vb, r);
+        st->iters = it; st->rel = rn / bn;
+        if (!isfinite(rn)) { st->status = rc = ORC_ERR_NAN; goto out; }
+        if (!refine || rn <= tol * bn) goto out;
+        if (k_in == 0) break;
+    }
+    st->status = rc = ORC_NOT_CONVERGED;
+out:
+    free(fr); free(fu); free(fw); free(fp); free(fs); free(fe); free(fd);
+    return rc;
+}
+
 static int poisson_solve_vb(orc_ctx *c, double *vb, double *x, int method, double omega, double tol,
                             int max_iter, int check, int fixed, orc_solve_stats *st) {
     int rc;
-    if (method == ORC_SOR_MP && c->per) return ORC_ERR_INVALID;  /* channel operator only */
+    if ((method == ORC_SOR_MP || method == ORC_PCG_MP) && c->per) return ORC_ERR_INVALID;  /* channel only */
     if (c->per) periodic_project_rhs(c, vb);
     if (method == ORC_PCG) rc = poisson_pcg(c, vb, x, tol, max_iter, fixed, st);
     else if (method == ORC_SOR_MP) rc = poisson_sor_mp(c, vb, x, omega, tol, max_iter, check, fixed, 1, st);
+    else if (method == ORC_CG1) rc = poisson_cg1(c, vb, x, tol, max_iter, fixed, st);
+    else if (method == ORC_PCG_MP) {
+        if (fixed > 0) return ORC_ERR_INVALID;
+        rc = poisson_pcg_mp(c, vb, x, tol, max_iter, check, c->P.p_inner_tol, 1, st);
+    }
     else rc = poisson_sor(c, vb, x, omega, tol, max_iter, check, fixed, st);
     if (c->per && rc >= 0) periodic_zero_mean(c, x);
     return rc;
@@ -483,6 +690,17 @@ int orc_poisson_sor_f32(orc_ctx *c, const double *b, double *x, double omega, in
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * b[ic(c, i, j)];
     return poisson_sor_mp(c, vb, x, omega, -1.0, iters, iters, iters, 0, st);
+}
+
+/* Single-precision CG without refinement: one inner solve of `iters`
+ * iterations on the correction of x, then x += e. */
+int orc_poisson_pcg_f32(orc_ctx *c, const double *b, double *x, int iters, orc_solve_stats *st) {
+    const int nx = c->nx, ny = c->ny;
+    double *vb = c->vb;
+    if (c->per || iters < 1) return ORC_ERR_INVALID;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * b[ic(c, i, j)];
+    return poisson_pcg_mp(c, vb, x, -1.0, iters, iters, 0.0, 0, st);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1012,7 +1230,7 @@ void orc_destroy(orc_ctx *c) {
     if (!c) return;
     double *ds[] = {c->xf, c->yf, c->dx, c->dy, c->xc, c->yc, c->dxu, c->dyv, c->u, c->v, c->p, c->phi,
                     c->nu, c->nv, c->ru, c->rv, c->ut, c->vt, c->fu, c->fv, c->nwu, c->nwv, c->vb, c->w0,
-                    c->w1, c->w2, c->w3, c->w4};
+                    c->w1, c->w2, c->w3, c->w4, c->w5, c->w6};
     for (size_t k = 0; k < sizeof(ds) / sizeof(ds[0]); ++k) free(ds[k]);
     free(c->flu); free(c->flv); free(c->msrc);
     free(c);
@@ -1052,6 +1270,7 @@ int orc_create(const orc_params *P, const double *xf, const double *yf, const do
     c->w0 = xalloc(sizeof(double) * nw); c->w1 = xalloc(sizeof(double) * nw);
     c->w2 = xalloc(sizeof(double) * nw); c->w3 = xalloc(sizeof(double) * nw);
     c->w4 = xalloc(sizeof(double) * nw);
+    c->w5 = xalloc(sizeof(double) * nw); c->w6 = xalloc(sizeof(double) * nw);
     c->flu = xalloc(nu); c->flv = xalloc(nv); c->msrc = xalloc(nc);
 
     memcpy(c->xf, xf, sizeof(double) * (nx + 1));

@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "libibm_oracle.so")
 
 CHANNEL, PERIODIC = 0, 1
 SOR, PCG, SOR_MP = 0, 1, 2   # SOR_MP: single-precision sweeps, double-precision refinement
+CG1, PCG_MP = 3, 4           # CG1: one reduction per iteration; PCG_MP: float inner CG, double refinement
 OK, NOT_CONVERGED, ERR_INVALID, ERR_NAN = 0, 1, -1, -5
 
 
@@ -53,6 +54,7 @@ class Params(C.Structure):
         ("uv_omega", C.c_double), ("uv_tol", C.c_double),
         ("uv_max_iter", C.c_int32), ("q_mode", C.c_int32),
         ("alpha_max", C.c_double),
+        ("p_inner_tol", C.c_double),
     ]
 
 
@@ -92,6 +94,8 @@ def lib():
         L.orc_poisson_solve.restype = C.c_int
         L.orc_poisson_sor_f32.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_int, C.POINTER(SolveStats)]
         L.orc_poisson_sor_f32.restype = C.c_int
+        L.orc_poisson_pcg_f32.argtypes = [C.c_void_p, dp, dp, C.c_int, C.POINTER(SolveStats)]
+        L.orc_poisson_pcg_f32.restype = C.c_int
         L.orc_momentum_terms.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp]
         L.orc_divergence.argtypes = [C.c_void_p, dp]
         ub = C.POINTER(C.c_ubyte)
@@ -135,7 +139,7 @@ DEFAULTS = dict(bc=CHANNEL, body=1, re=100.0, dt=1e-3, uinf=1.0, chord=1.0, thic
                 x0=4.0, y0=6.0, amp=0.0, freq=0.0, phase=0.0,
                 p_method=SOR, p_max_iter=2_000_000, p_check=10, p_init_prev=1,
                 p_omega=1.8, p_tol=1e-8, uv_omega=1.0, uv_tol=1e-10, uv_max_iter=200,
-                q_mode=1, alpha_max=1.0)
+                q_mode=1, alpha_max=1.0, p_inner_tol=1e-4)
 
 
 def make_params(nx: int, ny: int, **kw) -> Params:
@@ -241,6 +245,17 @@ class Oracle:
              else np.array(x0, dtype=np.float64, copy=True).reshape(self.ny, self.nx))
         st = SolveStats()
         rc = lib().orc_poisson_sor_f32(self._h, _dp(b), _dp(x), omega, iters, C.byref(st))
+        return x, {"iters": st.iters, "r0_rel": st.r0_rel, "rel": st.rel, "status": st.status}, rc
+
+    def poisson_pcg_f32(self, b, x0=None, iters=1000):
+        """Single-precision one-reduction CG on the correction of x without
+        refinement (iters float iterations, then x += e); returns (x, stats
+        dict, status)."""
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(self.ny, self.nx)
+        x = (np.zeros_like(b) if x0 is None
+             else np.array(x0, dtype=np.float64, copy=True).reshape(self.ny, self.nx))
+        st = SolveStats()
+        rc = lib().orc_poisson_pcg_f32(self._h, _dp(b), _dp(x), iters, C.byref(st))
         return x, {"iters": st.iters, "r0_rel": st.r0_rel, "rel": st.rel, "status": st.status}, rc
 
     def momentum_terms(self):
