@@ -29,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s per time step + Poisson cell-updates/s at 1024x768; learned/FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 compute units x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic FLOPs of one red-black SOR cell update: the four neighbour
+# products and their sum (7), minus V b (1), times 1/d (1), the relaxation
+# (1 - omega) x + omega g (3)
+SOR_FLOP_PER_UPDATE = 12.0
 BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak of the MI355X
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_17337_amd", "csrc", f)
@@ -43,9 +49,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload_tag: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken with the current kernel sources; else None."""
+def read_counters(kernel: str, workload_tag: str):
+    """key = value lines of the committed rocprofv3 counter summary of a
+    kernel (HBM bytes per launch, VALU busy fraction, ...), if it was taken
+    with the current kernel sources; else None."""
     path = os.path.join(PROFILES, f"{kernel}_{workload_tag}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -58,10 +65,18 @@ def read_traffic(kernel: str, workload_tag: str):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_digest():
         return None
+    return vals
+
+
+def _counter(vals, key):
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key]) if vals is not None else None
     except (KeyError, ValueError):
         return None
+
+
+def _round_phases(ph):
+    return None if ph is None else {k: round(v, 4) for k, v in ph.items()}
 
 
 def log(msg):
@@ -78,10 +93,13 @@ def build_if_missing():
 
 
 def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None, net=None, keep_fields=False,
-            check=None):
+            check=None, repeats=1):
     """Time `steps` steps after `warmup` untimed ones.  p_init overrides the
     initial guess; net = (params, out_scale, factor, every, options) attaches
-    a trained warm-start network; check overrides the stop-test interval."""
+    a trained warm-start network; check overrides the stop-test interval.
+    repeats > 1: the timed steps run that many times from the state after the
+    warm-up (restored from a checkpoint; the same iterates each time) and the
+    median run is reported (`wall`), with every run's time in `walls`."""
     import torch
     from paper_2402_17337_amd import ibm
 
@@ -107,26 +125,37 @@ def gpu_leg(case, method, steps, warmup, profile_every, max_iters=0, p_init=None
         st = g.step(1)
         if st["rc"] < 0:
             raise RuntimeError(f"warmup step failed: {st}")
-    g.profile(profile_every)
-    iters, stats = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st = g.step(1)
-        if st["rc"] < 0:
-            raise RuntimeError(f"timed step failed: {st}")
-        iters.append(st["p_iters"])
-        stats.append(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    log(f"{case['nx']}x{case['ny']} method {method} p_init {prm.get('p_init_prev')} check {prm.get('p_check', 10)} "
-        f"net {'yes' if net is not None else 'no'}: {steps} steps in {wall:.2f} s, iterations {iters}")
-    prof = {k: g.profile_query(k) for k in ibm.KERNEL_NAMES}
+    blob = g.get_state() if repeats > 1 else None
+    runs = []
+    for rep in range(repeats):
+        if rep > 0:
+            g.set_state(blob)
+        g.profile(profile_every)
+        iters, stats = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = g.step(1)
+            if st["rc"] < 0:
+                raise RuntimeError(f"timed step failed: {st}")
+            iters.append(st["p_iters"])
+            stats.append(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        log(f"{case['nx']}x{case['ny']} method {method} p_init {prm.get('p_init_prev')} "
+            f"check {prm.get('p_check', 10)} net {'yes' if net is not None else 'no'} run {rep + 1}/{repeats}: "
+            f"{steps} steps in {wall:.2f} s, iterations {iters}")
+        phases, nph = g.profile_phases() if profile_every > 0 else ({}, 0)
+        runs.append(dict(wall=wall, iters=iters, stats=stats, prof={k: g.profile_query(k) for k in ibm.KERNEL_NAMES},
+                         phases={k: v / nph for k, v in phases.items()} if nph else None))
+    med = sorted(runs, key=lambda r: r["wall"])[len(runs) // 2]
     fields = g.fields() if keep_fields else None
     g.close()
     cells = case["nx"] * case["ny"]
-    return dict(wall=wall, iters=iters, stats=stats, prof=prof, fields=fields,
-                cell_updates_per_s=cells * sum(iters) / wall if wall > 0 else 0.0)
+    wall = med["wall"]
+    return dict(wall=wall, walls=[r["wall"] for r in runs], iters=med["iters"], stats=med["stats"],
+                prof=med["prof"], phases_ms=med["phases"], fields=fields,
+                cell_updates_per_s=cells * sum(med["iters"]) / wall if wall > 0 else 0.0)
 
 
 def network_roofline(params, case, factor, reps=20):
@@ -342,6 +371,14 @@ def batch_leg(args):
 
     t_uniform, st_b = timed_batch(make({}))
     log(f"batched step of {len(cases)} cases, 104x32 tiles: {t_uniform:.3f} s")
+    # one tile shape for the whole batch, tuned on the batch itself
+    probe = ibm.Batch(make({}))
+    probe.step(1)
+    batch_shape, batch_times = probe.autotune_tiles()
+    probe.close()
+    log(f"batch-wide tile autotune: {batch_shape} from {batch_times}")
+    t_bt, st_bt = timed_batch(make({(c["nx"], c["ny"]): batch_shape for c in cases}))
+    log(f"batched step of {len(cases)} cases, batch-tuned tiles {batch_shape}: {t_bt:.3f} s")
     t_graph = None
     if args.c4_graph:
         t_graph, st_g = timed_batch(make({}), args.c4_graph)
@@ -371,8 +408,12 @@ def batch_leg(args):
         # batched (104x32 tiles) and case by case (per-size tiles; the tile
         # shape does not change the float iterates, nor the refinement's sums)
         over = dict(p_method=ibm.RBSOR_MP, p_check=args.mp_check)
-        t_mb, st_mb = timed_batch(make({}, **over))
+        bt = {(c["nx"], c["ny"]): batch_shape for c in cases}
+        t_mb, st_mb = timed_batch(make(bt, **over))
         log(f"mixed-precision batched step of {len(cases)} cases: {t_mb:.3f} s")
+        t_mbg, st_mbg = (timed_batch(make(bt, **over), args.c4_graph) if args.c4_graph else (None, None))
+        if t_mbg is not None:
+            log(f"mixed-precision batched step, graph of {args.c4_graph} intervals: {t_mbg:.3f} s")
         solo_mp = make(tuned, **over)
         for s in solo_mp:
             s.step(1)
@@ -385,10 +426,14 @@ def batch_leg(args):
             s.close()
         log(f"the same mixed-precision step case by case: {t_ms:.3f} s")
         mixed = {"check_interval": args.mp_check, "batched_s": round(t_mb, 4), "sequential_s": round(t_ms, 4),
-                 "speedup": round(t_ms / t_mb, 3),
+                 "speedup": round(t_ms / t_mb, 3), "tile": f"{batch_shape[0]}x{batch_shape[1]}",
+                 "batched_s_graph": round(t_mbg, 4) if t_mbg is not None else None,
+                 "graph_bitwise_equal_to_launched": None if t_mbg is None else all(
+                     a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"] and a["cd"] == b["cd"]
+                     for a, b in zip(st_mbg, st_mb)),
                  "bitwise_equal_to_sequential": all(a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"]
                                                     and a["cd"] == b["cd"] for a, b in zip(st_mb, st_ms))}
-    t_b = min(t for t in (t_uniform, t_tuned, t_graph) if t is not None)
+    t_b = min(t for t in (t_uniform, t_tuned, t_graph, t_bt) if t is not None)
     if mixed is not None:
         mixed["speedup_vs_f64_batch"] = round(t_b / mixed["batched_s"], 3)
     graph_same = None if t_graph is None else all(
@@ -402,6 +447,8 @@ def batch_leg(args):
             "batched_s_uniform_104x32": round(t_uniform, 4),
             "batched_s_per_size_tiles": round(t_tuned, 4) if t_tuned is not None else None,
             "batched_s_uniform_104x32_graph": round(t_graph, 4) if t_graph is not None else None,
+            "batched_s_batch_tuned": round(t_bt, 4), "batch_tuned_tile": f"{batch_shape[0]}x{batch_shape[1]}",
+            "batch_autotune_s": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in batch_times.items()},
             "graph_intervals": args.c4_graph or None,
             "graph_batch_bitwise_equal_to_launched": graph_same,
             "batched_cell_updates_per_s": round(upd / t_b, 1), "sequential_cell_updates_per_s": round(upd / t_s, 1),
@@ -409,7 +456,73 @@ def batch_leg(args):
             "per_size_batch_bitwise_equal_to_sequential": same,
             "uniform_batch_same_iterations_as_sequential": same_iters,
             "per_size_tiles": {f"{k[0]}x{k[1]}": f"{v[0]}x{v[1]}" for k, v in tuned.items()},
-            "mixed_precision": mixed}
+            "mixed_precision": mixed,
+            "uncapped": uncapped_batch(args, cases, tuned, batch_shape) if args.c4_uncapped else None}
+
+
+def uncapped_batch(args, cases, tuned, batch_shape):
+    """The many-case workload to the 1e-8 stop test, no iteration cap: every
+    case advanced two steps with Jacobi-PCG (per case), then one step with
+    FP32 sweeps and FP64 refinement every args.mp_check iterations, batched
+    (one tile shape tuned for the batch, the solve replayed from a HIP graph of
+    args.c4_graph intervals) and case by case (tiles tuned per grid size),
+    from the same states."""
+    import torch
+    from paper_2402_17337_amd import ibm
+
+    blobs = []
+    for c in cases:
+        s = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0",
+                       **dict(c["params"], p_method=ibm.PCG))
+        s.step(2)
+        blobs.append(s.get_state())
+        s.close()
+    over = dict(p_method=ibm.RBSOR_MP, p_check=args.mp_check, p_max_iter=20_000_000)
+
+    def make(shape_of):
+        out = []
+        for c, blob in zip(cases, blobs):
+            s = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], device="cuda:0", **dict(c["params"], **over))
+            tx, ty = shape_of(c)
+            s.set_option(ibm.OPT_TB_TILE_X, tx)
+            s.set_option(ibm.OPT_TB_TILE_Y, ty)
+            s.set_state(blob)
+            out.append(s)
+        return out
+
+    batch = ibm.Batch(make(lambda c: batch_shape))
+    if args.c4_graph:
+        batch.set_graph(args.c4_graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b = batch.step(1)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    batch.close()
+    log(f"uncapped mixed-precision batched step of {len(cases)} cases: {t_b:.2f} s, "
+        f"iterations {min(s['p_iters'] for s in st_b)}..{max(s['p_iters'] for s in st_b)}")
+    solo = make(lambda c: tuned.get((c["nx"], c["ny"]), (104, 32)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_s = [s.step(1) for s in solo]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    for s in solo:
+        s.close()
+    log(f"the same uncapped step case by case: {t_s:.2f} s")
+    ok = all(b["rc"] >= 0 and b["p_rel"] <= 1e-8 for b in st_b)
+    cells = [c["nx"] * c["ny"] for c in cases]
+    upd = sum(n * st["p_iters"] for n, st in zip(cells, st_b))
+    return {"workload": f"{len(cases)} plunging cases, step 3 (after two PCG steps per case), pressure solves to "
+                        f"1e-8 with no cap; FP32 sweeps + FP64 refinement every {args.mp_check} iterations",
+            "poisson_iteration_cap": None, "batched_s": round(t_b, 3), "sequential_s": round(t_s, 3),
+            "speedup": round(t_s / t_b, 3), "graph_intervals": args.c4_graph or None,
+            "tile": f"{batch_shape[0]}x{batch_shape[1]}",
+            "poisson_iters_min_max": [min(s["p_iters"] for s in st_b), max(s["p_iters"] for s in st_b)],
+            "all_converged_to_1e-8": ok,
+            "bitwise_equal_to_sequential": all(a["p_iters"] == b["p_iters"] and a["p_rel"] == b["p_rel"]
+                                               and a["cd"] == b["cd"] for a, b in zip(st_b, st_s)),
+            "batched_cell_updates_per_s": round(upd / t_b, 1)}
 
 
 def stress_leg(nx=8192, ny=6144, iters=60):
@@ -440,6 +553,110 @@ def stress_leg(nx=8192, ny=6144, iters=60):
     return out
 
 
+def c1_leg(cpu=True):
+    """The stationary 128x96 workload, all 100 steps (RB-SOR to 1e-8 every 10
+    iterations): GPU seconds for the whole run, and the oracle's (one thread:
+    a grid this small runs its loops serially) for the same run."""
+    import torch
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import workloads as W
+
+    c = W.stationary_128x96()
+    g = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0", **c["params"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [g.step(1) for _ in range(c["steps"])]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    iters = sum(s["p_iters"] for s in sts)
+    out = {"workload": c["name"] + ", all 100 steps", "gpu_s": round(wall, 4), "poisson_iters_total": iters,
+           "gpu_s_per_step": round(wall / c["steps"], 6)}
+    log(f"128x96, 100 steps on the GPU: {wall:.2f} s ({iters} Poisson iterations)")
+    if cpu:
+        from oracle import oracle as O
+        o = O.Oracle(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], **c["params"])
+        t0 = time.perf_counter()
+        rc, so = o.step(c["steps"])
+        cw = time.perf_counter() - t0
+        out.update(oracle_s=round(cw, 3), oracle_threads=1, speedup=round(cw / wall, 2),
+                   oracle_poisson_iters_total=sum(x["p_iters"] for x in so))
+        log(f"128x96, 100 steps on the oracle: {cw:.2f} s")
+    return out
+
+
+def pcg_long_leg(case, steps, method):
+    """Jacobi-PCG over a long stretch of the 1024x768 workload from t = 0
+    (the workload's full length is 2000 steps): seconds per step over the
+    run and over its last tenth."""
+    import torch
+    from paper_2402_17337_amd import ibm
+
+    g = ibm.Solver(case["nx"], case["ny"], case["xf"], case["yf"], case["u0"], case["v0"], case["p0"],
+                   device="cuda:0", **dict(case["params"], p_method=method))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks, iters = [], []
+    for k in range(steps):
+        st = g.step(1)
+        if st["rc"] < 0:
+            raise RuntimeError(f"PCG step {k} failed: {st}")
+        iters.append(st["p_iters"])
+        if (k + 1) % max(1, steps // 10) == 0:
+            torch.cuda.synchronize()
+            marks.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cd, cl = g.forces()
+    g.close()
+    log(f"1024x768 PCG, {steps} steps from t = 0: {wall:.2f} s")
+    last = (marks[-1] - marks[-2]) / max(1, steps // 10) if len(marks) >= 2 else wall / steps
+    return {"steps": steps, "solver": "one-reduction Jacobi-PCG" if method == ibm.CG1 else "Jacobi-PCG",
+            "s_per_time_step": round(wall / steps, 6),
+            "s_per_time_step_last_tenth": round(last, 6), "poisson_iters_mean": round(sum(iters) / steps, 1),
+            "poisson_iters_last": iters[-1], "cd_last": cd, "cl_last": cl}
+
+
+def scaling_leg(steps=3, warmup=2, sor_iters=2000):
+    """Input scaling at the paper's three mesh sizes (0.6, 1.2 and 1.8 M
+    cells): the plunging construction at 896x672, 1280x960 and 1536x1152,
+    seconds per step with Jacobi-PCG to 1e-8 after `warmup` steps, and the
+    red-black SOR rate (fixed iteration counts) on each grid."""
+    import torch
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import workloads as W
+
+    rows = []
+    for nx, ny in ((896, 672), (1280, 960), (1536, 1152)):
+        c = W.plunging_scaled(nx, ny)
+        g = ibm.Solver(nx, ny, c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0",
+                       **dict(c["params"], p_method=ibm.PCG))
+        for _ in range(warmup):
+            g.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [g.step(1) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gen = torch.Generator(device="cpu").manual_seed(0)
+        rhs = (torch.rand(ny, nx, generator=gen, dtype=torch.float64) - 0.5).to("cuda:0")
+        x = torch.zeros_like(rhs)
+        g.poisson_solve(rhs, x, fixed_iters=200)
+        x.zero_()
+        sor = g.poisson_solve(rhs, x, fixed_iters=sor_iters)
+        g.close()
+        cells = nx * ny
+        it = sum(s["p_iters"] for s in sts)
+        rows.append({"grid": f"{nx}x{ny}", "cells": cells, "pcg_s_per_time_step": round(wall / steps, 6),
+                     "pcg_iters_per_step": [s["p_iters"] for s in sts],
+                     "pcg_cell_updates_per_s": round(cells * it / wall, 1),
+                     "sor_cell_updates_per_s": round(cells * sor_iters / sor["seconds"], 1)})
+        log(f"scaling {nx}x{ny}: PCG {wall / steps:.4f} s per step, SOR {rows[-1]['sor_cell_updates_per_s']:.3e} "
+            f"cell-updates/s")
+    return {"workload": "plunging construction (core spacing 0.01 * 1024 / nx), Re 500, h 0.5, f 0.4; "
+                        f"steps {warmup + 1}..{warmup + steps}", "rows": rows}
+
+
 # The paper's own speedups (whole solver, 1000 steps of its plunging-ellipse
 # case on 0.6/1.2/1.8 M cells): OpenACC on one V100 against its serial C++ on
 # one Xeon Gold 6248 thread, and against OpenMP on 16 threads of that CPU.
@@ -451,13 +668,16 @@ PAPER_SPEEDUPS = {
 }
 
 
-def cpu_leg(case, target_seconds, gpu_iters_per_step):
+def cpu_leg(case, target_seconds, gpu_iters_per_step, threads=0):
     """Oracle on a bounded sample: one time step of the same workload with the
     pressure solve capped at M red-black SOR iterations (tolerance unreachable),
-    at two values of M; per-iteration and per-step costs from the difference."""
+    at two values of M; per-iteration and per-step costs from the difference.
+    threads > 0 runs the oracle on that many OpenMP threads (else all)."""
     from oracle import oracle as O
 
     prm = dict(case["params"], p_tol=1e-300)
+    if threads > 0:
+        O.set_num_threads(threads)
 
     def one(m):
         o = O.Oracle(case["nx"], case["ny"], case["xf"], case["yf"], case["u0"], case["v0"], case["p0"],
@@ -476,7 +696,10 @@ def cpu_leg(case, target_seconds, gpu_iters_per_step):
     overhead = max(t1 - m1 * per_it, 0.0)
     cells = case["nx"] * case["ny"]
     est_step = overhead + per_it * gpu_iters_per_step
-    return dict(value=cells / per_it, unit="cell-updates/s", cores=O.num_threads(), kind="oracle",
+    used = O.num_threads()
+    if threads > 0:
+        O.set_num_threads(os.cpu_count() or 1)
+    return dict(value=cells / per_it, unit="cell-updates/s", cores=used, kind="oracle",
                 sample=(f"one {case['nx']}x{case['ny']} time step of the same workload with the "
                         f"pressure solve capped at {m1} and at {m2} red-black SOR iterations; "
                         f"rate from the difference"),
@@ -527,6 +750,17 @@ def main():
     ap.add_argument("--c4-graph", type=int, default=10,
                     help="check intervals per HIP-graph stretch of the batched variant replayed from a graph "
                          "(even; 0: skip that variant)")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs of the headline, PCG and mixed-precision legs (the same steps from the same "
+                         "checkpoint); the median is reported")
+    ap.add_argument("--c1", type=int, default=1, help="1: time all 100 steps of the 128x96 workload (GPU and oracle)")
+    ap.add_argument("--pcg-long-steps", type=int, default=200,
+                    help="steps of the long Jacobi-PCG run of the 1024x768 workload from t = 0 (0: skip)")
+    ap.add_argument("--scaling", type=int, default=1,
+                    help="1: input-scaling rows at 0.6, 1.2 and 1.8 M cells (PCG steps, SOR rate)")
+    ap.add_argument("--c4-uncapped", type=int, default=1,
+                    help="1: also one uncapped batched step to 1e-8 (mixed precision, graph, batch-tuned tiles) "
+                         "against the same step case by case")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of this many MiB, 20 times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -558,17 +792,20 @@ def main():
     tag = "plunging1024x768"
     method = ibm.RBSOR if args.solver == "sor" else ibm.PCG
     learned = args.learned and args.solver == "sor" and not args.max_poisson_iters
+    reps = max(1, args.repeats)
     main_leg = gpu_leg(case, method, args.steps, args.warmup, args.profile_every, args.max_poisson_iters,
-                       keep_fields=learned)
-    pcg_leg = None
+                       keep_fields=learned, repeats=reps)
+    pcg_leg = cg1_leg = None
     if args.solver == "sor" and args.pcg_steps > 0:
         pcg_leg = gpu_leg(case, ibm.PCG, args.pcg_steps, args.warmup, args.profile_every,
-                          args.max_poisson_iters)
+                          args.max_poisson_iters, repeats=reps)
+        cg1_leg = gpu_leg(case, ibm.CG1, args.pcg_steps, args.warmup, args.profile_every,
+                          args.max_poisson_iters, repeats=reps)
 
     mp_leg = None
     if args.solver == "sor" and args.mp_steps > 0:
         mp_leg = gpu_leg(case, ibm.RBSOR_MP, args.mp_steps, args.warmup, args.profile_every,
-                         args.max_poisson_iters, check=args.mp_check)
+                         args.max_poisson_iters, check=args.mp_check, repeats=reps)
     f64_same = None
     if mp_leg is not None and args.mp_check != 10:
         f64_same = gpu_leg(case, ibm.RBSOR, args.mp_steps, args.warmup, 0, args.max_poisson_iters,
@@ -589,12 +826,33 @@ def main():
     kid = max(cands, key=lambda k: main_leg["prof"][k]["avg_ms"] * main_leg["prof"][k]["launches"])
     q = main_leg["prof"][kid]
     kname = ibm.KERNEL_NAMES[kid]
-    achieved = q["bytes_per_launch"] / (q["avg_ms"] * 1e-3) / 1e9 if q["avg_ms"] > 0 else 0.0
-    traffic = read_traffic(kname, tag)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+    dur = q["avg_ms"] * 1e-3
+    eff = q["bytes_per_launch"] / dur / 1e9 if dur > 0 else 0.0
+    cnt = read_counters(kname, tag)
+    traffic = _counter(cnt, "hbm_bytes_per_launch")
+    # The sweep's data (phi and V b, 12.6 MB) stays in L2 and the Infinity
+    # Cache: the counters show HBM-side traffic far below the algorithmic
+    # 24 B per update and the VALU busy about half the time, so the kernel is
+    # placed against the FP64 vector roofline with its algorithmic FLOPs.
+    if method == ibm.RBSOR:
+        flops = SOR_FLOP_PER_UPDATE * q["bytes_per_launch"] / 24.0
+        tf = flops / dur / 1e12 if dur > 0 else 0.0
+        head = {"bound": "alu", "achieved": round(tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP64_PEAK_TFLOPS, 4)}
+    else:  # the PCG kernels stream their vectors
+        flops = None
+        head = {"bound": "hbm", "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(eff / HBM_PEAK_GBS, 4)}
+    roofline = {**head, "traffic": traffic,
                 "kernel": kname, "avg_us": round(q["avg_ms"] * 1e3, 3), "samples": q["samples"],
-                "launches": q["launches"], "alg_bytes_per_launch": q["bytes_per_launch"]}
+                "launches": q["launches"], "alg_flops_per_launch": flops,
+                "alg_bytes_per_launch": q["bytes_per_launch"],
+                "effective_GBps_algorithmic": round(eff, 1),
+                "effective_frac_of_hbm_peak": round(eff / HBM_PEAK_GBS, 4),
+                "hbm_GBps_counters": round(traffic / dur / 1e9, 1) if traffic and dur > 0 else None,
+                "hbm_frac_counters": round(traffic / dur / 1e9 / HBM_PEAK_GBS, 4) if traffic and dur > 0 else None,
+                "valu_busy_counters": _counter(cnt, "valu_busy"),
+                "wait_frac_counters": _counter(cnt, "wait_frac")}
 
     steps = args.steps
     ms_per_step = 1e3 * main_leg["wall"] / steps
@@ -619,16 +877,33 @@ def main():
                    "initial_guess": "previous phi", "first_timed_step": args.warmup + 1,
                    "poisson_iteration_cap": args.max_poisson_iters or None},
         "s_per_time_step": round(main_leg["wall"] / steps, 6),
+        "s_per_time_step_runs": [round(w / steps, 6) for w in main_leg["walls"]],
+        "phases_ms_per_step": _round_phases(main_leg["phases_ms"]),
         "poisson_iters_per_step": main_leg["iters"],
         "poisson_iters_mean": iters_per_step,
         "roofline": roofline,
     }
     if pcg_leg is not None:
         out["pcg"] = {"s_per_time_step": round(pcg_leg["wall"] / args.pcg_steps, 6),
+                      "s_per_time_step_runs": [round(w / args.pcg_steps, 6) for w in pcg_leg["walls"]],
+                      "phases_ms_per_step": _round_phases(pcg_leg["phases_ms"]),
                       "poisson_iters_per_step": pcg_leg["iters"],
                       "cell_updates_per_s": round(pcg_leg["cell_updates_per_s"], 1),
                       "kernels_avg_us": {ibm.KERNEL_NAMES[k]: round(pcg_leg["prof"][k]["avg_ms"] * 1e3, 3)
                                          for k in (ibm.KERNEL_PCG_DIR_SPMV, ibm.KERNEL_PCG_UPDATE)}}
+    if cg1_leg is not None:
+        q = cg1_leg["prof"][ibm.KERNEL_CG1_ITER]
+        out["pcg_one_reduction"] = {
+            "solver": "Jacobi-PCG with one reduction per iteration (one kernel per iteration), tol 1e-8",
+            "s_per_time_step": round(cg1_leg["wall"] / args.pcg_steps, 6),
+            "s_per_time_step_runs": [round(w / args.pcg_steps, 6) for w in cg1_leg["walls"]],
+            "phases_ms_per_step": _round_phases(cg1_leg["phases_ms"]),
+            "poisson_iters_per_step": cg1_leg["iters"],
+            "cell_updates_per_s": round(cg1_leg["cell_updates_per_s"], 1),
+            "speedup_vs_pcg": round(pcg_leg["wall"] / cg1_leg["wall"], 3) if cg1_leg["wall"] > 0 else None,
+            "k_cg1_iter": {"avg_us": round(q["avg_ms"] * 1e3, 3),
+                           "effective_GBps": round(q["bytes_per_launch"] / (q["avg_ms"] * 1e-3) / 1e9, 1)
+                           if q["avg_ms"] > 0 else None}}
     if mp_leg is not None:
         mp_steps = args.mp_steps
         kern = {}
@@ -645,6 +920,8 @@ def main():
                       f"stop test every {args.mp_check} iterations, tol 1e-8",
             "check_interval": args.mp_check,
             "s_per_time_step": round(mp_s, 6),
+            "s_per_time_step_runs": [round(w / mp_steps, 6) for w in mp_leg["walls"]],
+            "phases_ms_per_step": _round_phases(mp_leg["phases_ms"]),
             "poisson_iters_per_step": mp_leg["iters"],
             "speedup_vs_f64_sor": round((main_leg["wall"] / steps) / mp_s, 3) if mp_s > 0 else None,
             "f64_same_interval": {"s_per_time_step": round(f64_same_s, 6),
@@ -662,9 +939,23 @@ def main():
         out["batched_cases"] = batch_leg(args)
     if args.stress:
         out["stress_hbm"] = stress_leg()
+    if args.c1:
+        out["c1_full_run"] = c1_leg(cpu=args.cpu_seconds > 0)
+    if args.solver == "sor" and args.pcg_long_steps > 0:
+        out["pcg_long"] = pcg_long_leg(case, args.pcg_long_steps, ibm.CG1)
+    if args.scaling:
+        out["input_scaling"] = scaling_leg()
     if args.cpu_seconds > 0:
+        # the oracle on all host threads (the paper's OpenMP SOL1 analogue)
+        # and on one (its serial SOL0 analogue); speedups as the paper forms
+        # them: S = T_reference / T_gpu per time step
+        gpu_step = main_leg["wall"] / steps
         cb = cpu_leg(case, args.cpu_seconds, iters_per_step)
-        cb["speedup_s_per_step"] = round(cb["s_per_time_step_est"] / (main_leg["wall"] / steps), 2)
+        cb1 = cpu_leg(case, args.cpu_seconds, iters_per_step, threads=1)
+        cb["speedup_s_per_step"] = round(cb["s_per_time_step_est"] / gpu_step, 2)
+        cb["one_thread"] = {k: cb1[k] for k in ("value", "cores", "sample", "seconds", "s_per_time_step_est")}
+        cb["one_thread"]["speedup_s_per_step"] = round(cb1["s_per_time_step_est"] / gpu_step, 2)
+        cb["threads_over_one_thread"] = round(cb1["s_per_time_step_est"] / cb["s_per_time_step_est"], 3)
         out["cpu_baseline"] = cb
         out["paper_speedups"] = PAPER_SPEEDUPS
     print(json.dumps(out), flush=True)

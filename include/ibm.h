@@ -80,6 +80,12 @@ extern "C" {
  * test and check interval as IBM_SOLVER_RBSOR; it uses the blocked sweep's
  * tile shape (IBM_OPT_TB_*). */
 #define IBM_SOLVER_RBSOR_MP 2
+/* Jacobi-PCG in the one-reduction form (Chronopoulos and Gear, 1989): the
+ * search direction's product s = M p is carried by its own recurrence, so
+ * both inner products of an iteration come from one reduction and an
+ * iteration is one kernel.  The same iterates as IBM_SOLVER_PCG in exact
+ * arithmetic (not bitwise); the same stop test and confirmation. */
+#define IBM_SOLVER_CG1 3
 
 /* initial guess of the pressure correction at each step */
 #define IBM_INIT_ZERO 0
@@ -105,7 +111,7 @@ typedef struct ibm_params {
     double thickness;        /* thickness / chord (minor axis = thickness * chord) */
     double x0, y0;           /* centre of the ellipse at rest position */
     double amp, freq, phase; /* plunge y_c = y0 + amp sin(2 pi freq t + phase) (Eqs. 1-2, k = 2 pi freq) */
-    int32_t p_method;        /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG or IBM_SOLVER_RBSOR_MP */
+    int32_t p_method;        /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG, IBM_SOLVER_RBSOR_MP or IBM_SOLVER_CG1 */
     int32_t p_max_iter;      /* iteration limit of one pressure solve, >= 1 */
     int32_t p_check_every;   /* SOR: residual tested every this many iterations, >= 1 */
     int32_t p_init;          /* IBM_INIT_ZERO, IBM_INIT_PREVIOUS or IBM_INIT_LEARNED */
@@ -138,7 +144,7 @@ typedef struct ibm_step_stats {
 
 /* Options of a stand-alone Poisson solve. */
 typedef struct ibm_solve_opts {
-    int32_t method;       /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG or IBM_SOLVER_RBSOR_MP */
+    int32_t method;       /* IBM_SOLVER_RBSOR, IBM_SOLVER_PCG, IBM_SOLVER_RBSOR_MP or IBM_SOLVER_CG1 */
     int32_t max_iter;     /* iteration limit, >= 1 */
     int32_t check_every;  /* SOR residual test interval, >= 1 (PCG tests every iteration) */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations, tol ignored */
@@ -355,9 +361,11 @@ int32_t ibm_batch_step(ibm_batch* batch, int32_t nsteps, ibm_step_stats* last);
  * inside a stretch leaves the rest of the stretch's launches to skip its
  * tiles.  The graph is captured at the next ibm_batch_step and again when
  * the cases' tile counts change.  intervals = 0 (the default): no graph.
- * IBM_ERR_INVALID for odd or out-of-range counts and for a batch of
- * IBM_SOLVER_RBSOR_MP contexts (no graph form); IBM_ERR_HIP if the stream
- * or the 8-byte device cursor cannot be made (then the setting is unchanged). */
+ * A batch of IBM_SOLVER_RBSOR_MP contexts captures, per interval, its float
+ * sweep launches, the refinement and the stop tests; its stretches start
+ * after an even number of intervals.  IBM_ERR_INVALID for odd or
+ * out-of-range counts; IBM_ERR_HIP if the stream or the 8-byte device cursor
+ * cannot be made (then the setting is unchanged). */
 int32_t ibm_batch_set_graph(ibm_batch* batch, int32_t intervals);
 void ibm_batch_destroy(ibm_batch* batch);
 const char* ibm_batch_last_error(const ibm_batch* batch);
@@ -378,8 +386,26 @@ const char* ibm_batch_last_error(const ibm_batch* batch);
 #define IBM_KERNEL_SOR_TB 4         /* blocked SOR (either variant): 24 B per cell and iteration */
 #define IBM_KERNEL_SOR_MP 5         /* mixed-precision sweeps: 12 B per cell and iteration (float e, r) */
 #define IBM_KERNEL_SOR_MP_REFINE 6  /* its refinement: 32 B per cell (phi, e, V b in; phi, r out) */
-#define IBM_KERNEL_COUNT 7
+#define IBM_KERNEL_CG1_ITER 7       /* one-reduction CG iteration: 88 B per cell (x, p, r, w, s, 1/d in;
+                                       x, p, r, w, s out) */
+#define IBM_KERNEL_COUNT 8
 int32_t ibm_profile(ibm_ctx* ctx, int32_t sample_every);
+/* Phase split of ibm_step (the four hot spots of Table 1, Sec. 3.4.1, with
+ * the other parts of a step beside them): while kernel timing is on
+ * (sample_every > 0), every ibm_step records HIP events on the context stream
+ * at the phase boundaries and adds each phase's GPU time (ms) to a running
+ * sum; ibm_profile resets the sums.  ibm_profile_phases copies the first n
+ * sums (n <= IBM_PHASE_COUNT; later entries 0) and the number of steps
+ * summed.  Batched steps are not phase-timed.  Synchronizes. */
+#define IBM_PHASE_FLAGGING 0     /* fluid/solid classification ("flagging") */
+#define IBM_PHASE_MOMENTUM 1     /* explicit momentum predictor */
+#define IBM_PHASE_FORCING 2      /* body-force interpolation, forces, outlet */
+#define IBM_PHASE_UV_SOLVE 3     /* implicit velocity solves ("U-V solver") */
+#define IBM_PHASE_POISSON_RHS 4  /* Poisson source and the initial guess */
+#define IBM_PHASE_P_SOLVE 5      /* pressure Poisson solve ("P solver") */
+#define IBM_PHASE_PROJECTION 6   /* projection, pressure update, statistics */
+#define IBM_PHASE_COUNT 7
+int32_t ibm_profile_phases(ibm_ctx* ctx, double* ms, int32_t n, int64_t* steps);
 int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t* samples, int64_t* launches,
                           double* bytes_per_launch);
 

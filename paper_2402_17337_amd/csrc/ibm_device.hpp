@@ -35,6 +35,12 @@ struct Grid {
     const double *pcE, *pcW, *pcD, *pcN, *pcS;
     const double *uce, *ucw, *ucn, *ucs;
     const double *vce, *vcw, *vcn, *vcs;
+    // 1/d of every cell in red/black split layout (d the diagonal of row (i, j)
+    // of A, with the operations of rb_diag), in double and, computed in
+    // single precision from the float-rounded coefficients, in float: the
+    // blocked sweeps load them instead of dividing in every launch
+    const double *rdr, *rdb;
+    const float *rdr32, *rdb32;
 };
 
 // Body position of the current step.
@@ -58,6 +64,7 @@ struct Ctl {
     double r0;      // initial residual norm
     double rn;      // latest residual norm
     double rz[2];   // PCG: r.z of iteration k in rz[k & 1]
+    double al[2];   // one-reduction CG: alpha of iteration k in al[k & 1]
 };
 
 // Host-mapped snapshot of a control block after a check.
@@ -169,12 +176,6 @@ __device__ inline void check_finish(Ctl* ctl, double r2, double b2, int phase, i
     if (it >= max_iter) { ctl->done = kDone; ctl->status = fixed ? kStOk : kStNotConverged; return; }
 }
 
-// Whether a residual test after `it` iterations ends the solve (the decision
-// check_finish records for phase 1): NaN, converged, or the iteration limit.
-__device__ inline bool check_stops(double rn, double bn, int it, int max_iter, double tol) {
-    const double den = bn > 0.0 ? bn : 1.0;
-    return !isfinite(rn) || rn <= tol * den || it >= max_iter;
-}
 
 // Strict inside test of the ellipse, evaluated without contraction so that it
 // takes exactly the decision of a plain IEEE evaluation.

@@ -129,6 +129,28 @@ __device__ inline double rb_row(const Grid& g, const double* __restrict__ other,
     return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
 }
 
+// 1/d of every cell in split layout, in double (the products of rb_row) and
+// in float (the products of the float-rounded coefficients, as the
+// single-precision sweeps form them); once per context.
+__global__ __launch_bounds__(kBlock) void k_rdiag_split(Grid g, double* __restrict__ rdr, double* __restrict__ rdb,
+                                                        float* __restrict__ rdr32, float* __restrict__ rdb32) {
+    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (m >= g.nh || j >= g.ny) return;
+    const size_t k = (size_t)j * g.nh + m;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int i = 2 * m + ((j + c) & 1);
+        const double dyj = g.dy[j], dxi = g.dx[i];
+        const double d = rb_diag(dyj * g.pcE[i], dyj * g.pcD[i], dyj * g.pcW[i], dxi * g.pcN[j], dxi * g.pcS[j]);
+        const float fy = (float)dyj, fx = (float)dxi;
+        const float f = rb_diag(fy * (float)g.pcE[i], fy * (float)g.pcD[i], fy * (float)g.pcW[i],
+                                fx * (float)g.pcN[j], fx * (float)g.pcS[j]);
+        (c ? rdb : rdr)[k] = 1.0 / d;
+        (c ? rdb32 : rdr32)[k] = 1.0f / f;
+    }
+}
+
 // One colour of a red-black SOR iteration (one launch per colour):
 //   phi_P <- (1 - omega) phi_P + omega (sum a_nb phi_nb - V b_P) / (sum a_nb + a_D)
 // COLOR 0 updates the red cells ((i+j) even), COLOR 1 the black cells.
@@ -250,33 +272,36 @@ struct TbCheck {
     Slot* slot;              // host-visible snapshot of the decision
 };
 
-// Start of a blocked launch: returns the solve's stop flag (block-uniform).
-// With a carried test, every block sums the partials in the same order and
-// takes the same decision; block 0 records it in ctl (as k_check does).  The
-// host-visible snapshot is written by tb_end, or here when the solve stops,
-// so that the system-scope fence does not delay block 0's sweeps.
-__device__ inline int tb_begin(Ctl* ctl, const TbCheck& chk, double* lds, int* s_flag) {
+// Start of a tile block of a blocked launch: the solve's stop flag as the
+// control block holds it when the block starts (block-uniform).
+__device__ inline int tb_begin(const Ctl* ctl, int* s_flag) {
     if (threadIdx.x == 0) *s_flag = ctl->done;
-    if (chk.nb > 0) {
-        double acc[2];
-        sum_partials(acc, chk.partials, chk.nb, lds);
-        if (threadIdx.x == 0) {
-            if (!*s_flag) {
-                const bool stop = check_stops(sqrt(acc[0]), ctl->bn, chk.it, chk.max_iter, chk.tol);
-                if (blockIdx.x == 0) check_finish(ctl, acc[0], acc[1], 1, chk.it, chk.max_iter, chk.tol, chk.fixed, 0);
-                *s_flag = stop ? 1 : 0;
-            }
-            if (blockIdx.x == 0 && *s_flag) publish(ctl, chk.slot);
-        }
-    }
     __syncthreads();
     return *s_flag;
 }
 
-// End of a blocked launch that did not stop: block 0 publishes the carried
-// test's decision.
-__device__ inline void tb_end(const Ctl* ctl, const TbCheck& chk) {
-    if (chk.nb > 0 && blockIdx.x == 0 && threadIdx.x == 0) publish(ctl, chk.slot);
+// The carried test of a blocked launch, taken by one extra block of the
+// launch (block 8 * per, past the tiles) so that no tile block waits for it:
+// it sums the previous interval's partials in the order k_check's callers
+// use (a kTbThreads block) and records the stop decision in ctl and in the
+// host-visible snapshot.  The tiles of the same launch do not wait for the
+// decision: after a finishing test they still sweep into the other pair of
+// phi arrays, which does not hold the result, and every later launch of the
+// solve returns at once.
+__device__ inline void tb_check_block(Ctl* ctl, const TbCheck& chk, double* lds, int* s_flag) {
+    if (threadIdx.x == 0) *s_flag = ctl->done;
+    __syncthreads();
+    if (!*s_flag) {
+        double acc[2];
+        sum_partials(acc, chk.partials, chk.nb, lds);
+        if (threadIdx.x == 0) check_finish(ctl, acc[0], acc[1], 1, chk.it, chk.max_iter, chk.tol, chk.fixed, 0);
+    }
+    if (threadIdx.x == 0) publish(ctl, chk.slot);
+}
+
+// Whether this block of a blocked launch is its check block.
+__device__ inline bool tb_is_check_block(const TbCheck& chk, const TbShape& ts) {
+    return chk.nb > 0 && (int)blockIdx.x == 8 * ts.per;
 }
 
 // Tile of block b.  Blocks are dispatched to the 8 XCDs round-robin, so each
@@ -293,10 +318,14 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
     __shared__ double tile[2 * kTbLds];
     __shared__ double lds[2 * kTbWaves];
     __shared__ int s_flag;
+    if (tb_is_check_block(chk, ts)) {
+        tb_check_block(ctl, chk, lds, &s_flag);
+        return;
+    }
     const int nt = ts.ntx * ts.nty;
     const int t = tb_tile(ts);
     if (t >= nt) return;
-    if (tb_begin(ctl, chk, lds, &s_flag)) return;
+    if (tb_begin(ctl, &s_flag)) return;
     const int txi = t % ts.ntx, tyi = t / ts.ntx;
     const int X0 = txi * ts.tx, Y0 = tyi * ts.ty;
     const int X1 = min(X0 + ts.tx, g.nx), Y1 = min(Y0 + ts.ty, g.ny);
@@ -433,7 +462,6 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
         }
     }
     if (residual) block_partials(acc, partials, nt, t, lds);
-    tb_end(ctl, chk);
 }
 
 // ---------------------------------------------------------------------------
@@ -722,14 +750,13 @@ __device__ __forceinline__ void tbr_tile(const Grid& g, const double* __restrict
             x[1][r] = black[kg];
             b[0][r] = bred[kg];
             b[1][r] = bblack[kg];
+            rd[0][r] = g.rdr[kg];  // 1/d, as tbr_rdiag forms it, precomputed per grid
+            rd[1][r] = g.rdb[kg];
         }
     }
-    const int nlive = min(kTbRows, ly - jw);
-    tbr_rdiag<P>(rd, cdx, cE, cW, cD, rdy, rpn, rps, nlive, col);
-    tbr_pin(rd);
-    // The stop test comes after the tile's loads are issued, so that its
+    // The stop flag is read after the tile's loads are issued, so that its
     // latency overlaps theirs (a finished solve only wastes the loads).
-    if (tb_begin(ctl, chk, lds, &s_flag)) return;
+    if (tb_begin(ctl, &s_flag)) return;
     // edge rows of both colours; slots 0 and kTrSlots-1 stay zero
     tbr_edges(x, edge, w, lane);
     __syncthreads();
@@ -745,7 +772,6 @@ __device__ __forceinline__ void tbr_tile(const Grid& g, const double* __restrict
         tbr_residual<P>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
         block_partials(acc, partials, nt, t, lds);
     }
-    tb_end(ctl, chk);
 }
 
 __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __restrict__ red,
@@ -757,6 +783,10 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tbr(Grid g, const double* __
     __shared__ double edge[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];
     __shared__ int s_flag;
+    if (tb_is_check_block(chk, ts)) {
+        tb_check_block(ctl, chk, lds, &s_flag);
+        return;
+    }
     const int t = tb_tile(ts);
     if (t >= ts.ntx * ts.nty) return;
     tbr_tile(g, red, black, ored, oblack, bred, bblack, omega, ctl, chk, ts, t, nsweep, residual, partials, edge,
@@ -888,7 +918,6 @@ __device__ __forceinline__ void mp_tile(const Grid& g, const MpArrays& a, double
     float fdx[2] = {(float)g.dx[ii0], (float)g.dx[ii1]};
     float fE[2] = {(float)g.pcE[ii0], (float)g.pcE[ii1]};
     float fW[2] = {(float)g.pcW[ii0], (float)g.pcW[ii1]};
-    const float fD[2] = {(float)g.pcD[ii0], (float)g.pcD[ii1]};
     float fdy[kTbRows], fpn[kTbRows], fps[kTbRows];
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
@@ -908,16 +937,15 @@ __device__ __forceinline__ void mp_tile(const Grid& g, const MpArrays& a, double
             }
             b32[0][r] = a.rr[k];
             b32[1][r] = a.rb[k];
+            rd[0][r] = g.rdr32[k];  // 1/d in float, precomputed per grid
+            rd[1][r] = g.rdb32[k];
         }
     }
-    tbr_rdiag<P>(rd, fdx, fE, fW, fD, fdy, fpn, fps, min(kTbRows, ly - jw), col);
-    tbr_pin(rd);
-    if (tb_begin(ctl, chk, lds, s_flag)) return;
+    if (tb_begin(ctl, s_flag)) return;
     tbr_edges(e, edge32, w, lane);
     __syncthreads();
     tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, 0, (float)omega);
     tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
-    tb_end(ctl, chk);
 }
 
 __global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp(
@@ -925,6 +953,10 @@ __global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8
     __shared__ float edge32[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];
     __shared__ int s_flag;
+    if (tb_is_check_block(chk, ts)) {
+        tb_check_block(ctl, chk, lds, &s_flag);
+        return;
+    }
     const int t = tb_tile(ts);
     if (t >= ts.ntx * ts.nty) return;
     mp_tile(g, a, omega, ctl, chk, ts, t, nsweep, e_zero, edge32, lds, &s_flag);
@@ -1065,9 +1097,15 @@ __global__ __launch_bounds__(kRedThreads) void k_mp_refine_batch(const MpCase* _
 // Stop tests after a refinement, one block per case: the nbr partials of set
 // pbuf (phase 0: the initial residual).  At most kRedMax partials, so every
 // block size sums them in the same order as the single-grid tests.
+// Inside a captured stretch the iteration base and snapshot entry come from
+// the cursor (cur non-null), as for k_check_batch.
 __global__ __launch_bounds__(kTbThreads) void k_check_mp_batch(const MpCase* __restrict__ cases, int phase, int it,
-                                                               int pbuf, Slot* slots) {
+                                                               int pbuf, Slot* slots, const int* __restrict__ cur) {
     __shared__ double lds[2 * kTbWaves];
+    if (cur) {
+        it += cur[0];
+        slots += (size_t)cur[1] * gridDim.x;
+    }
     const MpCase& C = cases[blockIdx.x];
     if (C.ctl->done) {
         if (threadIdx.x == 0) publish(C.ctl, slots + blockIdx.x);
@@ -1342,6 +1380,178 @@ __global__ __launch_bounds__(kBlock) void k_pcg_confirm(Ctl* ctl, const double* 
         }
         publish(ctl, hs);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-PCG with one reduction per iteration (Chronopoulos and Gear): on
+// M x = -V b with M = -A, u = D^-1 r (D = diag M, applied as a product with
+// the stored 1/D), w = M u, and s = M p carried by its own recurrence, so the
+// iteration's two inner products gamma = (r, u) and delta = (w, u) come from
+// one reduction:
+//   beta_i = gamma_i / gamma_{i-1},
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,
+//   w_{i+1} = M u_{i+1}.
+// One kernel per iteration: it reads r_i, w_i, s_{i-1} (double-buffered by
+// iteration parity), forms u_{i+1} of the cell and of its four neighbours
+// from those (each neighbour's value with exactly the operations its own
+// thread uses), and writes p, s_i, x, r_{i+1}, w_{i+1} and the partials of
+// gamma, delta and (r, r) of iteration i+1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_rdiag(Grid g, const double* __restrict__ dn, double* __restrict__ rdn) {
+    const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
+    if (i >= g.nx || j >= g.ny) return;
+    const size_t k = (size_t)j * g.nx + i;
+    rdn[k] = 1.0 / dn[k];
+}
+
+// Neighbour indices of cell (i, j) in natural layout and whether each
+// neighbour exists (periodic mode wraps; channel mode has none beyond the ends).
+struct NatNb {
+    size_t kE, kW, kN, kS;
+    bool hE, hW, hN, hS;
+    __device__ NatNb(const Grid& g, int i, int j, size_t k) {
+        const size_t nx = g.nx, top = (size_t)(g.ny - 1) * g.nx;
+        hE = i < g.nx - 1 || g.per;
+        hW = i > 0 || g.per;
+        hN = j < g.ny - 1 || g.per;
+        hS = j > 0 || g.per;
+        kE = i < g.nx - 1 ? k + 1 : k + 1 - nx;
+        kW = i > 0 ? k - 1 : k + nx - 1;
+        kN = j < g.ny - 1 ? k + nx : k - top;
+        kS = j > 0 ? k - nx : k + top;
+    }
+};
+
+// w = M u for u = r / D, with the partials of (r, u), (w, u), (r, r): the
+// start of a solve and of a restart.
+__global__ __launch_bounds__(kRedThreads) void k_cg1_w(Grid g, const double* __restrict__ r,
+                                                       const double* __restrict__ rdn, double* __restrict__ w,
+                                                       double* partials) {
+    __shared__ double lds[3 * kRedThreads / kWave];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const size_t k = c.k;
+        const int i = c.i, j = c.j;
+        const double dyj = g.dy[j], dxi = g.dx[i];
+        const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+        const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+        const double d = rb_diag(aE, aD, aW, aN, aS);
+        const NatNb nb(g, i, j, k);
+        const double rk = r[k], uk = rk * rdn[k];
+        const double uE = nb.hE ? r[nb.kE] * rdn[nb.kE] : 0.0;
+        const double uW = nb.hW ? r[nb.kW] * rdn[nb.kW] : 0.0;
+        const double uN = nb.hN ? r[nb.kN] * rdn[nb.kN] : 0.0;
+        const double uS = nb.hS ? r[nb.kS] * rdn[nb.kS] : 0.0;
+        const double wk = d * uk - rb_sum(aE, uE, aW, uW, aN, uN, aS, uS);
+        w[k] = wk;
+        acc[0] += rk * uk;
+        acc[1] += wk * uk;
+        acc[2] += rk * rk;
+    }
+    block_partials(acc, partials, gridDim.x, blockIdx.x, lds);
+}
+
+// u_{i+1} of a cell from r_i, w_i, s_{i-1} (s_i = w_i when first).
+__device__ inline double cg1_unext(double r, double w, double s, double rd, double alpha, double beta, bool first) {
+    const double si = first ? w : __fma_rn(beta, s, w);
+    return __fma_rn(-alpha, si, r) * rd;
+}
+
+// Iteration kk.  Every block sums the partials (gamma, delta, rho) of r_kk and
+// takes the same decision: for kk > 0 (not after a restart) stop on NaN, on
+// the recursive residual sqrt(rho) <= tol ||V b|| (kStConfirm: the host
+// confirms with the true residual) or at the iteration limit; block 0
+// records it (and gamma, alpha of iteration kk) and publishes it.
+__global__ __launch_bounds__(kRedThreads) void k_cg1_iter(
+    Grid g, double* __restrict__ x, double* __restrict__ p, const double* __restrict__ r_in,
+    const double* __restrict__ w_in, const double* __restrict__ s_in, double* __restrict__ r_out,
+    double* __restrict__ w_out, double* __restrict__ s_out, const double* __restrict__ rdn, Ctl* ctl,
+    const double* __restrict__ part_in, int nb, double* __restrict__ part_out, int kk, int max_iter, double tol,
+    int fixed, int first, Slot* hs) {
+    __shared__ double lds[3 * kRedThreads / kWave];
+    __shared__ double s_alpha, s_beta;
+    __shared__ int s_stop, s_done;
+    if (threadIdx.x == 0) s_done = ctl->done;
+    __syncthreads();
+    if (s_done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish(ctl, hs);
+        return;
+    }
+    double acc[3];
+    sum_partials(acc, part_in, nb, lds);
+    if (threadIdx.x == 0) {
+        const double gamma = acc[0], delta = acc[1], rn = sqrt(acc[2]);
+        int stop = 0, status = kStOk;
+        if (!first) {
+            if (!isfinite(rn)) { stop = 1; status = kStNan; }
+            else if (rn <= tol * ctl->bn) { stop = 1; status = kStConfirm; }
+            else if (kk >= max_iter) { stop = 1; status = fixed ? kStOk : kStNotConverged; }
+        } else if (kk >= max_iter) {
+            stop = 1;
+            status = fixed ? kStOk : kStNotConverged;
+        }
+        double beta = 0.0, alpha;
+        if (first) {
+            alpha = gamma / delta;
+        } else {
+            beta = gamma / ctl->rz[(kk - 1) & 1];
+            alpha = gamma / (delta - beta * gamma / ctl->al[(kk - 1) & 1]);
+        }
+        s_stop = stop;
+        s_alpha = alpha;
+        s_beta = beta;
+        if (blockIdx.x == 0) {
+            ctl->rn = rn;
+            ctl->iters = kk;
+            if (stop) {
+                ctl->done = kDone;
+                ctl->status = status;
+            } else {
+                ctl->rz[kk & 1] = gamma;
+                ctl->al[kk & 1] = alpha;
+            }
+            publish(ctl, hs);
+        }
+    }
+    __syncthreads();
+    if (s_stop) return;
+    const double alpha = s_alpha, beta = s_beta;
+    const bool fst = first != 0;
+    double pacc[3] = {0.0, 0.0, 0.0};
+    for (CellWalk c(g); c.ok(); c.next()) {
+        const size_t k = c.k;
+        const int i = c.i, j = c.j;
+        const double dyj = g.dy[j], dxi = g.dx[i];
+        const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+        const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+        const double d = rb_diag(aE, aD, aW, aN, aS);
+        const double rd = rdn[k], rk = r_in[k], wk = w_in[k];
+        const double sold = fst ? 0.0 : s_in[k];
+        const double pold = fst ? 0.0 : p[k];
+        const double uk = rk * rd;
+        const double pk = fst ? uk : __fma_rn(beta, pold, uk);
+        const double sk = fst ? wk : __fma_rn(beta, sold, wk);
+        x[k] = __fma_rn(alpha, pk, x[k]);
+        const double rnew = __fma_rn(-alpha, sk, rk);
+        const double unew = rnew * rd;
+        const NatNb n(g, i, j, k);
+        const double uE = n.hE ? cg1_unext(r_in[n.kE], w_in[n.kE], fst ? 0.0 : s_in[n.kE], rdn[n.kE], alpha, beta, fst) : 0.0;
+        const double uW = n.hW ? cg1_unext(r_in[n.kW], w_in[n.kW], fst ? 0.0 : s_in[n.kW], rdn[n.kW], alpha, beta, fst) : 0.0;
+        const double uN = n.hN ? cg1_unext(r_in[n.kN], w_in[n.kN], fst ? 0.0 : s_in[n.kN], rdn[n.kN], alpha, beta, fst) : 0.0;
+        const double uS = n.hS ? cg1_unext(r_in[n.kS], w_in[n.kS], fst ? 0.0 : s_in[n.kS], rdn[n.kS], alpha, beta, fst) : 0.0;
+        const double wnew = d * unew - rb_sum(aE, uE, aW, uW, aN, uN, aS, uS);
+        p[k] = pk;
+        s_out[k] = sk;
+        r_out[k] = rnew;
+        w_out[k] = wnew;
+        pacc[0] += rnew * unew;
+        pacc[1] += wnew * unew;
+        pacc[2] += rnew * rnew;
+    }
+    block_partials(pacc, part_out, gridDim.x, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------

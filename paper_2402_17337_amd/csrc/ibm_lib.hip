@@ -80,6 +80,7 @@ struct Layout {
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
     size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2, mpf, phi0, wsf, wscale;
+    size_t cgw, cgs, rdn, rdr, rdb, rdr32, rdb32;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -110,6 +111,9 @@ Offsets layout_for(int nx, int ny) {
     o.pr = L.take<double>(NC); o.pp = L.take<double>(NC); o.pp2 = L.take<double>(NC); o.pq = L.take<double>(NC);
     o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
     o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
+    o.cgw = L.take<double>(NC); o.cgs = L.take<double>(NC); o.rdn = L.take<double>(NC);  // one-reduction CG
+    o.rdr = L.take<double>(NH); o.rdb = L.take<double>(NH);      // 1/d, split layout (blocked sweeps)
+    o.rdr32 = L.take<float>(NH); o.rdb32 = L.take<float>(NH);
     o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
     o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
     o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step; the network's
@@ -121,7 +125,7 @@ Offsets layout_for(int nx, int ny) {
     // per-block partials: three sums of up to kRedMax blocks, p.q of PCG, and
     // two sums per tile of the blocked sweep (tiles of at least 2x1 cells)
     o.max_blocks = kRedMax;
-    o.partials = L.take<double>((size_t)4 * kRedMax + (size_t)2 * (nx / 2) * ny);
+    o.partials = L.take<double>(std::max((size_t)9 * kRedMax, (size_t)4 * kRedMax + (size_t)2 * (nx / 2) * ny));
     o.ctl = L.take<Ctl>(CTL_N);
     o.list_u = L.take<int>(NU); o.list_v = L.take<int>(NV); o.counts = L.take<int>(4);
     o.flu = L.take<uint8_t>(NU); o.flv = L.take<uint8_t>(NV); o.msrc = L.take<uint8_t>(NC);
@@ -149,7 +153,8 @@ const char* validate(const ibm_params* P, const double* xf, const double* yf) {
         return "periodic mode takes no body, no mixed-precision sweeps and no learned guess";
     if (P->precision != IBM_PREC_FP64 || P->reserved != 0) return "unsupported precision";
     if (!(P->dt > 0.0) || !(P->re > 0.0) || !std::isfinite(P->u_inf)) return "dt and re must be > 0";
-    if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG && P->p_method != IBM_SOLVER_RBSOR_MP)
+    if (P->p_method != IBM_SOLVER_RBSOR && P->p_method != IBM_SOLVER_PCG && P->p_method != IBM_SOLVER_RBSOR_MP &&
+        P->p_method != IBM_SOLVER_CG1)
         return "unknown p_method";
     if (!(P->p_omega > 0.0 && P->p_omega < 2.0) || !(P->uv_omega > 0.0 && P->uv_omega < 2.0))
         return "relaxation factors must lie in (0, 2)";
@@ -191,6 +196,7 @@ struct ibm_ctx {
     // device arrays
     double *u, *nu, *ru, *fufull, *v, *nv, *rv, *fvfull, *p, *phi, *vb, *pr, *pp, *pp2, *pq, *phr, *phb, *vbr, *vbb;
     double *pz, *dn;    // PCG: z = r / diag(M), and diag(M) (natural layout)
+    double *cgw, *cgs, *rdn;  // one-reduction CG: second w and s buffers, 1 / diag(M)
     double *phr2, *phb2;  // second pair of split phi arrays (blocked sweeps alternate)
     float* mpf;           // mixed-precision SOR: e pairs (4 NH), then r32 pairs (4 NH)
     double *phi0, *wscale;  // learned warm start: phi before the solve, (s_r, s_phi)
@@ -240,6 +246,13 @@ struct ibm_ctx {
     // device address of this device's static scratch array (the
     // allocation-free solve), resolved at ibm_init; nullptr if unavailable
     double* noalloc = nullptr;
+    // phase timing of ibm_step (on while kernel timing is on): events at the
+    // phase boundaries of each step, accumulated GPU milliseconds per phase
+    bool phase_on = false;
+    bool in_batch = false;  // steps of a batch are not phase-timed
+    hipEvent_t pev[IBM_PHASE_COUNT + 1] = {};
+    double phase_ms[IBM_PHASE_COUNT] = {};
+    long phase_steps = 0;
 };
 
 namespace {
@@ -416,6 +429,53 @@ int32_t wait_slot(ibm_ctx* c, int s, Slot* out) {
     return IBM_OK;
 }
 
+// Checks enqueued ahead of the host.  Each entry names the host-mapped slot
+// its check writes and a tag (the launch or refinement count behind it).
+// Only every kEventEvery-th entry gets an event recorded behind it on the
+// stream (an event record leaves the GPU idle for a few microseconds between
+// two launches); the host waits on the first event at or after the entry it
+// needs, and the entries before that event are complete with it.
+constexpr int kEventEvery = 6;
+struct PendingCheck {
+    int slot;
+    long tag;
+    bool ev, ready;
+};
+struct CheckQueue {
+    std::deque<PendingCheck> q;
+    long count = 0;
+    bool empty() const { return q.empty(); }
+    size_t size() const { return q.size(); }
+    void clear() { q.clear(); }
+};
+
+int32_t pend_push(ibm_ctx* c, CheckQueue& cq, int s, long tag) {
+    const bool ev = (cq.count++ % kEventEvery) == 0;
+    if (ev) HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+    cq.q.push_back(PendingCheck{s, tag, ev, false});
+    return IBM_OK;
+}
+
+// The oldest entry's snapshot, once its check has run; pops it.
+int32_t pend_pop(ibm_ctx* c, CheckQueue& cq, Slot* out, long* tag) {
+    std::deque<PendingCheck>& q = cq.q;
+    if (!q.front().ready) {
+        size_t k = 0;
+        while (k < q.size() && !q[k].ev) ++k;
+        if (k == q.size()) {  // no event behind any entry yet: one behind the newest
+            k = q.size() - 1;
+            HIP_TRY(hipEventRecord(c->ev[q[k].slot], c->stream));
+            q[k].ev = true;
+        }
+        HIP_TRY(hipEventSynchronize(c->ev[q[k].slot]));
+        for (size_t m = 0; m <= k; ++m) q[m].ready = true;
+    }
+    *out = read_slot(c, q.front().slot);
+    if (tag) *tag = q.front().tag;
+    q.pop_front();
+    return IBM_OK;
+}
+
 inline int red_blocks(size_t n) {
     return (int)std::max<size_t>(1, std::min<size_t>(kRedMax, (n + kRedThreads - 1) / kRedThreads));
 }
@@ -473,7 +533,7 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
     ++c->solve_id;
-    std::deque<std::pair<int, long>> pending;  // (slot, blocked launches before the test)
+    CheckQueue pending;  // tags: blocked launches before the test
     double* cur[2] = {c->phr, c->phb};
     double* alt[2] = {c->phr2, c->phb2};
     long nlaunch = 0;
@@ -486,9 +546,7 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
         hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, part, nb, phase, it, max_e, tol_e,
                            (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
-        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-        pending.emplace_back(s, nl);
-        return IBM_OK;
+        return pend_push(c, pending, s, nl);
     };
     timed(c, IBM_KERNEL_SOR_RESIDUAL, 0, [&](hipEvent_t ea, hipEvent_t eb) {
         LAUNCH_EV(ea, eb, k_sor_residual, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)c->phr,
@@ -515,7 +573,8 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                         chk.slot = c->dslots + cs;
                     }
                     auto launch = [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, tb_kernel, dim3(tb_blocks), dim3(kTbThreads), 0, c->g,
+                        // one more block takes the carried test (past the tiles)
+                        LAUNCH_EV(ea, eb, tb_kernel, dim3(tb_blocks + (chk.nb > 0 ? 1 : 0)), dim3(kTbThreads), 0, c->g,
                                   (const double*)cur[0], (const double*)cur[1], alt[0], alt[1],
                                   (const double*)c->vbr, (const double*)c->vbb, omega, ctl, chk, ts, n, resid,
                                   part);
@@ -523,8 +582,8 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                     if (n == S) timed(c, IBM_KERNEL_SOR_TB, it + n, launch);
                     else launch(nullptr, nullptr);
                     if (cs >= 0) {
-                        HIP_TRY(hipEventRecord(c->ev[cs], c->stream));
-                        pending.emplace_back(cs, carry_nl);
+                        rc = pend_push(c, pending, cs, carry_nl);
+                        if (rc) return rc;
                         carry.nb = 0;
                     }
                     std::swap(cur, alt);
@@ -576,10 +635,7 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
             c->err = "SOR loop ended without a finishing check";
             return IBM_ERR_STATE;
         }
-        const int s = pending.front().first;
-        done_launches = pending.front().second;
-        pending.pop_front();
-        rc = wait_slot(c, s, &sn);
+        rc = pend_pop(c, pending, &sn, &done_launches);
         if (rc) return rc;
         if (first) {
             out->bn = sn.bn;
@@ -636,7 +692,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     int32_t rc = reset_ctl(c, CTL_P);
     if (rc) return rc;
     ++c->solve_id;
-    std::deque<std::pair<int, long>> pending;  // (slot, refinements before the test)
+    CheckQueue pending;  // tags: refinements before the test
     long nref = 0;
     TbCheck carry = {nullptr, 0, 0, max_e, (int)fixed_mode, tol_e, nullptr};
     long carry_nl = 0;
@@ -645,9 +701,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
         hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, prt, nbr, phase, it, max_e, tol_e,
                            (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
-        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-        pending.emplace_back(s, nl);
-        return IBM_OK;
+        return pend_push(c, pending, s, nl);
     };
     // phi + e and its residual into the other pairs
     auto refine = [&](int e_zero, int it_after) -> int32_t {
@@ -680,15 +734,16 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
         a.er = ecur[0]; a.eb = ecur[1]; a.oer = ealt[0]; a.oeb = ealt[1];
         a.rr = rcur[0]; a.rb = rcur[1];
         auto go = [&](hipEvent_t ea, hipEvent_t eb) {
-            LAUNCH_EV(ea, eb, k_sor_mp, dim3(tb_blocks), dim3(kTbThreads), 0, c->g, a, omega, ctl, chk, ts, n,
+            LAUNCH_EV(ea, eb, k_sor_mp, dim3(tb_blocks + (chk.nb > 0 ? 1 : 0)), dim3(kTbThreads), 0, c->g, a, omega,
+                      ctl, chk, ts, n,
                       e_zero);
         };
         if (n == S) timed(c, IBM_KERNEL_SOR_MP, it_after, go);
         else go(nullptr, nullptr);
         LAUNCH_CHECK();
         if (cs >= 0) {
-            HIP_TRY(hipEventRecord(c->ev[cs], c->stream));
-            pending.emplace_back(cs, carry_nl);
+            const int32_t r2 = pend_push(c, pending, cs, carry_nl);
+            if (r2) return r2;
             carry.nb = 0;
         }
         std::swap(ecur, ealt);
@@ -728,10 +783,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
             c->err = "mixed-precision SOR loop ended without a finishing check";
             return IBM_ERR_STATE;
         }
-        const int s = pending.front().first;
-        done_refs = pending.front().second;
-        pending.pop_front();
-        rc = wait_slot(c, s, &sn);
+        rc = pend_pop(c, pending, &sn, &done_refs);
         if (rc) return rc;
         if (first) {
             out->bn = sn.bn;
@@ -775,14 +827,14 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
     if (!rc) rc = fill(c, c->pp2, n, 0.0);
     if (rc) return rc;
     ++c->solve_id;
-    std::deque<int> pending;
+    CheckQueue pending;
     hipLaunchKernelGGL(k_pcg_init, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, c->pr, c->pz, part_r);
     const int s0 = next_slot(c);
     hipLaunchKernelGGL(k_pcg_init_check, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e,
                        c->dslots + s0);
     LAUNCH_CHECK();
-    HIP_TRY(hipEventRecord(c->ev[s0], c->stream));
-    pending.push_back(s0);
+    rc = pend_push(c, pending, s0, 0);
+    if (rc) return rc;
     Slot sn;
     bool first = true;
     int kk = 0;          // next iteration to enqueue
@@ -804,8 +856,8 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
                 });
             }
             LAUNCH_CHECK();
-            HIP_TRY(hipEventRecord(c->ev[s], c->stream));
-            pending.push_back(s);
+            rc = pend_push(c, pending, s, k0);
+            if (rc) return rc;
             ++kk;
             if ((int)pending.size() < kAheadPcg && kk <= max_e) continue;
         }
@@ -813,9 +865,7 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
             c->err = "PCG loop ended without a finishing check";
             return IBM_ERR_STATE;
         }
-        const int s = pending.front();
-        pending.pop_front();
-        rc = wait_slot(c, s, &sn);
+        rc = pend_pop(c, pending, &sn, nullptr);
         if (rc) return rc;
         if (first) {
             out->bn = sn.bn;
@@ -846,6 +896,116 @@ int32_t pcg_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
                            c->pz, part_r);
         const int s = next_slot(c);
         hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_r, nb, tol_e, 1,
+                           c->dslots + s);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[s], c->stream));
+        Slot f;
+        rc = wait_slot(c, s, &f);
+        if (rc) return rc;
+        sn.rn = f.rn;
+    }
+    out->status = sn.status;
+    out->iters = sn.iters;
+    out->rn = sn.rn;
+    prune_samples(c, sn.iters);
+    return IBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One-reduction Jacobi-PCG on M x = -vb (natural layout).  r = -vb + A x and
+// the phase-0 test (k_pcg_init, k_pcg_init_check), w = M u (k_cg1_w), then
+// one k_cg1_iter per iteration; r, w and s alternate between two buffers by
+// iteration parity (r: pr / pz, w: pq / cgw, s: pp2 / cgs; p in pp), the
+// partials between two sets.  A recursive residual that passes is confirmed
+// with the true residual; on failure the recurrences restart from it.
+// ---------------------------------------------------------------------------
+int32_t cg1_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_iter, int fixed, LoopOut* out) {
+    Ctl* ctl = c->ctl + CTL_P;
+    const dim3 bl(kBlock), rb(kRedThreads);
+    const bool fixed_mode = fixed >= 0;
+    const double tol_e = fixed_mode ? -1.0 : tol;
+    const int max_e = fixed_mode ? fixed : max_iter;
+    const size_t n = (size_t)c->nx * c->ny;
+    const int nb = red_blocks(n);
+    double* part[2] = {c->partials, c->partials + 3 * (size_t)kRedMax};
+    double* part_b = c->partials + 6 * (size_t)kRedMax;  // r.r, r.z, b.b of the start
+    double* R[2] = {c->pr, c->pz};
+    double* Wb[2] = {c->pq, c->cgw};
+    double* S[2] = {c->pp2, c->cgs};
+    int32_t rc = reset_ctl(c, CTL_P);
+    if (rc) return rc;
+    ++c->solve_id;
+    CheckQueue pending;
+    hipLaunchKernelGGL(k_pcg_init, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, R[0], Wb[1], part_b);
+    const int s0 = next_slot(c);
+    hipLaunchKernelGGL(k_pcg_init_check, dim3(1), bl, 0, c->stream, ctl, (const double*)part_b, nb, tol_e,
+                       c->dslots + s0);
+    hipLaunchKernelGGL(k_cg1_w, dim3(nb), rb, 0, c->stream, c->g, (const double*)R[0], (const double*)c->rdn, Wb[0],
+                       part[0]);
+    LAUNCH_CHECK();
+    rc = pend_push(c, pending, s0, 0);
+    if (rc) return rc;
+    Slot sn;
+    bool first = true;
+    int kk = 0;  // next iteration to enqueue
+    int restart = 1;
+    for (;;) {
+        if (kk <= max_e) {
+            const int s = next_slot(c);
+            const int k0 = kk, fr = restart;
+            timed(c, IBM_KERNEL_CG1_ITER, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
+                LAUNCH_EV(ea, eb, k_cg1_iter, dim3(nb), rb, 0, c->g, x, c->pp, (const double*)R[k0 & 1],
+                          (const double*)Wb[k0 & 1], (const double*)S[(k0 + 1) & 1], R[(k0 + 1) & 1],
+                          Wb[(k0 + 1) & 1], S[k0 & 1], (const double*)c->rdn, ctl, (const double*)part[k0 & 1], nb,
+                          part[(k0 + 1) & 1], k0, max_e, tol_e, (int)fixed_mode, fr, c->dslots + s);
+            });
+            restart = 0;
+            LAUNCH_CHECK();
+            rc = pend_push(c, pending, s, k0);
+            if (rc) return rc;
+            ++kk;
+            if ((int)pending.size() < kAheadPcg && kk <= max_e) continue;
+        }
+        if (pending.empty()) {
+            c->err = "one-reduction CG loop ended without a finishing check";
+            return IBM_ERR_STATE;
+        }
+        rc = pend_pop(c, pending, &sn, nullptr);
+        if (rc) return rc;
+        if (first) {
+            out->bn = sn.bn;
+            out->r0 = sn.r0;
+            out->zero_rhs = sn.zero_rhs;
+            first = false;
+        }
+        if (!sn.done) continue;
+        if (sn.status != kStConfirm) break;
+        // the recursive residual passed: confirm with the true residual of x
+        // (into the r buffer of iteration sn.iters, for a restart)
+        pending.clear();
+        const int k1 = sn.iters;
+        hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, R[k1 & 1],
+                           Wb[(k1 + 1) & 1], part_b);
+        const int sc = next_slot(c);
+        hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_b, nb, tol_e, 0,
+                           c->dslots + sc);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(c->ev[sc], c->stream));
+        rc = wait_slot(c, sc, &sn);
+        if (rc) return rc;
+        if (sn.done) break;
+        // resume from the true residual: w = M u, then iteration k1 afresh
+        hipLaunchKernelGGL(k_cg1_w, dim3(nb), rb, 0, c->stream, c->g, (const double*)R[k1 & 1],
+                           (const double*)c->rdn, Wb[k1 & 1], part[k1 & 1]);
+        LAUNCH_CHECK();
+        kk = k1;
+        restart = 1;
+    }
+    if (fixed_mode && sn.status == kStOk && sn.iters > 0) {
+        hipLaunchKernelGGL(k_pcg_true_residual, dim3(nb), rb, 0, c->stream, c->g, (const double*)x, vb, R[0], R[1],
+                           part_b);
+        const int s = next_slot(c);
+        hipLaunchKernelGGL(k_pcg_confirm, dim3(1), bl, 0, c->stream, ctl, (const double*)part_b, nb, tol_e, 1,
                            c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
@@ -1080,8 +1240,9 @@ int32_t pressure_solve(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
 
 int32_t pressure_solve_body(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) {
     const ibm_params& P = c->P;
-    if (P.p_method == IBM_SOLVER_PCG) {
-        int32_t rc = pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out);
+    if (P.p_method == IBM_SOLVER_PCG || P.p_method == IBM_SOLVER_CG1) {
+        int32_t rc = P.p_method == IBM_SOLVER_PCG ? pcg_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out)
+                                                  : cg1_loop(c, c->phi, c->vb, P.p_tol, P.p_max_iter, fixed, out);
         if (rc) return rc;
         if (out->zero_rhs) return fill(c, c->phi, (size_t)c->nx * c->ny, 0.0);
         return IBM_OK;
@@ -1168,6 +1329,25 @@ int32_t pressure_solve_body(ibm_ctx* c, const Body& B, int fixed, LoopOut* out) 
     return IBM_OK;
 }
 
+// Phase boundary k of the current step (phase k starts here).
+int32_t phase_mark(ibm_ctx* c, int k) {
+    if (!c->phase_on || c->in_batch) return IBM_OK;
+    HIP_TRY(hipEventRecord(c->pev[k], c->stream));
+    return IBM_OK;
+}
+
+// After the step's final synchronisation: add the phases' durations.
+int32_t phase_accumulate(ibm_ctx* c) {
+    if (!c->phase_on || c->in_batch) return IBM_OK;
+    for (int k = 0; k < IBM_PHASE_COUNT; ++k) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->pev[k], c->pev[k + 1]));
+        c->phase_ms[k] += ms;
+    }
+    c->phase_steps += 1;
+    return IBM_OK;
+}
+
 // A time step is step_pre (everything up to the initial guess of the
 // pressure solve), the pressure solve, and step_post (projection, pressure
 // update, statistics).  A batch of contexts runs step_pre and step_post per
@@ -1183,14 +1363,20 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     const dim3 bl(kBlock);
 
     // flags and forced-node lists for the body at t^{n+1}
+    int32_t rc = phase_mark(c, IBM_PHASE_FLAGGING);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, c->stream, c->g, B, c->box, c->flu, c->flv, c->msrc,
                        c->list_u, c->list_v, c->counts);
     // explicit momentum predictor
+    rc = phase_mark(c, IBM_PHASE_MOMENTUM);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_momentum_u, grid2(nx + 1, ny), bl, 0, c->stream, c->g, (const double*)c->u,
                        (const double*)c->v, (const double*)c->p, c->nu, c->ru, dt, re, P.u_inf, c->have_hist);
     hipLaunchKernelGGL(k_momentum_v, grid2(nx, ny + 1), bl, 0, c->stream, c->g, (const double*)c->u,
                        (const double*)c->v, (const double*)c->p, c->nv, c->rv, dt, re, c->have_hist);
     // discrete forcing and forces
+    rc = phase_mark(c, IBM_PHASE_FORCING);
+    if (rc) return rc;
     const double uref = P.u_inf != 0.0 ? P.u_inf : 1.0;
     const double qn = 0.5 * uref * uref * P.chord;
     hipLaunchKernelGGL(k_forcing, dim3(1), dim3(1024), 0, c->stream, c->g, B, (const double*)c->u,
@@ -1204,8 +1390,10 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     c->have_hist = 1;
 
     // implicit viscous half
+    rc = phase_mark(c, IBM_PHASE_UV_SOLVE);
+    if (rc) return rc;
     LoopOut hu, hv;
-    int32_t rc = helm_loop(c, 0, beta, &hu);
+    rc = helm_loop(c, 0, beta, &hu);
     if (rc) return rc;
     rc = helm_loop(c, 1, beta, &hv);
     if (rc) return rc;
@@ -1220,6 +1408,8 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     }
 
     // pressure correction
+    rc = phase_mark(c, IBM_PHASE_POISSON_RHS);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_poisson_rhs, grid2(nx, ny), bl, 0, c->stream, c->g, (const double*)c->u,
                        (const double*)c->v, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
                        (const uint8_t*)c->msrc, B.vb, dt, P.q_mode, c->vb);
@@ -1228,6 +1418,8 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
     c->net_step = 1.0;
     if (c->net) HIP_TRY(hipMemsetAsync(c->wscale + 3, 0, sizeof(double), c->stream));
     rc = warm_start(c, B);
+    if (rc) return rc;
+    rc = phase_mark(c, IBM_PHASE_P_SOLVE);
     if (rc) return rc;
     *status_out = status;
     return IBM_OK;
@@ -1239,6 +1431,8 @@ int32_t step_post(ibm_ctx* c, ibm_step_stats* st, const LoopOut& po, int status)
     const double dt = P.dt, beta = dt / (2.0 * P.re);
     const double t1 = (double)(c->step + 1) * dt;
     const dim3 bl(kBlock);
+    int32_t rc = phase_mark(c, IBM_PHASE_PROJECTION);
+    if (rc) return rc;
     if (c->snap_target) {
         const Coarse cg = coarse_of(c);
         hipLaunchKernelGGL(k_ws_target, dim3(red_blocks((size_t)cg.ncx * cg.ncy)), dim3(kRedThreads), 0, c->stream,
@@ -1260,14 +1454,18 @@ int32_t step_post(ibm_ctx* c, ibm_step_stats* st, const LoopOut& po, int status)
     hipLaunchKernelGGL(k_project_v, grid2(nx, ny + 1), bl, 0, c->stream, c->g, c->v, (const double*)c->phi, dt);
     hipLaunchKernelGGL(k_update_p, grid2(nx, ny), bl, 0, c->stream, c->g, c->p, (const double*)c->phi, beta);
     LAUNCH_CHECK();
-    int32_t rc = sync_periodic(c);
+    rc = sync_periodic(c);
     if (rc) return rc;
 
     // statistics of the step
     HIP_TRY(hipMemcpyAsync(c->hstage, c->coef, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync((int*)(c->hstage + 2), c->counts, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     if (c->n_net) HIP_TRY(hipMemcpyAsync(c->hstage + 4, c->wscale + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    rc = phase_mark(c, IBM_PHASE_COUNT);
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
+    rc = phase_accumulate(c);
+    if (rc) return rc;
     c->cd = c->hstage[0];
     c->cl = c->hstage[1];
     const int* cnt = (const int*)(c->hstage + 2);
@@ -1401,6 +1599,7 @@ struct ibm_batch {
     MpCase* dmp = nullptr;  // device descriptors
     MpCase* hmp = nullptr;  // pinned staging
     int nrblk = 0;          // refinement blocks of all cases
+    int g_nrblk = -1;       // refinement blocks the captured graph was made for
     std::string err;
 };
 
@@ -1556,6 +1755,63 @@ int32_t batch_upload_mp(ibm_batch* b) {
     return IBM_OK;
 }
 
+// Captures graph_iv check intervals of the batched mixed-precision loop
+// (float sweeps from e = 0, refinement, stop tests) into one HIP graph.  A
+// stretch starts after an even number of intervals, i.e. after an odd number
+// of refinements (the initial one included) and an even number of sweep
+// launches, so its pair selectors are the same in every stretch; the checks
+// take their iteration base and snapshot entry from the cursor.
+int32_t batch_capture_mp(ibm_batch* b) {
+    if (b->gexec && b->g_ntotal == b->ntotal && b->g_per == b->per && b->g_iv == b->graph_iv &&
+        b->g_nrblk == b->nrblk)
+        return IBM_OK;
+    if (b->gexec) {
+        BATCH_TRY(hipStreamSynchronize(b->stream));  // a replay of the old graph may still run
+        BATCH_TRY(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
+    const int n = (int)b->cs.size();
+    BATCH_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    long nsw = 0, nref = 1;
+    for (int j = 0; j < b->graph_iv; ++j) {
+        int e_zero = 1;
+        for (int i = 0; i < b->K;) {
+            const int ns = std::min(b->S, b->K - i);
+            hipLaunchKernelGGL(k_sor_mp_batch, dim3(8 * b->per), dim3(kTbThreads), 0, b->cap, (const MpCase*)b->dmp,
+                               n, b->ntotal, b->per, (int)(nsw & 1), (int)(nref & 1), ns, e_zero);
+            ++nsw;
+            e_zero = 0;
+            i += ns;
+        }
+        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kRedThreads), 0, b->cap, (const MpCase*)b->dmp, n,
+                           b->nrblk, (int)(nref & 1), (int)(nsw & 1), 0, (int)((nref + 1) & 1), (int)(nref & 1));
+        ++nref;
+        hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(kTbThreads), 0, b->cap, (const MpCase*)b->dmp, 1,
+                           (j + 1) * b->K, (int)((nref - 1) & 1), b->dslots, (const int*)b->dcur);
+    }
+    const hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        b->err = std::string("capture of the batched mixed-precision solve failed: ") +
+                 hipGetErrorString(le != hipSuccess ? le : ce);
+        return IBM_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiateWithFlags(&b->gexec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        b->gexec = nullptr;
+        b->err = std::string("hipGraphInstantiateWithFlags: ") + hipGetErrorString(ie);
+        return IBM_ERR_HIP;
+    }
+    b->g_ntotal = b->ntotal;
+    b->g_per = b->per;
+    b->g_iv = b->graph_iv;
+    b->g_nrblk = b->nrblk;
+    return IBM_OK;
+}
+
 // The mixed-precision pressure solves of all contexts of the batch, in the
 // single-grid order: a refinement of the initial phi (phase-0 test), then per
 // check interval the float sweeps from e = 0, a refinement and the test.
@@ -1577,6 +1833,10 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
     }
     int32_t rc = batch_upload_mp(b);
     if (rc) return rc;
+    if (b->graph_iv > 0) {
+        rc = batch_capture_mp(b);
+        if (rc) return rc;
+    }
     long nref = 0, nsw = 0;
     auto refine = [&](int e_zero) -> int32_t {
         hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kRedThreads), 0, b->stream, (const MpCase*)b->dmp,
@@ -1593,7 +1853,8 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
     auto check = [&](int phase, int it) -> int32_t {
         const int e = (int)(b->seq++ % kBatchRing);
         hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
-                           (const MpCase*)b->dmp, phase, it, (int)((nref - 1) & 1), b->dslots + (size_t)e * n);
+                           (const MpCase*)b->dmp, phase, it, (int)((nref - 1) & 1), b->dslots + (size_t)e * n,
+                           (const int*)nullptr);
         if (hipGetLastError() != hipSuccess) {
             b->err = "k_check_mp_batch launch failed";
             return IBM_ERR_HIP;
@@ -1608,11 +1869,33 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
     if (rc) return rc;
     std::vector<char> finished(n, 0);
     std::vector<long> done_refs(n, 0);
-    int nfin = 0, it = 0;
+    int nfin = 0, it = 0, nint = 0;
     bool first = true;
     const int max_e = b->max_iter;
+    const long stretch = (long)b->graph_iv * b->K;
+    const long per_iv = (b->K + b->S - 1) / b->S;
+    const int ahead = b->graph_iv > 0 ? std::max(2, kAheadSor / b->graph_iv) : kAheadSor;
     for (;;) {
-        if (it < max_e) {
+        if (it < max_e && b->gexec && (nint & 1) == 0 && it + stretch <= max_e) {
+            // a captured stretch of graph_iv intervals (it starts after an even
+            // number of intervals: an odd number of refinements, an even
+            // number of sweep launches, as at its capture)
+            const int e = (int)(b->seq++ % kBatchRing);
+            hipLaunchKernelGGL(k_batch_cursor, dim3(1), dim3(kWave), 0, b->stream, b->dcur, it, e);
+            if (hipGetLastError() != hipSuccess) {
+                b->err = "k_batch_cursor launch failed";
+                return IBM_ERR_HIP;
+            }
+            BATCH_TRY(hipGraphLaunch(b->gexec, b->stream));
+            BATCH_TRY(hipEventRecord(b->ev[e], b->stream));
+            pending.emplace_back(e, -1L);
+            it += (int)stretch;
+            nint += b->graph_iv;
+            nsw += per_iv * b->graph_iv;
+            nref += b->graph_iv;
+            if ((int)pending.size() < ahead && it < max_e) continue;
+        } else if (it < max_e) {
+            ++nint;
             const int next = std::min(it + b->K, max_e);
             int e_zero = 1;
             while (it < next) {
@@ -1653,7 +1936,9 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
             if (hs->done) {
                 finished[k] = 1;
                 ++nfin;
-                done_refs[k] = nr;
+                // inside a captured stretch: the initial refinement and one per
+                // interval up to the case's test
+                done_refs[k] = nr >= 0 ? nr : 1 + (hs->iters + b->K - 1) / b->K;
                 outs[k].status = hs->status;
                 outs[k].iters = hs->iters;
                 outs[k].rn = hs->rn;
@@ -1937,6 +2222,13 @@ int32_t ibm_batch_step(ibm_batch* b, int32_t nsteps, ibm_step_stats* last) {
             return IBM_ERR_STATE;
         }
     }
+    // the steps of a batch are not phase-timed (a case's phases would span
+    // the other cases' work)
+    struct InBatch {
+        std::vector<ibm_ctx*>& cs;
+        explicit InBatch(std::vector<ibm_ctx*>& v) : cs(v) { for (ibm_ctx* c : cs) c->in_batch = true; }
+        ~InBatch() { for (ibm_ctx* c : cs) c->in_batch = false; }
+    } in_batch(b->cs);
     std::vector<ibm_step_stats> st(n);
     std::vector<int> status(n, IBM_OK);
     std::vector<double> wall(n, 0.0);
@@ -2023,10 +2315,6 @@ void ibm_batch_destroy(ibm_batch* b) {
 int32_t ibm_batch_set_graph(ibm_batch* b, int32_t intervals) {
     if (!b) return IBM_ERR_INVALID;
     if (intervals != 0 && (intervals < 2 || intervals > kMaxGraphIntervals || (intervals & 1))) return IBM_ERR_INVALID;
-    if (intervals != 0 && b->mp) {
-        b->err = "graph replay is for double-precision batches";
-        return IBM_ERR_INVALID;
-    }
     b->err.clear();
     if (intervals > 0) {
         if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -2081,6 +2369,8 @@ void ibm_destroy(ibm_ctx* c) {
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->t0) (void)hipEventDestroy(c->t0);
     if (c->t1) (void)hipEventDestroy(c->t1);
+    for (int k = 0; k <= IBM_PHASE_COUNT; ++k)
+        if (c->pev[k]) (void)hipEventDestroy(c->pev[k]);
     if (c->hslots) (void)hipHostFree(c->hslots);
     if (c->hstage) (void)hipHostFree(c->hstage);
     delete c;
@@ -2114,12 +2404,15 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     g.pcE = D(off.pcE); g.pcW = D(off.pcW); g.pcD = D(off.pcD); g.pcN = D(off.pcN); g.pcS = D(off.pcS);
     g.uce = D(off.uce); g.ucw = D(off.ucw); g.ucn = D(off.ucn); g.ucs = D(off.ucs);
     g.vce = D(off.vce); g.vcw = D(off.vcw); g.vcn = D(off.vcn); g.vcs = D(off.vcs);
+    g.rdr = D(off.rdr); g.rdb = D(off.rdb);
+    g.rdr32 = (const float*)(w + off.rdr32); g.rdb32 = (const float*)(w + off.rdb32);
     c->u = D(off.u); c->nu = D(off.nu); c->ru = D(off.ru); c->fufull = D(off.fufull);
     c->v = D(off.v); c->nv = D(off.nv); c->rv = D(off.rv); c->fvfull = D(off.fvfull);
     c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp);
     c->pp2 = D(off.pp2); c->pq = D(off.pq);
     c->phr = D(off.phr); c->phb = D(off.phb); c->vbr = D(off.vbr); c->vbb = D(off.vbb);
     c->pz = D(off.pz); c->dn = D(off.dn);
+    c->cgw = D(off.cgw); c->cgs = D(off.cgs); c->rdn = D(off.rdn);
     c->phr2 = D(off.phr2); c->phb2 = D(off.phb2);
     c->mpf = (float*)(w + off.mpf);
     c->phi0 = D(off.phi0);
@@ -2186,6 +2479,9 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     if (!rc) {
         hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, c->stream, c->ctl, (int)CTL_N);
         hipLaunchKernelGGL(k_ndiag, grid2(nx, ny), dim3(kBlock), 0, c->stream, c->g, c->dn);
+        hipLaunchKernelGGL(k_rdiag, grid2(nx, ny), dim3(kBlock), 0, c->stream, c->g, (const double*)c->dn, c->rdn);
+        hipLaunchKernelGGL(k_rdiag_split, grid2(c->nh, ny), dim3(kBlock), 0, c->stream, c->g, (double*)c->g.rdr,
+                           (double*)c->g.rdb, (float*)c->g.rdr32, (float*)c->g.rdb32);
         if (hipGetLastError() != hipSuccess) rc = IBM_ERR_HIP;
     }
     if (rc) return fail(rc);
@@ -2232,8 +2528,10 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
                           ibm_solve_stats* st) {
     if (!c) return IBM_ERR_INVALID;
     if (!rhs_dev || !x_dev || !o || o->max_iter < 1 || o->check_every < 1 || o->fixed_iters < 0 ||
-        (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG && o->method != IBM_SOLVER_RBSOR_MP) ||
-        (o->method != IBM_SOLVER_PCG && !(o->omega > 0.0 && o->omega < 2.0)) || !std::isfinite(o->tol) ||
+        (o->method != IBM_SOLVER_RBSOR && o->method != IBM_SOLVER_PCG && o->method != IBM_SOLVER_RBSOR_MP &&
+         o->method != IBM_SOLVER_CG1) ||
+        ((o->method == IBM_SOLVER_RBSOR || o->method == IBM_SOLVER_RBSOR_MP) && !(o->omega > 0.0 && o->omega < 2.0)) ||
+        !std::isfinite(o->tol) ||
         (c->g.per && o->method == IBM_SOLVER_RBSOR_MP)) {
         c->err = "invalid solve options";
         return IBM_ERR_INVALID;
@@ -2244,7 +2542,7 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
     LoopOut lo;
     HIP_TRY(hipEventRecord(c->t0, c->stream));
     int32_t rc;
-    if (o->method == IBM_SOLVER_PCG) {
+    if (o->method == IBM_SOLVER_PCG || o->method == IBM_SOLVER_CG1) {
         // V b in the natural-layout scratch, x in place
         const dim3 gr = grid2(c->nh, c->ny);
         hipLaunchKernelGGL(k_split, gr, bl, 0, c->stream, c->g, rhs_dev, c->vbr, c->vbb, 1);
@@ -2252,7 +2550,8 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
         LAUNCH_CHECK();
         rc = per_project(c, c->vb, 1);
         if (rc) return rc;
-        rc = pcg_loop(c, x_dev, c->vb, o->tol, o->max_iter, fixed, &lo);
+        rc = o->method == IBM_SOLVER_PCG ? pcg_loop(c, x_dev, c->vb, o->tol, o->max_iter, fixed, &lo)
+                                         : cg1_loop(c, x_dev, c->vb, o->tol, o->max_iter, fixed, &lo);
         if (rc) return rc;
         if (lo.zero_rhs) {
             rc = fill(c, x_dev, (size_t)c->nx * c->ny, 0.0);
@@ -2542,6 +2841,22 @@ int32_t ibm_profile(ibm_ctx* c, int32_t sample_every) {
         c->launches[k] = 0;
     }
     c->prof_every = sample_every;
+    for (int k = 0; k < IBM_PHASE_COUNT; ++k) c->phase_ms[k] = 0.0;
+    c->phase_steps = 0;
+    c->phase_on = false;
+    if (sample_every > 0) {
+        for (int k = 0; k <= IBM_PHASE_COUNT; ++k)
+            if (!c->pev[k]) HIP_TRY(hipEventCreate(&c->pev[k]));
+        c->phase_on = true;
+    }
+    return IBM_OK;
+}
+
+int32_t ibm_profile_phases(ibm_ctx* c, double* ms, int32_t n, int64_t* steps) {
+    if (!c || n < 0 || (n > 0 && !ms)) return IBM_ERR_INVALID;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) ms[k] = k < IBM_PHASE_COUNT ? c->phase_ms[k] : 0.0;
+    if (steps) *steps = c->phase_steps;
     return IBM_OK;
 }
 
@@ -2559,7 +2874,7 @@ int32_t ibm_profile_query(ibm_ctx* c, int32_t kernel, double* avg_ms, int64_t* s
     const double cells = (double)c->nx * c->ny;
     const double S = c->tb_sweeps;
     const double bytes[IBM_KERNEL_COUNT] = {24.0 * cells / 2.0, 16.0 * cells, 32.0 * cells, 64.0 * cells,
-                                            24.0 * cells * S, 12.0 * cells * S, 32.0 * cells};
+                                            24.0 * cells * S, 12.0 * cells * S, 32.0 * cells, 88.0 * cells};
     if (avg_ms) *avg_ms = n ? tot / n : 0.0;
     if (samples) *samples = (int64_t)n;
     if (launches) *launches = c->launches[kernel];

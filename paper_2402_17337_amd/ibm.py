@@ -21,17 +21,21 @@ LIB_PATH = os.path.join(HERE, "libibm_hip.so")
 OK, NOT_CONVERGED, ERR_INVALID, ERR_HIP, ERR_STATE, ERR_NAN = 0, 1, -1, -2, -3, -5
 BC_CHANNEL, BC_PERIODIC = 0, 1
 RBSOR, PCG, RBSOR_MP = 0, 1, 2   # RBSOR_MP: float sweeps on the correction, double refinement
+CG1 = 3                          # Jacobi-PCG with one reduction per iteration
 INIT_ZERO, INIT_PREVIOUS, INIT_LEARNED = 0, 1, 2
 (KERNEL_SOR_SWEEP, KERNEL_SOR_RESIDUAL, KERNEL_PCG_DIR_SPMV, KERNEL_PCG_UPDATE, KERNEL_SOR_TB, KERNEL_SOR_MP,
- KERNEL_SOR_MP_REFINE) = range(7)
+ KERNEL_SOR_MP_REFINE, KERNEL_CG1_ITER) = range(8)
 # KERNEL_SOR_TB times whichever blocked sweep runs; named for the default one
 # (k_sor_tb is the LDS-tile variant).
 KERNEL_NAMES = {KERNEL_SOR_SWEEP: "k_sor_sweep", KERNEL_SOR_RESIDUAL: "k_sor_residual",
                 KERNEL_PCG_DIR_SPMV: "k_pcg_dir_spmv", KERNEL_PCG_UPDATE: "k_pcg_update",
-                KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_mp_refine"}
+                KERNEL_SOR_TB: "k_sor_tbr", KERNEL_SOR_MP: "k_sor_mp", KERNEL_SOR_MP_REFINE: "k_mp_refine",
+                KERNEL_CG1_ITER: "k_cg1_iter"}
 (OPT_SOR_KERNEL, OPT_TB_SWEEPS, OPT_TB_TILE_X, OPT_TB_TILE_Y, OPT_NET_FACTOR, OPT_NET_EVERY, OPT_SNAPSHOT_ITER,
  OPT_NET_SMOOTH, OPT_NET_STEP, OPT_NET_MAPS) = range(10)
 NET_STEP_ENERGY, NET_STEP_BACKTRACK = 0, 1
+# phases of ibm_step timed while kernel timing is on (ibm_profile_phases)
+PHASES = ("flagging", "momentum", "forcing", "uv_solve", "poisson_rhs", "p_solve", "projection")
 SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_poisson_solve_noalloc",
@@ -39,7 +43,7 @@ EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", 
             "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
             "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot",
             "ibm_batch_create", "ibm_batch_step", "ibm_batch_set_graph", "ibm_batch_destroy", "ibm_batch_last_error",
-            "ibm_profile", "ibm_profile_query", "ibm_destroy",
+            "ibm_profile", "ibm_profile_query", "ibm_profile_phases", "ibm_destroy",
             "ibm_status_string", "ibm_last_error")
 
 
@@ -135,6 +139,8 @@ def lib():
         L.ibm_profile.restype = C.c_int32
         L.ibm_profile_query.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), dp]
         L.ibm_profile_query.restype = C.c_int32
+        L.ibm_profile_phases.argtypes = [vp, dp, C.c_int32, C.POINTER(C.c_int64)]
+        L.ibm_profile_phases.restype = C.c_int32
         L.ibm_destroy.argtypes = [vp]
         L.ibm_destroy.restype = None
         L.ibm_status_string.argtypes = [C.c_int32]
@@ -385,6 +391,16 @@ class Solver:
         if rc != OK:
             self._err("ibm_profile", rc)
 
+    def profile_phases(self):
+        """Accumulated GPU ms per phase of ibm_step since profile(n > 0), and
+        the number of steps summed."""
+        ms = (C.c_double * len(PHASES))()
+        n = C.c_int64()
+        rc = lib().ibm_profile_phases(self._h, ms, len(PHASES), C.byref(n))
+        if rc != OK:
+            self._err("ibm_profile_phases", rc)
+        return dict(zip(PHASES, list(ms))), n.value
+
     def profile_query(self, kernel: int):
         avg, ns, nl, by = C.c_double(), C.c_int64(), C.c_int64(), C.c_double()
         rc = lib().ibm_profile_query(self._h, kernel, C.byref(avg), C.byref(ns), C.byref(nl), C.byref(by))
@@ -441,6 +457,45 @@ class Batch:
         rc = lib().ibm_batch_set_graph(self._h, intervals)
         if rc != OK:
             raise IbmError(f"ibm_batch_set_graph({intervals}) failed: {status_string(rc)}")
+
+    def autotune_tiles(self, candidates=((104, 32), (104, 40), (80, 32), (64, 32), (48, 16)),
+                       iters: int = 400):
+        """Time one batched step of every case with its pressure solve replayed
+        for `iters` iterations (ibm_set_poisson_schedule), from the current
+        state (restored after each trial), with each candidate tile shape set
+        on every case, and keep the fastest shape for the whole batch.  The
+        tile shape never changes a case's iterates.  Returns the chosen shape
+        and the timings (s)."""
+        import time
+        import torch
+        blobs = [s.get_state() for s in self.solvers]
+        times = {}
+        for tx, ty in candidates:
+            if any(s.set_option(OPT_TB_TILE_X, tx) != OK or s.set_option(OPT_TB_TILE_Y, ty) != OK
+                   for s in self.solvers):
+                continue
+            try:
+                for s in self.solvers:
+                    s.set_poisson_schedule([iters])
+                self.step(1)  # warm-up (descriptor upload, first touch)
+                for s, blob in zip(self.solvers, blobs):
+                    s.set_state(blob)
+                    s.set_poisson_schedule([iters])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                self.step(1)
+                torch.cuda.synchronize()
+                times[(tx, ty)] = time.perf_counter() - t0
+            except IbmError:
+                pass  # a shape with more tiles than the batched sweep takes
+            for s, blob in zip(self.solvers, blobs):
+                s.set_state(blob)
+                s.set_poisson_schedule([])
+        best = min(times, key=times.get)
+        for s in self.solvers:
+            s.set_option(OPT_TB_TILE_X, best[0])
+            s.set_option(OPT_TB_TILE_Y, best[1])
+        return best, times
 
     def step(self, n: int = 1):
         """n time steps of every case; returns the last step's statistics per case."""

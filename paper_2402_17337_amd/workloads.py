@@ -171,6 +171,19 @@ def plunging_stretched(nx: int, ny: int, core_h: float):
                  grid_info=dict(x=ix, y=iy), re=500.0, dt=5e-4, amp=0.5, freq=0.4)
 
 
+def plunging_scaled(nx: int, ny: int):
+    """The 1024x768 plunging case (h = 0.5, f = 0.4, Re 500, dt 5e-4) on an
+    nx x ny grid of the same construction, its core spacing 0.01 * 1024 / nx
+    rounded so that the core [3, 5.5] x [5.2, 6.8] holds a whole number of
+    cells in each direction (the input-scaling series)."""
+    h0 = 0.01 * 1024 / nx
+    xf, ix = stretched_faces(nx, 16.0, 3.0, 5.5, 2.5 / round(2.5 / h0))
+    yf, iy = stretched_faces(ny, 12.0, 5.2, 6.8, 1.6 / round(1.6 / h0))
+    u0, v0, p0 = initial_fields(nx, ny, 1.0)
+    return _pack(f"plunging ellipse {nx}x{ny}, Re 500", nx, ny, xf, yf, u0, v0, p0, 2000,
+                 grid_info=dict(x=ix, y=iy), re=500.0, dt=5e-4, amp=0.5, freq=0.4)
+
+
 def batched_plunging(n: int = 64, seed: int = 0):
     """The many-case workload: n plunging-ellipse cases from a seeded
     generator, nx uniform on the multiples of 32 in [256, 1024], ny = 3 nx / 4,

@@ -62,8 +62,9 @@ def test_workspace_bytes_is_pure_and_scales():
     b = ibm.workspace_bytes(1024, 768)
     assert a > 0 and b > 50 * a
     assert b % 256 == 0
-    # about 20 doubles per cell at the plunging 1024x768 workload
-    assert 15 * 8 * 1024 * 768 < b < 30 * 8 * 1024 * 768
+    # about 33 doubles per cell at the plunging 1024x768 workload (fields,
+    # solver vectors, split copies, network maps)
+    assert 25 * 8 * 1024 * 768 < b < 40 * 8 * 1024 * 768
     assert ibm.workspace_bytes(127, 96) == 0
     assert ibm.workspace_bytes(6, 96) == 0
 

@@ -64,8 +64,6 @@ def test_mixed_precision_batch_equals_solo_steps_bitwise(check):
     over = dict(p_method=ibm.RBSOR_MP, p_check=check)
     solo = [_solver(w, t, **over) for w, t in zip(wls, TILES)]
     batch = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
-    with pytest.raises(ibm.IbmError):
-        batch.set_graph(2)  # no graph form of the mixed-precision batch
     for step in range(3):
         st_b = batch.step(1)
         for k, s in enumerate(solo):
@@ -79,19 +77,24 @@ def test_mixed_precision_batch_equals_solo_steps_bitwise(check):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("intervals,cap", [(4, None), (6, 1234)])
-def test_graph_replayed_batch_equals_launched_batch_bitwise(intervals, cap):
+@pytest.mark.parametrize("intervals,cap,mixed", [(4, None, False), (6, 1234, False), (4, None, True),
+                                                 (6, 1234, True)])
+def test_graph_replayed_batch_equals_launched_batch_bitwise(intervals, cap, mixed):
     """Stretches of `intervals` check intervals replayed from one HIP graph,
     with each case's steps around the solve run eagerly between the replays:
     every step equals the batch launched interval by interval.  With the cap
     (1234 iterations: 30 stretches of 40 or 20 of 60, then intervals launched
     one by one, the last of 4 iterations) some solves end at the limit; in
     the uncapped run the cases finish inside stretches.  The last step runs
-    with the graph switched off again."""
+    with the graph switched off again.  mixed: FP32 sweeps with FP64
+    refinement every 10 iterations (the stretch holds the sweeps, the
+    refinement and the stop tests of each interval)."""
     _need_gpu()
     from paper_2402_17337_amd import ibm
     wls = _cases()
     over = {} if cap is None else {"p_max_iter": cap}
+    if mixed:
+        over.update(p_method=ibm.RBSOR_MP, p_check=10)
     plain = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
     graphed = ibm.Batch([_solver(w, t, **over) for w, t in zip(wls, TILES)])
     graphed.set_graph(intervals)

@@ -229,3 +229,84 @@ def test_blocked_sweep_rejects_shapes_that_do_not_fit(torch):
     assert g.set_option(ibm.OPT_TB_TILE_X, 256) == ibm.ERR_INVALID     # halo tile > LDS
     assert g.set_option(99, 1) == ibm.ERR_INVALID
     assert g.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK
+
+
+# --- one-reduction Jacobi-PCG (IBM_SOLVER_CG1) -------------------------------
+
+@pytest.mark.parametrize("nx,ny,stretched", [(128, 96, False), (200, 150, True), (16, 8, False)])
+def test_cg1_fixed_iterations_match_oracle(torch, nx, ny, stretched):
+    """The GPU's one-reduction CG against the oracle's (the same recurrences;
+    sums in another order), and against textbook PCG on the GPU."""
+    o, g = _pair(torch, nx, ny, stretched)
+    rng = np.random.default_rng(17)
+    b = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    k = 60 if nx > 16 else 20
+    xo, so, rc = o.poisson_solve(b, x0=x0, method=O.CG1, fixed=k)
+    xd = _dev(torch, x0)
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.CG1, fixed_iters=k)
+    xg = xd.cpu().numpy()
+    xp = _dev(torch, x0)
+    g.poisson_solve(_dev(torch, b), xp, method=ibm.PCG, fixed_iters=k)
+    print(f"cg1 rel {rel_l2(xg, xo):.3e} vs gpu pcg {rel_l2(xg, xp.cpu().numpy()):.3e}", flush=True)
+    assert sg["iters"] == so["iters"] == k
+    assert rel_l2(xg, xo) <= TOL
+    assert rel_l2(xg, xp.cpu().numpy()) <= TOL
+    assert abs(sg["rel"] - so["rel"]) <= 1e-8 * so["rel"]
+
+
+def test_cg1_to_tolerance_agrees_with_oracle(torch):
+    nx, ny = 96, 64
+    o, g = _pair(torch, nx, ny, True)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((ny, nx))
+    xo, so, rc = o.poisson_solve(b, method=O.CG1, tol=1e-12, max_iter=20000)
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.CG1, tol=1e-12, max_iter=20000)
+    xg = xd.cpu().numpy()
+    print(f"cg1 iters gpu {sg['iters']} oracle {so['iters']} rel {rel_l2(xg, xo):.3e}", flush=True)
+    assert rc == O.OK and sg["rc"] == ibm.OK
+    assert abs(sg["iters"] - so["iters"]) <= 3
+    assert sg["rel"] <= 1e-12
+    assert rel_l2(xg, xo) <= TOL
+    V = np.outer(np.diff(o.yf), np.diff(o.xf))
+    r = V * b - o.apply_A(xg)
+    assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(V * b)
+
+
+def test_cg1_zero_rhs_limit_and_nan(torch):
+    nx, ny = 64, 48
+    _, g = _pair(torch, nx, ny)
+    xd = torch.ones((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(torch.zeros_like(xd), xd, method=ibm.CG1)
+    assert sg["iters"] == 0 and sg["rc"] == ibm.OK and float(xd.abs().max()) == 0.0
+    b = torch.ones_like(xd)
+    xd.zero_()
+    sg = g.poisson_solve(b, xd, method=ibm.CG1, tol=1e-15, max_iter=25)
+    assert sg["rc"] == ibm.NOT_CONVERGED and sg["iters"] == 25
+    b[5, 7] = float("nan")
+    xd.zero_()
+    sg = g.poisson_solve(b, xd, method=ibm.CG1)
+    assert sg["rc"] == ibm.ERR_NAN
+
+
+def test_cg1_full_size_grid_to_tolerance(torch):
+    """The 1024x768 stretched grid in the benchmark's launch configuration, to
+    1e-10: the result meets the stop test by the oracle's operator and lies
+    within the solver tolerance of the oracle's textbook PCG."""
+    c = W.plunging_1024x768()
+    nx, ny = c["nx"], c["ny"]
+    o, g = _pair(torch, nx, ny, faces=(c["xf"], c["yf"]))
+    X, Y = np.meshgrid(0.5 * (c["xf"][1:] + c["xf"][:-1]), 0.5 * (c["yf"][1:] + c["yf"][:-1]))
+    b = np.exp(-((X - 4.0) ** 2 + (Y - 6.0) ** 2)) - np.exp(-((X - 9.0) ** 2 + (Y - 4.0) ** 2))
+    xd = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    sg = g.poisson_solve(_dev(torch, b), xd, method=ibm.CG1, tol=1e-10, max_iter=200000)
+    xg = xd.cpu().numpy()
+    V = np.outer(np.diff(o.yf), np.diff(o.xf))
+    r = V * b - o.apply_A(xg)
+    print(f"cg1 1024x768 iters {sg['iters']} rel {np.linalg.norm(r) / np.linalg.norm(V * b):.3e}", flush=True)
+    assert sg["rc"] == ibm.OK
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(V * b)
+    xo, so, _ = o.poisson_solve(b, method=O.PCG, tol=1e-10, max_iter=200000)
+    assert abs(sg["iters"] - so["iters"]) <= max(10, so["iters"] // 100)
+    assert rel_l2(xg, xo) <= 1e-6  # both within the tolerance of the exact solution (cond ~ 1e4)

@@ -209,3 +209,19 @@ def test_free_stream_preserved_on_gpu(torch):
     assert st["rc"] == ibm.OK
     u, v, p, _ = g.fields()
     assert np.max(np.abs(u - 1.0)) < 1e-14 and np.max(np.abs(v)) < 1e-14 and np.max(np.abs(p)) < 1e-14
+
+
+def test_cg1_steps_match_oracle(torch):
+    """Steps of the small plunging case with the one-reduction CG to 1e-12:
+    u, v, p within 1e-10 of the oracle's steps with the same solver."""
+    c = W.small_plunging()
+    prm = dict(c["params"], p_method=O.CG1, p_tol=1e-12, p_max_iter=50000)
+    o = O.Oracle(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], **prm)
+    rc, so = o.step(5)
+    assert rc == O.OK
+    g = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], **dict(prm, p_method=ibm.CG1))
+    for k in range(5):
+        st = g.step(1)
+        assert st["rc"] == ibm.OK and abs(st["p_iters"] - so[k]["p_iters"]) <= 3, (st, so[k])
+    for a, b, name in zip(g.fields()[:3], o.fields()[:3], "uvp"):
+        assert rel_l2(a, b) <= 1e-10, (name, rel_l2(a, b))
