@@ -74,7 +74,8 @@
 #define ORC_PCG 1
 #define ORC_SOR_MP 2
 #define ORC_CG1 3     /* Jacobi-PCG with one reduction per iteration */
-#define ORC_PCG_MP 4  /* single-precision CG on the correction, double refinement */
+#define ORC_PCG_MP 4  /* single-precision CG with double reliable updates */
+#define ORC_MP_DROP 0.1  /* reliable update once the float residual drops by this factor */
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -99,7 +100,6 @@ typedef struct {
     double uv_omega, uv_tol;
     int32_t uv_max_iter, q_mode;
     double alpha_max;
-    double p_inner_tol;  /* ORC_PCG_MP: relative residual of each inner solve */
 } orc_params;
 
 typedef struct {
@@ -537,6 +537,7 @@ static int poisson_cg1(const orc_ctx *c, const double *vb, double *x, double tol
  * arithmetic throughout. */
 static void apply_M_f32(const orc_ctx *c, const float *x, float *y) {
     const int nx = c->nx, ny = c->ny;
+
 #pragma omp parallel for schedule(static) if (c->nx * c->ny >= ORC_OMP_MIN_CELLS)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -577,19 +578,23 @@ static double dot_f32(const float *a, const float *b, size_t n) {
     return s + comp;
 }
 
-/* Mixed precision Jacobi-PCG: iterative refinement in double around an inner
- * single-precision CG.  Each cycle takes the double residual r = vb - A x of
- * the current x, solves the correction equation M e = -r (M = -A) by the
- * one-reduction CG of poisson_cg1 in single precision (vectors and operator
- * in float, inner products in double, the scalars rounded to float for the
- * vector updates) from e = 0 until its recursive residual falls to
- * inner_tol times its initial one or the cycle reaches `cap` iterations, then
- * x += e in double and the residual and stop test are evaluated in double.
- * Iterations count inner CG iterations.  refine = 0 runs a single inner
- * solve of max_iter iterations and adds its correction (the stall of
- * single-precision CG that the refinement removes). */
-static int poisson_pcg_mp(const orc_ctx *c, const double *vb, double *x, double tol, int max_iter, int cap,
-                          double inner_tol, int refine, orc_solve_stats *st) {
+/* Mixed precision Jacobi-PCG with reliable updates: the one-reduction CG of
+ * poisson_cg1 runs in single precision on the correction equation M e = -r of
+ * the current double x (vectors e, r, u = D^-1 r, w = M u, p, s and the
+ * operator in float; inner products in double; alpha and beta rounded to
+ * float for the vector updates), and the recurrences are never restarted.
+ * Whenever the float residual has dropped to ORC_MP_DROP times the largest
+ * one since the last update, after at most `every` iterations, and when it
+ * passes the stop test, x += e in double, e = 0, the double residual
+ * r = vb - A x is formed and tested, and its float rounding replaces the
+ * recursive residual (residual replacement, as in reliable-update CG): the
+ * search direction and its product s = M p carry on, so the Krylov space is
+ * kept, while the residual the iteration works on stays the true one up to
+ * float rounding.  Iterations count CG iterations.  refine = 0: single
+ * precision alone, no replacement; the solve ends when the float residual
+ * passes the test or at max_iter, then x += e. */
+static int poisson_pcg_mp(const orc_ctx *c, const double *vb, double *x, double tol, int max_iter, int every,
+                          int refine, orc_solve_stats *st) {
     const size_t n = (size_t)c->nx * c->ny;
     double *r = c->w0;
     float *fr = calloc(n, sizeof(float)), *fu = calloc(n, sizeof(float)), *fw = calloc(n, sizeof(float));
@@ -601,50 +606,58 @@ static int poisson_pcg_mp(const orc_ctx *c, const double *vb, double *x, double 
     if (!fr || !fu || !fw || !fp || !fs || !fe || !fd) { rc = ORC_ERR_INVALID; goto out; }
     if (!isfinite(bn)) { st->status = rc = ORC_ERR_NAN; goto out; }
     if (bn == 0.0) { memset(x, 0, n * sizeof(double)); goto out; }
-    if (cap < 1) cap = max_iter;
     diag_M_f32(c, fd);
     double rn = poisson_resid_norm(c, x, vb, r);
     st->r0_rel = rn / bn; st->rel = rn / bn;
     if (!isfinite(rn)) { st->status = rc = ORC_ERR_NAN; goto out; }
-    int it = 0;
     if (refine && rn <= tol * bn) goto out;
-    while (it < max_iter) {
-        /* inner solve of M e = -r from e = 0: its residual starts at -r */
-        const int lim = refine ? (cap < max_iter - it ? cap : max_iter - it) : max_iter;
-        for (size_t k = 0; k < n; ++k) { fr[k] = (float)(-r[k]); fe[k] = 0.0f; }
-        const double r0in = sqrt(dot_f32(fr, fr, n));
-        double gamma_old = 0.0, alpha = 0.0;
-        int start = 1, k_in = 0;
-        for (;;) {
-            for (size_t k = 0; k < n; ++k) fu[k] = fr[k] / fd[k];
-            apply_M_f32(c, fu, fw);
-            double gamma = dot_f32(fr, fu, n), delta = dot_f32(fw, fu, n);
-            if (start) {
-                alpha = gamma / delta;
-                for (size_t k = 0; k < n; ++k) { fp[k] = fu[k]; fs[k] = fw[k]; }
-                start = 0;
-            } else {
-                double beta = gamma / gamma_old;
-                alpha = gamma / (delta - beta * gamma / alpha);
-                const float fb = (float)beta;
-                for (size_t k = 0; k < n; ++k) { fp[k] = fu[k] + fb * fp[k]; fs[k] = fw[k] + fb * fs[k]; }
-            }
-            gamma_old = gamma;
-            if (k_in >= lim) break;
-            const float fa = (float)alpha;
-            for (size_t k = 0; k < n; ++k) { fe[k] += fa * fp[k]; fr[k] -= fa * fs[k]; }
-            ++k_in;
-            double rin = sqrt(dot_f32(fr, fr, n));
-            if (!isfinite(rin)) break;
-            if (refine && rin <= inner_tol * r0in) break;
+    for (size_t k = 0; k < n; ++k) { fr[k] = (float)(-r[k]); fe[k] = 0.0f; }
+    int it = 0, start = 1, since = 0;
+    double rmax = sqrt(dot_f32(fr, fr, n));  /* largest float residual since the last update */
+    double gamma_old = 0.0, alpha = 0.0;
+    for (;;) {
+        for (size_t k = 0; k < n; ++k) fu[k] = fr[k] / fd[k];
+        apply_M_f32(c, fu, fw);
+        double gamma = dot_f32(fr, fu, n), delta = dot_f32(fw, fu, n);
+        if (start) {
+            alpha = gamma / delta;
+            for (size_t k = 0; k < n; ++k) { fp[k] = fu[k]; fs[k] = fw[k]; }
+            start = 0;
+        } else {
+            double beta = gamma / gamma_old;
+            alpha = gamma / (delta - beta * gamma / alpha);
+            const float fb = (float)beta;
+            for (size_t k = 0; k < n; ++k) { fp[k] = fu[k] + fb * fp[k]; fs[k] = fw[k] + fb * fs[k]; }
         }
+        gamma_old = gamma;
+        if (it >= max_iter) break;
+        const float fa = (float)alpha;
+        for (size_t k = 0; k < n; ++k) { fe[k] += fa * fp[k]; fr[k] -= fa * fs[k]; }
+        ++it; ++since;
+        double rin = sqrt(dot_f32(fr, fr, n));
+        if (!isfinite(rin)) { st->iters = it; st->status = rc = ORC_ERR_NAN; goto out; }
+        const int passed = rin <= tol * bn;
+        if (!refine) { if (passed || it >= max_iter) break; continue; }
+        if (rin > rmax) rmax = rin;
+        if (passed || rin <= ORC_MP_DROP * rmax || (every > 0 && since >= every) || it >= max_iter) {
+            /* reliable update: x += e, the double residual, its test, and
+             * the float residual replaced by it */
+            for (size_t k = 0; k < n; ++k) { x[k] += (double)fe[k]; fe[k] = 0.0f; }
+            rn = poisson_resid_norm(c, x, vb, r);
+            st->iters = it; st->rel = rn / bn;
+            if (!isfinite(rn)) { st->status = rc = ORC_ERR_NAN; goto out; }
+            if (rn <= tol * bn) goto out;
+            if (it >= max_iter) break;
+            for (size_t k = 0; k < n; ++k) fr[k] = (float)(-r[k]);
+            since = 0;
+            rmax = sqrt(dot_f32(fr, fr, n));
+        }
+    }
+    if (!refine) {
         for (size_t k = 0; k < n; ++k) x[k] += (double)fe[k];
-        it += k_in;
         rn = poisson_resid_norm(c, x, vb, r);
         st->iters = it; st->rel = rn / bn;
-        if (!isfinite(rn)) { st->status = rc = ORC_ERR_NAN; goto out; }
-        if (!refine || rn <= tol * bn) goto out;
-        if (k_in == 0) break;
+        goto out;
     }
     st->status = rc = ORC_NOT_CONVERGED;
 out:
@@ -662,7 +675,7 @@ static int poisson_solve_vb(orc_ctx *c, double *vb, double *x, int method, doubl
     else if (method == ORC_CG1) rc = poisson_cg1(c, vb, x, tol, max_iter, fixed, st);
     else if (method == ORC_PCG_MP) {
         if (fixed > 0) return ORC_ERR_INVALID;
-        rc = poisson_pcg_mp(c, vb, x, tol, max_iter, check, c->P.p_inner_tol, 1, st);
+        rc = poisson_pcg_mp(c, vb, x, tol, max_iter, check, 1, st);
     }
     else rc = poisson_sor(c, vb, x, omega, tol, max_iter, check, fixed, st);
     if (c->per && rc >= 0) periodic_zero_mean(c, x);
@@ -700,7 +713,7 @@ int orc_poisson_pcg_f32(orc_ctx *c, const double *b, double *x, int iters, orc_s
     if (c->per || iters < 1) return ORC_ERR_INVALID;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) vb[ic(c, i, j)] = (c->dx[i] * c->dy[j]) * b[ic(c, i, j)];
-    return poisson_pcg_mp(c, vb, x, -1.0, iters, iters, 0.0, 0, st);
+    return poisson_pcg_mp(c, vb, x, -1.0, iters, 0, 0, st);
 }
 
 /* ------------------------------------------------------------------------ */

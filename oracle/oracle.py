@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "libibm_oracle.so")
 
 CHANNEL, PERIODIC = 0, 1
 SOR, PCG, SOR_MP = 0, 1, 2   # SOR_MP: single-precision sweeps, double-precision refinement
-CG1, PCG_MP = 3, 4           # CG1: one reduction per iteration; PCG_MP: float inner CG, double refinement
+CG1, PCG_MP = 3, 4           # CG1: one reduction per iteration; PCG_MP: float CG, double reliable updates
 OK, NOT_CONVERGED, ERR_INVALID, ERR_NAN = 0, 1, -1, -5
 
 
@@ -54,7 +54,6 @@ class Params(C.Structure):
         ("uv_omega", C.c_double), ("uv_tol", C.c_double),
         ("uv_max_iter", C.c_int32), ("q_mode", C.c_int32),
         ("alpha_max", C.c_double),
-        ("p_inner_tol", C.c_double),
     ]
 
 
@@ -139,7 +138,7 @@ DEFAULTS = dict(bc=CHANNEL, body=1, re=100.0, dt=1e-3, uinf=1.0, chord=1.0, thic
                 x0=4.0, y0=6.0, amp=0.0, freq=0.0, phase=0.0,
                 p_method=SOR, p_max_iter=2_000_000, p_check=10, p_init_prev=1,
                 p_omega=1.8, p_tol=1e-8, uv_omega=1.0, uv_tol=1e-10, uv_max_iter=200,
-                q_mode=1, alpha_max=1.0, p_inner_tol=1e-4)
+                q_mode=1, alpha_max=1.0)
 
 
 def make_params(nx: int, ny: int, **kw) -> Params:
