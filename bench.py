@@ -277,8 +277,7 @@ def learned_legs(case, args, sor_leg):
                          "poisson_iters_per_step": sor_leg["iters"]}}
     legs = [("zero_guess", ibm.INIT_ZERO, None, ibm.RBSOR, None),
             ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts), ibm.RBSOR, None),
-            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR, None),
-            ("learned_guess_and_correction", ibm.INIT_LEARNED, (params, scale, F, every, opts), ibm.RBSOR, None)]
+            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR, None)]
     if every % args.mp_check == 0:
         # the learned correction with FP32 sweeps and FP64 refinement (the
         # refinement interval divides the correction interval)

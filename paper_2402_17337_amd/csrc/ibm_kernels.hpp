@@ -1015,7 +1015,14 @@ __device__ __forceinline__ void mp_refine_rows(const Grid& g, const double* __re
     block_partials(acc, partials, nblk, blk, lds);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
+// The refinement runs on small blocks, each over a short range of rows (about
+// kMpRefinePositions split positions, two per thread): many blocks resident
+// per compute unit hide the latency of one block's loads behind the others'.
+constexpr int kMpRefineThreads = 256;
+constexpr int kMpRefinePositions = 512;
+constexpr int kMpRefineMaxBlocks = 4096;
+
+__global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
                                                            const double* __restrict__ phb,
                                                            const float* __restrict__ er,
                                                            const float* __restrict__ eb, int e_zero,
@@ -1082,7 +1089,7 @@ __global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8
 
 // Refinement: phi pair `pin` plus e pair `ein` into the other phi pair, the
 // float residual into pair rout, partials into set pbuf.
-__global__ __launch_bounds__(kRedThreads) void k_mp_refine_batch(const MpCase* __restrict__ cases, int ncase,
+__global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine_batch(const MpCase* __restrict__ cases, int ncase,
                                                                  int nblocks, int pin, int ein, int e_zero, int rout,
                                                                  int pbuf) {
     __shared__ double lds[2 * kRedThreads / kWave];
@@ -1460,18 +1467,30 @@ __device__ inline double cg1_unext(double r, double w, double s, double rd, doub
     return __fma_rn(-alpha, si, r) * rd;
 }
 
-// Iteration kk.  Every block sums the partials (gamma, delta, rho) of r_kk and
-// takes the same decision: for kk > 0 (not after a restart) stop on NaN, on
-// the recursive residual sqrt(rho) <= tol ||V b|| (kStConfirm: the host
-// confirms with the true residual) or at the iteration limit; block 0
-// records it (and gamma, alpha of iteration kk) and publishes it.
-__global__ __launch_bounds__(kRedThreads) void k_cg1_iter(
+// Iteration kk on 2-D tiles of kCgTx x kCgTy cells, one tile per block.
+// Every block first sums the partials (gamma, delta, rho) of r_kk and takes
+// the same decision: for kk > 0 (not after a restart) stop on NaN, on the
+// recursive residual sqrt(rho) <= tol ||V b|| (kStConfirm: the host confirms
+// with the true residual) or at the iteration limit; block 0 records it (and
+// gamma, alpha of iteration kk) and publishes it.  Then wave w, lane l own
+// the cells (bx kCgTx + l, by kCgTy + kCgRows w + r), r < kCgRows: each
+// thread forms u_{kk+1} of its cells (kept in registers and in LDS), the
+// first threads also those of the tile's one-cell frame, and after a barrier
+// every cell takes its neighbours' u_{kk+1} from LDS: the frame is read once
+// per tile instead of once per neighbour.  Blocks past the last tile (the
+// XCD banding rounds the grid up) add zero partials.
+constexpr int kCgTx = 64, kCgTy = 32, kCgRows = 4;
+constexpr int kCgThreads = kCgTx * kCgTy / kCgRows;  // 512: 8 waves of kCgRows rows
+constexpr int kCgPitch = kCgTx + 2;
+
+__global__ __launch_bounds__(kCgThreads) void k_cg1_iter(
     Grid g, double* __restrict__ x, double* __restrict__ p, const double* __restrict__ r_in,
     const double* __restrict__ w_in, const double* __restrict__ s_in, double* __restrict__ r_out,
     double* __restrict__ w_out, double* __restrict__ s_out, const double* __restrict__ rdn, Ctl* ctl,
     const double* __restrict__ part_in, int nb, double* __restrict__ part_out, int kk, int max_iter, double tol,
-    int fixed, int first, Slot* hs) {
-    __shared__ double lds[3 * kRedThreads / kWave];
+    int fixed, int first, Slot* hs, int ntx, int ntiles, int per) {
+    __shared__ double su[(kCgTy + 2) * kCgPitch];  // u_{kk+1} of the tile and its frame
+    __shared__ double lds[3 * kCgThreads / kWave];
     __shared__ double s_alpha, s_beta;
     __shared__ int s_stop, s_done;
     if (threadIdx.x == 0) s_done = ctl->done;
@@ -1521,35 +1540,99 @@ __global__ __launch_bounds__(kRedThreads) void k_cg1_iter(
     const double alpha = s_alpha, beta = s_beta;
     const bool fst = first != 0;
     double pacc[3] = {0.0, 0.0, 0.0};
-    for (CellWalk c(g); c.ok(); c.next()) {
-        const size_t k = c.k;
-        const int i = c.i, j = c.j;
-        const double dyj = g.dy[j], dxi = g.dx[i];
-        const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
-        const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
-        const double d = rb_diag(aE, aD, aW, aN, aS);
-        const double rd = rdn[k], rk = r_in[k], wk = w_in[k];
-        const double sold = fst ? 0.0 : s_in[k];
-        const double pold = fst ? 0.0 : p[k];
-        const double uk = rk * rd;
-        const double pk = fst ? uk : __fma_rn(beta, pold, uk);
-        const double sk = fst ? wk : __fma_rn(beta, sold, wk);
-        x[k] = __fma_rn(alpha, pk, x[k]);
-        const double rnew = __fma_rn(-alpha, sk, rk);
-        const double unew = rnew * rd;
-        const NatNb n(g, i, j, k);
-        const double uE = n.hE ? cg1_unext(r_in[n.kE], w_in[n.kE], fst ? 0.0 : s_in[n.kE], rdn[n.kE], alpha, beta, fst) : 0.0;
-        const double uW = n.hW ? cg1_unext(r_in[n.kW], w_in[n.kW], fst ? 0.0 : s_in[n.kW], rdn[n.kW], alpha, beta, fst) : 0.0;
-        const double uN = n.hN ? cg1_unext(r_in[n.kN], w_in[n.kN], fst ? 0.0 : s_in[n.kN], rdn[n.kN], alpha, beta, fst) : 0.0;
-        const double uS = n.hS ? cg1_unext(r_in[n.kS], w_in[n.kS], fst ? 0.0 : s_in[n.kS], rdn[n.kS], alpha, beta, fst) : 0.0;
-        const double wnew = d * unew - rb_sum(aE, uE, aW, uW, aN, uN, aS, uS);
-        p[k] = pk;
-        s_out[k] = sk;
-        r_out[k] = rnew;
-        w_out[k] = wnew;
-        pacc[0] += rnew * unew;
-        pacc[1] += wnew * unew;
-        pacc[2] += rnew * rnew;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD band of tiles
+    if (t < ntiles) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int w = threadIdx.x / kWave;
+        const int X0 = (t % ntx) * kCgTx, Y0 = (t / ntx) * kCgTy;
+        const int i = X0 + lane;
+        const bool col = i < g.nx;
+        double rr[kCgRows], ww[kCgRows], ss[kCgRows], rd[kCgRows], un[kCgRows];
+#pragma unroll
+        for (int r = 0; r < kCgRows; ++r) {
+            const int tr = kCgRows * w + r, j = Y0 + tr;
+            rr[r] = ww[r] = ss[r] = rd[r] = un[r] = 0.0;
+            if (col && j < g.ny) {
+                const size_t k = (size_t)j * g.nx + i;
+                rr[r] = r_in[k];
+                ww[r] = w_in[k];
+                ss[r] = fst ? 0.0 : s_in[k];
+                rd[r] = rdn[k];
+                un[r] = cg1_unext(rr[r], ww[r], ss[r], rd[r], alpha, beta, fst);
+            }
+            su[(tr + 1) * kCgPitch + lane + 1] = un[r];
+        }
+        // the frame: rows -1 and kCgTy (threads 0..127), columns -1 and kCgTx
+        // (threads 128..191); cells outside the domain read as 0 (channel),
+        // periodic mode wraps
+        const int ft = threadIdx.x;
+        if (ft < 2 * kCgTx + 2 * kCgTy) {
+            int hx, hy;
+            if (ft < 2 * kCgTx) {
+                hx = ft & (kCgTx - 1);
+                hy = ft < kCgTx ? -1 : kCgTy;
+            } else {
+                const int q = ft - 2 * kCgTx;
+                hx = q < kCgTy ? -1 : kCgTx;
+                hy = q < kCgTy ? q : q - kCgTy;
+            }
+            int gi = X0 + hx, gj = Y0 + hy;
+            bool in = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+            if (g.per && !in) {
+                // only across the domain's ends (a ragged tile's frame past
+                // nx or ny inside the grid does not exist there)
+                if (gi == -1) gi = g.nx - 1;
+                else if (gi == g.nx) gi = 0;
+                if (gj == -1) gj = g.ny - 1;
+                else if (gj == g.ny) gj = 0;
+                in = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+            }
+            double u = 0.0;
+            if (in) {
+                const size_t k = (size_t)gj * g.nx + gi;
+                u = cg1_unext(r_in[k], w_in[k], fst ? 0.0 : s_in[k], rdn[k], alpha, beta, fst);
+            }
+            su[(hy + 1) * kCgPitch + hx + 1] = u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kCgRows; ++r) {
+            const int tr = kCgRows * w + r, j = Y0 + tr;
+            if (!col || j >= g.ny) continue;
+            const size_t k = (size_t)j * g.nx + i;
+            const double dyj = g.dy[j], dxi = g.dx[i];
+            const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
+            const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+            const double d = rb_diag(aE, aD, aW, aN, aS);
+            const double uk = rr[r] * rd[r];
+            const double pk = fst ? uk : __fma_rn(beta, p[k], uk);
+            const double sk = fst ? ww[r] : __fma_rn(beta, ss[r], ww[r]);
+            x[k] = __fma_rn(alpha, pk, x[k]);
+            const double rnew = __fma_rn(-alpha, sk, rr[r]);
+            const double unew = un[r];  // rnew * rd[r], formed as for the neighbours
+            const int o = (tr + 1) * kCgPitch + lane + 1;
+            double uE = su[o + 1], uN = su[o + kCgPitch];
+            if (g.per) {
+                // the domain's last column or row inside a ragged tile: the
+                // wrapped neighbour is not in the tile's frame
+                if (i == g.nx - 1 && lane + 1 < kCgTx) {
+                    const size_t kn = (size_t)j * g.nx;
+                    uE = cg1_unext(r_in[kn], w_in[kn], fst ? 0.0 : s_in[kn], rdn[kn], alpha, beta, fst);
+                }
+                if (j == g.ny - 1 && tr + 1 < kCgTy) {
+                    const size_t kn = (size_t)i;
+                    uN = cg1_unext(r_in[kn], w_in[kn], fst ? 0.0 : s_in[kn], rdn[kn], alpha, beta, fst);
+                }
+            }
+            const double wnew = d * unew - rb_sum(aE, uE, aW, su[o - 1], aN, uN, aS, su[o - kCgPitch]);
+            p[k] = pk;
+            s_out[k] = sk;
+            r_out[k] = rnew;
+            w_out[k] = wnew;
+            pacc[0] += rnew * unew;
+            pacc[1] += wnew * unew;
+            pacc[2] += rnew * rnew;
+        }
     }
     block_partials(pacc, part_out, gridDim.x, blockIdx.x, lds);
 }

@@ -476,6 +476,13 @@ int32_t pend_pop(ibm_ctx* c, CheckQueue& cq, Slot* out, long* tag) {
     return IBM_OK;
 }
 
+// Blocks of the mixed-precision refinement of a grid with nh_ny split
+// positions (the same split for the single-grid and the batched refinement).
+inline int mp_refine_blocks(size_t nh_ny) {
+    return (int)std::max<size_t>(1, std::min<size_t>(kMpRefineMaxBlocks, (nh_ny + kMpRefinePositions - 1) /
+                                                                          kMpRefinePositions));
+}
+
 inline int red_blocks(size_t n) {
     return (int)std::max<size_t>(1, std::min<size_t>(kRedMax, (n + kRedThreads - 1) / kRedThreads));
 }
@@ -681,8 +688,8 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     const int S = c->tb_sweeps;
     const int tb_blocks = 8 * ts.per;
     const size_t NH = (size_t)c->nh * c->ny;
-    const int nbr = red_blocks(NH);
-    double* part[2] = {c->partials, c->partials + 2 * (size_t)kRedMax};
+    const int nbr = mp_refine_blocks(NH);
+    double* part[2] = {c->partials, c->partials + 2 * (size_t)nbr};
     double* cur[2] = {c->phr, c->phb};
     double* alt[2] = {c->phr2, c->phb2};
     float* ecur[2] = {c->mpf, c->mpf + NH};
@@ -707,7 +714,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     auto refine = [&](int e_zero, int it_after) -> int32_t {
         double* prt = part[nref & 1];
         timed(c, IBM_KERNEL_SOR_MP_REFINE, it_after, [&](hipEvent_t ea, hipEvent_t eb) {
-            LAUNCH_EV(ea, eb, k_mp_refine, dim3(nbr), dim3(kRedThreads), 0, c->g, (const double*)cur[0],
+            LAUNCH_EV(ea, eb, k_mp_refine, dim3(nbr), dim3(kMpRefineThreads), 0, c->g, (const double*)cur[0],
                       (const double*)cur[1], (const float*)ecur[0], (const float*)ecur[1], e_zero,
                       (const double*)c->vbr, (const double*)c->vbb, alt[0], alt[1], ralt[0], ralt[1],
                       (const Ctl*)ctl, prt);
@@ -926,9 +933,14 @@ int32_t cg1_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
     const double tol_e = fixed_mode ? -1.0 : tol;
     const int max_e = fixed_mode ? fixed : max_iter;
     const size_t n = (size_t)c->nx * c->ny;
-    const int nb = red_blocks(n);
-    double* part[2] = {c->partials, c->partials + 3 * (size_t)kRedMax};
-    double* part_b = c->partials + 6 * (size_t)kRedMax;  // r.r, r.z, b.b of the start
+    const int nb = red_blocks(n);  // blocks of the start kernels
+    // the iteration kernel: one tile of kCgTx x kCgTy cells per block, tiles
+    // banded over the XCDs as the blocked sweeps' are
+    const int ntx = (c->nx + kCgTx - 1) / kCgTx, nty = (c->ny + kCgTy - 1) / kCgTy;
+    const int ntiles = ntx * nty, tper = (ntiles + 7) / 8, nbt = 8 * tper;
+    const size_t pstride = 3 * (size_t)std::max(nbt, kRedMax);
+    double* part[2] = {c->partials, c->partials + pstride};
+    double* part_b = c->partials + 2 * pstride;  // r.r, r.z, b.b of the start
     double* R[2] = {c->pr, c->pz};
     double* Wb[2] = {c->pq, c->cgw};
     double* S[2] = {c->pp2, c->cgs};
@@ -954,10 +966,12 @@ int32_t cg1_loop(ibm_ctx* c, double* x, const double* vb, double tol, int max_it
             const int s = next_slot(c);
             const int k0 = kk, fr = restart;
             timed(c, IBM_KERNEL_CG1_ITER, k0 + 1, [&](hipEvent_t ea, hipEvent_t eb) {
-                LAUNCH_EV(ea, eb, k_cg1_iter, dim3(nb), rb, 0, c->g, x, c->pp, (const double*)R[k0 & 1],
-                          (const double*)Wb[k0 & 1], (const double*)S[(k0 + 1) & 1], R[(k0 + 1) & 1],
-                          Wb[(k0 + 1) & 1], S[k0 & 1], (const double*)c->rdn, ctl, (const double*)part[k0 & 1], nb,
-                          part[(k0 + 1) & 1], k0, max_e, tol_e, (int)fixed_mode, fr, c->dslots + s);
+                // the partials it reads come from k_cg1_w after a (re)start
+                LAUNCH_EV(ea, eb, k_cg1_iter, dim3(nbt), dim3(kCgThreads), 0, c->g, x, c->pp,
+                          (const double*)R[k0 & 1], (const double*)Wb[k0 & 1], (const double*)S[(k0 + 1) & 1],
+                          R[(k0 + 1) & 1], Wb[(k0 + 1) & 1], S[k0 & 1], (const double*)c->rdn, ctl,
+                          (const double*)part[k0 & 1], fr ? nb : nbt, part[(k0 + 1) & 1], k0, max_e, tol_e,
+                          (int)fixed_mode, fr, c->dslots + s, ntx, ntiles, tper);
             });
             restart = 0;
             LAUNCH_CHECK();
@@ -1733,8 +1747,9 @@ int32_t batch_upload_mp(ibm_batch* b) {
             }
         d.bred = c->vbr;
         d.bblack = c->vbb;
+        d.nbr = mp_refine_blocks(NH);
         d.partials[0] = c->partials;
-        d.partials[1] = c->partials + 2 * (size_t)kRedMax;
+        d.partials[1] = c->partials + 2 * (size_t)d.nbr;
         d.ctl = c->ctl + CTL_P;
         d.omega = c->P.p_omega;
         d.tol = c->batch_fixed >= 0 ? -1.0 : c->P.p_tol;
@@ -1744,7 +1759,6 @@ int32_t batch_upload_mp(ibm_batch* b) {
         d.tile0 = tile0;
         d.ntiles = d.ts.ntx * d.ts.nty;
         d.rblk0 = rblk0;
-        d.nbr = red_blocks(NH);
         tile0 += d.ntiles;
         rblk0 += d.nbr;
     }
@@ -1783,7 +1797,7 @@ int32_t batch_capture_mp(ibm_batch* b) {
             e_zero = 0;
             i += ns;
         }
-        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kRedThreads), 0, b->cap, (const MpCase*)b->dmp, n,
+        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kMpRefineThreads), 0, b->cap, (const MpCase*)b->dmp, n,
                            b->nrblk, (int)(nref & 1), (int)(nsw & 1), 0, (int)((nref + 1) & 1), (int)(nref & 1));
         ++nref;
         hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(kTbThreads), 0, b->cap, (const MpCase*)b->dmp, 1,
@@ -1839,7 +1853,7 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
     }
     long nref = 0, nsw = 0;
     auto refine = [&](int e_zero) -> int32_t {
-        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kRedThreads), 0, b->stream, (const MpCase*)b->dmp,
+        hipLaunchKernelGGL(k_mp_refine_batch, dim3(b->nrblk), dim3(kMpRefineThreads), 0, b->stream, (const MpCase*)b->dmp,
                            n, b->nrblk, (int)(nref & 1), (int)(nsw & 1), e_zero, (int)((nref + 1) & 1),
                            (int)(nref & 1));
         if (hipGetLastError() != hipSuccess) {

@@ -150,3 +150,35 @@ def test_periodic_mode_rejections(torch):
         g.poisson_solve(z, z.clone(), method=ibm.RBSOR_MP)
     with pytest.raises(ibm.IbmError):
         ibm.Batch([g])
+
+
+@pytest.mark.parametrize("nx,ny", [(96, 64), (200, 150)])
+def test_singular_poisson_one_reduction_cg(torch, nx, ny):
+    """The one-reduction CG (tiled kernel; 200x150 leaves ragged tiles whose
+    wrapped neighbours lie outside the tile's frame) to 1e-13 against the
+    oracle's, and fixed iteration counts against the GPU's textbook PCG."""
+    xf, yf = _faces(nx, ny, nx == 200)
+    o = O.Oracle(nx, ny, xf, yf, bc=O.PERIODIC, body=0)
+    g = ibm.Solver(nx, ny, xf, yf, bc=ibm.BC_PERIODIC, body=0)
+    rng = np.random.default_rng(ny)
+    b = rng.standard_normal((ny, nx))
+    xo, so, _ = o.poisson_solve(b, method=O.CG1, tol=1e-13, max_iter=50000)
+    x = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    st = g.poisson_solve(_dev(torch, b), x, method=ibm.CG1, tol=1e-13, max_iter=50000)
+    assert st["rc"] == ibm.OK and st["rel"] <= 1e-13
+    assert rel_l2(x.cpu().numpy(), xo) <= TOL
+    xa = torch.zeros_like(x)
+    xb = torch.zeros_like(x)
+    g.poisson_solve(_dev(torch, b), xa, method=ibm.CG1, fixed_iters=40)
+    g.poisson_solve(_dev(torch, b), xb, method=ibm.PCG, fixed_iters=40)
+    assert rel_l2(xa.cpu().numpy(), xb.cpu().numpy()) <= TOL
+
+
+def test_taylor_green_one_reduction_cg_steps_match_oracle(torch):
+    o, g = _tg(48, 32, p_method=O.CG1, p_tol=1e-12, p_max_iter=20000)
+    rc, so = o.step(20)
+    assert rc == O.OK
+    for k in range(20):
+        assert g.step(1)["rc"] == ibm.OK
+    for a, b, name in zip(g.fields()[:3], o.fields()[:3], "uvp"):
+        assert rel_l2(a, b) <= TOL, (name, rel_l2(a, b))
