@@ -39,6 +39,8 @@ BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak of the MI355X
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_17337_amd", "csrc", f)
                   for f in ("ibm_kernels.hpp", "ibm_device.hpp")]
+# the library's default interior tile of the blocked sweep (10 iterations per launch)
+DEFAULT_TILE = (76, 44)
 
 
 def kernel_source_digest() -> str:
@@ -318,16 +320,16 @@ def learned_legs(case, args, sor_leg):
 def batch_leg(args):
     """The many-case workload (64 plunging cases, grids 256x192 to 1024x768):
     one time step of every case with the pressure solves batched (one blocked
-    launch per 5 iterations over all cases' tiles), against the same cases
+    launch per 10 iterations over all cases' tiles), against the same cases
     stepped one after another.  Each pressure solve is capped at
     args.c4_iters iterations (the cases' full solves take up to 1.4 M
     iterations).  Tile shapes: the one-by-one run uses the shape tuned for each
     grid size alone (small grids want small tiles to fill the GPU); the batch
-    is timed with those and with the largest default shape (104x32) for every
-    case, since a batch has parallelism to spare and small tiles cost halo
-    work; the faster of the two is reported as the batched time.  The
-    104x32 batch is also timed replaying stretches of args.c4_graph check
-    intervals from a HIP graph."""
+    is timed with those and with the library's default shape (DEFAULT_TILE)
+    for every case, since a batch has parallelism to spare and small tiles
+    cost halo work; the faster of the two is reported as the batched time.
+    The default-shape batch is also timed replaying stretches of
+    args.c4_graph check intervals from a HIP graph."""
     import torch
     from paper_2402_17337_amd import ibm
     from paper_2402_17337_amd import workloads as W
@@ -340,7 +342,7 @@ def batch_leg(args):
         for c in cases:
             s = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"], device="cuda:0",
                            **dict(c["params"], p_max_iter=cap, **over))
-            tx, ty = tiles.get((c["nx"], c["ny"]), (104, 32))
+            tx, ty = tiles.get((c["nx"], c["ny"]), DEFAULT_TILE)
             s.set_option(ibm.OPT_TB_TILE_X, tx)
             s.set_option(ibm.OPT_TB_TILE_Y, ty)
             out.append(s)
@@ -369,7 +371,7 @@ def batch_leg(args):
         return dt, st
 
     t_uniform, st_b = timed_batch(make({}))
-    log(f"batched step of {len(cases)} cases, 104x32 tiles: {t_uniform:.3f} s")
+    log(f"batched step of {len(cases)} cases, default tiles: {t_uniform:.3f} s")
     # one tile shape for the whole batch, tuned on the batch itself
     probe = ibm.Batch(make({}))
     probe.step(1)
@@ -381,7 +383,7 @@ def batch_leg(args):
     t_graph = None
     if args.c4_graph:
         t_graph, st_g = timed_batch(make({}), args.c4_graph)
-        log(f"batched step of {len(cases)} cases, 104x32 tiles, graph of {args.c4_graph} intervals: {t_graph:.3f} s")
+        log(f"batched step of {len(cases)} cases, default tiles, graph of {args.c4_graph} intervals: {t_graph:.3f} s")
     t_tuned = None
     if tuned:
         t_tuned, st_t = timed_batch(make(tuned))
@@ -404,7 +406,7 @@ def batch_leg(args):
     mixed = None
     if args.c4_mixed:
         # FP32 sweeps with FP64 refinement every args.mp_check iterations:
-        # batched (104x32 tiles) and case by case (per-size tiles; the tile
+        # batched (default tiles) and case by case (per-size tiles; the tile
         # shape does not change the float iterates, nor the refinement's sums)
         over = dict(p_method=ibm.RBSOR_MP, p_check=args.mp_check)
         bt = {(c["nx"], c["ny"]): batch_shape for c in cases}
@@ -443,9 +445,9 @@ def batch_leg(args):
                         f"pressure solves capped at {cap} iterations",
             "cells": sum(cells), "batched_s": round(t_b, 4), "sequential_s": round(t_s, 4),
             "speedup": round(t_s / t_b, 3) if t_b > 0 else None,
-            "batched_s_uniform_104x32": round(t_uniform, 4),
+            "batched_s_default_tiles": round(t_uniform, 4),
             "batched_s_per_size_tiles": round(t_tuned, 4) if t_tuned is not None else None,
-            "batched_s_uniform_104x32_graph": round(t_graph, 4) if t_graph is not None else None,
+            "batched_s_default_tiles_graph": round(t_graph, 4) if t_graph is not None else None,
             "batched_s_batch_tuned": round(t_bt, 4), "batch_tuned_tile": f"{batch_shape[0]}x{batch_shape[1]}",
             "batch_autotune_s": {f"{k[0]}x{k[1]}": round(v, 4) for k, v in batch_times.items()},
             "graph_intervals": args.c4_graph or None,
@@ -500,7 +502,7 @@ def uncapped_batch(args, cases, tuned, batch_shape):
     batch.close()
     log(f"uncapped mixed-precision batched step of {len(cases)} cases: {t_b:.2f} s, "
         f"iterations {min(s['p_iters'] for s in st_b)}..{max(s['p_iters'] for s in st_b)}")
-    solo = make(lambda c: tuned.get((c["nx"], c["ny"]), (104, 32)))
+    solo = make(lambda c: tuned.get((c["nx"], c["ny"]), DEFAULT_TILE))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st_s = [s.step(1) for s in solo]

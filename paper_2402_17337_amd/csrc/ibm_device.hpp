@@ -35,12 +35,6 @@ struct Grid {
     const double *pcE, *pcW, *pcD, *pcN, *pcS;
     const double *uce, *ucw, *ucn, *ucs;
     const double *vce, *vcw, *vcn, *vcs;
-    // 1/d of every cell in red/black split layout (d the diagonal of row (i, j)
-    // of A, with the operations of rb_diag), in double and, computed in
-    // single precision from the float-rounded coefficients, in float: the
-    // blocked sweeps load them instead of dividing in every launch
-    const double *rdr, *rdb;
-    const float *rdr32, *rdb32;
 };
 
 // Body position of the current step.
@@ -76,12 +70,35 @@ struct Slot {
 // ---------------------------------------------------------------------------
 // reductions (deterministic for a fixed launch shape)
 // ---------------------------------------------------------------------------
+// Cross-lane move of a double by a DPP control (both 32-bit halves); lanes
+// with no source, and the lanes of rows outside ROWS, receive 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move_d(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWS, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave (every lane active), returned in every lane: prefix sums
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total into
+// row 1 and row 2's into row 3 (row_bcast:15), then lane 31 into rows 2 and 3
+// (row_bcast:31); lane 63 holds the total.  A fixed order, so deterministic.
 template <int N>
 __device__ inline void wave_sum(double (&v)[N]) {
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], off, kWave);
+    for (int k = 0; k < N; ++k) {
+        double x = v[k];
+        x += dpp_move_d<0x111, 0xf>(x);
+        x += dpp_move_d<0x112, 0xf>(x);
+        x += dpp_move_d<0x114, 0xf>(x);
+        x += dpp_move_d<0x118, 0xf>(x);
+        x += dpp_move_d<0x142, 0xa>(x);
+        x += dpp_move_d<0x143, 0xc>(x);
+        const long long bits = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readlane((int)bits, kWave - 1);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), kWave - 1);
+        v[k] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
     }
 }
 

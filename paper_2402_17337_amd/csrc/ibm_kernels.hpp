@@ -73,11 +73,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(Grid g, const double* __restri
 // Pressure Poisson: red-black SOR on A phi = V b in split storage
 // ---------------------------------------------------------------------------
 // Neighbour sum and diagonal of row (i, j) of A with explicit fused
-// multiply-adds, so that every kernel that updates a cell rounds alike:
+// multiply-adds, so that every kernel that forms them rounds alike:
 //   sum = aE xE + aW xW + aN xN + aS xS   (absent neighbours: a = 0, x = 0)
 //   d   = (((aE + aD) + aW) + aN) + aS    (aD: outlet term, nonzero at i = nx-1)
 // with aE = dy_j pcE_i, aW = dy_j pcW_i, aD = dy_j pcD_i, aN = dx_i pcN_j,
-// aS = dx_i pcS_j; the coefficient arrays are zero on Neumann faces.
+// aS = dx_i pcS_j; the coefficient arrays are zero on Neumann faces.  The CG
+// kernels and the refinement of the mixed-precision solve use this form.
 __device__ inline double rb_sum(double aE, double xE, double aW, double xW, double aN, double xN, double aS,
                                 double xS) {
     double sum = aE * xE;
@@ -88,35 +89,42 @@ __device__ inline double rb_sum(double aE, double xE, double aW, double xW, doub
 __device__ inline double rb_diag(double aE, double aD, double aW, double aN, double aS) {
     return (((aE + aD) + aW) + aN) + aS;
 }
-// SOR update with the reciprocal diagonal rd = 1/d:
-//   phi <- (1 - omega) phi + omega (sum - V b) rd
-__device__ inline double sor_update(double x, double sum, double b, double rd, double omega) {
-    const double gs = (sum - b) * rd;
-    return __fma_rn(omega, gs, (1.0 - omega) * x);
-}
-
-// The same three operations in single precision (the mixed-precision sweeps).
-__device__ inline float rb_sum(float aE, float xE, float aW, float xW, float aN, float xN, float aS, float xS) {
-    float sum = aE * xE;
-    sum = __fmaf_rn(aW, xW, sum);
-    sum = __fmaf_rn(aN, xN, sum);
-    return __fmaf_rn(aS, xS, sum);
-}
 __device__ inline float rb_diag(float aE, float aD, float aW, float aN, float aS) {
     return (((aE + aD) + aW) + aN) + aS;
 }
-__device__ inline float sor_update(float x, float sum, float b, float rd, float omega) {
-    const float gs = (sum - b) * rd;
-    return __fmaf_rn(omega, gs, (1.0f - omega) * x);
+
+// The red-black SOR kernels (every sweep and the residual of their stop
+// test) take the neighbour sum with the grid spacings factored out,
+//   sum = dy_j (pcE_i xE + pcW_i xW) + dx_i (pcN_j xN + pcS_j xS),
+// three multiplications and three fused multiply-adds, and the update
+//   phi <- (sum - V b) wrd + (1 - omega) phi,   wrd = omega (1/d),
+// three more; 1/d is the reciprocal of rb_diag of the products above.
+__device__ inline double sor_sum(double dy, double cE, double xE, double cW, double xW, double dx, double pn,
+                                 double xN, double ps, double xS) {
+    const double ew = __fma_rn(cW, xW, cE * xE);
+    const double ns = __fma_rn(ps, xS, pn * xN);
+    return __fma_rn(dx, ns, dy * ew);
+}
+__device__ inline double sor_step(double x, double sum, double b, double wrd, double omx) {
+    return __fma_rn(sum - b, wrd, omx * x);
+}
+// The same two operations in single precision (the mixed-precision sweeps).
+__device__ inline float sor_sum(float dy, float cE, float xE, float cW, float xW, float dx, float pn, float xN,
+                                float ps, float xS) {
+    const float ew = __fmaf_rn(cW, xW, cE * xE);
+    const float ns = __fmaf_rn(ps, xS, pn * xN);
+    return __fmaf_rn(dx, ns, dy * ew);
+}
+__device__ inline float sor_step(float x, float sum, float b, float wrd, float omx) {
+    return __fmaf_rn(sum - b, wrd, omx * x);
 }
 
-// Neighbour sum and diagonal of row (i, j) of A, reading the other colour
-// (split index k of the cell, s = its position parity in the row).
+// Neighbour sum (sor_sum) and diagonal of row (i, j) of A, reading the other
+// colour (split index k of the cell, s = its position parity in the row).
 __device__ inline double rb_row(const Grid& g, const double* __restrict__ other, int i, int j, size_t k, int s,
                                 double& d) {
     const double dyj = g.dy[j], dxi = g.dx[i];
-    const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
-    const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
+    const double pE = g.pcE[i], pW = g.pcW[i], pN = g.pcN[j], pS = g.pcS[j];
     // periodic mode wraps: cell nx-1's east neighbour is position 0 of the
     // row, cell 0's west neighbour position nh-1, rows ny-1 and 0 are
     // neighbours (same position: the colours alternate, nx and ny are even)
@@ -125,30 +133,8 @@ __device__ inline double rb_row(const Grid& g, const double* __restrict__ other,
     const double xW = i > 0 ? other[k + s - 1] : (g.per ? other[k + nh - 1] : 0.0);
     const double xN = j < g.ny - 1 ? other[k + nh] : (g.per ? other[k - top] : 0.0);
     const double xS = j > 0 ? other[k - nh] : (g.per ? other[k + top] : 0.0);
-    d = rb_diag(aE, aD, aW, aN, aS);
-    return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
-}
-
-// 1/d of every cell in split layout, in double (the products of rb_row) and
-// in float (the products of the float-rounded coefficients, as the
-// single-precision sweeps form them); once per context.
-__global__ __launch_bounds__(kBlock) void k_rdiag_split(Grid g, double* __restrict__ rdr, double* __restrict__ rdb,
-                                                        float* __restrict__ rdr32, float* __restrict__ rdb32) {
-    const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (m >= g.nh || j >= g.ny) return;
-    const size_t k = (size_t)j * g.nh + m;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int i = 2 * m + ((j + c) & 1);
-        const double dyj = g.dy[j], dxi = g.dx[i];
-        const double d = rb_diag(dyj * g.pcE[i], dyj * g.pcD[i], dyj * g.pcW[i], dxi * g.pcN[j], dxi * g.pcS[j]);
-        const float fy = (float)dyj, fx = (float)dxi;
-        const float f = rb_diag(fy * (float)g.pcE[i], fy * (float)g.pcD[i], fy * (float)g.pcW[i],
-                                fx * (float)g.pcN[j], fx * (float)g.pcS[j]);
-        (c ? rdb : rdr)[k] = 1.0 / d;
-        (c ? rdb32 : rdr32)[k] = 1.0f / f;
-    }
+    d = rb_diag(dyj * pE, dyj * g.pcD[i], dyj * pW, dxi * pN, dxi * pS);
+    return sor_sum(dyj, pE, xE, pW, xW, dxi, pN, xN, pS, xS);
 }
 
 // One colour of a red-black SOR iteration (one launch per colour):
@@ -168,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_sor_sweep(Grid g, double* __restrict
     const size_t k = (size_t)j * g.nh + m;
     double d;
     const double sum = rb_row(g, other, i, j, k, s, d);
-    self[k] = sor_update(self[k], sum, bself[k], 1.0 / d, omega);
+    self[k] = sor_step(self[k], sum, bself[k], omega * (1.0 / d), 1.0 - omega);
 }
 
 // Residual r = V b - A phi over both colours: per-block partial sums of r^2
@@ -207,9 +193,10 @@ __global__ __launch_bounds__(kRedThreads) void k_sor_residual(Grid g, const doub
 // One block: sum the residual partials (r^2, b^2) and run the stop test of a
 // solve (phase 0 = before the first iteration).  den_one: ||rhs|| = 0 turns
 // the test absolute instead of meaning a zero solution.
-__global__ __launch_bounds__(kBlock) void k_check(Ctl* ctl, const double* __restrict__ partials, int nb, int phase,
-                                                  int it, int max_iter, double tol, int fixed, int den_one, Slot* hs) {
-    __shared__ double lds[2 * kBlock / kWave];
+__global__ __launch_bounds__(kRedThreads) void k_check(Ctl* ctl, const double* __restrict__ partials, int nb,
+                                                       int phase, int it, int max_iter, double tol, int fixed,
+                                                       int den_one, Slot* hs) {
+    __shared__ double lds[2 * kRedThreads / kWave];
     if (ctl->done) {
         if (threadIdx.x == 0) publish(ctl, hs);
         return;
@@ -229,30 +216,37 @@ __global__ __launch_bounds__(kBlock) void k_check(Ctl* ctl, const double* __rest
 // After h half-sweeps only cells farther than h-1 from the loaded edge are
 // still exact, so with H >= 2S (+1 when the residual of the interior is
 // summed at the end) the interior equals S global iterations bit for bit: each
-// cell is updated by sor_update with the same neighbour values.  The tiles
+// cell is updated by sor_step with the same neighbour values.  The tiles
 // read one pair of split arrays and write the other (a tile's halo is another
 // tile's interior, and blocks of one launch run in no fixed order).  Half-sweep h
-// updates only the cells within e_h = 2S - h (+1) of the interior; with
-// H = 2S + 2 those cells never touch the loaded edge, so only a domain edge
-// can bound them, and there the LDS holds a ring of zeros (the coefficient of
-// an absent neighbour is zero as well).
+// updates the rows within e_h = 2S - h (+1) of the interior, whole: a cell of
+// such a row farther than e_h in x takes a value that is no exact iterate,
+// but inexact values spread one cell per half-sweep from the loaded edge and
+// stop two cells short of the interior (H = 2S + 2); at a domain edge the LDS
+// holds a ring of zeros (the coefficient of an absent neighbour is zero as
+// well), and lanes without a cell hold phi = V b = 1/d = 0, which the update
+// keeps at zero.
 //
 // Work layout: lane l of every wave owns split column l of the loaded tile
 // (at most 64 columns, i.e. a loaded width of 128 cells); wave w owns rows
-// w, w + 16, w + 32, w + 48, so the position parity of a wave's colour-C cell
+// w + 16 r (r < kTbRows), so the position parity of a wave's colour-C cell
 // is the same in all its rows and the x coefficients of a lane are fixed per
 // colour.  A thread keeps phi, V b and 1/d of its cells in registers (it is
 // the only writer of phi); the LDS copy of phi serves the neighbours.  The LDS
 // pitch is fixed, so every neighbour address is a register plus a constant.
 // ---------------------------------------------------------------------------
 constexpr int kTbThreads = 1024;
+// the stop tests (k_check, the check block of a sweep launch, the batched
+// checks) all sum partials with this many threads, so in the same order
+static_assert(kTbThreads == kRedThreads, "one thread count for every stop test");
 constexpr int kTbWaves = kTbThreads / kWave;   // 16
-constexpr int kTbRows = 4;                     // rows per wave: loaded height <= 64
+constexpr int kTbRows = 6;                     // rows per wave (even): loaded height <= 96
 constexpr int kTbCols = kWave;                 // split columns: loaded width <= 128
 constexpr int kTbPitch = kTbCols + 2;          // LDS row: ghost, 64 columns, ghost
 constexpr int kTbLdsRows = kTbWaves * kTbRows + 2;
 constexpr int kTbLds = kTbLdsRows * kTbPitch;  // doubles per colour
 constexpr int kTbGroup = 2;                    // rows whose reads are issued together
+static_assert(kTbRows % 2 == 0 && kTbRows % kTbGroup == 0, "strips start on even rows; rows go in groups");
 
 struct TbShape {
     int tx, ty;    // interior tile size (tx even)
@@ -346,6 +340,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
     const int ic = 2 * (m0 + lane);
     double cdx[2], cE[2], cW[2], cD[2];
     int sC[2], dist[2];
+    const double omx = 1.0 - omega;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         sC[c] = (ya + w + c) & 1;
@@ -360,7 +355,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
     // per row: wave-uniform coefficients and y distance from the interior
     double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
     int rdist[kTbRows];
-    double x[2][kTbRows], b[2][kTbRows], rd[2][kTbRows];
+    double x[2][kTbRows], b[2][kTbRows], wrd[2][kTbRows];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
@@ -371,7 +366,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
         rps[r] = g.pcS[j];
         rdist[r] = jl < ly ? max(max(Y0 - j, j - (Y1 - 1)), 0) : (1 << 20);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = rd[c][r] = 0.0;
+        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = wrd[c][r] = 0.0;
         if (jl < ly && col) {
             const size_t kg = (size_t)(ya + jl) * g.nh + m0 + lane;
             x[0][r] = red[kg];
@@ -382,7 +377,7 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
             for (int c = 0; c < 2; ++c) {
                 const double d = rb_diag(rdy[r] * cE[c], rdy[r] * cD[c], rdy[r] * cW[c], cdx[c] * rpn[r],
                                          cdx[c] * rps[r]);
-                rd[c][r] = 1.0 / d;
+                wrd[c][r] = omega * (1.0 / d);
             }
             const int p = (jl + 1) * kTbPitch + lane + 1;
             tile[p] = x[0][r];
@@ -401,7 +396,6 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
             double* self = tile + c * kTbLds;
             const double* other = tile + (1 - c) * kTbLds;
             const int pe = p0 + sC[c];  // east neighbour of row 0 in the other colour
-            const bool upd = dist[c] <= e;
             // rows in groups of kTbGroup: the group's reads, then its updates
 #pragma unroll
             for (int r0 = 0; r0 < kTbRows; r0 += kTbGroup) {
@@ -419,11 +413,9 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
                 for (int q = 0; q < kTbGroup; ++q) {
                     const int r = r0 + q;
                     if (rdist[r] <= e) {
-                        const double aE = rdy[r] * cE[c], aW = rdy[r] * cW[c];
-                        const double aN = cdx[c] * rpn[r], aS = cdx[c] * rps[r];
-                        const double sum = rb_sum(aE, vE[q], aW, vW[q], aN, vN[q], aS, vS[q]);
-                        const double xn = sor_update(x[c][r], sum, b[c][r], rd[c][r], omega);
-                        x[c][r] = upd ? xn : x[c][r];
+                        const double sum = sor_sum(rdy[r], cE[c], vE[q], cW[c], vW[q], cdx[c], rpn[r], vN[q],
+                                                   rps[r], vS[q]);
+                        x[c][r] = sor_step(x[c][r], sum, b[c][r], wrd[c][r], omx);
                         self[p0 + r * kTbWaves * kTbPitch] = x[c][r];
                     }
                 }
@@ -447,13 +439,11 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_tb(Grid g, const double* __r
             (c ? oblack : ored)[kg] = x[c][r];
             if (residual) {
                 const double* other = tile + (1 - c) * kTbLds;
-                const int i = ic + sC[c];
-                const double aE = rdy[r] * cE[c], aW = rdy[r] * cW[c], aD = rdy[r] * cD[c];
-                const double aN = cdx[c] * rpn[r], aS = cdx[c] * rps[r];
                 const double xE = other[p0 + sC[c] + o], xW = other[p0 + sC[c] + o - 1];
                 const double xN = other[p0 + o + kTbPitch], xS = other[p0 + o - kTbPitch];
-                const double d = rb_diag(aE, aD, aW, aN, aS);
-                const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+                const double d = rb_diag(rdy[r] * cE[c], rdy[r] * cD[c], rdy[r] * cW[c], cdx[c] * rpn[r],
+                                         cdx[c] * rps[r]);
+                const double sum = sor_sum(rdy[r], cE[c], xE, cW[c], xW, cdx[c], rpn[r], xN, rps[r], xS);
                 const double bb = b[c][r];
                 const double rres = bb - (sum - d * x[c][r]);
                 acc[0] += rres * rres;
@@ -503,30 +493,15 @@ constexpr int kTrSlots = 2 * kTbWaves + 2;  // edge rows: zero, (first, last) pe
 // into the thread's small arrays is then a constant and the arrays stay in
 // registers.
 
-// 1/d of the thread's cells: colour c of row r sits at position parity
-// (P + r + c) & 1; rows or lanes without cells get 0.
-template <int P, class T>
-__device__ inline void tbr_rdiag(T (&rd)[2][kTbRows], const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
-                                 const T (&cD)[2], const T (&rdy)[kTbRows], const T (&rpn)[kTbRows],
-                                 const T (&rps)[kTbRows], int nlive, bool col) {
-#pragma unroll
-    for (int r = 0; r < kTbRows; ++r) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int q = (P + r + c) & 1;
-            const T d = rb_diag(rdy[r] * cE[q], rdy[r] * cD[q], rdy[r] * cW[q], cdx[q] * rpn[r], cdx[q] * rps[r]);
-            rd[c][r] = (col && r < nlive) ? T(1) / d : T(0);
-        }
-    }
+// A wave-uniform value as such (held in scalar registers: the row
+// coefficients of a strip are the same in every lane).
+__device__ inline double wave_uniform(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)bits), hi = __builtin_amdgcn_readfirstlane((int)(bits >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-// Pins the values of a thread's per-cell array in registers at this point, so
-// that their computation is not sunk past the barrier that follows (it then
-// overlaps the latency of the tile's loads).
-template <class T>
-__device__ inline void tbr_pin(T (&v)[2][kTbRows]) {
-#pragma unroll
-    for (int r = 0; r < kTbRows; ++r) asm volatile("" : "+v"(v[0][r]), "+v"(v[1][r]));
+__device__ inline float wave_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 // Stores the interior cells of v (colour 0 to o0, colour 1 to o1); row r of
@@ -563,52 +538,47 @@ __device__ inline T tbr_sum(const T (&x)[2][kTbRows], T xS0, T xNR, const T (&cd
     }
     const T xN = (R + 1 < kTbRows) ? x[O][R + 1 < kTbRows ? R + 1 : R] : xNR;
     const T xS = (R > 0) ? x[O][R > 0 ? R - 1 : 0] : xS0;
-    const T aE = dy * cE[s], aW = dy * cW[s];
-    const T aN = cdx[s] * pn, aS = cdx[s] * ps;
-    return rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+    return sor_sum(dy, cE[s], xE, cW[s], xW, cdx[s], pn, xN, ps, xS);
 }
 
+// Update of the colour-C cell of row R (whole rows: see the blocked sweep's
+// notes); wrd = omega / d per cell, omx = 1 - omega.
 template <int C, int P, int R, class T>
-__device__ inline void tbr_row(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows], T xS0,
-                               T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2], const int (&dq)[2],
+__device__ inline void tbr_row(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows], T xS0,
+                               T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
                                const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
-                               const int (&rdist)[kTbRows], int e, T omega) {
+                               const int (&rdist)[kTbRows], int e, T omx) {
     if (rdist[R] > e) return;  // wave-uniform
-    constexpr int s = (P + R + C) & 1;
     const T sum = tbr_sum<C, P, R>(x, xS0, xNR, cdx, cE, cW, rdy[R], rpn[R], rps[R]);
-    const T xn = sor_update(x[C][R], sum, b[C][R], rd[C][R], omega);
-    x[C][R] = dq[s] <= e ? xn : x[C][R];
+    x[C][R] = sor_step(x[C][R], sum, b[C][R], wrd[C][R], omx);
 }
 
-template <int C, int P, class T>
-__device__ inline void tbr_half(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows], T xS0,
-                                T xNR, T (&cdx)[2], T (&cE)[2], T (&cW)[2], const int (&dq)[2],
+// One colour's half-sweep over the strip, rows R..kTbRows-1 (unrolled at
+// compile time, so every index into the thread's arrays is a constant).
+template <int C, int P, class T, int R = 0>
+__device__ inline void tbr_half(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows], T xS0,
+                                T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
                                 const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
-                                const int (&rdist)[kTbRows], int e, T omega) {
-    static_assert(kTbRows == 4, "rows of a strip are unrolled by hand");
-    // Keep the east/west coefficient products inside the sweep loop: all
-    // four products hoisted out of it would need 64 more registers per
-    // thread in double precision; the north/south ones may be hoisted.
-    asm volatile("" : "+v"(cE[0]), "+v"(cE[1]), "+v"(cW[0]), "+v"(cW[1]));
-    tbr_row<C, P, 0>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-    tbr_row<C, P, 1>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-    tbr_row<C, P, 2>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
-    tbr_row<C, P, 3>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+                                const int (&rdist)[kTbRows], int e, T omx) {
+    tbr_row<C, P, R>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    if constexpr (R + 1 < kTbRows)
+        tbr_half<C, P, T, R + 1>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
 }
 
 // S red-black iterations on the thread's registers with the shrinking update
-// region (e = 2 S - h + extra at half-sweep h), exchanging the strip-end rows
-// through `edge` after each half-sweep.  On entry `edge` holds both colours.
+// region (rows within e = 2 S - h + extra at half-sweep h), exchanging the
+// strip-end rows through `edge` after each half-sweep.  On entry `edge`
+// holds both colours.
 template <int P, class T>
-__device__ inline void tbr_sweeps(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&rd)[2][kTbRows],
-                                  T (&cdx)[2], T (&cE)[2], T (&cW)[2], const int (&dq)[2], const T (&rdy)[kTbRows],
+__device__ inline void tbr_sweeps(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows],
+                                  const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2], const T (&rdy)[kTbRows],
                                   const T (&rpn)[kTbRows], const T (&rps)[kTbRows], const int (&rdist)[kTbRows],
-                                  T (&edge)[2][kTrSlots][kWave], int w, int lane, int nsweep, int extra, T omega) {
+                                  T (&edge)[2][kTrSlots][kWave], int w, int lane, int nsweep, int extra, T omx) {
     for (int it = 0; it < nsweep; ++it) {
-        {   // red half-sweep h = 2 it + 1: cells within e of the interior
+        {   // red half-sweep h = 2 it + 1
             const int e = 2 * nsweep - (2 * it + 1) + extra;
             const T xS0 = edge[1][2 * w][lane], xNR = edge[1][2 * w + 3][lane];
-            tbr_half<0, P>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            tbr_half<0, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
             edge[0][2 * w + 1][lane] = x[0][0];
             edge[0][2 * w + 2][lane] = x[0][kTbRows - 1];
             __syncthreads();
@@ -616,7 +586,7 @@ __device__ inline void tbr_sweeps(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], 
         {   // black half-sweep h = 2 it + 2
             const int e = 2 * nsweep - (2 * it + 2) + extra;
             const T xS0 = edge[0][2 * w][lane], xNR = edge[0][2 * w + 3][lane];
-            tbr_half<1, P>(x, b, rd, xS0, xNR, cdx, cE, cW, dq, rdy, rpn, rps, rdist, e, omega);
+            tbr_half<1, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
             edge[1][2 * w + 1][lane] = x[1][0];
             edge[1][2 * w + 2][lane] = x[1][kTbRows - 1];
             __syncthreads();
@@ -671,20 +641,17 @@ __device__ inline void tbr_resid(const double (&x)[2][kTbRows], const double (&b
     acc[1] += bb * bb;
 }
 
-template <int P>
+// Residual contributions of both colours of rows R..kTbRows-1.
+template <int P, int R = 0>
 __device__ inline void tbr_residual(const double (&x)[2][kTbRows], const double (&b)[2][kTbRows],
                                     const double (&xS0)[2], const double (&xNR)[2], const double (&cdx)[2],
                                     const double (&cE)[2], const double (&cW)[2], const double (&cD)[2],
                                     const int (&dq)[2], const double (&rdy)[kTbRows], const double (&rpn)[kTbRows],
                                     const double (&rps)[kTbRows], const int (&rdist)[kTbRows], double (&acc)[2]) {
-    tbr_resid<0, P, 0>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<1, P, 0>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<0, P, 1>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<1, P, 1>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<0, P, 2>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<1, P, 2>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<0, P, 3>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
-    tbr_resid<1, P, 3>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<0, P, R>(x, b, xS0[1], xNR[1], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    tbr_resid<1, P, R>(x, b, xS0[0], xNR[0], cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
+    if constexpr (R + 1 < kTbRows)
+        tbr_residual<P, R + 1>(x, b, xS0, xNR, cdx, cE, cW, cD, dq, rdy, rpn, rps, rdist, acc);
 }
 
 // One tile t of the register-resident blocked sweep (the body of k_sor_tbr and
@@ -733,25 +700,32 @@ __device__ __forceinline__ void tbr_tile(const Grid& g, const double* __restrict
     }
     double rdy[kTbRows], rpn[kTbRows], rps[kTbRows];
     int rdist[kTbRows];
-    double x[2][kTbRows], b[2][kTbRows], rd[2][kTbRows];
+    double x[2][kTbRows], b[2][kTbRows], wrd[2][kTbRows];
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
         const int jl = jw + r;
         const int j = min(ya + jl, g.ny - 1);
-        rdy[r] = g.dy[j];
-        rpn[r] = g.pcN[j];
-        rps[r] = g.pcS[j];
+        rdy[r] = wave_uniform(g.dy[j]);
+        rpn[r] = wave_uniform(g.pcN[j]);
+        rps[r] = wave_uniform(g.pcS[j]);
         rdist[r] = jl < ly ? max(max(Y0 - j, j - (Y1 - 1)), 0) : (1 << 20);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = rd[c][r] = 0.0;
+        for (int c = 0; c < 2; ++c) x[c][r] = b[c][r] = 0.0;
         if (jl < ly && col) {
             const size_t kg = (size_t)(ya + jl) * g.nh + m0 + lane;
             x[0][r] = red[kg];
             x[1][r] = black[kg];
             b[0][r] = bred[kg];
             b[1][r] = bblack[kg];
-            rd[0][r] = g.rdr[kg];  // 1/d, as tbr_rdiag forms it, precomputed per grid
-            rd[1][r] = g.rdb[kg];
+        }
+        // omega / d of the thread's cells, formed while the loads are in
+        // flight (colour c of row r sits at position parity (P + r + c) & 1)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int q = (P + r + c) & 1;
+            const double d = rb_diag(rdy[r] * cE[q], rdy[r] * cD[q], rdy[r] * cW[q], cdx[q] * rpn[r],
+                                     cdx[q] * rps[r]);
+            wrd[c][r] = (jl < ly && col) ? omega * (1.0 / d) : 0.0;
         }
     }
     // The stop flag is read after the tile's loads are issued, so that its
@@ -760,7 +734,7 @@ __device__ __forceinline__ void tbr_tile(const Grid& g, const double* __restrict
     // edge rows of both colours; slots 0 and kTrSlots-1 stay zero
     tbr_edges(x, edge, w, lane);
     __syncthreads();
-    tbr_sweeps<P>(x, b, rd, cdx, cE, cW, dq, rdy, rpn, rps, rdist, edge, w, lane, nsweep, residual ? 1 : 0, omega);
+    tbr_sweeps<P>(x, b, wrd, cdx, cE, cW, rdy, rpn, rps, rdist, edge, w, lane, nsweep, residual ? 1 : 0, 1.0 - omega);
 
     // interior back to global memory (both colours), and its residual
     const size_t kg0 = (size_t)(ya + jw) * g.nh + m0 + lane;
@@ -880,8 +854,7 @@ __global__ void k_batch_cursor(int* cur, int base, int entry) {
 // SOR is a stationary iteration, so these iterates equal the double-precision
 // ones up to rounding relative to the correction.  The single-precision
 // coefficients are products of the float-rounded 1-D arrays, and 1/d a float
-// division.  The sweep kernel holds 8 waves per SIMD (two blocks per compute
-// unit), so that one block's loads overlap another's sweeps.
+// division.
 // ---------------------------------------------------------------------------
 struct MpArrays {
     const float *er, *eb;  // e in (unless e_zero)
@@ -914,19 +887,21 @@ __device__ __forceinline__ void mp_tile(const Grid& g, const MpArrays& a, double
 #pragma unroll
     for (int q = 0; q < 2; ++q) dq[q] = col ? max(max(X0 - (ic + q), (ic + q) - (X1 - 1)), 0) : (1 << 20);
     int rdist[kTbRows];
-    float e[2][kTbRows], b32[2][kTbRows], rd[2][kTbRows];
+    float e[2][kTbRows], b32[2][kTbRows], wrd[2][kTbRows];
+    const float fom = (float)omega;
     float fdx[2] = {(float)g.dx[ii0], (float)g.dx[ii1]};
     float fE[2] = {(float)g.pcE[ii0], (float)g.pcE[ii1]};
     float fW[2] = {(float)g.pcW[ii0], (float)g.pcW[ii1]};
+    const float fD[2] = {(float)g.pcD[ii0], (float)g.pcD[ii1]};
     float fdy[kTbRows], fpn[kTbRows], fps[kTbRows];
 #pragma unroll
     for (int r = 0; r < kTbRows; ++r) {
         const int jl = jw + r;
         const int j = min(ya + jl, g.ny - 1);
         rdist[r] = jl < ly ? max(max(Y0 - (ya + jl), (ya + jl) - (Y1 - 1)), 0) : (1 << 20);
-        fdy[r] = (float)g.dy[j];
-        fpn[r] = (float)g.pcN[j];
-        fps[r] = (float)g.pcS[j];
+        fdy[r] = wave_uniform((float)g.dy[j]);
+        fpn[r] = wave_uniform((float)g.pcN[j]);
+        fps[r] = wave_uniform((float)g.pcS[j]);
 #pragma unroll
         for (int c = 0; c < 2; ++c) e[c][r] = b32[c][r] = 0.0f;
         if (jl < ly && col) {
@@ -937,18 +912,24 @@ __device__ __forceinline__ void mp_tile(const Grid& g, const MpArrays& a, double
             }
             b32[0][r] = a.rr[k];
             b32[1][r] = a.rb[k];
-            rd[0][r] = g.rdr32[k];  // 1/d in float, precomputed per grid
-            rd[1][r] = g.rdb32[k];
+        }
+        // omega / d in single precision, from the products of the
+        // float-rounded coefficients
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int q = (P + r + c) & 1;
+            const float f = rb_diag(fdy[r] * fE[q], fdy[r] * fD[q], fdy[r] * fW[q], fdx[q] * fpn[r], fdx[q] * fps[r]);
+            wrd[c][r] = (jl < ly && col) ? fom * (1.0f / f) : 0.0f;
         }
     }
     if (tb_begin(ctl, s_flag)) return;
     tbr_edges(e, edge32, w, lane);
     __syncthreads();
-    tbr_sweeps<P>(e, b32, rd, fdx, fE, fW, dq, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, 0, (float)omega);
+    tbr_sweeps<P>(e, b32, wrd, fdx, fE, fW, fdy, fpn, fps, rdist, edge32, w, lane, nsweep, 0, 1.0f - fom);
     tbr_store<P>(e, a.oer, a.oeb, kg0, (size_t)g.nh, dq, rdist);
 }
 
-__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp(
+__global__ __launch_bounds__(kTbThreads) void k_sor_mp(
     Grid g, MpArrays a, double omega, Ctl* ctl, TbCheck chk, TbShape ts, int nsweep, int e_zero) {
     __shared__ float edge32[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];
@@ -1068,7 +1049,7 @@ __device__ inline int batch_case(const CaseT* __restrict__ cases, int ncase, int
 }
 
 // Sweeps: e pair `eflip` in, the other out; float residual pair rsel.
-__global__ __launch_bounds__(kTbThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sor_mp_batch(
+__global__ __launch_bounds__(kTbThreads) void k_sor_mp_batch(
     const MpCase* __restrict__ cases, int ncase, int ntotal, int per, int eflip, int rsel, int nsweep, int e_zero) {
     __shared__ float edge32[2][kTrSlots][kWave];
     __shared__ double lds[2 * kTbWaves];

@@ -80,7 +80,7 @@ struct Layout {
 struct Offsets {
     size_t xf, yf, dx, dy, xc, yc, dxu, dyv, pcE, pcW, pcD, pcN, pcS, uce, ucw, ucn, ucs, vce, vcw, vcn, vcs;
     size_t u, nu, ru, fufull, v, nv, rv, fvfull, p, phi, vb, pr, pp, pp2, pq, phr, phb, vbr, vbb, pz, dn, phr2, phb2, mpf, phi0, wsf, wscale;
-    size_t cgw, cgs, rdn, rdr, rdb, rdr32, rdb32;
+    size_t cgw, cgs, rdn;
     size_t f_u, f_v, coef, partials, ctl, list_u, list_v, counts, flu, flv, msrc;
     size_t total;
     int max_blocks;
@@ -112,8 +112,6 @@ Offsets layout_for(int nx, int ny) {
     o.phr = L.take<double>(NH); o.phb = L.take<double>(NH); o.vbr = L.take<double>(NH); o.vbb = L.take<double>(NH);
     o.pz = L.take<double>(NC); o.dn = L.take<double>(NC);
     o.cgw = L.take<double>(NC); o.cgs = L.take<double>(NC); o.rdn = L.take<double>(NC);  // one-reduction CG
-    o.rdr = L.take<double>(NH); o.rdb = L.take<double>(NH);      // 1/d, split layout (blocked sweeps)
-    o.rdr32 = L.take<float>(NH); o.rdb32 = L.take<float>(NH);
     o.phr2 = L.take<double>(NH); o.phb2 = L.take<double>(NH);
     o.mpf = L.take<float>(8 * NH);  // mixed-precision SOR: e and r32, two pairs each
     o.phi0 = L.take<double>(NC);    // learned warm start: phi of the previous step; the network's
@@ -241,8 +239,8 @@ struct ibm_ctx {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     // red-black SOR launch shape
     int sor_kernel = IBM_SOR_TEMPORAL;
-    int tb_sweeps = 5;
-    int tb_tx = 104, tb_ty = 32;
+    int tb_sweeps = 10;
+    int tb_tx = 76, tb_ty = 44;
     // device address of this device's static scratch array (the
     // allocation-free solve), resolved at ibm_init; nullptr if unavailable
     double* noalloc = nullptr;
@@ -492,7 +490,7 @@ inline int red_blocks(size_t n) {
 // when the loaded tile would not fit the LDS budget or the per-thread
 // position registers.
 bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts) {
-    if (S < 1 || S > 8 || tx < 2 || (tx & 1) || ty < 2 || (ty & 1)) return false;
+    if (S < 1 || S > 12 || tx < 2 || (tx & 1) || ty < 2 || (ty & 1)) return false;
     const int H = 2 * S + 2;
     const int lx = std::min(c->nx, tx + 2 * H), ly = std::min(c->ny, ty + 2 * H);
     // one lane per split column, kTbRows rows per wave
@@ -550,7 +548,7 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
     long carry_nl = 0;
     auto check = [&](int phase, int it, int nb, const double* part, long nl) -> int32_t {
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, part, nb, phase, it, max_e, tol_e,
+        hipLaunchKernelGGL(k_check, dim3(1), dim3(kRedThreads), 0, c->stream, ctl, part, nb, phase, it, max_e, tol_e,
                            (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
         return pend_push(c, pending, s, nl);
@@ -676,7 +674,6 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
 // ---------------------------------------------------------------------------
 int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
-    const dim3 bl(kBlock);
     const bool fixed_mode = fixed >= 0;
     const double tol_e = fixed_mode ? -1.0 : tol;
     const int max_e = fixed_mode ? fixed : max_iter;
@@ -705,7 +702,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     long carry_nl = 0;
     auto check = [&](int phase, int it, const double* prt, long nl) -> int32_t {
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, prt, nbr, phase, it, max_e, tol_e,
+        hipLaunchKernelGGL(k_check, dim3(1), dim3(kRedThreads), 0, c->stream, ctl, prt, nbr, phase, it, max_e, tol_e,
                            (int)fixed_mode, 0, c->dslots + s);
         LAUNCH_CHECK();
         return pend_push(c, pending, s, nl);
@@ -1056,7 +1053,7 @@ int32_t helm_loop(ibm_ctx* c, int comp, double beta, LoopOut* out) {
         hipLaunchKernelGGL(k_helm_residual, dim3(nb), dim3(kRedThreads), 0, c->stream, c->g, comp, (const double*)x,
                            rhs, beta, (const Ctl*)ctl, c->partials);
         const int s = next_slot(c);
-        hipLaunchKernelGGL(k_check, dim3(1), bl, 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
+        hipLaunchKernelGGL(k_check, dim3(1), dim3(kRedThreads), 0, c->stream, ctl, (const double*)c->partials, nb, phase, it, max_e,
                            tol, 0, 1, c->dslots + s);
         LAUNCH_CHECK();
         HIP_TRY(hipEventRecord(c->ev[s], c->stream));
@@ -2418,8 +2415,6 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
     g.pcE = D(off.pcE); g.pcW = D(off.pcW); g.pcD = D(off.pcD); g.pcN = D(off.pcN); g.pcS = D(off.pcS);
     g.uce = D(off.uce); g.ucw = D(off.ucw); g.ucn = D(off.ucn); g.ucs = D(off.ucs);
     g.vce = D(off.vce); g.vcw = D(off.vcw); g.vcn = D(off.vcn); g.vcs = D(off.vcs);
-    g.rdr = D(off.rdr); g.rdb = D(off.rdb);
-    g.rdr32 = (const float*)(w + off.rdr32); g.rdb32 = (const float*)(w + off.rdb32);
     c->u = D(off.u); c->nu = D(off.nu); c->ru = D(off.ru); c->fufull = D(off.fufull);
     c->v = D(off.v); c->nv = D(off.nv); c->rv = D(off.rv); c->fvfull = D(off.fvfull);
     c->p = D(off.p); c->phi = D(off.phi); c->vb = D(off.vb); c->pr = D(off.pr); c->pp = D(off.pp);
@@ -2494,8 +2489,6 @@ int32_t ibm_init(const ibm_params* prm, const double* xf, const double* yf, cons
         hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, c->stream, c->ctl, (int)CTL_N);
         hipLaunchKernelGGL(k_ndiag, grid2(nx, ny), dim3(kBlock), 0, c->stream, c->g, c->dn);
         hipLaunchKernelGGL(k_rdiag, grid2(nx, ny), dim3(kBlock), 0, c->stream, c->g, (const double*)c->dn, c->rdn);
-        hipLaunchKernelGGL(k_rdiag_split, grid2(c->nh, ny), dim3(kBlock), 0, c->stream, c->g, (double*)c->g.rdr,
-                           (double*)c->g.rdb, (float*)c->g.rdr32, (float*)c->g.rdb32);
         if (hipGetLastError() != hipSuccess) rc = IBM_ERR_HIP;
     }
     if (rc) return fail(rc);

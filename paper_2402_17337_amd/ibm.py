@@ -340,7 +340,7 @@ class Solver:
             self.net_f = int(value)
         return rc
 
-    def autotune_tiles(self, candidates=((104, 32), (64, 32), (64, 24), (48, 16), (32, 16)), iters: int = 200,
+    def autotune_tiles(self, candidates=((76, 44), (84, 52), (64, 40), (48, 32), (48, 16), (32, 16)), iters: int = 200,
                        seed: int = 0):
         """Time `iters` fixed SOR iterations of a stand-alone solve (random
         right-hand side) with each candidate tile shape of the blocked sweep,
@@ -458,7 +458,7 @@ class Batch:
         if rc != OK:
             raise IbmError(f"ibm_batch_set_graph({intervals}) failed: {status_string(rc)}")
 
-    def autotune_tiles(self, candidates=((104, 32), (104, 40), (80, 32), (64, 32), (48, 16)),
+    def autotune_tiles(self, candidates=((76, 44), (84, 52), (80, 48), (64, 40), (48, 16)),
                        iters: int = 400):
         """Time one batched step of every case with its pressure solve replayed
         for `iters` iterations (ibm_set_poisson_schedule), from the current

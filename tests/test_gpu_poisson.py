@@ -176,12 +176,15 @@ def test_full_size_grid_fixed_iterations(torch):
 
 @pytest.mark.parametrize("nx,ny,sweeps,tile", [
     (128, 96, 5, (64, 40)),      # 2x3 tiles
-    (200, 150, 5, (104, 32)),    # the default shape; ragged tiles in x and y, stretched
+    (200, 150, 10, (76, 44)),    # the default shape; ragged tiles in x and y, stretched
+    (200, 150, 5, (104, 32)),    # ragged tiles in x and y, stretched
     (200, 150, 1, (32, 24)),
     (200, 150, 3, (16, 8)),      # many small tiles
     (256, 192, 2, (16, 12)),     # 256 tiles in the XCD-banded order
     (64, 48, 8, (64, 48)),       # one tile, deep halo clipped by the domain
-    (1024, 768, 5, (104, 32)),   # the plunging-workload grid, 240 tiles
+    (64, 48, 12, (64, 48)),      # the deepest halo (S = 12)
+    (1024, 768, 10, (76, 44)),   # the plunging-workload grid in the default shape, 252 tiles
+    (1024, 768, 5, (104, 32)),   # the same grid, 240 tiles of 5 iterations
     (1024, 768, 5, (104, 28)),   # 280 tiles: more blocks than compute units
     (512, 384, 2, (16, 12)),     # 1024 small tiles, several blocks per compute unit in turn
 ])
@@ -225,7 +228,8 @@ def test_blocked_sweep_rejects_shapes_that_do_not_fit(torch):
     xf, yf = _grid(256, 192, False)
     g = ibm.Solver(256, 192, xf, yf, body=0)
     assert g.set_option(ibm.OPT_TB_TILE_X, 63) == ibm.ERR_INVALID      # odd width
-    assert g.set_option(ibm.OPT_TB_SWEEPS, 9) == ibm.ERR_INVALID       # too deep
+    assert g.set_option(ibm.OPT_TB_SWEEPS, 13) == ibm.ERR_INVALID      # too deep
+    assert g.set_option(ibm.OPT_TB_TILE_X, 100) == ibm.ERR_INVALID     # 100 + 2 x 22 > 128 at S = 10
     assert g.set_option(ibm.OPT_TB_TILE_X, 256) == ibm.ERR_INVALID     # halo tile > LDS
     assert g.set_option(99, 1) == ibm.ERR_INVALID
     assert g.set_option(ibm.OPT_TB_SWEEPS, 4) == ibm.OK

@@ -92,7 +92,7 @@ def test_every_sweep_kernel_and_fixed_iterations(torch, kernel):
 
 
 def test_full_size_grid_in_the_benchmark_launch_shape(torch):
-    # the 1024x768 plunging grid (the largest the scratch holds), 104x32 tiles
+    # the 1024x768 plunging grid (the largest the scratch holds), default launch shape
     c = W.plunging_1024x768()
     g = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], body=0)
     b, x0 = _rhs(torch, c["nx"], c["ny"], 4)
