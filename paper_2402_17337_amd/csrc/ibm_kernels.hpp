@@ -945,63 +945,103 @@ __global__ __launch_bounds__(kTbThreads) void k_sor_mp(
 
 // Refinement of a mixed-precision interval: x = phi + e (e = 0 with e_zero)
 // into ophi, r = V b - A x rounded to float into or32; per-block partials of
-// r^2 and (V b)^2 in double.  Block b takes a contiguous range of rows (so the
-// rows above and below are mostly in its XCD's L2); the neighbours' x is
-// formed the same way where it is read.
+// r^2 and (V b)^2 in double.  The work is split into items of one wave: a
+// chunk of kMpRefineCols consecutive split positions (lanes 1..62; lanes 0 and
+// 63 carry the neighbouring positions) by kMpRefineRows rows.  A wave loads
+// x of both colours for its rows and the rows above and below once, takes
+// the east/west neighbours from the adjacent lanes (cross-lane moves) and
+// the north/south ones from its own registers; positions and rows outside
+// the grid hold x = 0, the value of an absent neighbour.
+constexpr int kMpRefineThreads = 256;          // four items per block
+constexpr int kMpRefineRows = 4;
+constexpr int kMpRefineCols = kWave - 2;
+
 __device__ inline double mp_x(const double* __restrict__ ph, const float* __restrict__ e, size_t k, int e_zero) {
     return e_zero ? ph[k] : ph[k] + (double)e[k];
 }
 
-// Block blk of nblk: its rows' refinement and its partials.
-__device__ __forceinline__ void mp_refine_rows(const Grid& g, const double* __restrict__ phr,
-                                               const double* __restrict__ phb, const float* __restrict__ er,
-                                               const float* __restrict__ eb, int e_zero,
-                                               const double* __restrict__ vbr, const double* __restrict__ vbb,
-                                               double* __restrict__ ophr, double* __restrict__ ophb,
-                                               float* __restrict__ orr, float* __restrict__ orb, int blk, int nblk,
-                                               double* partials, double* lds) {
+// Block blk of nblk: its items' refinement and its partials.
+__device__ __forceinline__ void mp_refine_block(const Grid& g, const double* __restrict__ phr,
+                                                const double* __restrict__ phb, const float* __restrict__ er,
+                                                const float* __restrict__ eb, int e_zero,
+                                                const double* __restrict__ vbr, const double* __restrict__ vbb,
+                                                double* __restrict__ ophr, double* __restrict__ ophb,
+                                                float* __restrict__ orr, float* __restrict__ orb, int blk, int nblk,
+                                                const Ctl* __restrict__ ctl, double* partials, double* lds) {
+    constexpr int R = kMpRefineRows;
     double acc[2] = {0.0, 0.0};
-    const int rows = (g.ny + nblk - 1) / nblk;
-    const int j0 = blk * rows, j1 = min(g.ny, j0 + rows);
-    const int npos = (j1 - j0) * g.nh;  // split positions of the block's rows
-    for (int q = threadIdx.x; q < npos; q += blockDim.x) {
-        const int jr = q / g.nh, m = q - jr * g.nh;
-        const int j = j0 + jr;
-        const size_t k = (size_t)j * g.nh + m;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int nchunk = (g.nh + kMpRefineCols - 1) / kMpRefineCols;
+    const int nstrip = (g.ny + R - 1) / R;
+    const int item = blk * (kMpRefineThreads / kWave) + w;
+    const bool work = item < nchunk * nstrip;  // wave-uniform
+    const int chunk = work ? item % nchunk : 0, strip = work ? item / nchunk : 0;
+    const int m = chunk * kMpRefineCols - 1 + lane;  // the lane's split position
+    const bool inx = work && m >= 0 && m < g.nh;
+    const bool own = inx && lane > 0 && lane < kWave - 1;
+    const int j0 = strip * R;
+    // x of both colours in rows j0 - 1 .. j0 + R, and V b of the lane's cells:
+    // one round trip of loads
+    double X[2][R + 2], bv[2][R];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const double* ps = c ? phb : phr;
-            const double* po = c ? phr : phb;
-            const float* es = c ? eb : er;
-            const float* eo = c ? er : eb;
-            const int s = (j + c) & 1, i = 2 * m + s;
-            const double dyj = g.dy[j], dxi = g.dx[i];
-            const double aE = dyj * g.pcE[i], aW = dyj * g.pcW[i], aD = dyj * g.pcD[i];
-            const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
-            const double x = mp_x(ps, es, k, e_zero);
-            const double xE = i < g.nx - 1 ? mp_x(po, eo, k + s, e_zero) : 0.0;
-            const double xW = i > 0 ? mp_x(po, eo, k + s - 1, e_zero) : 0.0;
-            const double xN = j < g.ny - 1 ? mp_x(po, eo, k + g.nh, e_zero) : 0.0;
-            const double xS = j > 0 ? mp_x(po, eo, k - g.nh, e_zero) : 0.0;
-            const double d = rb_diag(aE, aD, aW, aN, aS);
-            const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
-            const double bv = (c ? vbb : vbr)[k];
-            const double r = bv - (sum - d * x);
-            (c ? ophb : ophr)[k] = x;
-            (c ? orb : orr)[k] = (float)r;
-            acc[0] += r * r;
-            acc[1] += bv * bv;
+    for (int q = 0; q < R + 2; ++q) {
+        const int j = j0 - 1 + q;
+        X[0][q] = X[1][q] = 0.0;
+        if (inx && j >= 0 && j < g.ny) {
+            const size_t k = (size_t)j * g.nh + m;
+            X[0][q] = mp_x(phr, er, k, e_zero);
+            X[1][q] = mp_x(phb, eb, k, e_zero);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        bv[0][r] = bv[1][r] = 0.0;
+        if (own && j < g.ny) {
+            const size_t k = (size_t)j * g.nh + m;
+            bv[0][r] = vbr[k];
+            bv[1][r] = vbb[k];
+        }
+    }
+    // a finished solve is seen after the loads are issued (the flag's latency
+    // overlaps theirs; a finished solve only wastes them)
+    if (ctl->done) return;  // the same for the whole block
+    if (work) {
+        // x coefficients by position parity q (cell i = 2 m + q)
+        const int i0 = inx ? 2 * m : 0;
+        const double cdx[2] = {g.dx[i0], g.dx[i0 + 1]}, cE[2] = {g.pcE[i0], g.pcE[i0 + 1]};
+        const double cW[2] = {g.pcW[i0], g.pcW[i0 + 1]}, cD[2] = {g.pcD[i0], g.pcD[i0 + 1]};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = j0 + r;
+            if (j >= g.ny) break;  // wave-uniform
+            const double dyj = g.dy[j], pN = g.pcN[j], pS = g.pcS[j];
+            const size_t k = (size_t)j * g.nh + (inx ? m : 0);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int s = (j + c) & 1;  // position parity of colour c in row j
+                const double xo = X[1 - c][r + 1];
+                const double up = from_upper_lane(xo), dn = from_lower_lane(xo);
+                const double xE = s ? up : xo, xW = s ? xo : dn;
+                const double xN = X[1 - c][r + 2], xS = X[1 - c][r];
+                const double aE = dyj * cE[s], aW = dyj * cW[s], aD = dyj * cD[s];
+                const double aN = cdx[s] * pN, aS = cdx[s] * pS;
+                const double d = rb_diag(aE, aD, aW, aN, aS);
+                const double sum = rb_sum(aE, xE, aW, xW, aN, xN, aS, xS);
+                if (own) {
+                    const double x = X[c][r + 1];
+                    const double res = bv[c][r] - (sum - d * x);
+                    (c ? ophb : ophr)[k] = x;
+                    (c ? orb : orr)[k] = (float)res;
+                    acc[0] += res * res;
+                    acc[1] += bv[c][r] * bv[c][r];
+                }
+            }
         }
     }
     block_partials(acc, partials, nblk, blk, lds);
 }
-
-// The refinement runs on small blocks, each over a short range of rows (about
-// kMpRefinePositions split positions, two per thread): many blocks resident
-// per compute unit hide the latency of one block's loads behind the others'.
-constexpr int kMpRefineThreads = 256;
-constexpr int kMpRefinePositions = 512;
-constexpr int kMpRefineMaxBlocks = 4096;
 
 __global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine(Grid g, const double* __restrict__ phr,
                                                            const double* __restrict__ phb,
@@ -1013,8 +1053,8 @@ __global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine(Grid g, const do
                                                            float* __restrict__ orr, float* __restrict__ orb,
                                                            const Ctl* __restrict__ ctl, double* partials) {
     __shared__ double lds[2 * kRedThreads / kWave];
-    if (ctl->done) return;
-    mp_refine_rows(g, phr, phb, er, eb, e_zero, vbr, vbb, ophr, ophb, orr, orb, blockIdx.x, gridDim.x, partials, lds);
+    mp_refine_block(g, phr, phb, er, eb, e_zero, vbr, vbb, ophr, ophb, orr, orb, blockIdx.x, gridDim.x, ctl, partials,
+                    lds);
 }
 
 // Many cases of the mixed-precision solve in one launch per step of the
@@ -1076,10 +1116,9 @@ __global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine_batch(const MpCa
     __shared__ double lds[2 * kRedThreads / kWave];
     if ((int)blockIdx.x >= nblocks) return;
     const MpCase& C = cases[batch_case(cases, ncase, (int)blockIdx.x, &MpCase::rblk0)];
-    if (C.ctl->done) return;
-    mp_refine_rows(C.g, C.ph[pin][0], C.ph[pin][1], C.e[ein][0], C.e[ein][1], e_zero, C.bred, C.bblack,
-                   C.ph[pin ^ 1][0], C.ph[pin ^ 1][1], C.r[rout][0], C.r[rout][1], (int)blockIdx.x - C.rblk0, C.nbr,
-                   C.partials[pbuf], lds);
+    mp_refine_block(C.g, C.ph[pin][0], C.ph[pin][1], C.e[ein][0], C.e[ein][1], e_zero, C.bred, C.bblack,
+                    C.ph[pin ^ 1][0], C.ph[pin ^ 1][1], C.r[rout][0], C.r[rout][1], (int)blockIdx.x - C.rblk0, C.nbr,
+                    C.ctl, C.partials[pbuf], lds);
 }
 
 // Stop tests after a refinement, one block per case: the nbr partials of set
@@ -1474,12 +1513,75 @@ __global__ __launch_bounds__(kCgThreads) void k_cg1_iter(
     __shared__ double lds[3 * kCgThreads / kWave];
     __shared__ double s_alpha, s_beta;
     __shared__ int s_stop, s_done;
+    // The tile's loads that do not depend on this iteration's alpha and beta
+    // are issued first, so that their latency overlaps the control block's
+    // and the partial sums' (a finished solve only wastes them).
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD band of tiles
+    const bool tile = t < ntiles;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int X0 = tile ? (t % ntx) * kCgTx : 0, Y0 = tile ? (t / ntx) * kCgTy : 0;
+    const int i = X0 + lane;
+    const bool col = tile && i < g.nx;
+    const bool fst = first != 0;
+    double rr[kCgRows], ww[kCgRows], ss[kCgRows], rd[kCgRows], xo[kCgRows], po[kCgRows];
+#pragma unroll
+    for (int r = 0; r < kCgRows; ++r) {
+        const int j = Y0 + kCgRows * w + r;
+        rr[r] = ww[r] = ss[r] = rd[r] = xo[r] = po[r] = 0.0;
+        if (col && j < g.ny) {
+            const size_t k = (size_t)j * g.nx + i;
+            rr[r] = r_in[k];
+            ww[r] = w_in[k];
+            ss[r] = fst ? 0.0 : s_in[k];
+            rd[r] = rdn[k];
+            xo[r] = x[k];
+            po[r] = fst ? 0.0 : p[k];
+        }
+    }
+    // the frame: rows -1 and kCgTy (threads 0..127), columns -1 and kCgTx
+    // (threads 128..191); cells outside the domain read as 0 (channel),
+    // periodic mode wraps
+    const int ft = threadIdx.x;
+    const bool frame = tile && ft < 2 * kCgTx + 2 * kCgTy;
+    int hx = 0, hy = 0;
+    bool fin = false;
+    double fr = 0.0, fw = 0.0, fs = 0.0, frd = 0.0;
+    if (frame) {
+        if (ft < 2 * kCgTx) {
+            hx = ft & (kCgTx - 1);
+            hy = ft < kCgTx ? -1 : kCgTy;
+        } else {
+            const int q = ft - 2 * kCgTx;
+            hx = q < kCgTy ? -1 : kCgTx;
+            hy = q < kCgTy ? q : q - kCgTy;
+        }
+        int gi = X0 + hx, gj = Y0 + hy;
+        fin = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+        if (g.per && !fin) {
+            // only across the domain's ends (a ragged tile's frame past
+            // nx or ny inside the grid does not exist there)
+            if (gi == -1) gi = g.nx - 1;
+            else if (gi == g.nx) gi = 0;
+            if (gj == -1) gj = g.ny - 1;
+            else if (gj == g.ny) gj = 0;
+            fin = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+        }
+        if (fin) {
+            const size_t k = (size_t)gj * g.nx + gi;
+            fr = r_in[k];
+            fw = w_in[k];
+            fs = fst ? 0.0 : s_in[k];
+            frd = rdn[k];
+        }
+    }
     if (threadIdx.x == 0) s_done = ctl->done;
     __syncthreads();
     if (s_done) {
         if (blockIdx.x == 0 && threadIdx.x == 0) publish(ctl, hs);
         return;
     }
+
     double acc[3];
     sum_partials(acc, part_in, nb, lds);
     if (threadIdx.x == 0) {
@@ -1519,62 +1621,16 @@ __global__ __launch_bounds__(kCgThreads) void k_cg1_iter(
     __syncthreads();
     if (s_stop) return;
     const double alpha = s_alpha, beta = s_beta;
-    const bool fst = first != 0;
     double pacc[3] = {0.0, 0.0, 0.0};
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);  // XCD band of tiles
-    if (t < ntiles) {
-        const int lane = threadIdx.x & (kWave - 1);
-        const int w = threadIdx.x / kWave;
-        const int X0 = (t % ntx) * kCgTx, Y0 = (t / ntx) * kCgTy;
-        const int i = X0 + lane;
-        const bool col = i < g.nx;
-        double rr[kCgRows], ww[kCgRows], ss[kCgRows], rd[kCgRows], un[kCgRows];
+    if (tile) {
+        double un[kCgRows];
 #pragma unroll
         for (int r = 0; r < kCgRows; ++r) {
             const int tr = kCgRows * w + r, j = Y0 + tr;
-            rr[r] = ww[r] = ss[r] = rd[r] = un[r] = 0.0;
-            if (col && j < g.ny) {
-                const size_t k = (size_t)j * g.nx + i;
-                rr[r] = r_in[k];
-                ww[r] = w_in[k];
-                ss[r] = fst ? 0.0 : s_in[k];
-                rd[r] = rdn[k];
-                un[r] = cg1_unext(rr[r], ww[r], ss[r], rd[r], alpha, beta, fst);
-            }
+            un[r] = (col && j < g.ny) ? cg1_unext(rr[r], ww[r], ss[r], rd[r], alpha, beta, fst) : 0.0;
             su[(tr + 1) * kCgPitch + lane + 1] = un[r];
         }
-        // the frame: rows -1 and kCgTy (threads 0..127), columns -1 and kCgTx
-        // (threads 128..191); cells outside the domain read as 0 (channel),
-        // periodic mode wraps
-        const int ft = threadIdx.x;
-        if (ft < 2 * kCgTx + 2 * kCgTy) {
-            int hx, hy;
-            if (ft < 2 * kCgTx) {
-                hx = ft & (kCgTx - 1);
-                hy = ft < kCgTx ? -1 : kCgTy;
-            } else {
-                const int q = ft - 2 * kCgTx;
-                hx = q < kCgTy ? -1 : kCgTx;
-                hy = q < kCgTy ? q : q - kCgTy;
-            }
-            int gi = X0 + hx, gj = Y0 + hy;
-            bool in = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-            if (g.per && !in) {
-                // only across the domain's ends (a ragged tile's frame past
-                // nx or ny inside the grid does not exist there)
-                if (gi == -1) gi = g.nx - 1;
-                else if (gi == g.nx) gi = 0;
-                if (gj == -1) gj = g.ny - 1;
-                else if (gj == g.ny) gj = 0;
-                in = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-            }
-            double u = 0.0;
-            if (in) {
-                const size_t k = (size_t)gj * g.nx + gi;
-                u = cg1_unext(r_in[k], w_in[k], fst ? 0.0 : s_in[k], rdn[k], alpha, beta, fst);
-            }
-            su[(hy + 1) * kCgPitch + hx + 1] = u;
-        }
+        if (frame) su[(hy + 1) * kCgPitch + hx + 1] = fin ? cg1_unext(fr, fw, fs, frd, alpha, beta, fst) : 0.0;
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kCgRows; ++r) {
@@ -1586,9 +1642,9 @@ __global__ __launch_bounds__(kCgThreads) void k_cg1_iter(
             const double aN = dxi * g.pcN[j], aS = dxi * g.pcS[j];
             const double d = rb_diag(aE, aD, aW, aN, aS);
             const double uk = rr[r] * rd[r];
-            const double pk = fst ? uk : __fma_rn(beta, p[k], uk);
+            const double pk = fst ? uk : __fma_rn(beta, po[r], uk);
             const double sk = fst ? ww[r] : __fma_rn(beta, ss[r], ww[r]);
-            x[k] = __fma_rn(alpha, pk, x[k]);
+            x[k] = __fma_rn(alpha, pk, xo[r]);
             const double rnew = __fma_rn(-alpha, sk, rr[r]);
             const double unew = un[r];  // rnew * rd[r], formed as for the neighbours
             const int o = (tr + 1) * kCgPitch + lane + 1;

@@ -476,9 +476,11 @@ int32_t pend_pop(ibm_ctx* c, CheckQueue& cq, Slot* out, long* tag) {
 
 // Blocks of the mixed-precision refinement of a grid with nh_ny split
 // positions (the same split for the single-grid and the batched refinement).
-inline int mp_refine_blocks(size_t nh_ny) {
-    return (int)std::max<size_t>(1, std::min<size_t>(kMpRefineMaxBlocks, (nh_ny + kMpRefinePositions - 1) /
-                                                                          kMpRefinePositions));
+// Blocks of the refinement of an nx x ny grid (nh = nx / 2): items of
+// kMpRefineCols split positions by kMpRefineRows rows, four per block.
+inline int mp_refine_blocks(int nh, int ny) {
+    const long items = (long)((nh + kMpRefineCols - 1) / kMpRefineCols) * ((ny + kMpRefineRows - 1) / kMpRefineRows);
+    return (int)((items + kMpRefineThreads / kWave - 1) / (kMpRefineThreads / kWave));
 }
 
 inline int red_blocks(size_t n) {
@@ -685,7 +687,7 @@ int32_t mp_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int f
     const int S = c->tb_sweeps;
     const int tb_blocks = 8 * ts.per;
     const size_t NH = (size_t)c->nh * c->ny;
-    const int nbr = mp_refine_blocks(NH);
+    const int nbr = mp_refine_blocks(c->nh, c->ny);
     double* part[2] = {c->partials, c->partials + 2 * (size_t)nbr};
     double* cur[2] = {c->phr, c->phb};
     double* alt[2] = {c->phr2, c->phb2};
@@ -1744,7 +1746,7 @@ int32_t batch_upload_mp(ibm_batch* b) {
             }
         d.bred = c->vbr;
         d.bblack = c->vbb;
-        d.nbr = mp_refine_blocks(NH);
+        d.nbr = mp_refine_blocks(c->nh, c->ny);
         d.partials[0] = c->partials;
         d.partials[1] = c->partials + 2 * (size_t)d.nbr;
         d.ctl = c->ctl + CTL_P;
