@@ -1122,8 +1122,8 @@ __global__ __launch_bounds__(kMpRefineThreads) void k_mp_refine_batch(const MpCa
 }
 
 // Stop tests after a refinement, one block per case: the nbr partials of set
-// pbuf (phase 0: the initial residual).  At most kRedMax partials, so every
-// block size sums them in the same order as the single-grid tests.
+// pbuf (phase 0: the initial residual), summed with the single-grid tests'
+// thread count, so in their order.
 // Inside a captured stretch the iteration base and snapshot entry come from
 // the cursor (cur non-null), as for k_check_batch.
 __global__ __launch_bounds__(kTbThreads) void k_check_mp_batch(const MpCase* __restrict__ cases, int phase, int it,

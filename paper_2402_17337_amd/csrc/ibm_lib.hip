@@ -1865,7 +1865,7 @@ int32_t batch_sor_mp(ibm_batch* b, std::vector<LoopOut>& outs) {
     std::deque<std::pair<int, long>> pending;  // (ring entry, refinements before its test)
     auto check = [&](int phase, int it) -> int32_t {
         const int e = (int)(b->seq++ % kBatchRing);
-        hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
+        hipLaunchKernelGGL(k_check_mp_batch, dim3(n), dim3(kTbThreads), 0, b->stream,
                            (const MpCase*)b->dmp, phase, it, (int)((nref - 1) & 1), b->dslots + (size_t)e * n,
                            (const int*)nullptr);
         if (hipGetLastError() != hipSuccess) {
@@ -2004,9 +2004,9 @@ int32_t batch_sor(ibm_batch* b, std::vector<LoopOut>& outs) {
     std::deque<std::pair<int, long>> pending;
     auto check = [&](int phase, int it, int pbuf, long nl) -> int32_t {
         const int e = (int)(b->seq++ % kBatchRing);
-        // phase 0 sums the initial residual's partials as the single-grid k_check
-        // does (kBlock threads); later phases as the folded test (kTbThreads)
-        hipLaunchKernelGGL(k_check_batch, dim3(n), dim3(phase == 0 ? kBlock : kTbThreads), 0, b->stream,
+        // every phase sums its partials with the thread count of the
+        // single-grid tests (k_check and the folded test), so in their order
+        hipLaunchKernelGGL(k_check_batch, dim3(n), dim3(kTbThreads), 0, b->stream,
                            (const TbCase*)b->dcases, phase, it, pbuf, b->dslots + (size_t)e * n,
                            (const int*)nullptr);
         if (hipGetLastError() != hipSuccess) {
