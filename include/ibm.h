@@ -417,13 +417,14 @@ int32_t ibm_profile_query(ibm_ctx* ctx, int32_t kernel, double* avg_ms, int64_t*
  *                       held in registers; IBM_SOR_TEMPORAL_LDS: the same
  *                       with the tile in LDS; IBM_SOR_PER_COLOUR: one launch
  *                       per colour sweep;
- *   IBM_OPT_TB_SWEEPS   iterations per blocked launch, 1..8 (default 5);
- *   IBM_OPT_TB_TILE_X   interior tile width, even (default 104);
- *   IBM_OPT_TB_TILE_Y   interior tile height, even (default 32).
+ *   IBM_OPT_TB_SWEEPS   iterations per blocked launch S, 1..12 (default 10);
+ *   IBM_OPT_TB_TILE_X   interior tile width, even (default 76);
+ *   IBM_OPT_TB_TILE_Y   interior tile height, even (default 44).
  * The loaded tile (interior plus a halo of 2 S + 2 on each side, clamped to
- * the grid) must fit 128 x 64 cells.
- * IBM_ERR_INVALID for an unknown option or a tile shape whose halo does not
- * fit the block's LDS.  Applies to solves started after the call. */
+ * the grid) must fit 128 x 96 cells (one block of 16 waves, 6 rows per wave).
+ * IBM_ERR_INVALID for an unknown option or a tile shape whose loaded tile
+ * does not fit.  Applies to solves started after the call; the options
+ * apply to the mixed-precision sweeps and the batched solves as well. */
 #define IBM_OPT_SOR_KERNEL 0
 #define IBM_OPT_TB_SWEEPS 1
 #define IBM_OPT_TB_TILE_X 2
