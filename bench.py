@@ -586,10 +586,11 @@ def c1_leg(cpu=True):
     return out
 
 
-def pcg_long_leg(case, steps, method):
+def pcg_long_leg(case, steps, method, late_sor_steps=0):
     """Jacobi-PCG over a long stretch of the 1024x768 workload from t = 0
     (the workload's full length is 2000 steps): seconds per step over the
-    run and over its last tenth."""
+    run and over its last tenth; then, from the state it reached, a window of
+    late_sor_steps red-black SOR steps (the late-window SOR timing)."""
     import torch
     from paper_2402_17337_amd import ibm
 
@@ -609,13 +610,70 @@ def pcg_long_leg(case, steps, method):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cd, cl = g.forces()
+    blob = g.get_state() if late_sor_steps > 0 else None
     g.close()
     log(f"1024x768 PCG, {steps} steps from t = 0: {wall:.2f} s")
     last = (marks[-1] - marks[-2]) / max(1, steps // 10) if len(marks) >= 2 else wall / steps
-    return {"steps": steps, "solver": "one-reduction Jacobi-PCG" if method == ibm.CG1 else "Jacobi-PCG",
-            "s_per_time_step": round(wall / steps, 6),
-            "s_per_time_step_last_tenth": round(last, 6), "poisson_iters_mean": round(sum(iters) / steps, 1),
-            "poisson_iters_last": iters[-1], "cd_last": cd, "cl_last": cl}
+    out = {"steps": steps, "solver": "one-reduction Jacobi-PCG" if method == ibm.CG1 else "Jacobi-PCG",
+           "s_per_time_step": round(wall / steps, 6),
+           "s_per_time_step_last_tenth": round(last, 6), "poisson_iters_mean": round(sum(iters) / steps, 1),
+           "poisson_iters_last": iters[-1], "cd_last": cd, "cl_last": cl}
+    if late_sor_steps > 0:
+        s = ibm.Solver(case["nx"], case["ny"], case["xf"], case["yf"], device="cuda:0",
+                       **dict(case["params"], p_method=ibm.RBSOR))
+        s.set_state(blob)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [s.step(1) for _ in range(late_sor_steps)]
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        s.close()
+        if any(x["rc"] < 0 for x in sts):
+            raise RuntimeError(f"late SOR step failed: {sts}")
+        it = [x["p_iters"] for x in sts]
+        log(f"1024x768 SOR, steps {steps + 1}..{steps + late_sor_steps}: {w:.2f} s, iterations {it}")
+        out["sor_late_window"] = {
+            "steps": f"{steps + 1}..{steps + late_sor_steps}", "initial_guess": "previous phi (from the PCG run)",
+            "s_per_time_step": round(w / late_sor_steps, 6), "poisson_iters_per_step": it,
+            "cell_updates_per_s": round(case["nx"] * case["ny"] * sum(it) / w, 1)}
+    return out
+
+
+def poisson_bench_leg(case, fixed=10000):
+    """Stand-alone Poisson solves on the 1024x768 grid with a manufactured
+    right-hand side: the Laplacian of p = cos(pi x / 2 Lx) cos(pi y / Ly),
+    which meets the channel conditions (Neumann, p = 0 on the outlet face).
+    Red-black SOR and the one-reduction CG for `fixed` iterations (rate), and
+    each to 1e-8 from zero (iterations, seconds, error against p)."""
+    import numpy as np
+    import torch
+    from paper_2402_17337_amd import ibm
+
+    xf, yf = np.asarray(case["xf"]), np.asarray(case["yf"])
+    Lx, Ly = xf[-1] - xf[0], yf[-1] - yf[0]
+    xc, yc = 0.5 * (xf[1:] + xf[:-1]) - xf[0], 0.5 * (yf[1:] + yf[:-1]) - yf[0]
+    X, Y = np.meshgrid(xc, yc)
+    pe = np.cos(np.pi * X / (2 * Lx)) * np.cos(np.pi * Y / Ly)
+    b = -((np.pi / (2 * Lx)) ** 2 + (np.pi / Ly) ** 2) * pe
+    g = ibm.Solver(case["nx"], case["ny"], case["xf"], case["yf"], device="cuda:0", body=0)
+    rhs = torch.from_numpy(b).to("cuda:0")
+    cells = case["nx"] * case["ny"]
+    out = {"rhs": "Laplacian of cos(pi x / 2 Lx) cos(pi y / Ly) on the stretched grid", "fixed_iterations": fixed}
+    for name, m in (("sor", ibm.RBSOR), ("cg1", ibm.CG1)):
+        x = torch.zeros_like(rhs)
+        g.poisson_solve(rhs, x, method=m, fixed_iters=100)  # warm-up
+        x.zero_()
+        st = g.poisson_solve(rhs, x, method=m, fixed_iters=fixed)
+        x.zero_()
+        st2 = g.poisson_solve(rhs, x, method=m, tol=1e-8, max_iter=20_000_000)
+        err = float(np.max(np.abs(x.cpu().numpy() - pe)))
+        out[name] = {"fixed_s": round(st["seconds"], 6), "cell_updates_per_s": round(cells * fixed / st["seconds"], 1),
+                     "to_1e-8_iters": st2["iters"], "to_1e-8_s": round(st2["seconds"], 4), "rc": st2["rc"],
+                     "max_error_vs_p": err}
+        log(f"Poisson bench {name}: {fixed} iterations in {st['seconds'] * 1e3:.2f} ms; to 1e-8: "
+            f"{st2['iters']} iterations in {st2['seconds']:.3f} s, max |x - p| {err:.2e}")
+    g.close()
+    return out
 
 
 def scaling_leg(steps=3, warmup=2, sor_iters=2000):
@@ -755,7 +813,11 @@ def main():
                     help="timed runs of the headline, PCG and mixed-precision legs (the same steps from the same "
                          "checkpoint); the median is reported")
     ap.add_argument("--c1", type=int, default=1, help="1: time all 100 steps of the 128x96 workload (GPU and oracle)")
-    ap.add_argument("--pcg-long-steps", type=int, default=200,
+    ap.add_argument("--late-sor-steps", type=int, default=10,
+                    help="SOR steps timed after the long PCG run, from its state (0: skip)")
+    ap.add_argument("--poisson-bench", type=int, default=1,
+                    help="1: stand-alone Poisson solves with a manufactured right-hand side")
+    ap.add_argument("--pcg-long-steps", type=int, default=1000,
                     help="steps of the long Jacobi-PCG run of the 1024x768 workload from t = 0 (0: skip)")
     ap.add_argument("--scaling", type=int, default=1,
                     help="1: input-scaling rows at 0.6, 1.2 and 1.8 M cells (PCG steps, SOR rate)")
@@ -948,7 +1010,9 @@ def main():
     if args.c1:
         out["c1_full_run"] = c1_leg(cpu=args.cpu_seconds > 0)
     if args.solver == "sor" and args.pcg_long_steps > 0:
-        out["pcg_long"] = pcg_long_leg(case, args.pcg_long_steps, ibm.CG1)
+        out["pcg_long"] = pcg_long_leg(case, args.pcg_long_steps, ibm.CG1, args.late_sor_steps)
+    if args.poisson_bench:
+        out["poisson_bench"] = poisson_bench_leg(case)
     if args.scaling:
         out["input_scaling"] = scaling_leg()
     if args.cpu_seconds > 0:
