@@ -813,11 +813,11 @@ def main():
                     help="timed runs of the headline, PCG and mixed-precision legs (the same steps from the same "
                          "checkpoint); the median is reported")
     ap.add_argument("--c1", type=int, default=1, help="1: time all 100 steps of the 128x96 workload (GPU and oracle)")
-    ap.add_argument("--late-sor-steps", type=int, default=10,
+    ap.add_argument("--late-sor-steps", type=int, default=5,
                     help="SOR steps timed after the long PCG run, from its state (0: skip)")
     ap.add_argument("--poisson-bench", type=int, default=1,
                     help="1: stand-alone Poisson solves with a manufactured right-hand side")
-    ap.add_argument("--pcg-long-steps", type=int, default=1000,
+    ap.add_argument("--pcg-long-steps", type=int, default=400,
                     help="steps of the long Jacobi-PCG run of the 1024x768 workload from t = 0 (0: skip)")
     ap.add_argument("--scaling", type=int, default=1,
                     help="1: input-scaling rows at 0.6, 1.2 and 1.8 M cells (PCG steps, SOR rate)")
