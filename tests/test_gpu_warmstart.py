@@ -334,3 +334,47 @@ def test_zero_network_corrections_at_full_size(mixed):
         assert sa[key] == sb[key], (key, sa[key], sb[key])
     for x, y in zip(a.fields(), b.fields()):
         assert np.array_equal(x, y)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_learned_corrections_agree_with_the_oracle_within_the_stop_tests_spread():
+    """Steps with network corrections inside the SOR solve against the
+    oracle's plain SOR steps.  Both stop at a residual of p_tol, at different
+    points of different iterate paths, so they agree to the spread the stop
+    test allows, not to rounding: the bar is ten times the spread between the
+    oracle's own runs from the previous-step and the zero initial guess (two
+    valid stopping points of the same steps)."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    wl = _wl()
+    n = 3
+
+    def oracle(prev):
+        o = O.Oracle(wl["nx"], wl["ny"], wl["xf"], wl["yf"], wl["u0"], wl["v0"], wl["p0"],
+                     **dict(wl["params"], p_init_prev=prev))
+        rc, _ = o.step(n)
+        assert rc == O.OK
+        return o.fields()[:3]
+
+    fo, fz = oracle(1), oracle(0)
+    spread = [_rel(a, b) for a, b in zip(fz, fo)]
+    b = _solver(wl, p_init_prev=ibm.INIT_LEARNED)
+    assert b.set_option(ibm.OPT_NET_FACTOR, 2) == ibm.OK
+    assert b.set_option(ibm.OPT_NET_EVERY, 200) == ibm.OK
+    net = U.UNet(1, wl["ny"] // 2, wl["nx"] // 2, stream=b.stream)
+    net.set_params(U.flatten_params(OU.init_params(8)))
+    b.set_warm_start(net, 0.1)
+    nets = 0
+    for _ in range(n):
+        st = b.step(1)
+        assert st["rc"] == ibm.OK and st["p_rel"] <= wl["params"]["p_tol"]
+        nets += st["n_net"]
+    assert nets > 0  # the network did correct the iterates
+    errs = [_rel(a, c) for a, c in zip(b.fields()[:3], fo)]
+    print("learned vs oracle", errs, "oracle spread", spread, flush=True)
+    for name, e, s in zip("uvp", errs, spread):
+        assert e <= 10 * s, (name, e, s)
