@@ -256,12 +256,12 @@ def c3_learned_leg(params, scale, steps, mp_check=10):
 
 
 def learned_legs(case, args, sor_leg):
-    """Train the warm-start network on the GPU (two rounds, see
+    """Train the warm-start network on the GPU (the recipe of
     paper_2402_17337_amd.warmstart.train_default), then time the same steps as
-    the headline leg with the zero guess, the learned guess alone, and the
-    learned correction every args.learned_every SOR iterations (from the
-    previous step's phi, and from the learned guess); PCG with the learned
-    guess beside PCG's own legs."""
+    the headline leg with the learned correction every args.learned_every SOR
+    iterations from the previous step's phi (FP64 and FP32 sweeps), and with
+    args.learned_guess_legs also the zero guess and the learned guess alone;
+    PCG with the learned guess beside PCG's own legs."""
     import numpy as np
     from paper_2402_17337_amd import ibm
     from paper_2402_17337_amd import warmstart as WS
@@ -278,8 +278,9 @@ def learned_legs(case, args, sor_leg):
            "reference": {"initial_guess": "previous phi", "s_per_time_step": round(base_s, 6),
                          "poisson_iters_per_step": sor_leg["iters"]}}
     legs = [("zero_guess", ibm.INIT_ZERO, None, ibm.RBSOR, None),
-            ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts), ibm.RBSOR, None),
-            ("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR, None)]
+            ("learned_guess", ibm.INIT_LEARNED, (params, scale, F, 0, opts), ibm.RBSOR, None)] \
+        if args.learned_guess_legs else []
+    legs.append(("learned_correction", ibm.INIT_PREVIOUS, (params, scale, F, every, opts), ibm.RBSOR, None))
     if every % args.mp_check == 0:
         # the learned correction with FP32 sweeps and FP64 refinement (the
         # refinement interval divides the correction interval)
@@ -791,6 +792,8 @@ def main():
                     help="1: also time the SOR kernels on the HBM-resident 8192x6144 grid")
     ap.add_argument("--learned", type=int, default=1,
                     help="1: train the warm-start network on the GPU and time the learned guess and correction")
+    ap.add_argument("--learned-guess-legs", type=int, default=0,
+                    help="1: also time the zero guess and the learned guess alone (about 50 s more)")
     ap.add_argument("--mp-check", type=int, default=100,
                     help="stop-test (= refinement) interval of the FP32-sweep legs; the FP64 legs test every 10")
     ap.add_argument("--c3-learned-steps", type=int, default=2,
