@@ -587,11 +587,14 @@ def c1_leg(cpu=True):
     return out
 
 
-def pcg_long_leg(case, steps, method, late_sor_steps=0):
+def pcg_long_leg(case, steps, method, late_sor_steps=0, capture=()):
     """Jacobi-PCG over a long stretch of the 1024x768 workload from t = 0
     (the workload's full length is 2000 steps): seconds per step over the
     run and over its last tenth; then, from the state it reached, a window of
-    late_sor_steps red-black SOR steps (the late-window SOR timing)."""
+    late_sor_steps red-black SOR steps (the late-window SOR timing).  For
+    each step number in `capture`, the pressure system of that step (V b,
+    the previous phi, the step's iterations) is kept in `captured` (host
+    copies, taken between steps; not part of the returned line)."""
     import torch
     from paper_2402_17337_amd import ibm
 
@@ -599,12 +602,16 @@ def pcg_long_leg(case, steps, method, late_sor_steps=0):
                    device="cuda:0", **dict(case["params"], p_method=method))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    marks, iters = [], []
+    marks, iters, captured = [], [], []
     for k in range(steps):
+        phi_prev = g.fields()[3] if k + 1 in capture else None
         st = g.step(1)
         if st["rc"] < 0:
             raise RuntimeError(f"PCG step {k} failed: {st}")
         iters.append(st["p_iters"])
+        if phi_prev is not None:
+            captured.append({"step": k + 1, "vb": g.poisson_rhs(), "phi_prev": phi_prev,
+                             "step_iters": st["p_iters"]})
         if (k + 1) % max(1, steps // 10) == 0:
             torch.cuda.synchronize()
             marks.append(time.perf_counter() - t0)
@@ -637,15 +644,17 @@ def pcg_long_leg(case, steps, method, late_sor_steps=0):
             "steps": f"{steps + 1}..{steps + late_sor_steps}", "initial_guess": "previous phi (from the PCG run)",
             "s_per_time_step": round(w / late_sor_steps, 6), "poisson_iters_per_step": it,
             "cell_updates_per_s": round(case["nx"] * case["ny"] * sum(it) / w, 1)}
-    return out
+    return out, captured
 
 
-def poisson_bench_leg(case, fixed=10000):
+def poisson_bench_leg(case, fixed=10000, captured=()):
     """Stand-alone Poisson solves on the 1024x768 grid with a manufactured
     right-hand side: the Laplacian of p = cos(pi x / 2 Lx) cos(pi y / Ly),
     which meets the channel conditions (Neumann, p = 0 on the outlet face).
     Red-black SOR and the one-reduction CG for `fixed` iterations (rate), and
-    each to 1e-8 from zero (iterations, seconds, error against p)."""
+    each to 1e-8 from zero (iterations, seconds, error against p).  Then the
+    pressure systems captured from time steps of the workload (V b, from the
+    previous step's phi): the same rate and to-tolerance runs."""
     import numpy as np
     import torch
     from paper_2402_17337_amd import ibm
@@ -673,6 +682,27 @@ def poisson_bench_leg(case, fixed=10000):
                      "max_error_vs_p": err}
         log(f"Poisson bench {name}: {fixed} iterations in {st['seconds'] * 1e3:.2f} ms; to 1e-8: "
             f"{st2['iters']} iterations in {st2['seconds']:.3f} s, max |x - p| {err:.2e}")
+    area = np.diff(yf)[:, None] * np.diff(xf)[None, :]
+    rows = []
+    for cap in captured:
+        b = torch.from_numpy(cap["vb"] / area).to("cuda:0")
+        x0 = torch.from_numpy(cap["phi_prev"]).to("cuda:0")
+        row = {"step": cap["step"], "step_iters_cg1": cap["step_iters"]}
+        for name, m in (("sor", ibm.RBSOR), ("cg1", ibm.CG1)):
+            x = x0.clone()
+            st = g.poisson_solve(b, x, method=m, fixed_iters=fixed)
+            x.copy_(x0)
+            st2 = g.poisson_solve(b, x, method=m, tol=1e-8, max_iter=20_000_000)
+            row[name] = {"fixed_s": round(st["seconds"], 6),
+                         "cell_updates_per_s": round(cells * fixed / st["seconds"], 1),
+                         "to_1e-8_iters": st2["iters"], "to_1e-8_s": round(st2["seconds"], 4), "rc": st2["rc"]}
+        log(f"Poisson bench, step {cap['step']}'s system from the previous phi: SOR {row['sor']['to_1e-8_iters']} "
+            f"iterations in {row['sor']['to_1e-8_s']:.3f} s, CG1 {row['cg1']['to_1e-8_iters']} in "
+            f"{row['cg1']['to_1e-8_s']:.4f} s (the step took {cap['step_iters']} CG1 iterations)")
+        rows.append(row)
+    if rows:
+        out["captured_systems"] = {"rhs": "V b of time steps of the 1024x768 workload (one-reduction CG run from "
+                                          "t = 0), solved from the previous step's phi", "rows": rows}
     g.close()
     return out
 
@@ -819,7 +849,8 @@ def main():
     ap.add_argument("--late-sor-steps", type=int, default=5,
                     help="SOR steps timed after the long PCG run, from its state (0: skip)")
     ap.add_argument("--poisson-bench", type=int, default=1,
-                    help="1: stand-alone Poisson solves with a manufactured right-hand side")
+                    help="1: stand-alone Poisson solves with a manufactured right-hand side, and with the "
+                         "systems of steps 1, 10, 100 and the last of the long PCG run")
     ap.add_argument("--pcg-long-steps", type=int, default=400,
                     help="steps of the long Jacobi-PCG run of the 1024x768 workload from t = 0 (0: skip)")
     ap.add_argument("--scaling", type=int, default=1,
@@ -1012,10 +1043,14 @@ def main():
         out["stress_hbm"] = stress_leg()
     if args.c1:
         out["c1_full_run"] = c1_leg(cpu=args.cpu_seconds > 0)
+    captured = []
     if args.solver == "sor" and args.pcg_long_steps > 0:
-        out["pcg_long"] = pcg_long_leg(case, args.pcg_long_steps, ibm.CG1, args.late_sor_steps)
+        marks = tuple(k for k in (1, 10, 100, args.pcg_long_steps) if k <= args.pcg_long_steps) \
+            if args.poisson_bench else ()
+        out["pcg_long"], captured = pcg_long_leg(case, args.pcg_long_steps, ibm.CG1, args.late_sor_steps,
+                                                 capture=marks)
     if args.poisson_bench:
-        out["poisson_bench"] = poisson_bench_leg(case)
+        out["poisson_bench"] = poisson_bench_leg(case, captured=captured)
     if args.scaling:
         out["input_scaling"] = scaling_leg()
     if args.cpu_seconds > 0:

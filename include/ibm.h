@@ -253,6 +253,19 @@ int32_t ibm_forces(ibm_ctx* ctx, double* cd, double* cl);
  * u[(nx+1)*ny], v[nx*(ny+1)], p[nx*ny], phi[nx*ny].  Synchronizes. */
 int32_t ibm_get_fields(ibm_ctx* ctx, double* u, double* v, double* p, double* phi);
 
+/* The right-hand side V b of the pressure-correction equation A phi = V b
+ * that the last time step solved.  Paper: the pressure correction of the
+ * fractional-step method (Sec. 2.2) with the mass source q of Eq. 4:
+ * V b = V (D(u^) - q) / dt, V the cell area; in the periodic mode after its
+ * zero-mean projection.  vb[nx*ny] (natural layout, row j at j*nx), host or
+ * device memory; the copy runs on the context stream and the call returns
+ * when it is done.  To solve the same system with ibm_poisson_solve, divide by
+ * the cell areas (that call takes b per unit area).  IBM_ERR_INVALID (message
+ * in ibm_last_error) when no step's right-hand side is held: before the first
+ * step, and after a stand-alone solve (ibm_poisson_solve or its noalloc form,
+ * which use the same storage) or ibm_set_state, until the next step. */
+int32_t ibm_get_poisson_rhs(ibm_ctx* ctx, double* vb);
+
 /* Immersed-boundary data of the last step (each pointer nullable).
  * Paper: the solid/fluid flags of Sec. 2.2 (Table 1, "fluid/solid
  * flagging"), the cells of the mass source q (Eq. 4) and the forcing f

@@ -1347,6 +1347,12 @@ void orc_get_fields(const orc_ctx *c, double *u, double *v, double *p, double *p
     if (phi) memcpy(phi, c->phi, sizeof(double) * nx * ny);
 }
 
+/* V b of the last pressure solve (a time step's, after the zero-mean
+ * projection in the periodic mode, or orc_poisson_solve's), natural layout. */
+void orc_get_rhs(const orc_ctx *c, double *vb) {
+    memcpy(vb, c->vb, sizeof(double) * c->nx * c->ny);
+}
+
 void orc_set_fields(orc_ctx *c, const double *u, const double *v, const double *p) {
     const int nx = c->nx, ny = c->ny;
     if (u) memcpy(c->u, u, sizeof(double) * (nx + 1) * ny);

@@ -87,6 +87,7 @@ def lib():
         L.orc_step.restype = C.c_int
         L.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_set_fields.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_get_rhs.argtypes = [C.c_void_p, dp]
         L.orc_apply_A.argtypes = [C.c_void_p, dp, dp]
         L.orc_poisson_solve.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_double, C.c_double,
                                         C.c_int, C.c_int, C.c_int, C.POINTER(SolveStats)]
@@ -199,6 +200,13 @@ class Oracle:
         p = np.empty((ny, nx)); phi = np.empty((ny, nx))
         lib().orc_get_fields(self._h, _dp(u), _dp(v), _dp(p), _dp(phi))
         return u, v, p, phi
+
+    def poisson_rhs(self):
+        """V b of the last pressure solve (A phi = V b; a time step's, or
+        poisson_solve's), shape (ny, nx)."""
+        vb = np.empty((self.ny, self.nx))
+        lib().orc_get_rhs(self._h, _dp(vb))
+        return vb
 
     def set_fields(self, u=None, v=None, p=None):
         f = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (u, v, p)]

@@ -222,6 +222,7 @@ struct ibm_ctx {
     hipEvent_t ev[kSlots];
     double* hstage = nullptr;  // pinned: coef[2], counts[3], sum of the network steps
     int n_net = 0;             // network guesses and corrections of the current step
+    int rhs_held = 0;          // vb holds the last time step's V b
     // time stepping
     int have_hist = 0;
     long step = 0;
@@ -1427,6 +1428,7 @@ int32_t step_pre(ibm_ctx* c, ibm_step_stats* st, Body* Bout, int* status_out) {
                        (const double*)c->v, (const uint8_t*)c->flu, (const uint8_t*)c->flv,
                        (const uint8_t*)c->msrc, B.vb, dt, P.q_mode, c->vb);
     LAUNCH_CHECK();
+    c->rhs_held = 1;
     c->n_net = 0;
     c->net_step = 1.0;
     if (c->net) HIP_TRY(hipMemsetAsync(c->wscale + 3, 0, sizeof(double), c->stream));
@@ -2546,6 +2548,7 @@ int32_t ibm_poisson_solve(ibm_ctx* c, const double* rhs_dev, double* x_dev, cons
         return IBM_ERR_INVALID;
     }
     c->err.clear();
+    c->rhs_held = 0;
     const dim3 bl(kBlock);
     const int fixed = o->fixed_iters > 0 ? o->fixed_iters : -1;
     LoopOut lo;
@@ -2603,6 +2606,7 @@ int32_t ibm_poisson_solve_noalloc(ibm_ctx* c, const double* rhs_dev, double* x_d
         return IBM_ERR_HIP;
     }
     c->err.clear();
+    c->rhs_held = 0;
     double* base = c->noalloc;
     double* saved[] = {c->phr, c->phb, c->phr2, c->phb2, c->vbr, c->vbb, c->partials};
     Ctl* saved_ctl = c->ctl;
@@ -2652,6 +2656,18 @@ int32_t ibm_get_fields(ibm_ctx* c, double* u, double* v, double* p, double* phi)
     if (v) HIP_TRY(hipMemcpyAsync(v, c->v, NV * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (p) HIP_TRY(hipMemcpyAsync(p, c->p, NC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (phi) HIP_TRY(hipMemcpyAsync(phi, c->phi, NC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return IBM_OK;
+}
+
+int32_t ibm_get_poisson_rhs(ibm_ctx* c, double* vb) {
+    if (!c || !vb) return IBM_ERR_INVALID;
+    if (!c->rhs_held) {
+        c->err = "no time step's right-hand side is held (no step yet, or a stand-alone solve or a restored "
+                 "state since the last step)";
+        return IBM_ERR_INVALID;
+    }
+    HIP_TRY(hipMemcpyAsync(vb, c->vb, (size_t)c->nx * c->ny * sizeof(double), hipMemcpyDefault, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return IBM_OK;
 }
@@ -2725,6 +2741,7 @@ int32_t ibm_set_state(ibm_ctx* c, const void* host, size_t bytes) {
         d += n[k];
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
+    c->rhs_held = 0;
     c->have_hist = h.have_hist;
     c->step = h.step;
     c->t = h.t;

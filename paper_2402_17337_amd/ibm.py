@@ -40,7 +40,7 @@ SOR_TEMPORAL, SOR_PER_COLOUR, SOR_TEMPORAL_LDS = 0, 1, 2
 
 EXPORTED = ("ibm_workspace_bytes", "ibm_init", "ibm_step", "ibm_poisson_solve", "ibm_poisson_solve_noalloc",
             "ibm_forces",
-            "ibm_get_fields", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
+            "ibm_get_fields", "ibm_get_poisson_rhs", "ibm_get_ibm", "ibm_state_bytes", "ibm_get_state", "ibm_set_state",
             "ibm_set_poisson_schedule", "ibm_set_option", "ibm_set_warm_start", "ibm_set_snapshot",
             "ibm_batch_create", "ibm_batch_step", "ibm_batch_set_graph", "ibm_batch_destroy", "ibm_batch_last_error",
             "ibm_profile", "ibm_profile_query", "ibm_profile_phases", "ibm_destroy",
@@ -109,6 +109,8 @@ def lib():
         L.ibm_forces.restype = C.c_int32
         L.ibm_get_fields.argtypes = [vp, dp, dp, dp, dp]
         L.ibm_get_fields.restype = C.c_int32
+        L.ibm_get_poisson_rhs.argtypes = [vp, vp]
+        L.ibm_get_poisson_rhs.restype = C.c_int32
         L.ibm_get_ibm.argtypes = [vp, u8, u8, u8, dp, dp]
         L.ibm_get_ibm.restype = C.c_int32
         L.ibm_state_bytes.argtypes = [vp]
@@ -272,6 +274,23 @@ class Solver:
         if rc != OK:
             self._err("ibm_get_fields", rc)
         return u, v, p, phi
+
+    def poisson_rhs(self, out=None):
+        """V b of the last time step's pressure equation A phi = V b, (ny, nx)
+        float64: into `out` (a contiguous float64 tensor on this device) when
+        given, else a new host array."""
+        if out is None:
+            out = np.empty((self.ny, self.nx))
+            ptr = out.ctypes.data_as(C.c_void_p)
+        else:
+            if out.dtype != self.torch.float64 or not out.is_contiguous() or out.device != self.device \
+                    or out.numel() != self.nx * self.ny:
+                raise ValueError("out must be a contiguous float64 device tensor of nx*ny")
+            ptr = C.c_void_p(out.data_ptr())
+        rc = lib().ibm_get_poisson_rhs(self._h, ptr)
+        if rc != OK:
+            self._err("ibm_get_poisson_rhs", rc)
+        return out
 
     def ibm(self):
         nx, ny = self.nx, self.ny

@@ -96,6 +96,48 @@ def test_small_plunging_steps_match_oracle(torch):
     assert abs(last["cl"] - so[-1]["cl"]) <= 1e-8 * max(1.0, abs(so[-1]["cl"]))
 
 
+def test_step_rhs_matches_oracle_and_solves_to_the_steps_phi(torch):
+    # the right-hand side V b of each step's pressure equation (Sec. 2.2,
+    # Eq. 4's mass source) against the oracle's; the same system solved stand-
+    # alone from the previous phi stops where the step stopped
+    c = W.small_plunging()
+    nx, ny = c["nx"], c["ny"]
+    o = _oracle(c)
+    rc, so = o.step(3)
+    assert rc == O.OK
+    iters = [s["p_iters"] for s in so]
+    g = _solver(c)
+    with pytest.raises(ibm.IbmError):
+        g.poisson_rhs()  # no step yet
+    g.set_poisson_schedule(iters)
+    for _ in range(3):
+        phi_prev = g.fields()[3]
+        g.step(1)
+    phi_step = g.fields()[3]
+    vb = g.poisson_rhs()
+    err = rel_l2(vb, o.poisson_rhs())
+    print("V b against the oracle", f"{err:.2e}", flush=True)
+    assert err <= TOL
+    dev = torch.empty((ny, nx), dtype=torch.float64, device="cuda:0")
+    g.poisson_rhs(dev)
+    assert np.array_equal(dev.cpu().numpy(), vb)
+    area = np.diff(np.asarray(c["yf"]))[:, None] * np.diff(np.asarray(c["xf"]))[None, :]
+    b = torch.from_numpy(vb / area).to("cuda:0")
+    x = torch.from_numpy(phi_prev).to("cuda:0")
+    P = c["params"]
+    st = g.poisson_solve(b, x, method=ibm.RBSOR, omega=P["p_omega"], tol=P["p_tol"], check_every=P["p_check"])
+    print("stand-alone solve", st["iters"], "step", iters[-1], flush=True)
+    assert st["rc"] == ibm.OK and abs(st["iters"] - iters[-1]) <= P["p_check"]
+    assert rel_l2(x.cpu().numpy(), phi_step) <= 1e-6
+    with pytest.raises(ibm.IbmError):
+        g.poisson_rhs()  # the stand-alone solve used the same storage
+    g.step(1)
+    assert np.all(np.isfinite(g.poisson_rhs()))
+    g.set_state(g.get_state())
+    with pytest.raises(ibm.IbmError):
+        g.poisson_rhs()
+
+
 def test_pcg_steps_match_oracle(torch):
     c = W.small_plunging()
     over = dict(p_method=O.PCG, p_tol=1e-12, p_max_iter=50000)

@@ -427,6 +427,47 @@ def test_divergence_after_projection_equals_the_mass_source():
         assert np.max(np.abs(D - q)) < 1e-9 * max(1.0, scale), np.max(np.abs(D - q))
 
 
+def test_step_rhs_follows_its_definition_and_the_solve_meets_it():
+    """The right-hand side a time step hands to its pressure solve (Sec. 2.2,
+    the pressure-correction equation with Eq. 4's mass source), as the oracle
+    returns it, rebuilt from its definition V (D(u^) - q) / dt: u^ from
+    u^{n+1} + dt G phi (the outlet face too, phi = 0 half a cell beyond the
+    last centre), q from the forced faces found by the ellipse test.  The
+    solution phi meets it with the relative residual the step reports, at or
+    below the tolerance."""
+    nx, ny = 128, 96
+    xf, yf = W.uniform_faces(nx, 8.0), W.uniform_faces(ny, 6.0)
+    prm = dict(x0=4.0, y0=3.0, chord=2.0, thick=0.4, amp=0.3, freq=0.4, re=200.0, dt=2e-3,
+               p_method=O.PCG, p_tol=1e-10, p_max_iter=100000)
+    o = O.Oracle(nx, ny, xf, yf, **prm)
+    xc, yc = 0.5 * (xf[1:] + xf[:-1]), 0.5 * (yf[1:] + yf[:-1])
+    dx, dy = np.diff(xf), np.diff(yf)
+    a, b = 0.5 * prm["chord"], 0.5 * prm["thick"] * prm["chord"]
+    dt = prm["dt"]
+    for _ in range(3):
+        rc, st = o.step(1)
+        assert rc == O.OK
+        yb, vbody, _ = o.kinematics(st[-1]["t"])
+        u, v, _, phi = o.fields()
+        uh, vh = u.copy(), v.copy()
+        uh[:, 1:nx] += dt * (phi[:, 1:] - phi[:, :-1]) / (xc[1:] - xc[:-1])
+        uh[:, nx] += dt * (0.0 - phi[:, nx - 1]) / (xf[nx] - xc[nx - 1])
+        vh[1:ny, :] += dt * (phi[1:, :] - phi[:-1, :]) / (yc[1:] - yc[:-1])[:, None]
+        inu = _brute_inside(*np.meshgrid(xf, yc), prm["x0"], yb, a, b)
+        inv = _brute_inside(*np.meshgrid(xc, yf), prm["x0"], yb, a, b)
+        fu = np.where(inu, uh, 0.0)
+        fv = np.where(inv, vh - vbody, 0.0)
+        q = (fu[:, 1:] - fu[:, :-1]) / dx + (fv[1:, :] - fv[:-1, :]) / dy[:, None]
+        d = (uh[:, 1:] - uh[:, :-1]) / dx + (vh[1:, :] - vh[:-1, :]) / dy[:, None]
+        ref = (dx[None, :] * dy[:, None]) * ((d - q) / dt)
+        vb = o.poisson_rhs()
+        assert np.max(np.abs(ref)) > 1.0
+        assert np.max(np.abs(vb - ref)) <= 1e-9 * np.max(np.abs(ref)), np.max(np.abs(vb - ref))
+        rel = np.linalg.norm(vb - o.apply_A(phi)) / np.linalg.norm(vb)
+        assert rel <= prm["p_tol"]
+        assert abs(rel - st[-1]["p_rel"]) <= 1e-6 * rel
+
+
 def test_other_mass_source_reading_is_unstable():
     """The reading in which a cut cell's whole divergence is the mass source
     (its Poisson source vanishes, fully inside cells keep theirs) lets mass
