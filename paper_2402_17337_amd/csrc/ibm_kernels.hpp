@@ -553,16 +553,40 @@ __device__ inline void tbr_row(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], con
     x[C][R] = sor_step(x[C][R], sum, b[C][R], wrd[C][R], omx);
 }
 
-// One colour's half-sweep over the strip, rows R..kTbRows-1 (unrolled at
-// compile time, so every index into the thread's arrays is a constant).
-template <int C, int P, class T, int R = 0>
-__device__ inline void tbr_half(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows], T xS0,
+// Rows R..R1-1 of one colour's half-sweep (unrolled at compile time, so every
+// index into the thread's arrays is a constant).
+template <int C, int P, class T, int R, int R1>
+__device__ inline void tbr_rows(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows], T xS0,
                                 T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
                                 const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
                                 const int (&rdist)[kTbRows], int e, T omx) {
-    tbr_row<C, P, R>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
-    if constexpr (R + 1 < kTbRows)
-        tbr_half<C, P, T, R + 1>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    if constexpr (R < R1) {
+        tbr_row<C, P, R>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+        tbr_rows<C, P, T, R + 1, R1>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    }
+}
+
+// One colour's half-sweep over the strip, and the store of its two strip-end
+// rows into `edge` for the neighbouring waves.  The cells of one colour do not
+// depend on each other, so the row order is free: half of the inner rows
+// first, as the strip-end rows need the other waves' rows, read from LDS just
+// before the half-sweep (the inner rows hide that read's latency); then the
+// strip-end rows and their store; then the other inner rows, which hide the
+// store's latency before the barrier that ends the half-sweep.
+template <int C, int P, class T>
+__device__ inline void tbr_half(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], const T (&wrd)[2][kTbRows], T xS0,
+                                T xNR, const T (&cdx)[2], const T (&cE)[2], const T (&cW)[2],
+                                const T (&rdy)[kTbRows], const T (&rpn)[kTbRows], const T (&rps)[kTbRows],
+                                const int (&rdist)[kTbRows], int e, T omx, T (&edge)[2][kTrSlots][kWave], int w,
+                                int lane) {
+    static_assert(kTbRows >= 3, "the strip needs inner rows");
+    constexpr int M = 1 + (kTbRows - 2) / 2;
+    tbr_rows<C, P, T, 1, M>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    tbr_row<C, P, 0>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    tbr_row<C, P, kTbRows - 1>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
+    edge[C][2 * w + 1][lane] = x[C][0];
+    edge[C][2 * w + 2][lane] = x[C][kTbRows - 1];
+    tbr_rows<C, P, T, M, kTbRows - 1>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
 }
 
 // S red-black iterations on the thread's registers with the shrinking update
@@ -578,17 +602,13 @@ __device__ inline void tbr_sweeps(T (&x)[2][kTbRows], const T (&b)[2][kTbRows], 
         {   // red half-sweep h = 2 it + 1
             const int e = 2 * nsweep - (2 * it + 1) + extra;
             const T xS0 = edge[1][2 * w][lane], xNR = edge[1][2 * w + 3][lane];
-            tbr_half<0, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
-            edge[0][2 * w + 1][lane] = x[0][0];
-            edge[0][2 * w + 2][lane] = x[0][kTbRows - 1];
+            tbr_half<0, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx, edge, w, lane);
             __syncthreads();
         }
         {   // black half-sweep h = 2 it + 2
             const int e = 2 * nsweep - (2 * it + 2) + extra;
             const T xS0 = edge[0][2 * w][lane], xNR = edge[0][2 * w + 3][lane];
-            tbr_half<1, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx);
-            edge[1][2 * w + 1][lane] = x[1][0];
-            edge[1][2 * w + 2][lane] = x[1][kTbRows - 1];
+            tbr_half<1, P>(x, b, wrd, xS0, xNR, cdx, cE, cW, rdy, rpn, rps, rdist, e, omx, edge, w, lane);
             __syncthreads();
         }
     }
