@@ -468,6 +468,42 @@ def test_step_rhs_follows_its_definition_and_the_solve_meets_it():
         assert abs(rel - st[-1]["p_rel"]) <= 1e-6 * rel
 
 
+def test_projection_leaves_the_solve_residual_as_divergence():
+    """D G = A / V, so after the projection u^{n+1} = u^ - dt G phi every
+    cell without a forced face has V D(u^{n+1}) = dt (V b - A phi): the
+    divergence left is the pressure solve's residual, at any tolerance
+    (checked at 1e-3, where that residual is far above rounding).  D is
+    written out here from the faces; V b and A come from the oracle."""
+    nx, ny = 128, 96
+    xf, yf = W.uniform_faces(nx, 8.0), W.uniform_faces(ny, 6.0)
+    prm = dict(x0=4.0, y0=3.0, chord=2.0, thick=0.4, amp=0.3, freq=0.4, re=200.0, dt=2e-3,
+               p_method=O.SOR, p_tol=1e-3)
+    o = O.Oracle(nx, ny, xf, yf, **prm)
+    xc, yc = 0.5 * (xf[1:] + xf[:-1]), 0.5 * (yf[1:] + yf[:-1])
+    dx, dy = np.diff(xf), np.diff(yf)
+    a, b = 0.5 * prm["chord"], 0.5 * prm["thick"] * prm["chord"]
+    for _ in range(3):
+        rc, st = o.step(1)
+        assert rc == O.OK and st[-1]["p_rel"] <= 1e-3
+        yb, _, _ = o.kinematics(st[-1]["t"])
+        u, v, _, phi = o.fields()
+        vol = dy[:, None] * dx[None, :]
+        div = (u[:, 1:] - u[:, :-1]) / dx + (v[1:, :] - v[:-1, :]) / dy[:, None]
+        res = prm["dt"] * (o.poisson_rhs() - o.apply_A(phi))
+        inu = _brute_inside(*np.meshgrid(xf, yc), prm["x0"], yb, a, b)
+        inv = _brute_inside(*np.meshgrid(xc, yf), prm["x0"], yb, a, b)
+        free = (inu[:, :-1] | inu[:, 1:] | inv[:-1, :] | inv[1:, :]) == 0
+        assert free.sum() > 0.9 * nx * ny
+        # both sides are sums of a few face fluxes dy u, dx v: a few ulps of
+        # the largest flux, far below the residual at this tolerance
+        flux = dy[:, None] * (np.abs(u[:, 1:]) + np.abs(u[:, :-1])) + dx * (np.abs(v[1:, :]) + np.abs(v[:-1, :]))
+        bar = 64 * np.finfo(float).eps * np.max(flux)
+        scale = np.max(np.abs(res[free]))
+        assert scale > 1e4 * bar  # the residual is far above rounding
+        err = np.max(np.abs(vol * div - res)[free])
+        assert err <= bar, (err, bar, scale)
+
+
 def test_other_mass_source_reading_is_unstable():
     """The reading in which a cut cell's whole divergence is the mass source
     (its Poisson source vanishes, fully inside cells keep theirs) lets mass
