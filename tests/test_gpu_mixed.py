@@ -199,3 +199,27 @@ def test_full_size_grids_in_the_benchmark_configuration(torch, which):
     assert rco == O.OK and st["rc"] == ibm.OK and st["iters"] == fixed
     assert d_or <= bar and d_64 <= bar
     assert abs(st["rel"] - so["rel"]) <= 1e-4 * so["rel"]
+
+
+def test_full_size_mixed_step_to_tolerance_leaves_the_residual_as_divergence(torch):
+    """The 2048x1536 workload, one step with FP32 sweeps refined every 100
+    iterations to the 1e-8 tolerance, as the benchmark runs it: the FP64
+    refinement leaves a residual that meets the double stop test, and the
+    projection turns it into the divergence, V D(u^{n+1}) = dt (V b - A phi),
+    in every cell without a mass source (a property that holds at any size;
+    A is the oracle's operator)."""
+    from paper_2402_17337_amd import workloads as W
+    from projection_identity import divergence_identity
+    c = W.plunging_2048x1536()
+    g = ibm.Solver(c["nx"], c["ny"], c["xf"], c["yf"], c["u0"], c["v0"], c["p0"],
+                   **dict(c["params"], p_method=ibm.RBSOR_MP, p_check=100))
+    st = g.step(1)
+    print("2048x1536 mixed step: iterations", st["p_iters"], "p_rel", st["p_rel"], flush=True)
+    assert st["rc"] == ibm.OK and st["p_rel"] <= c["params"]["p_tol"]
+    u, v, _, phi = g.fields()
+    A = O.Oracle(c["nx"], c["ny"], c["xf"], c["yf"], **c["params"]).apply_A
+    d = divergence_identity(u, v, g.poisson_rhs(), phi, g.ibm()["msrc"], c["xf"], c["yf"], c["params"]["dt"], A)
+    print("divergence identity", d, flush=True)
+    assert d["rel"] <= c["params"]["p_tol"] and abs(d["rel"] - st["p_rel"]) <= 1e-3 * d["rel"]
+    assert d["scale"] > 100 * d["bar"] and d["err"] <= d["bar"]
+    g.close()

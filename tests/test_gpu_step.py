@@ -205,35 +205,21 @@ def test_full_size_steps_to_tolerance_leave_the_residual_as_divergence(torch):
     2.2's projection of Eqs. 3-4), and that residual meets the stop test.  D is
     written out from the GPU's faces, A is the oracle's operator, V b the
     GPU's (ibm_get_poisson_rhs)."""
+    from projection_identity import divergence_identity
     c = W.plunging_1024x768()
     nx, ny = c["nx"], c["ny"]
     g = _solver(c)
     A = _oracle(c).apply_A
-    xf, yf = np.asarray(c["xf"]), np.asarray(c["yf"])
-    dx, dy = np.diff(xf), np.diff(yf)
-    vol = dy[:, None] * dx[None, :]
-    dt = c["params"]["dt"]
     for k in range(2):
         sg = g.step(1)
         print("step", k + 1, "iterations", sg["p_iters"], "p_rel", sg["p_rel"], flush=True)
         assert sg["rc"] == ibm.OK and sg["p_rel"] <= c["params"]["p_tol"]
         u, v, _, phi = g.fields()
-        vb = g.poisson_rhs()
-        r = vb - A(phi)
-        rel = np.linalg.norm(r) / np.linalg.norm(vb)
-        assert rel <= c["params"]["p_tol"] and abs(rel - sg["p_rel"]) <= 1e-3 * rel
-        div = (u[:, 1:] - u[:, :-1]) / dx + (v[1:, :] - v[:-1, :]) / dy[:, None]
-        free = g.ibm()["msrc"] == 0
-        assert free.sum() > 0.99 * nx * ny
-        scale = np.max(np.abs(dt * r[free]))
-        err = np.max(np.abs(vol * div - dt * r)[free])
-        # both sides are sums of a few face fluxes dy u, dx v (V b is V D(u^)
-        # of the predicted velocity u^ = u^{n+1} + dt G phi): their rounding
-        # is a few ulps of the largest flux, far below the residual itself
-        flux = dy[:, None] * (np.abs(u[:, 1:]) + np.abs(u[:, :-1])) + dx * (np.abs(v[1:, :]) + np.abs(v[:-1, :]))
-        bar = 64 * np.finfo(float).eps * np.max(flux)
-        print("divergence against dt r:", f"{err:.2e}", "bar", f"{bar:.2e}", "residual", f"{scale:.2e}", flush=True)
-        assert scale > 100 * bar and err <= bar
+        d = divergence_identity(u, v, g.poisson_rhs(), phi, g.ibm()["msrc"], c["xf"], c["yf"], c["params"]["dt"], A)
+        print("divergence identity", d, flush=True)
+        assert d["rel"] <= c["params"]["p_tol"] and abs(d["rel"] - sg["p_rel"]) <= 1e-3 * d["rel"]
+        assert d["cells"] > 0.99 * nx * ny
+        assert d["scale"] > 100 * d["bar"] and d["err"] <= d["bar"]
 
 
 def test_runs_are_deterministic(torch):
