@@ -336,6 +336,41 @@ def test_zero_network_corrections_at_full_size(mixed):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_network_corrected_full_size_step_leaves_the_residual_as_divergence(mixed):
+    """The learned correction in the benchmark's configuration on the
+    1024x768 workload (a random network, factor-8 maps, a correction every 4000
+    iterations; FP64 sweeps, or FP32 sweeps refined every 100 iterations), one
+    step to the 1e-8 tolerance: the corrected solve meets the stop test and the
+    projection leaves V D(u^{n+1}) = dt (V b - A phi) where no mass source
+    acts (a property that holds at any size; A is the oracle's operator)."""
+    _need_gpu()
+    from paper_2402_17337_amd import ibm
+    from paper_2402_17337_amd import unet as U
+    from paper_2402_17337_amd import warmstart as WS
+    from paper_2402_17337_amd import workloads as W
+    from projection_identity import divergence_identity
+    wl = W.plunging_1024x768()
+    over = dict(p_init_prev=ibm.INIT_PREVIOUS)
+    if mixed:
+        over.update(p_method=ibm.RBSOR_MP, p_check=100)
+    b = _solver(wl, **over)
+    for opt, val in {ibm.OPT_NET_FACTOR: 8, ibm.OPT_NET_EVERY: 4000, **WS.RECIPE_OPTIONS}.items():
+        assert b.set_option(opt, val) == ibm.OK
+    net = U.UNet(1, wl["ny"] // 8, wl["nx"] // 8, stream=b.stream)
+    net.set_params(U.flatten_params(OU.init_params(8)))
+    b.set_warm_start(net, 1.0)
+    st = b.step(1)
+    print("corrected step: iterations", st["p_iters"], "corrections", st["n_net"], "p_rel", st["p_rel"], flush=True)
+    assert st["rc"] == ibm.OK and st["p_rel"] <= wl["params"]["p_tol"] and st["n_net"] > 10
+    u, v, _, phi = b.fields()
+    A = O.Oracle(wl["nx"], wl["ny"], wl["xf"], wl["yf"], **wl["params"]).apply_A
+    d = divergence_identity(u, v, b.poisson_rhs(), phi, b.ibm()["msrc"], wl["xf"], wl["yf"], wl["params"]["dt"], A)
+    print("divergence identity", d, flush=True)
+    assert d["rel"] <= wl["params"]["p_tol"] and abs(d["rel"] - st["p_rel"]) <= 1e-3 * d["rel"]
+    assert d["scale"] > 100 * d["bar"] and d["err"] <= d["bar"]
+
+
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
