@@ -117,6 +117,19 @@ def test_taylor_green_pcg_steps_match_oracle(torch):
         assert st["rc"] == ibm.OK, st
     for a, b, name in zip(g.fields()[:3], o.fields()[:3], "uvp"):
         assert rel_l2(a, b) <= TOL, (name, rel_l2(a, b))
+    # the last step's right-hand side V b, after its zero-sum projection (the
+    # singular periodic problem), on both sides.  V b = (dy (u_E - u_W) +
+    # dx (v_N - v_S)) / dt of the predicted velocity is a small difference of
+    # O(1) face fluxes, so the fields' relative bar carries over to it through
+    # the largest flux, not through V b's own size
+    vb, vo = g.poisson_rhs(), o.poisson_rhs()
+    u, v = o.fields()[:2]
+    dx, dy = 2 * np.pi / 48, 2 * np.pi / 32
+    flux = dy * (np.abs(u[:, 1:]) + np.abs(u[:, :-1])) + dx * (np.abs(v[1:, :]) + np.abs(v[:-1, :]))
+    bar = TOL * np.max(flux) / 2.5e-3
+    assert np.max(np.abs(vb - vo)) <= bar, (np.max(np.abs(vb - vo)), bar)
+    assert bar < 1e-2 * np.max(np.abs(vo))  # the bar still resolves V b
+    assert abs(vb.sum()) <= 1e-12 * np.abs(vb).sum() and abs(vo.sum()) <= 1e-12 * np.abs(vo).sum()
     # the vortex decayed as the exact solution does (the oracle's own pin, to
     # the discretisation error at this resolution)
     u = g.fields()[0]
