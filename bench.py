@@ -822,8 +822,9 @@ def main():
                     help="1: also time the SOR kernels on the HBM-resident 8192x6144 grid")
     ap.add_argument("--learned", type=int, default=1,
                     help="1: train the warm-start network on the GPU and time the learned guess and correction")
-    ap.add_argument("--learned-guess-legs", type=int, default=0,
-                    help="1: also time the zero guess and the learned guess alone (about 50 s more)")
+    ap.add_argument("--learned-guess-legs", type=int, default=1,
+                    help="1: also time the zero guess and the learned guess alone (the warm start proper, "
+                         "about 50 s)")
     ap.add_argument("--mp-check", type=int, default=100,
                     help="stop-test (= refinement) interval of the FP32-sweep legs; the FP64 legs test every 10")
     ap.add_argument("--c3-learned-steps", type=int, default=2,
