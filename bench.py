@@ -615,6 +615,7 @@ def pcg_long_leg(case, steps, method, late_sor_steps=0, capture=()):
         if (k + 1) % max(1, steps // 10) == 0:
             torch.cuda.synchronize()
             marks.append(time.perf_counter() - t0)
+            log(f"1024x768 PCG from t = 0: step {k + 1} of {steps}, {marks[-1]:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cd, cl = g.forces()
