@@ -139,7 +139,43 @@ __device__ inline double rb_row(const Grid& g, const double* __restrict__ other,
 
 // One colour of a red-black SOR iteration (one launch per colour):
 //   phi_P <- (1 - omega) phi_P + omega (sum a_nb phi_nb - V b_P) / (sum a_nb + a_D)
-// COLOR 0 updates the red cells ((i+j) even), COLOR 1 the black cells.
+// COLOR 0 updates the red cells ((i+j) even), COLOR 1 the black cells.  A
+// thread owns split position m and walks kSwRows rows of it (a block: 64
+// positions by kBlockRows such strips), keeping the other colour's values at
+// its position in rows j-1, j and j+1 in registers: per cell it loads phi,
+// V b, the other colour one row up and the one east/west neighbour that is
+// not at its own position, and stores phi; the x coefficients of its two
+// cells (i = 2m and 2m + 1) are loaded once.  Each cell's arithmetic is that
+// of rb_row and sor_step, so the iterates are those of every other SOR kernel.
+constexpr int kSwRows = 8;
+
+template <int S>
+__device__ inline void sweep_cell(const Grid& g, double* __restrict__ self, const double* __restrict__ other,
+                                  const double* __restrict__ bself, double wom, double omx, int m, int j,
+                                  const double (&cdx)[2], const double (&cE)[2], const double (&cW)[2],
+                                  const double (&cD)[2], double& xS, double& xC) {
+    // periodic mode wraps: cell nx-1's east neighbour is position 0 of the
+    // row, cell 0's west neighbour position nh-1, rows ny-1 and 0 are
+    // neighbours (same position: the colours alternate, nx and ny are even)
+    const size_t nh = g.nh, k = (size_t)j * nh + m;
+    const int i = 2 * m + S;
+    const double xN = j < g.ny - 1 ? other[k + nh] : (g.per ? other[m] : 0.0);
+    double xE, xW;
+    if (S) {
+        xW = xC;
+        xE = i < g.nx - 1 ? other[k + 1] : (g.per ? other[k + 1 - nh] : 0.0);
+    } else {
+        xE = xC;
+        xW = i > 0 ? other[k - 1] : (g.per ? other[k + nh - 1] : 0.0);
+    }
+    const double dyj = g.dy[j], dxi = cdx[S], pN = g.pcN[j], pS = g.pcS[j];
+    const double d = rb_diag(dyj * cE[S], dyj * cD[S], dyj * cW[S], dxi * pN, dxi * pS);
+    const double sum = sor_sum(dyj, cE[S], xE, cW[S], xW, dxi, pN, xN, pS, xS);
+    self[k] = sor_step(self[k], sum, bself[k], wom * (1.0 / d), omx);
+    xS = xC;
+    xC = xN;
+}
+
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void k_sor_sweep(Grid g, double* __restrict__ self,
                                                       const double* __restrict__ other,
@@ -147,14 +183,29 @@ __global__ __launch_bounds__(kBlock) void k_sor_sweep(Grid g, double* __restrict
                                                       const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int m = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
-    const int j = blockIdx.y * kBlockRows + threadIdx.x / kWave;
-    if (m >= g.nh || j >= g.ny) return;
-    const int s = (j + COLOR) & 1;
-    const int i = 2 * m + s;
-    const size_t k = (size_t)j * g.nh + m;
-    double d;
-    const double sum = rb_row(g, other, i, j, k, s, d);
-    self[k] = sor_step(self[k], sum, bself[k], omega * (1.0 / d), 1.0 - omega);
+    const int j0 = (blockIdx.y * kBlockRows + threadIdx.x / kWave) * kSwRows;  // even
+    if (m >= g.nh || j0 >= g.ny) return;
+    const int j1 = min(j0 + kSwRows, g.ny);
+    double cdx[2], cE[2], cW[2], cD[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int i = 2 * m + q;
+        cdx[q] = g.dx[i];
+        cE[q] = g.pcE[i];
+        cW[q] = g.pcW[i];
+        cD[q] = g.pcD[i];
+    }
+    const size_t nh = g.nh;
+    double xS = j0 > 0 ? other[(size_t)(j0 - 1) * nh + m] : (g.per ? other[(size_t)(g.ny - 1) * nh + m] : 0.0);
+    double xC = other[(size_t)j0 * nh + m];
+    const double omx = 1.0 - omega;
+    // rows in pairs: the even row's cell sits at position parity COLOR, the
+    // odd row's at the other one
+#pragma unroll 2
+    for (int j = j0; j < j1; j += 2) {
+        sweep_cell<COLOR & 1>(g, self, other, bself, omega, omx, m, j, cdx, cE, cW, cD, xS, xC);
+        if (j + 1 < j1) sweep_cell<(COLOR + 1) & 1>(g, self, other, bself, omega, omx, m, j + 1, cdx, cE, cW, cD, xS, xC);
+    }
 }
 
 // Residual r = V b - A phi over both colours: per-block partial sums of r^2

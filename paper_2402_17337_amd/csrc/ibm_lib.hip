@@ -523,7 +523,7 @@ bool tb_shape(const ibm_ctx* c, int S, int tx, int ty, TbShape* ts) {
 // ---------------------------------------------------------------------------
 int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int fixed, LoopOut* out) {
     Ctl* ctl = c->ctl + CTL_P;
-    const dim3 gr = grid2(c->nh, c->ny), bl(kBlock);
+    const dim3 bl(kBlock);
     const bool fixed_mode = fixed >= 0;
     const double tol_e = fixed_mode ? -1.0 : tol;
     const int max_e = fixed_mode ? fixed : max_iter;
@@ -610,12 +610,14 @@ int32_t sor_loop(ibm_ctx* c, double omega, double tol, int max_iter, int K, int 
                     }
                 } else {
                     const int itk = it + 1;
+                    const dim3 grs((unsigned)((c->nh + kWave - 1) / kWave),
+                                   (unsigned)((c->ny + kBlockRows * kSwRows - 1) / (kBlockRows * kSwRows)));
                     timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, k_sor_sweep<0>, gr, bl, 0, c->g, cur[0], (const double*)cur[1],
+                        LAUNCH_EV(ea, eb, k_sor_sweep<0>, grs, bl, 0, c->g, cur[0], (const double*)cur[1],
                                   (const double*)c->vbr, omega, (const Ctl*)ctl);
                     });
                     timed(c, IBM_KERNEL_SOR_SWEEP, itk, [&](hipEvent_t ea, hipEvent_t eb) {
-                        LAUNCH_EV(ea, eb, k_sor_sweep<1>, gr, bl, 0, c->g, cur[1], (const double*)cur[0],
+                        LAUNCH_EV(ea, eb, k_sor_sweep<1>, grs, bl, 0, c->g, cur[1], (const double*)cur[0],
                                   (const double*)c->vbb, omega, (const Ctl*)ctl);
                     });
                     it = itk;
